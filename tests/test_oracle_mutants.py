@@ -1,0 +1,55 @@
+"""The oracle's pins must catch plausible mistakes. Each mutant below plants one mistake in
+a temporary copy of the oracle source (CPU only), and the quick pin subset must fail on it.
+
+Mutants of the restart heuristics (constants, primal-weight smoothing) are deliberately
+absent: the paper does not fix them, so no external pin exists (parity unpinned)."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "pdhg_oracle.c")
+
+MUTANTS = {
+    "primal_step_sign": ("double xn = x[j] - tau * g;", "double xn = x[j] + tau * g;"),
+    "no_extrapolation": ("double w = 2.0 * axn[i] - ax[i];", "double w = axn[i];"),
+    "dual_prox_sign": ("double lo = v + sigma * P.blo[i];", "double lo = v - sigma * P.blo[i];"),
+    "swapped_sign_cone": ("else if (flo && !fhi) zs = ls > 0.0 ? ls : 0.0;",
+                          "else if (flo && !fhi) zs = ls < 0.0 ? ls : 0.0;"),
+    "dropped_dual_bound_term": ("if (zo > 0.0) dobj += P->oxlo[k] * zo;", "if (zo > 0.0) dobj += 0.0;"),
+    "transpose_wrong_index": ("ciT[dst] = i;", "ciT[dst] = ci[e];"),
+    "average_sign": ("xa[j] = xa[j] + wt * (x[j] - xa[j]);", "xa[j] = xa[j] + wt * (xa[j] - x[j]);"),
+    "residual_swapped_bounds": ("double rs = ax[i] - clampd(ax[i], P->blo[i], P->bhi[i]);",
+                                "double rs = ax[i] - clampd(ax[i], P->bhi[i], P->blo[i]);"),
+    "scaling_exponent_sign": ("return ldexp(1.0, -h);", "return ldexp(1.0, h);"),
+    "power_iteration_transposed_operand": ("csr_mv(n, rpT, ciT, vT, u, w);", "csr_mv(n, rp, ci, v, u, w);"),
+    "gap_denominator": ("K->rel_gap = fabs(p - d) / (1.0 + fabs(p) + fabs(d));",
+                        "K->rel_gap = fabs(p - d) / (1.0 + fabs(p));"),
+    "dual_residual_unscaled": ("double rdo = rds * P->Ci[k];", "double rdo = rds;"),
+}
+
+QUICK = [
+    "tests/test_oracle_pins.py",
+    "tests/test_oracle_exact.py::test_linear_recurrence_all_free_equalities",
+    "tests/test_oracle_exact.py::test_vertex_enumeration",
+    "tests/test_oracle_exact.py::test_kkt_point_is_fixed_point",
+    "tests/test_oracle_structure.py",
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(tmp_path, name):
+    import oracle
+
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    mut_src = tmp_path / "mutant.c"
+    mut_src.write_text(src.replace(old, new))
+    lib = oracle.compile_source(str(mut_src), str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, ORACLE_LIB_OVERRIDE=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", *QUICK],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
