@@ -1,0 +1,181 @@
+/*
+ * lp.h - C ABI of the MI355X restarted-PDHG linear-programming solver.
+ *
+ * Problem (the paper's Section 2, eq. 1):
+ *
+ *     minimize    c^T x + c0
+ *     subject to  b_lo <= A x <= b_hi
+ *                 x_lo <= x <= x_hi
+ *
+ * with A an m x n matrix in CSR form. Infinite entries of b_lo, b_hi, x_lo, x_hi are
+ * IEEE +-inf and mean "no bound"; an equality row has b_lo = b_hi.
+ *
+ * Solution (eq. 2): a primal x and duals (y, z) with c - A^T y - z = 0 up to the dual
+ * residual, y_i > 0 only where (Ax)_i = b_lo_i, y_i < 0 only where (Ax)_i = b_hi_i,
+ * z_k > 0 only where x_k = x_lo_k, z_k < 0 only where x_k = x_hi_k, z_k = 0 for a free
+ * x_k, y_i <= 0 where b_lo_i = -inf and y_i >= 0 where b_hi_i = +inf. z is returned as
+ * the reduced cost c - A^T y projected onto that sign pattern (Section 2.1, the dual
+ * postsolve identity z_k = c_k - a_k^T y).
+ *
+ * Termination: one relative tolerance eps_rel (Section 4.2) on
+ *   E_rel = max(||r_p|| / (1 + ||q||), ||r_d|| / (1 + ||c||), |p - d| / (1 + |p| + |d|)),
+ * with r_p the bound violation of Ax, r_d = c - A^T y - z (plus any sign violation of y),
+ * p, d the primal and dual objectives and q_i the largest finite |b_lo_i|, |b_hi_i|.
+ *
+ * Conventions for every function:
+ *  - The return value is an lp_error code (LP_OK = 0). No C++ exception crosses the ABI.
+ *  - Array arguments are host pointers unless stated otherwise; the library copies what
+ *    it needs before returning, so the caller may free its arrays afterwards.
+ *  - A handle owns all host and device memory it allocates until lp_destroy.
+ *  - A handle is not re-entrant: one call at a time per handle. Distinct handles may be
+ *    used from different threads.
+ *  - After a failed call, lp_last_error(h) (or lp_last_error(NULL) when no handle exists)
+ *    returns a message describing the failure.
+ */
+#ifndef LPGPU_LP_H
+#define LPGPU_LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_handle lp_handle;
+
+typedef enum {
+    LP_OK = 0,
+    LP_ERR_INVALID_ARG = 1,         /* null pointer, negative size, bad option value */
+    LP_ERR_INVALID_MATRIX = 2,      /* row_ptr not monotone / not 0..nnz, col_idx out of range or not strictly increasing in a row */
+    LP_ERR_INCONSISTENT_BOUNDS = 3, /* lower > upper, or a lower bound of +inf / an upper bound of -inf */
+    LP_ERR_NAN_INPUT = 4,           /* NaN anywhere, or an infinite matrix value or cost */
+    LP_ERR_OUT_OF_MEMORY = 5,       /* host or device allocation failed */
+    LP_ERR_DEVICE = 6,              /* a HIP runtime call failed */
+    LP_ERR_NOT_SOLVED = 7,          /* solution requested before lp_solve */
+    LP_ERR_INTERNAL = 8
+} lp_error;
+
+typedef enum {
+    LP_OPTIMAL = 0,         /* E_rel <= eps_rel */
+    LP_ITERATION_LIMIT = 1, /* max_iters reached (also the outcome for infeasible / unbounded LPs) */
+    LP_TIME_LIMIT = 2,
+    LP_NUMERICAL_ERROR = 3  /* a NaN appeared in the residuals */
+} lp_termination;
+
+typedef enum {
+    LP_PREC_FP64 = 0 /* matrix, iterates and all reductions in FP64 */
+} lp_precision;
+
+typedef struct lp_options {
+    double eps_rel;        /* relative tolerance on E_rel (default 1e-4) */
+    int64_t max_iters;     /* iteration limit (default 100000) */
+    double time_limit_s;   /* wall-clock limit of lp_solve, checked every eval_every iterations (default: none, 0) */
+    int32_t eval_every;    /* iterations between KKT evaluations / restart checks (default 64) */
+    int32_t precision;     /* lp_precision (default LP_PREC_FP64) */
+    int32_t scaling;       /* 1: power-of-two Ruiz + Pock-Chambolle scaling (default), 0: none */
+    int32_t ruiz_passes;   /* number of infinity-norm Ruiz passes (default 10) */
+    int32_t pow_iters;     /* power-iteration steps for ||A~||_2 (default 200) */
+    int32_t restarts;      /* 1: adaptive restarts and primal-weight updates (default), 0: off */
+    double step_size;      /* eta; <= 0 selects 0.998 / ||A~||_2 (default 0) */
+    double omega0;         /* initial primal weight; <= 0 selects ||c~|| / ||q~|| (default 0) */
+    uint64_t seed;         /* seed of the power-iteration start vector */
+    void *hip_stream;      /* hipStream_t to run on; NULL: the library creates its own */
+    int32_t device;        /* HIP device ordinal (default 0) */
+    int32_t trace_cap;     /* number of evaluation records kept for lp_get_trace (default 4096) */
+    const double *x0;      /* optional warm start (host, length n, original scale) */
+    const double *y0;      /* optional warm start (host, length m, original scale) */
+} lp_options;
+
+typedef struct lp_info {
+    int32_t status;        /* lp_termination */
+    int32_t output_is_avg; /* 1 if the returned point is the running average */
+    int64_t iterations;
+    int64_t restarts;
+    double primal_obj, dual_obj;          /* p and d of the returned point, c0 included */
+    double rel_primal_res, rel_dual_res, rel_gap, rel_kkt; /* the three E_rel terms and E_rel */
+    double sigma_max;      /* power-iteration estimate of ||A~||_2 (0 if step_size was given) */
+    double step_size;      /* eta used */
+    double omega;          /* final primal weight */
+    double setup_seconds;  /* lp_create: upload, transpose, scaling, norm estimate */
+    double solve_seconds;  /* last lp_solve */
+} lp_info;
+
+/* Fill *opt with the defaults listed above. */
+void lp_default_options(lp_options *opt);
+
+/* Create a solver handle for the LP of eq. (1) and prepare it on the GPU.
+ *   m >= 0 rows, n >= 1 columns, nnz = row_ptr[m] entries.
+ *   row_ptr[m+1] (int32, row_ptr[0] = 0, non-decreasing), col_idx[nnz] (int32 in [0, n),
+ *   strictly increasing inside each row), vals[nnz] (finite float64; explicit zeros kept).
+ *   c[n] finite; c0 finite constant; b_lo[m], b_hi[m], x_lo[n], x_hi[n] with lower <= upper,
+ *   lower < +inf, upper > -inf. For m = 0, row_ptr must still hold one entry (0) and b_lo,
+ *   b_hi may be NULL.
+ *   opt may be NULL (defaults). The option struct is copied; x0/y0 are copied if given.
+ * The setup (a CSR transpose, the scaling, the ||A~||_2 estimate and the step size) runs
+ * on the device selected by opt->device. On success *out receives the handle. */
+int32_t lp_create(lp_handle **out, int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                  const int32_t *col_idx, const double *vals, const double *c, double c0,
+                  const double *b_lo, const double *b_hi, const double *x_lo, const double *x_hi,
+                  const lp_options *opt);
+
+/* Run restarted, averaged PDHG from the start point until E_rel <= eps_rel or a limit.
+ * Every call starts again from x0, y0 (the handle keeps the problem, not the iterates). */
+int32_t lp_solve(lp_handle *h);
+
+/* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every
+ * and restarts are taken from *opt; every other field of *opt is ignored (the problem
+ * setup, the step size and the trace capacity are fixed at lp_create). */
+int32_t lp_update_options(lp_handle *h, const lp_options *opt);
+
+/* Copy the returned point (original scale) to caller buffers x[n], y[m], z[n] and the run
+ * record to *info. Any pointer may be NULL to skip it. LP_ERR_NOT_SOLVED before lp_solve. */
+int32_t lp_get_solution(lp_handle *h, double *x, double *y, double *z, lp_info *info);
+
+/* Release everything the handle owns. NULL is ignored. */
+void lp_destroy(lp_handle *h);
+
+/* Static description of an error code. */
+const char *lp_error_string(int32_t code);
+
+/* Message of the last failed call on h (thread-local last error when h is NULL). */
+const char *lp_last_error(const lp_handle *h);
+
+/* ---- inspection (used by the parity tests) ------------------------------------------ */
+
+/* Iterate state in the scaled space right now: x~[n], y~[m], the running averages
+ * x~avg[n], y~avg[m]. After lp_solve with max_iters = k this is the state after the update
+ * of iteration k, before that iteration's evaluation acts on it. Any pointer may be NULL. */
+int32_t lp_get_iterates(lp_handle *h, double *x, double *y, double *x_avg, double *y_avg);
+
+/* The scaled problem: A~ values in the caller's CSR order vals[nnz], the factors R[m] and
+ * C[n] (A~ = diag(R) A diag(C)), and A~^T as CSR: t_row_ptr[n+1], t_col_idx[nnz],
+ * t_vals[nnz]. Any pointer may be NULL. */
+int32_t lp_get_scaled(lp_handle *h, double *vals, double *R, double *C, int32_t *t_row_ptr,
+                      int32_t *t_col_idx, double *t_vals);
+
+/* Evaluation records of the last lp_solve, LP_TRACE_WIDTH doubles each:
+ *   [k, t, KKT_w(current), KKT_w(average), E_rel(current), E_rel(average), candidate
+ *    (1 = average), restart reason (0 none, 1 deep decay, 2 no progress, 3 long cycle),
+ *    omega after the decision, KKT_w of the anchor, previous candidate KKT_w, margin]
+ * margin = the smallest relative gap between two quantities a decision compared.
+ * Writes min(cap, available) records to out and the available count to *n_records. */
+#define LP_TRACE_WIDTH 12
+int32_t lp_get_trace(lp_handle *h, double *out, int32_t cap, int32_t *n_records);
+
+/* Per-kernel timing of the next lp_solve calls: when enabled, the primal (A^T y + primal
+ * update) and dual (A x + dual update) kernels of one iteration per evaluation period are
+ * bracketed by HIP events on the solver stream. lp_get_kernel_times returns the mean
+ * duration in milliseconds of each and the number of samples since enabling. */
+int32_t lp_set_kernel_timing(lp_handle *h, int32_t enable);
+int32_t lp_get_kernel_times(lp_handle *h, double *primal_ms, double *dual_ms, int64_t *samples);
+
+/* Sizes the solver chose: sizes[0] = tiles of A, [1] = tiles of A^T, [2] = long rows of
+ * A, [3] = long rows of A^T, [4] = device bytes held by the handle. */
+int32_t lp_get_layout(lp_handle *h, int64_t *sizes, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LPGPU_LP_H */

@@ -1,0 +1,303 @@
+"""Python binding of the MI355X restarted-PDHG LP solver (include/lp.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library
+`_lib/liblpgpu.so`. Importing this package does not need a GPU; calling the solver
+does, and a missing library is an error (there is no CPU path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblpgpu.so")
+
+LP_OK = 0
+ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONSISTENT_BOUNDS",
+          4: "LP_ERR_NAN_INPUT", 5: "LP_ERR_OUT_OF_MEMORY", 6: "LP_ERR_DEVICE", 7: "LP_ERR_NOT_SOLVED",
+          8: "LP_ERR_INTERNAL"}
+STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_error"}
+TRACE_WIDTH = 12
+
+# names of every function include/lp.h declares
+EXPORTS = (
+    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
+    "lp_get_kernel_times", "lp_get_layout",
+)
+
+
+class LpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lp_options(C.Structure):
+    _fields_ = [
+        ("eps_rel", C.c_double), ("max_iters", C.c_int64), ("time_limit_s", C.c_double),
+        ("eval_every", C.c_int32), ("precision", C.c_int32), ("scaling", C.c_int32), ("ruiz_passes", C.c_int32),
+        ("pow_iters", C.c_int32), ("restarts", C.c_int32), ("step_size", C.c_double), ("omega0", C.c_double),
+        ("seed", C.c_uint64), ("hip_stream", C.c_void_p), ("device", C.c_int32), ("trace_cap", C.c_int32),
+        ("x0", C.c_void_p), ("y0", C.c_void_p),
+    ]
+
+
+class lp_info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("output_is_avg", C.c_int32), ("iterations", C.c_int64), ("restarts", C.c_int64),
+        ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_primal_res", C.c_double),
+        ("rel_dual_res", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double), ("sigma_max", C.c_double),
+        ("step_size", C.c_double), ("omega", C.c_double), ("setup_seconds", C.c_double),
+        ("solve_seconds", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def library_loaded() -> bool:
+    return _lib is not None
+
+
+def lib():
+    """Load the HIP library; raise if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP solver library missing: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.lp_default_options.argtypes = [P]
+        L.lp_default_options.restype = None
+        L.lp_create.argtypes = [P, I32, I32, I64, P, P, P, P, D, P, P, P, P, P]
+        L.lp_create.restype = I32
+        L.lp_update_options.argtypes = [P, P]
+        L.lp_update_options.restype = I32
+        L.lp_solve.argtypes = [P]
+        L.lp_solve.restype = I32
+        L.lp_get_solution.argtypes = [P, P, P, P, P]
+        L.lp_get_solution.restype = I32
+        L.lp_destroy.argtypes = [P]
+        L.lp_destroy.restype = None
+        L.lp_error_string.argtypes = [I32]
+        L.lp_error_string.restype = C.c_char_p
+        L.lp_last_error.argtypes = [P]
+        L.lp_last_error.restype = C.c_char_p
+        L.lp_get_iterates.argtypes = [P, P, P, P, P]
+        L.lp_get_iterates.restype = I32
+        L.lp_get_scaled.argtypes = [P, P, P, P, P, P, P]
+        L.lp_get_scaled.restype = I32
+        L.lp_get_trace.argtypes = [P, P, I32, P]
+        L.lp_get_trace.restype = I32
+        L.lp_set_kernel_timing.argtypes = [P, I32]
+        L.lp_set_kernel_timing.restype = I32
+        L.lp_get_kernel_times.argtypes = [P, P, P, P]
+        L.lp_get_kernel_times.restype = I32
+        L.lp_get_layout.argtypes = [P, P, I32]
+        L.lp_get_layout.restype = I32
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _check(rc: int, handle=None):
+    if rc != LP_OK:
+        msg = lib().lp_last_error(handle).decode(errors="replace")
+        raise LpError(rc, msg)
+
+
+# ---- raw C-ABI names ----------------------------------------------------------------
+
+def lp_default_options() -> lp_options:
+    o = lp_options()
+    lib().lp_default_options(C.byref(o))
+    return o
+
+
+def lp_create(m, n, nnz, row_ptr, col_idx, vals, c, c0, b_lo, b_hi, x_lo, x_hi, opt: Optional[lp_options] = None):
+    """Host numpy arrays in, opaque handle (c_void_p) out."""
+    h = C.c_void_p()
+    rc = lib().lp_create(C.byref(h), m, n, nnz, _p(row_ptr), _p(col_idx), _p(vals), _p(c), float(c0), _p(b_lo),
+                         _p(b_hi), _p(x_lo), _p(x_hi), None if opt is None else C.byref(opt))
+    _check(rc)
+    return h
+
+
+def lp_update_options(h, opt: lp_options):
+    _check(lib().lp_update_options(h, C.byref(opt)), h)
+
+
+def lp_solve(h):
+    _check(lib().lp_solve(h), h)
+
+
+def lp_get_solution(h, x=None, y=None, z=None) -> lp_info:
+    info = lp_info()
+    _check(lib().lp_get_solution(h, _p(x), _p(y), _p(z), C.byref(info)), h)
+    return info
+
+
+def lp_destroy(h):
+    if h:
+        lib().lp_destroy(h)
+
+
+def lp_error_string(code: int) -> str:
+    return lib().lp_error_string(code).decode()
+
+
+def lp_last_error(h=None) -> str:
+    return lib().lp_last_error(h).decode(errors="replace")
+
+
+def lp_get_iterates(h, x=None, y=None, x_avg=None, y_avg=None):
+    _check(lib().lp_get_iterates(h, _p(x), _p(y), _p(x_avg), _p(y_avg)), h)
+
+
+def lp_get_scaled(h, vals=None, R=None, Cc=None, t_row_ptr=None, t_col_idx=None, t_vals=None):
+    _check(lib().lp_get_scaled(h, _p(vals), _p(R), _p(Cc), _p(t_row_ptr), _p(t_col_idx), _p(t_vals)), h)
+
+
+def lp_get_trace(h, cap: int = 4096) -> np.ndarray:
+    out = np.zeros((max(cap, 1), TRACE_WIDTH))
+    n = C.c_int32()
+    _check(lib().lp_get_trace(h, _p(out), cap, C.byref(n)), h)
+    return out[: min(n.value, cap)].copy()
+
+
+def lp_set_kernel_timing(h, enable: bool):
+    _check(lib().lp_set_kernel_timing(h, int(enable)), h)
+
+
+def lp_get_kernel_times(h):
+    p, d, k = C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().lp_get_kernel_times(h, C.byref(p), C.byref(d), C.byref(k)), h)
+    return p.value, d.value, k.value
+
+
+def lp_get_layout(h):
+    out = np.zeros(5, np.int64)
+    _check(lib().lp_get_layout(h, _p(out), 5), h)
+    return dict(tiles_a=int(out[0]), tiles_at=int(out[1]), long_rows_a=int(out[2]), long_rows_at=int(out[3]),
+                device_bytes=int(out[4]))
+
+
+# ---- convenience wrapper ---------------------------------------------------------------
+
+@dataclass
+class Solution:
+    status: str
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    info: lp_info
+    trace: np.ndarray = field(default_factory=lambda: np.zeros((0, TRACE_WIDTH)))
+
+    def __getattr__(self, k):
+        info = self.__dict__.get("info")
+        if info is not None and k in dict(lp_info._fields_):
+            return getattr(info, k)
+        raise AttributeError(k)
+
+
+_OPT_KEYS = {f[0] for f in lp_options._fields_} - {"x0", "y0", "hip_stream"}
+
+
+def make_options(**kw) -> lp_options:
+    o = lp_default_options()
+    for k, v in kw.items():
+        if k not in _OPT_KEYS:
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Solver:
+    """Owns one lp_handle. `lp` is any object with the fields of eq. (1):
+    m, n, row_ptr, col_idx, vals, c, c0, b_lo, b_hi, x_lo, x_hi."""
+
+    def __init__(self, lp, *, x0=None, y0=None, stream=None, **options):
+        self._keep = []
+        o = make_options(**options)
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a
+
+        if x0 is not None:
+            o.x0 = arr(x0, np.float64).ctypes.data
+        if y0 is not None:
+            o.y0 = arr(y0, np.float64).ctypes.data
+        if stream is not None:  # a torch.cuda.Stream or a raw hipStream_t integer
+            o.hip_stream = getattr(stream, "cuda_stream", stream)
+        self.m, self.n = int(lp.m), int(lp.n)
+        rp = arr(lp.row_ptr, np.int32)
+        self.nnz = int(rp[self.m])
+        ci = arr(lp.col_idx if self.nnz else np.zeros(1), np.int32)
+        v = arr(lp.vals if self.nnz else np.zeros(1), np.float64)
+        bl = arr(lp.b_lo, np.float64) if self.m else None
+        bu = arr(lp.b_hi, np.float64) if self.m else None
+        self.h = lp_create(self.m, self.n, self.nnz, rp, ci, v, arr(lp.c, np.float64), float(getattr(lp, "c0", 0.0)),
+                           bl, bu, arr(lp.x_lo, np.float64), arr(lp.x_hi, np.float64), o)
+        self.trace_cap = o.trace_cap
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            lp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def update(self, **options):
+        """Change solve-time options (eps_rel, max_iters, time_limit_s, eval_every, restarts)."""
+        lp_update_options(self.h, make_options(**options))
+
+    def solve(self, with_trace: bool = False) -> Solution:
+        lp_solve(self.h)
+        x = np.empty(self.n)
+        y = np.empty(max(self.m, 1))
+        z = np.empty(self.n)
+        info = lp_get_solution(self.h, x, y, z)
+        tr = lp_get_trace(self.h, self.trace_cap) if with_trace else np.zeros((0, TRACE_WIDTH))
+        return Solution(STATUS.get(info.status, str(info.status)), x, y[: self.m], z, info, tr)
+
+    def iterates(self):
+        x, xa = np.empty(self.n), np.empty(self.n)
+        y, ya = np.empty(max(self.m, 1)), np.empty(max(self.m, 1))
+        lp_get_iterates(self.h, x, y, xa, ya)
+        return x, y[: self.m], xa, ya[: self.m]
+
+    def scaled(self):
+        nz = max(self.nnz, 1)
+        v, R, Cc = np.empty(nz), np.empty(max(self.m, 1)), np.empty(self.n)
+        trp, tci, tv = np.empty(self.n + 1, np.int32), np.empty(nz, np.int32), np.empty(nz)
+        lp_get_scaled(self.h, v, R, Cc, trp, tci, tv)
+        return v[: self.nnz], R[: self.m], Cc, trp, tci[: self.nnz], tv[: self.nnz]
+
+    def layout(self):
+        return lp_get_layout(self.h)
+
+
+def solve(lp, **options) -> Solution:
+    with Solver(lp, **options) as s:
+        return s.solve()

@@ -1,0 +1,90 @@
+// Internal device-side types and kernel launchers of the restarted-PDHG solver.
+// Everything here is private to the library; the public surface is include/lp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lpgpu {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kTileNnz = 2048;    // nonzeros staged in LDS per SpMV tile
+constexpr int kTileRows = 1024;   // rows per SpMV tile at most
+constexpr int kMaxRedBlocks = 512;
+constexpr int kNQ = 8;            // reduced quantities per candidate
+constexpr int kTraceW = 12;
+
+constexpr int kRunning = -1;
+
+// Device-resident scalar state of one solve. The iteration kernels read it; only the
+// single-workgroup decision kernels write it.
+struct Scalars {
+    double tau, sigma, omega, eta, omega0;
+    double eps_rel, c0, qnorm, cnorm, sigma_max;
+    double kkt_anchor, kkt_prev;
+    double anc_rps2, anc_rds2, anc_gap;
+    // statistics of the returned point
+    double out_pobj, out_dobj, out_rel_p, out_rel_d, out_rel_gap, out_erel;
+    long long k, t, max_iters, restarts, n_trace, trace_cap;
+    int status;        // kRunning or an lp_termination value
+    int out_avg;       // returned point: 1 = running average
+    int last_restart;  // what the apply kernel must do: 0 nothing, 1 keep current, 2 take average
+    int eval_every;
+    int restarts_on;
+    int pad;
+};
+
+// CSR matrix with its LDS tiling: tile b covers rows [tiles[b], tiles[b+1]).
+struct Csr {
+    int rows;
+    int ntiles;
+    const int* rp;
+    const int* ci;
+    const double* v;
+    const int* tiles;
+};
+
+struct DevLP {
+    int m, n;
+    long long nnz;
+    int nred;          // blocks of the fixed-grid reductions
+    Csr A, AT;
+    // scaled problem data
+    const double *c, *bl, *bu, *xl, *xu;
+    const double *R, *C, *Ri, *Ci;
+    // iterate state (scaled space)
+    double *x, *y, *xa, *ya;          // current and running averages
+    double *ax, *axa, *aty, *atya;    // A~x, A~x_avg, A~^T y, A~^T y_avg
+    double *xan, *yan;                // anchor (start of the current restart cycle)
+    double *partials;                 // nred * 2 * kNQ
+    Scalars* sc;
+    double* trace;
+    double *out_x, *out_y, *out_z;
+};
+
+// ---- setup ------------------------------------------------------------------------
+void launch_fill(double* p, long long n, double v, hipStream_t s);
+void launch_scale_pass(const DevLP& P, int* A_rp, int* A_ci, double* A_v, const int* AT_rp, const int* perm,
+                       double* R, double* C, double* rf, double* cf, int use_sum, hipStream_t s);
+void launch_gather(const int* perm, const double* src, double* dst, long long nnz, hipStream_t s);
+void launch_prepare(const DevLP& P, double* c, double* bl, double* bu, double* xl, double* xu, double* R, double* C,
+                    double* Ri, double* Ci, double* x0, double* y0, hipStream_t s);
+void launch_norms(const DevLP& P, hipStream_t s);
+void launch_power_norm(const DevLP& P, int iters, unsigned long long seed, double* v, double* u, double* w,
+                       hipStream_t s);
+void launch_finalize_setup(const DevLP& P, double eta_override, double omega_override, double c0, hipStream_t s);
+
+// ---- solve ------------------------------------------------------------------------
+void launch_reset(const DevLP& P, double eps_rel, long long max_iters, int eval_every, int restarts_on,
+                  long long trace_cap, hipStream_t s);
+void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s);
+void launch_spmv_store(const Csr& M, const double* xin, double* out, const Scalars* gate, hipStream_t s);
+void launch_primal(const DevLP& P, int it, hipStream_t s);
+void launch_dual(const DevLP& P, int it, hipStream_t s);
+void launch_evaluate(const DevLP& P, int mode, hipStream_t s);  // mode 0 regular, 1 init, 2 final
+void launch_apply_restart(const DevLP& P, hipStream_t s);
+void launch_stop(const DevLP& P, int status, hipStream_t s);
+void launch_extract(const DevLP& P, hipStream_t s);
+
+}  // namespace lpgpu

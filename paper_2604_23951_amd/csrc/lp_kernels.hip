@@ -1,0 +1,851 @@
+// HIP kernels of the restarted, averaged PDHG solver for gfx950 (MI355X).
+//
+// The method (the PDLP-family averaged PDHG that the paper's presolve feeds, Section 1 and
+// Section 4 name it; the iteration itself is the published one) spends its time in two
+// sparse products per iteration, A^T y and A x, each followed by an elementwise update.
+// Both are HBM-bound: the products are streamed from CSR (values + int32 indices) with the
+// nonzeros of a tile staged in LDS and the row sums formed from LDS, and the primal / dual
+// updates are fused into the epilogue of the product that feeds them, so every vector is
+// read and written once per iteration. No step is a dense contraction: no MFMA.
+//
+// Determinism: every row sum is formed sequentially in CSR order from the products
+// (a_e * x_col(e) rounded, then added in order), which is also the plain definition of the
+// sum; rows longer than one tile use a fixed-shape workgroup tree. All reductions use a
+// fixed grid, fixed wave64 shuffles and a fixed-order second stage, so a solve is bitwise
+// reproducible run to run.
+#include "lp_device.h"
+
+#include <math.h>
+
+namespace lpgpu {
+
+namespace {
+
+__device__ inline double clampd(double v, double lo, double hi) {
+    if (v < lo) v = lo;
+    if (v > hi) v = hi;
+    return v;
+}
+
+__device__ inline bool finite_d(double v) { return __builtin_isfinite(v); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup in a fixed order; the result is valid in thread 0. `red` holds
+// kBlock / 64 doubles of LDS. Ends with a barrier so `red` may be reused.
+__device__ inline double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+    }
+    __syncthreads();
+    return t;
+}
+
+// Same, but every thread gets the total.
+__device__ inline double block_sum_all(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) t += red[i];
+    __syncthreads();
+    return t;
+}
+
+// Power-of-two stand-in for 1/sqrt(v): v = f 2^E with f in [1/2, 1) gives 2^(-floor(E/2)).
+__device__ inline double pow2_rsqrt(double v) {
+    if (!(v > 0.0) || !finite_d(v)) return 1.0;
+    int e;
+    frexp(v, &e);
+    const int h = (e >= 0) ? e / 2 : -((1 - e) / 2);
+    return ldexp(1.0, -h);
+}
+
+// SplitMix64 finaliser applied to seed + (k+1) * golden gamma, mapped to [-1/2, 1/2).
+__device__ inline double splitmix_centered(unsigned long long seed, unsigned long long k) {
+    unsigned long long z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= (z >> 31);
+    return static_cast<double>(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+inline unsigned grid_for(long long n, int per_block = kBlock) {
+    long long g = (n + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65535LL * 64) g = 65535LL * 64;
+    return static_cast<unsigned>(g);
+}
+
+// ------------------------------------------------------------------ SpMV with epilogues
+
+// One workgroup per tile. Short tiles: the tile's nonzeros are multiplied by the gathered
+// vector entries with coalesced loads and stored to LDS, then each thread forms the sum of
+// one row from LDS in CSR order and hands it to the epilogue. A tile that is a single row
+// longer than kTileNnz is reduced by the whole workgroup.
+template <class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double* __restrict__ xin, Epi epi) {
+    __shared__ double prod[kTileNnz];
+    __shared__ double red[kBlock / 64];
+    if (!epi.begin()) return;
+    const int b = blockIdx.x;
+    const int r0 = M.tiles[b], r1 = M.tiles[b + 1];
+    const int p0 = M.rp[r0], p1 = M.rp[r1];
+    const int tid = threadIdx.x;
+    if (p1 - p0 <= kTileNnz) {
+        for (int e = p0 + tid; e < p1; e += kBlock) prod[e - p0] = M.v[e] * xin[M.ci[e]];
+        __syncthreads();
+        for (int r = r0 + tid; r < r1; r += kBlock) {
+            const int q0 = M.rp[r] - p0, q1 = M.rp[r + 1] - p0;
+            double s = 0.0;
+            for (int q = q0; q < q1; ++q) s += prod[q];
+            epi(r, s);
+        }
+    } else {
+        double s = 0.0;
+        for (int e = p0 + tid; e < p1; e += kBlock) {
+            const double pr = M.v[e] * xin[M.ci[e]];
+            s += pr;
+        }
+        s = block_sum(s, red);
+        if (tid == 0) epi(r0, s);
+    }
+}
+
+struct EpiStore {
+    double* out;
+    const Scalars* gate;
+    __device__ bool begin() const { return gate == nullptr || gate->status == kRunning; }
+    __device__ void operator()(int r, double s) const { out[r] = s; }
+};
+
+// Primal step on column j of A (row j of A^T), s = (A~^T y)_j:
+//   x_j <- clamp(x_j - tau (c~_j - s), x~lo_j, x~hi_j);  running mean of x since the restart.
+struct EpiPrimal {
+    const Scalars* sc;
+    int it;
+    const double *c, *xl, *xu;
+    double *x, *xa;
+    double tau, wt;
+    bool first;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it + 1;
+        tau = sc->tau;
+        first = (t == 1);
+        wt = 1.0 / static_cast<double>(t);
+        return true;
+    }
+    __device__ void operator()(int j, double s) const {
+        const double g = c[j] - s;
+        const double xn = clampd(x[j] - tau * g, xl[j], xu[j]);
+        x[j] = xn;
+        const double a = xa[j];
+        xa[j] = first ? xn : a + wt * (xn - a);
+    }
+};
+
+// Dual step on row i, s = (A~ x+)_i, with the extrapolation 2 A~x+ - A~x:
+//   v = y_i - sigma (2 s - (A~x)_i),  y_i <- max(v + sigma b~lo_i, 0) + min(v + sigma b~hi_i, 0)
+// (the closed-form proximal step of the row-bound term; it keeps y_i >= 0 where b_hi = +inf
+// and y_i <= 0 where b_lo = -inf), running mean of y, and A~x <- A~x+ for the next step.
+struct EpiDual {
+    const Scalars* sc;
+    int it;
+    const double *bl, *bu;
+    double *y, *ya, *ax;
+    double sigma, wt;
+    bool first;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it + 1;
+        sigma = sc->sigma;
+        first = (t == 1);
+        wt = 1.0 / static_cast<double>(t);
+        return true;
+    }
+    __device__ void operator()(int i, double s) const {
+        const double w = 2.0 * s - ax[i];
+        const double v = y[i] - sigma * w;
+        const double lo = v + sigma * bl[i];
+        const double hi = v + sigma * bu[i];
+        const double yn = (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
+        y[i] = yn;
+        const double a = ya[i];
+        ya[i] = first ? yn : a + wt * (yn - a);
+        ax[i] = s;
+    }
+};
+
+template <class Epi>
+void launch_tiles(const Csr& M, const double* xin, const Epi& epi, hipStream_t s) {
+    if (M.ntiles <= 0) return;
+    hipLaunchKernelGGL(spmv_tiles_kernel<Epi>, dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
+}
+
+// ------------------------------------------------------------------- setup kernels
+
+__global__ void fill_kernel(double* p, long long n, double v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Row statistic of |A~| (max, or the sum in CSR order) turned into a power-of-two factor.
+__global__ void scale_rowstat_kernel(int rows, const int* rp, const double* v, int use_sum, double* f) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double s = 0.0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+        const double a = fabs(v[e]);
+        if (use_sum) s += a;
+        else if (a > s) s = a;
+    }
+    f[i] = pow2_rsqrt(s);
+}
+
+// Column statistic through the transpose permutation (entries of a column in ascending row).
+__global__ void scale_colstat_kernel(int cols, const int* rpT, const int* perm, const double* v, int use_sum,
+                                     double* f) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    double s = 0.0;
+    for (int p = rpT[j]; p < rpT[j + 1]; ++p) {
+        const double a = fabs(v[perm[p]]);
+        if (use_sum) s += a;
+        else if (a > s) s = a;
+    }
+    f[j] = pow2_rsqrt(s);
+}
+
+__global__ void scale_apply_rows_kernel(int rows, const int* rp, const int* ci, double* v, const double* rf,
+                                        const double* cf, double* R) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    const double r = rf[i];
+    for (int e = rp[i]; e < rp[i + 1]; ++e) v[e] = v[e] * r * cf[ci[e]];
+    R[i] *= r;
+}
+
+__global__ void scale_apply_cols_kernel(int cols, const double* cf, double* C) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    C[j] *= cf[j];
+}
+
+__global__ void gather_kernel(const int* perm, const double* src, double* dst, long long nnz) {
+    for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < nnz;
+         p += (long long)gridDim.x * blockDim.x)
+        dst[p] = src[perm[p]];
+}
+
+// Scaled data: c~ = C c, b~ = R b, x~bounds = x bounds / C, inverse factors, warm start.
+__global__ void prepare_kernel(int m, int n, double* c, double* bl, double* bu, double* xl, double* xu,
+                               const double* R, const double* C, double* Ri, double* Ci, double* x0, double* y0) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) {
+        const double cc = C[g], ci = 1.0 / cc;
+        Ci[g] = ci;
+        c[g] = c[g] * cc;
+        xl[g] = xl[g] * ci;
+        xu[g] = xu[g] * ci;
+        if (x0) x0[g] = x0[g] * ci;
+    }
+    if (g < m) {
+        const double r = R[g], ri = 1.0 / r;
+        Ri[g] = ri;
+        bl[g] = bl[g] * r;
+        bu[g] = bu[g] * r;
+        if (y0) y0[g] = y0[g] * ri;
+    }
+}
+
+// Partial sums of ||c||^2, ||q||^2 (original data, recovered exactly from the scaled data)
+// and ||c~||^2, ||q~||^2 (scaled data). q_i = max finite |row bound|.
+__global__ __launch_bounds__(kBlock) void norms_kernel(DevLP P) {
+    __shared__ double red[kBlock / 64];
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += stride) {
+        const double cs = P.c[j], co = cs * P.Ci[j];
+        a0 += co * co;
+        a2 += cs * cs;
+    }
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.m; i += stride) {
+        const double bl = P.bl[i], bu = P.bu[i], ri = P.Ri[i];
+        double qs = 0.0;
+        if (finite_d(bl) && fabs(bl) > qs) qs = fabs(bl);
+        if (finite_d(bu) && fabs(bu) > qs) qs = fabs(bu);
+        double qo = 0.0;
+        const double blo = bl * ri, buo = bu * ri;
+        if (finite_d(blo) && fabs(blo) > qo) qo = fabs(blo);
+        if (finite_d(buo) && fabs(buo) > qo) qo = fabs(buo);
+        a1 += qo * qo;
+        a3 += qs * qs;
+    }
+    const double s0 = block_sum(a0, red), s1 = block_sum(a1, red), s2 = block_sum(a2, red), s3 = block_sum(a3, red);
+    if (threadIdx.x == 0) {
+        double* out = P.partials + blockIdx.x * 4;
+        out[0] = s0;
+        out[1] = s1;
+        out[2] = s2;
+        out[3] = s3;
+    }
+}
+
+// Power iteration pieces. Start vector v_k = U[-1/2, 1/2)(seed, k).
+__global__ void power_init_kernel(int n, unsigned long long seed, double* v) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) v[k] = splitmix_centered(seed, (unsigned long long)k);
+}
+
+// Partial sums of sum(a^2) over [0, na) and sum(b^2) over [0, nb) -> partials[blk*2 + {0,1}].
+__global__ __launch_bounds__(kBlock) void sumsq2_kernel(const double* a, int na, const double* b, int nb,
+                                                        double* partials) {
+    __shared__ double red[kBlock / 64];
+    double sa = 0.0, sb = 0.0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < na; i += stride) sa += a[i] * a[i];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) sb += b[i] * b[i];
+    sa = block_sum(sa, red);
+    sb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x * 2] = sa;
+        partials[blockIdx.x * 2 + 1] = sb;
+    }
+}
+
+// dst = src / sqrt(sum of partial slot `slot`) when that norm is positive (every block
+// forms the same total in the same order). Optionally records sqrt(slot 0) as sigma_max.
+__global__ __launch_bounds__(kBlock) void normalize_kernel(const double* src, double* dst, int n,
+                                                           const double* partials, int nparts, int slot,
+                                                           Scalars* sc) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) s += partials[b * 2 + slot];
+    s = block_sum_all(s, red);
+    double s0 = 0.0;
+    if (sc) {
+        for (int b = threadIdx.x; b < nparts; b += kBlock) s0 += partials[b * 2];
+        s0 = block_sum_all(s0, red);
+    }
+    const double nrm = sqrt(s);
+    if (sc && blockIdx.x == 0 && threadIdx.x == 0) sc->sigma_max = sqrt(s0);
+    if (!(nrm > 0.0)) return;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) dst[k] = src[k] / nrm;
+}
+
+__global__ __launch_bounds__(kBlock) void finalize_setup_kernel(DevLP P, int nparts, double eta_override,
+                                                                double omega_override, double c0) {
+    __shared__ double red[kBlock / 64];
+    double s[4];
+    for (int q = 0; q < 4; ++q) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += kBlock) v += P.partials[b * 4 + q];
+        s[q] = block_sum(v, red);
+    }
+    if (threadIdx.x != 0) return;
+    Scalars* sc = P.sc;
+    sc->c0 = c0;
+    sc->cnorm = sqrt(s[0]);
+    sc->qnorm = sqrt(s[1]);
+    const double cs = sqrt(s[2]), qs = sqrt(s[3]);
+    double eta = eta_override;
+    if (!(eta > 0.0)) eta = sc->sigma_max > 0.0 ? 0.998 / sc->sigma_max : 1.0;
+    else sc->sigma_max = 0.0;
+    double omega = omega_override;
+    if (!(omega > 0.0)) omega = (cs > 1e-10 && qs > 1e-10) ? cs / qs : 1.0;
+    sc->eta = eta;
+    sc->omega0 = omega;
+}
+
+// ------------------------------------------------------------------- solve kernels
+
+__global__ void reset_kernel(Scalars* sc, double eps_rel, long long max_iters, int eval_every, int restarts_on,
+                             long long trace_cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    sc->omega = sc->omega0;
+    sc->tau = sc->eta / sc->omega;
+    sc->sigma = sc->eta * sc->omega;
+    sc->eps_rel = eps_rel;
+    sc->max_iters = max_iters;
+    sc->eval_every = eval_every;
+    sc->restarts_on = restarts_on;
+    sc->trace_cap = trace_cap;
+    sc->k = 0;
+    sc->t = 0;
+    sc->restarts = 0;
+    sc->n_trace = 0;
+    sc->status = kRunning;
+    sc->out_avg = 0;
+    sc->last_restart = 0;
+    sc->kkt_prev = __builtin_inf();
+}
+
+__global__ void init_state_kernel(DevLP P, const double* x0, const double* y0) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P.n) {
+        const double v = clampd(x0 ? x0[g] : 0.0, P.xl[g], P.xu[g]);
+        P.x[g] = v;
+        P.xa[g] = v;
+        P.xan[g] = v;
+    }
+    if (g < P.m) {
+        const double v = y0 ? y0[g] : 0.0;
+        P.y[g] = v;
+        P.ya[g] = v;
+        P.yan[g] = v;
+    }
+}
+
+// Residual and objective terms of one row for a candidate (A~x~, y~); see the evaluation
+// kernel for the definitions. acc: 0 rp2, 1 rps2, 2 rd2, 3 rds2, 4 pobj, 5 dobj, 6 dx2, 7 dy2.
+__device__ inline void row_terms(const DevLP& P, int i, const double* ax, const double* y, double* acc) {
+    const double bl = P.bl[i], bu = P.bu[i], R = P.R[i], Ri = P.Ri[i];
+    const double v = ax[i];
+    const double rs = v - clampd(v, bl, bu);
+    const double ro = rs * Ri;
+    acc[1] += rs * rs;
+    acc[0] += ro * ro;
+    const double yv = y[i];
+    const double yo = yv * R;
+    const double blo = bl * Ri, buo = bu * Ri;
+    if (yo > 0.0 && finite_d(blo)) acc[5] += blo * yo;
+    if (yo < 0.0 && finite_d(buo)) acc[5] += buo * yo;
+    double vs = 0.0;
+    if (bl == -__builtin_inf() && yv > 0.0) vs += yv;
+    if (bu == __builtin_inf() && yv < 0.0) vs -= yv;
+    const double vo = vs * R;
+    acc[3] += vs * vs;
+    acc[2] += vo * vo;
+    const double dy = yv - P.yan[i];
+    acc[7] += dy * dy;
+}
+
+__device__ inline void col_terms(const DevLP& P, int j, const double* x, const double* aty, double* acc) {
+    const double cs = P.c[j], lo = P.xl[j], hi = P.xu[j], Cj = P.C[j], Ci = P.Ci[j];
+    const double ls = cs - aty[j];
+    const bool flo = finite_d(lo), fhi = finite_d(hi);
+    double zs = ls;
+    if (!flo && !fhi) zs = 0.0;
+    else if (flo && !fhi) zs = ls > 0.0 ? ls : 0.0;
+    else if (!flo && fhi) zs = ls < 0.0 ? ls : 0.0;
+    const double rds = ls - zs;
+    const double zo = zs * Ci;
+    const double rdo = rds * Ci;
+    acc[3] += rds * rds;
+    acc[2] += rdo * rdo;
+    const double xv = x[j];
+    const double xo = xv * Cj;
+    acc[4] += (cs * Ci) * xo;
+    if (zo > 0.0) acc[5] += (lo * Cj) * zo;
+    if (zo < 0.0) acc[5] += (hi * Cj) * zo;
+    const double dx = xv - P.xan[j];
+    acc[6] += dx * dx;
+}
+
+// Partial sums of the KKT quantities of the current iterate (slots 0..7) and of the running
+// average (slots 8..15). mode 1 (initial point) and mode 2 (final point after a stop)
+// evaluate the current iterate only; mode 2 runs whatever the status.
+__global__ __launch_bounds__(kBlock) void kkt_partials_kernel(DevLP P, int mode) {
+    __shared__ double red[kBlock / 64][2 * kNQ];
+    if (mode != 2 && P.sc->status != kRunning) return;
+    double acc[2 * kNQ];
+#pragma unroll
+    for (int q = 0; q < 2 * kNQ; ++q) acc[q] = 0.0;
+    const bool both = (mode == 0);
+    const int stride = gridDim.x * blockDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.m; i += stride) {
+        row_terms(P, i, P.ax, P.y, acc);
+        if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
+    }
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += stride) {
+        col_terms(P, j, P.x, P.aty, acc);
+        if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2 * kNQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red[w][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kNQ) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / 64; ++k) t += red[k][threadIdx.x];
+        P.partials[blockIdx.x * 2 * kNQ + threadIdx.x] = t;
+    }
+}
+
+struct Kkt {
+    double rp2, rps2, rd2, rds2, pobj, dobj, dx2, dy2;
+    double rel_p, rel_d, rel_gap, erel;
+};
+
+__device__ inline Kkt make_kkt(const double* q, const Scalars* sc) {
+    Kkt K;
+    K.rp2 = q[0];
+    K.rps2 = q[1];
+    K.rd2 = q[2];
+    K.rds2 = q[3];
+    K.pobj = q[4];
+    K.dobj = q[5];
+    K.dx2 = q[6];
+    K.dy2 = q[7];
+    const double p = K.pobj + sc->c0, d = K.dobj + sc->c0;
+    K.rel_p = sqrt(K.rp2) / (1.0 + sc->qnorm);
+    K.rel_d = sqrt(K.rd2) / (1.0 + sc->cnorm);
+    K.rel_gap = fabs(p - d) / (1.0 + fabs(p) + fabs(d));
+    double e = K.rel_p;
+    if (K.rel_d > e) e = K.rel_d;
+    if (K.rel_gap > e) e = K.rel_gap;
+    if (isnan(K.rel_p) || isnan(K.rel_d) || isnan(K.rel_gap)) e = __builtin_nan("");
+    K.erel = e;
+    return K;
+}
+
+// KKT error in the primal-weighted norm on the scaled problem (the restart metric).
+__device__ inline double kkt_w(double rps2, double rds2, double gap, double omega) {
+    const double w2 = omega * omega;
+    return sqrt(w2 * rps2 + rds2 / w2 + gap * gap);
+}
+
+__device__ inline void set_output(Scalars* sc, const Kkt& K, int avg) {
+    sc->out_avg = avg;
+    sc->out_pobj = K.pobj + sc->c0;
+    sc->out_dobj = K.dobj + sc->c0;
+    sc->out_rel_p = K.rel_p;
+    sc->out_rel_d = K.rel_d;
+    sc->out_rel_gap = K.rel_gap;
+    sc->out_erel = K.erel;
+}
+
+// Evaluation and decision, one workgroup:
+//  E_rel = max(||r_p||/(1+||q||), ||r_d||/(1+||c||), |p-d|/(1+|p|+|d|)) on the original data;
+//  termination when E_rel(current) <= eps (then the average), or at max_iters the better one;
+//  restart candidate = average if its KKT_w is strictly smaller; restart on
+//  (1) KKT_c <= 0.2 KKT_anchor, (2) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev,
+//  (3) t >= 0.36 k; on restart omega <- sqrt(omega dy / dx) when dx, dy > 1e-10.
+__global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) {
+    __shared__ double red[kBlock / 64];
+    __shared__ double tot[2 * kNQ];
+    Scalars* sc = P.sc;
+    if (mode != 2 && sc->status != kRunning) return;
+    const int nq = (mode == 0) ? 2 * kNQ : kNQ;
+    for (int q = 0; q < nq; ++q) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < P.nred; b += kBlock) v += P.partials[b * 2 * kNQ + q];
+        v = block_sum(v, red);
+        if (threadIdx.x == 0) tot[q] = v;
+    }
+    if (threadIdx.x != 0) return;
+    const Kkt cur = make_kkt(tot, sc);
+    if (mode == 2) {  // statistics of the current point after a host-side stop
+        set_output(sc, cur, 0);
+        return;
+    }
+    if (mode == 1) {
+        sc->anc_rps2 = cur.rps2;
+        sc->anc_rds2 = cur.rds2;
+        sc->anc_gap = cur.pobj - cur.dobj;
+        sc->kkt_anchor = kkt_w(cur.rps2, cur.rds2, cur.pobj - cur.dobj, sc->omega);
+        sc->kkt_prev = __builtin_inf();
+        if (isnan(cur.erel)) sc->status = 3;
+        else if (cur.erel <= sc->eps_rel) sc->status = 0;
+        else if (sc->max_iters <= 0) sc->status = 1;
+        if (sc->status != kRunning) set_output(sc, cur, 0);
+        return;
+    }
+    const Kkt avg = make_kkt(tot + kNQ, sc);
+    long long ex = sc->max_iters - sc->k;
+    if (ex > sc->eval_every) ex = sc->eval_every;
+    const long long k = sc->k + ex;
+    long long t = sc->t + ex;
+    const double omega = sc->omega;
+    const double kc = kkt_w(cur.rps2, cur.rds2, cur.pobj - cur.dobj, omega);
+    const double ka = kkt_w(avg.rps2, avg.rds2, avg.pobj - avg.dobj, omega);
+    double rec[kTraceW];
+    for (int f = 0; f < kTraceW; ++f) rec[f] = 0.0;
+    rec[0] = (double)k;
+    rec[1] = (double)t;
+    rec[2] = kc;
+    rec[3] = ka;
+    rec[4] = cur.erel;
+    rec[5] = avg.erel;
+    rec[9] = sc->kkt_anchor;
+    rec[10] = sc->kkt_prev;
+    int status = kRunning, out_avg = 0;
+    if (isnan(cur.erel) || isnan(avg.erel)) {
+        status = 3;
+    } else if (cur.erel <= sc->eps_rel) {
+        status = 0;
+    } else if (avg.erel <= sc->eps_rel) {
+        status = 0;
+        out_avg = 1;
+    } else if (k >= sc->max_iters) {
+        status = 1;
+        out_avg = avg.erel < cur.erel;
+    }
+    sc->k = k;
+    if (status != kRunning) {
+        sc->t = t;
+        sc->status = status;
+        sc->last_restart = 0;
+        set_output(sc, out_avg ? avg : cur, out_avg);
+        rec[6] = out_avg;
+        rec[8] = omega;
+        rec[11] = __builtin_inf();
+    } else {
+        const int use_avg = ka < kc;
+        const double kcand = use_avg ? ka : kc;
+        const double anc = sc->kkt_anchor, prev = sc->kkt_prev;
+        double margin = fabs(ka - kc) / fmax(fmax(ka, kc), 1e-300);
+        int why = 0;
+        if (sc->restarts_on) {
+            const double mi = fabs(kcand - 0.2 * anc) / fmax(anc, 1e-300);
+            const double mii = fabs(kcand - 0.8 * anc) / fmax(anc, 1e-300);
+            const double mprev = finite_d(prev) ? fabs(kcand - prev) / fmax(prev, 1e-300) : __builtin_inf();
+            const double miii = fabs((double)t - 0.36 * (double)k) / (double)k;
+            margin = fmin(margin, fmin(fmin(mi, mii), fmin(mprev, miii)));
+            if (kcand <= 0.2 * anc) why = 1;
+            else if (kcand <= 0.8 * anc && kcand > prev) why = 2;
+            else if ((double)t >= 0.36 * (double)k) why = 3;
+        }
+        rec[6] = use_avg;
+        rec[7] = why;
+        rec[11] = margin;
+        double om = omega;
+        if (why) {
+            const Kkt& cd = use_avg ? avg : cur;
+            const double dx = sqrt(cd.dx2), dy = sqrt(cd.dy2);
+            if (dx > 1e-10 && dy > 1e-10) om = sqrt((om * dy) / dx);
+            sc->omega = om;
+            sc->tau = sc->eta / om;
+            sc->sigma = sc->eta * om;
+            sc->anc_rps2 = cd.rps2;
+            sc->anc_rds2 = cd.rds2;
+            sc->anc_gap = cd.pobj - cd.dobj;
+            sc->kkt_anchor = kkt_w(cd.rps2, cd.rds2, cd.pobj - cd.dobj, om);
+            sc->kkt_prev = __builtin_inf();
+            sc->last_restart = use_avg ? 2 : 1;
+            sc->restarts += 1;
+            t = 0;
+        } else {
+            sc->kkt_prev = kcand;
+            sc->last_restart = 0;
+        }
+        sc->t = t;
+        rec[8] = om;
+        // keep the latest statistics of both candidates for a host-side stop
+        set_output(sc, (avg.erel < cur.erel) ? avg : cur, avg.erel < cur.erel);
+    }
+    const long long nt = sc->n_trace;
+    if (P.trace && nt < sc->trace_cap) {
+        for (int f = 0; f < kTraceW; ++f) P.trace[nt * kTraceW + f] = rec[f];
+    }
+    sc->n_trace = nt + 1;
+}
+
+// Restart: the candidate becomes the iterate, the anchor and the average.
+__global__ void apply_restart_kernel(DevLP P) {
+    const int lr = P.sc->last_restart;
+    if (lr == 0) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P.n) {
+        double v;
+        if (lr == 2) {
+            v = P.xa[g];
+            P.x[g] = v;
+        } else {
+            v = P.x[g];
+            P.xa[g] = v;
+        }
+        P.xan[g] = v;
+    }
+    if (g < P.m) {
+        double v;
+        if (lr == 2) {
+            v = P.ya[g];
+            P.y[g] = v;
+            P.ax[g] = P.axa[g];
+        } else {
+            v = P.y[g];
+            P.ya[g] = v;
+        }
+        P.yan[g] = v;
+    }
+}
+
+__global__ void stop_kernel(Scalars* sc, int status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && sc->status == kRunning) {
+        sc->status = status;
+        sc->out_avg = 0;
+        sc->last_restart = 0;
+    }
+}
+
+// Returned point on the original scale: x = C x~, y = R y~, z = projected reduced cost.
+__global__ void extract_kernel(DevLP P) {
+    const int avg = P.sc->out_avg;
+    const double* xs = avg ? P.xa : P.x;
+    const double* ys = avg ? P.ya : P.y;
+    const double* at = avg ? P.atya : P.aty;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P.n) {
+        P.out_x[g] = xs[g] * P.C[g];
+        const double ls = P.c[g] - at[g];
+        const bool flo = finite_d(P.xl[g]), fhi = finite_d(P.xu[g]);
+        double zs = ls;
+        if (!flo && !fhi) zs = 0.0;
+        else if (flo && !fhi) zs = ls > 0.0 ? ls : 0.0;
+        else if (!flo && fhi) zs = ls < 0.0 ? ls : 0.0;
+        P.out_z[g] = zs * P.Ci[g];
+    }
+    if (g < P.m) P.out_y[g] = ys[g] * P.R[g];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------- launchers
+
+void launch_fill(double* p, long long n, double v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n) > 4096 ? 4096 : grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+}
+
+void launch_scale_pass(const DevLP& P, int* A_rp, int* A_ci, double* A_v, const int* AT_rp, const int* perm,
+                       double* R, double* C, double* rf, double* cf, int use_sum, hipStream_t s) {
+    if (P.m > 0)
+        hipLaunchKernelGGL(scale_rowstat_kernel, dim3(grid_for(P.m)), dim3(kBlock), 0, s, P.m, A_rp, A_v, use_sum,
+                           rf);
+    hipLaunchKernelGGL(scale_colstat_kernel, dim3(grid_for(P.n)), dim3(kBlock), 0, s, P.n, AT_rp, perm, A_v,
+                       use_sum, cf);
+    if (P.m > 0)
+        hipLaunchKernelGGL(scale_apply_rows_kernel, dim3(grid_for(P.m)), dim3(kBlock), 0, s, P.m, A_rp, A_ci, A_v,
+                           rf, cf, R);
+    hipLaunchKernelGGL(scale_apply_cols_kernel, dim3(grid_for(P.n)), dim3(kBlock), 0, s, P.n, cf, C);
+}
+
+void launch_gather(const int* perm, const double* src, double* dst, long long nnz, hipStream_t s) {
+    if (nnz <= 0) return;
+    unsigned g = grid_for(nnz);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(gather_kernel, dim3(g), dim3(kBlock), 0, s, perm, src, dst, nnz);
+}
+
+void launch_prepare(const DevLP& P, double* c, double* bl, double* bu, double* xl, double* xu, double* R, double* C,
+                    double* Ri, double* Ci, double* x0, double* y0, hipStream_t s) {
+    const int mx = P.m > P.n ? P.m : P.n;
+    hipLaunchKernelGGL(prepare_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P.m, P.n, c, bl, bu, xl, xu, R, C,
+                       Ri, Ci, x0, y0);
+}
+
+void launch_norms(const DevLP& P, hipStream_t s) {
+    hipLaunchKernelGGL(norms_kernel, dim3(P.nred), dim3(kBlock), 0, s, P);
+}
+
+void launch_power_norm(const DevLP& P, int iters, unsigned long long seed, double* v, double* u, double* w,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(power_init_kernel, dim3(grid_for(P.n)), dim3(kBlock), 0, s, P.n, seed, v);
+    hipLaunchKernelGGL(sumsq2_kernel, dim3(P.nred), dim3(kBlock), 0, s, v, P.n, v, 0, P.partials);
+    unsigned gn = grid_for(P.n);
+    if (gn > 2048) gn = 2048;
+    hipLaunchKernelGGL(normalize_kernel, dim3(gn), dim3(kBlock), 0, s, v, v, P.n, P.partials, P.nred, 0,
+                       (Scalars*)nullptr);
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(1), 0, s, &P.sc->sigma_max, 1LL, 0.0);
+    for (int it = 0; it < iters; ++it) {
+        if (P.m > 0) launch_spmv_store(P.A, v, u, nullptr, s);
+        if (P.m > 0) launch_spmv_store(P.AT, u, w, nullptr, s);
+        else launch_fill(w, P.n, 0.0, s);
+        hipLaunchKernelGGL(sumsq2_kernel, dim3(P.nred), dim3(kBlock), 0, s, u, P.m, w, P.n, P.partials);
+        hipLaunchKernelGGL(normalize_kernel, dim3(gn), dim3(kBlock), 0, s, w, v, P.n, P.partials, P.nred, 1, P.sc);
+    }
+}
+
+void launch_finalize_setup(const DevLP& P, double eta_override, double omega_override, double c0, hipStream_t s) {
+    launch_norms(P, s);
+    hipLaunchKernelGGL(finalize_setup_kernel, dim3(1), dim3(kBlock), 0, s, P, P.nred, eta_override, omega_override,
+                       c0);
+}
+
+void launch_reset(const DevLP& P, double eps_rel, long long max_iters, int eval_every, int restarts_on,
+                  long long trace_cap, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, P.sc, eps_rel, max_iters, eval_every, restarts_on,
+                       trace_cap);
+}
+
+void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s) {
+    const int mx = P.m > P.n ? P.m : P.n;
+    hipLaunchKernelGGL(init_state_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, x0, y0);
+}
+
+void launch_spmv_store(const Csr& M, const double* xin, double* out, const Scalars* gate, hipStream_t s) {
+    EpiStore e{out, gate};
+    launch_tiles(M, xin, e, s);
+}
+
+void launch_primal(const DevLP& P, int it, hipStream_t s) {
+    EpiPrimal e{};
+    e.sc = P.sc;
+    e.it = it;
+    e.c = P.c;
+    e.xl = P.xl;
+    e.xu = P.xu;
+    e.x = P.x;
+    e.xa = P.xa;
+    // with no rows every row of A^T is empty and the tiles still carry the primal update
+    launch_tiles(P.AT, P.y, e, s);
+}
+
+void launch_dual(const DevLP& P, int it, hipStream_t s) {
+    if (P.m == 0) return;
+    EpiDual e{};
+    e.sc = P.sc;
+    e.it = it;
+    e.bl = P.bl;
+    e.bu = P.bu;
+    e.y = P.y;
+    e.ya = P.ya;
+    e.ax = P.ax;
+    launch_tiles(P.A, P.x, e, s);
+}
+
+void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
+    if (mode == 1) {
+        if (P.m > 0) launch_spmv_store(P.A, P.x, P.ax, P.sc, s);
+        launch_spmv_store(P.AT, P.y, P.aty, P.sc, s);
+    } else if (mode == 0) {
+        launch_spmv_store(P.AT, P.y, P.aty, P.sc, s);
+        if (P.m > 0) launch_spmv_store(P.A, P.xa, P.axa, P.sc, s);
+        launch_spmv_store(P.AT, P.ya, P.atya, P.sc, s);
+    } else {
+        launch_spmv_store(P.AT, P.y, P.aty, nullptr, s);
+    }
+    hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
+}
+
+void launch_apply_restart(const DevLP& P, hipStream_t s) {
+    const int mx = P.m > P.n ? P.m : P.n;
+    hipLaunchKernelGGL(apply_restart_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
+void launch_stop(const DevLP& P, int status, hipStream_t s) {
+    hipLaunchKernelGGL(stop_kernel, dim3(1), dim3(1), 0, s, P.sc, status);
+}
+
+void launch_extract(const DevLP& P, hipStream_t s) {
+    const int mx = P.m > P.n ? P.m : P.n;
+    hipLaunchKernelGGL(extract_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
+}  // namespace lpgpu

@@ -1,0 +1,127 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function the header
+declares, and rejects invalid input with the documented error codes before touching a
+device (validation runs on the host, ahead of any HIP call)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2604_23951_amd as lpg
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(lp_\w+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lpg.lib()
+    declared = _declared()
+    assert declared, "no declarations found"
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(lpg.EXPORTS) == declared
+
+
+def test_error_strings():
+    for code in range(9):
+        assert lpg.lp_error_string(code)
+    assert lpg.lp_error_string(99) == "unknown error code"
+
+
+def _args(lp):
+    return dict(m=lp.m, n=lp.n, nnz=lp.nnz, row_ptr=np.ascontiguousarray(lp.row_ptr, np.int32),
+                col_idx=np.ascontiguousarray(lp.col_idx, np.int32), vals=np.ascontiguousarray(lp.vals),
+                c=np.ascontiguousarray(lp.c), c0=0.0, b_lo=np.ascontiguousarray(lp.b_lo),
+                b_hi=np.ascontiguousarray(lp.b_hi), x_lo=np.ascontiguousarray(lp.x_lo),
+                x_hi=np.ascontiguousarray(lp.x_hi))
+
+
+def _create_code(**a):
+    try:
+        h = lpg.lp_create(**a)
+    except lpg.LpError as e:
+        return e.code
+    lpg.lp_destroy(h)
+    return 0
+
+
+@pytest.mark.parametrize("case,code", [
+    ("nan_value", 4), ("inf_value", 4), ("nan_cost", 4), ("inf_cost", 4), ("nan_bound", 4),
+    ("lo_gt_hi_row", 3), ("lo_gt_hi_col", 3), ("lo_plus_inf", 3), ("hi_minus_inf", 3),
+    ("unsorted_row", 2), ("duplicate_col", 2), ("col_out_of_range", 2), ("row_ptr_decreasing", 2),
+    ("row_ptr_bad_end", 2), ("negative_m", 1), ("zero_n", 1), ("null_cost", 1), ("bad_eval_every", 1),
+    ("nan_c0", 4),
+])
+def test_invalid_input_codes(case, code):
+    lp = synth.cfg0(0)
+    a = _args(lp)
+    r = int(np.flatnonzero(np.diff(lp.row_ptr) >= 2)[0])
+    e0 = int(lp.row_ptr[r])
+    if case == "nan_value":
+        a["vals"] = a["vals"].copy(); a["vals"][3] = math.nan
+    elif case == "inf_value":
+        a["vals"] = a["vals"].copy(); a["vals"][3] = math.inf
+    elif case == "nan_cost":
+        a["c"] = a["c"].copy(); a["c"][1] = math.nan
+    elif case == "inf_cost":
+        a["c"] = a["c"].copy(); a["c"][1] = -math.inf
+    elif case == "nan_bound":
+        a["b_lo"] = a["b_lo"].copy(); a["b_lo"][2] = math.nan
+    elif case == "lo_gt_hi_row":
+        a["b_lo"] = a["b_lo"].copy(); a["b_hi"] = a["b_hi"].copy(); a["b_lo"][0] = 2.0; a["b_hi"][0] = 1.0
+    elif case == "lo_gt_hi_col":
+        a["x_lo"] = a["x_lo"].copy(); a["x_lo"][0] = 11.0
+    elif case == "lo_plus_inf":
+        a["x_lo"] = a["x_lo"].copy(); a["x_hi"] = a["x_hi"].copy(); a["x_lo"][0] = math.inf; a["x_hi"][0] = math.inf
+    elif case == "hi_minus_inf":
+        a["b_lo"] = a["b_lo"].copy(); a["b_hi"] = a["b_hi"].copy(); a["b_lo"][0] = -math.inf
+        a["b_hi"][0] = -math.inf
+    elif case == "unsorted_row":
+        a["col_idx"] = a["col_idx"].copy(); a["col_idx"][e0], a["col_idx"][e0 + 1] = a["col_idx"][e0 + 1], a["col_idx"][e0]
+    elif case == "duplicate_col":
+        a["col_idx"] = a["col_idx"].copy(); a["col_idx"][e0 + 1] = a["col_idx"][e0]
+    elif case == "col_out_of_range":
+        a["col_idx"] = a["col_idx"].copy(); a["col_idx"][-1] = lp.n
+    elif case == "row_ptr_decreasing":
+        a["row_ptr"] = a["row_ptr"].copy(); a["row_ptr"][r + 1] = a["row_ptr"][r] - 1
+    elif case == "row_ptr_bad_end":
+        a["nnz"] = lp.nnz + 1
+    elif case == "negative_m":
+        a["m"] = -1
+    elif case == "zero_n":
+        a["n"] = 0
+    elif case == "null_cost":
+        a["c"] = None
+    elif case == "bad_eval_every":
+        a["opt"] = lpg.make_options(eval_every=0)
+    elif case == "nan_c0":
+        a["c0"] = math.nan
+    assert _create_code(**a) == code
+    assert lpg.lp_last_error()  # a message is recorded
+
+
+def test_null_out_pointer():
+    import ctypes
+    lp = synth.cfg0(0)
+    a = _args(lp)
+    rc = lpg.lib().lp_create(None, a["m"], a["n"], a["nnz"], a["row_ptr"].ctypes.data, a["col_idx"].ctypes.data,
+                             a["vals"].ctypes.data, a["c"].ctypes.data, 0.0, a["b_lo"].ctypes.data,
+                             a["b_hi"].ctypes.data, a["x_lo"].ctypes.data, a["x_hi"].ctypes.data, None)
+    assert rc == 1
+
+
+def test_null_handle_calls():
+    assert lpg.lib().lp_solve(None) == 1
+    assert lpg.lib().lp_get_solution(None, None, None, None, None) == 1
+    lpg.lib().lp_destroy(None)  # ignored
