@@ -1,0 +1,185 @@
+"""Benchmark of the restarted-PDHG hot path on one MI355X.
+
+Workload: the single large LP (m = 1e6 rows, n = 2e6 columns, nnz = 1.2e7, power-law
+column degrees with exponent 2.2 and maximum 5000, every row with >= 2 entries, values
+N(0,1), 20% free columns, 35% equality / 35% one-sided / 30% two-sided rows,
+KKT-constructed so the optimum is known), solved in FP64 with the power-of-two
+Ruiz + Pock-Chambolle scaling.
+
+A step is one evaluation period of the solver: eval_every = 64 PDHG iterations (each a
+fused A^T y + primal update and a fused A x + dual update), the FP64 KKT evaluation of
+the current and the average iterate, and the restart / primal-weight / termination
+decision. `value` is PDHG iterations per second with the problem resident in HBM.
+
+The per-kernel durations of the primal and the dual kernel are measured with HIP events
+on the solver stream during the timed region (one sampled iteration per step).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "PDHG iters/s & HBM GB/s vs roofline; batched LPs/s to 1e-4 KKT, p50/p99"
+
+
+def algorithmic_bytes(m: int, n: int, nnz: int, sv: int = 8):
+    """Bytes the method must move per launch (int32 indices, sv-byte values).
+
+    primal kernel: A^T values + indices, A^T row pointers, one gather of y, read x, c,
+                   x_lo, x_hi, x_avg and write x, x_avg.
+    dual kernel:   A values + indices, A row pointers, one gather of x, read y, b_lo, b_hi,
+                   y_avg, A x and write y, y_avg, A x.
+    """
+    primal = (sv + 4) * nnz + 4 * (n + 1) + sv * (7 * n + m)
+    dual = (sv + 4) * nnz + 4 * (m + 1) + sv * (n + 8 * m)
+    return primal, dual
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def run_cpu_baseline(lp, iters: int) -> dict:
+    """The oracle as it stands, single-threaded on the host, on a bounded sample."""
+    import oracle
+
+    r = oracle.solve(lp, eps_rel=0.0, max_iters=iters, pow_iters=10)
+    rate = iters / r.iter_s
+    return {"value": rate, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"same LP, first {iters} PDHG iterations incl. {iters // 64} KKT evaluations; "
+                      f"setup (transpose, scaling, 10-step power iteration) not timed; "
+                      f"{r.iter_s:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--eval-every", type=int, default=64)
+    ap.add_argument("--cpu-iters", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-1e-4 measurement")
+    ap.add_argument("--solve-time-limit", type=float, default=60.0)
+    ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU layout is a design note, not built", file=sys.stderr)
+        return 2
+
+    import numpy as np
+
+    import paper_2604_23951_amd as lpg
+    import synth
+
+    if args.size == "full":
+        m, n, nnz = 1_000_000, 2_000_000, 12_000_000
+    else:
+        m, n, nnz = (int(v) for v in args.size.split(","))
+    t0 = time.time()
+    lp = synth.cfg1(0, m=m, n=n, nnz=nnz)
+    gen_s = time.time() - t0
+    print(f"[bench] generated {lp.name} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    E = args.eval_every
+    solver = lpg.Solver(lp, eps_rel=0.0, max_iters=E * max(args.warmup, 1), eval_every=E)
+    sol = solver.solve()  # warmup (also captures the iteration graph)
+    setup_s = sol.info.setup_seconds
+    print(f"[bench] setup {setup_s:.2f}s, warmup {sol.info.iterations} iterations in {sol.info.solve_seconds:.3f}s",
+          file=sys.stderr, flush=True)
+
+    # timed region: exactly `steps` evaluation periods, kernel events on the solver stream
+    K = args.steps
+    solver.update(eps_rel=0.0, max_iters=E * K, eval_every=E)
+    lpg.lp_set_kernel_timing(solver.h, True)
+    t1 = time.perf_counter()
+    sol = solver.solve()
+    dt = time.perf_counter() - t1
+    p_ms, d_ms, samples = lpg.lp_get_kernel_times(solver.h)
+    lpg.lp_set_kernel_timing(solver.h, False)
+    assert sol.info.iterations == E * K
+    iters_per_s = E * K / dt
+    print(f"[bench] timed {K} steps ({E * K} iterations) in {dt:.3f}s: {iters_per_s:.1f} it/s; "
+          f"primal {p_ms * 1e3:.1f} us, dual {d_ms * 1e3:.1f} us ({samples} samples)", file=sys.stderr, flush=True)
+
+    # same region replayed as hipGraph bundles without events
+    t2 = time.perf_counter()
+    sol_g = solver.solve()
+    dt_g = time.perf_counter() - t2
+
+    bp, bd = algorithmic_bytes(m, n, nnz)
+    gbs_p = bp / (p_ms * 1e-3) / 1e9
+    gbs_d = bd / (d_ms * 1e-3) / 1e9
+    if p_ms >= d_ms:
+        dom = dict(kernel="primal: A^T y + primal update", bytes=bp, ms=p_ms, gbs=gbs_p)
+    else:
+        dom = dict(kernel="dual: A x + dual update", bytes=bd, ms=d_ms, gbs=gbs_d)
+    iter_bytes = bp + bd
+    result = {
+        "metric": METRIC,
+        "value": iters_per_s,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": dt / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single large LP, FP64: m=%d n=%d nnz=%d, power-law columns (exp 2.2, max 5000), "
+                               "20%% free columns, 30%% two-sided rows, KKT-constructed" % (m, n, nnz),
+                   "m": m, "n": n, "nnz": nnz, "iters_per_step": E, "precision": "fp64", "scaling": "ruiz10+pc"},
+        "roofline": {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom["kernel"],
+                     "alg_bytes_per_launch": dom["bytes"], "avg_launch_ms": dom["ms"]},
+        "kernels": {"primal_ms": p_ms, "primal_alg_bytes": bp, "primal_gbs": gbs_p,
+                    "dual_ms": d_ms, "dual_alg_bytes": bd, "dual_gbs": gbs_d, "samples": samples},
+        "iteration_alg_bytes": iter_bytes,
+        "effective_gbs_per_iteration": iter_bytes * iters_per_s / 1e9,
+        "graph_mode_iters_per_s": E * K / dt_g,
+        "setup_s": setup_s,
+        "generate_s": gen_s,
+    }
+    if not args.no_solve:
+        solver.update(eps_rel=1e-4, max_iters=10**7, time_limit_s=args.solve_time_limit, eval_every=E)
+        t3 = time.perf_counter()
+        s4 = solver.solve()
+        dt4 = time.perf_counter() - t3
+        result["solve_to_1e-4"] = {"status": s4.status, "iterations": int(s4.info.iterations),
+                                   "restarts": int(s4.info.restarts), "seconds": dt4,
+                                   "rel_kkt": s4.info.rel_kkt, "primal_obj": s4.info.primal_obj,
+                                   "p_star": lp.p_star,
+                                   "rel_obj_err": abs(s4.info.primal_obj - lp.p_star) / (1 + abs(lp.p_star))}
+        print(f"[bench] solve to 1e-4: {s4.status} after {s4.info.iterations} iterations in {dt4:.2f}s",
+              file=sys.stderr, flush=True)
+    solver.close()
+    if not args.no_cpu_baseline:
+        print(f"[bench] cpu baseline: oracle, {args.cpu_iters} iterations", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = run_cpu_baseline(lp, args.cpu_iters)
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -64,12 +64,24 @@ def library_loaded() -> bool:
     return _lib is not None
 
 
+def _share_torch_runtime():
+    """PyTorch-ROCm ships its own libamdhip64 with the same soname as the system one. Loading
+    torch first makes the dynamic loader bind this library to torch's copy, so a process
+    that uses both has one HIP runtime (and torch streams and device pointers are valid
+    here). Without torch the system runtime is used."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def lib():
     """Load the HIP library; raise if it was not built (no fallback exists)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP solver library missing: {LIB_PATH} (run __graft_entry__.build())")
+        _share_torch_runtime()
         L = C.CDLL(LIB_PATH)
         P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.lp_default_options.argtypes = [P]

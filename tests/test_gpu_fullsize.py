@@ -1,0 +1,57 @@
+"""Parity at the full size of the large workload (m = 1e6, n = 2e6, nnz = 1.2e7), in the
+launch configuration the benchmark times: the scaled matrix and its transpose bit-exact,
+the iterates of the first 66 iterations (crossing the first evaluation and restart)
+element by element against the oracle, and the converged point checked by the oracle's
+KKT function on the original data against the known optimum."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_23951_amd as lpg
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def big():
+    return synth.cfg1(0)
+
+
+def test_full_size_structure_and_iterates(oracle_lib, big):
+    lp = big
+    ks = [1, 2, 64, 65, 66]
+    ref = oracle.solve(lp, eps_rel=0.0, max_iters=66, pow_iters=20, snap_k=ks)
+    with lpg.Solver(lp, eps_rel=0.0, max_iters=1, pow_iters=20) as s:
+        lay = s.layout()
+        assert lay["long_rows_at"] >= 1  # power-law columns longer than one LDS tile
+        gv, gR, gC, grp, gci, gvt = s.scaled()
+        av, R, Cc, rpT, ciT, avT = oracle.scaled_problem(lp)
+        assert np.array_equal(grp, rpT) and np.array_equal(gci, ciT)
+        assert np.array_equal(gv.view(np.uint64), av.view(np.uint64))
+        assert np.array_equal(gvt.view(np.uint64), avT.view(np.uint64))
+        assert np.array_equal(gR, R) and np.array_equal(gC, Cc)
+        del gv, gvt, av, avT
+        for i, k in enumerate(ks):
+            s.update(eps_rel=0.0, max_iters=k)
+            sol = s.solve()
+            assert sol.info.iterations == k
+            for a, b in zip(s.iterates(), oracle.split_snap(ref.snaps[i], lp.n, lp.m)):
+                d = float(np.max(np.abs(a - b))) / max(1.0, float(np.max(np.abs(b))))
+                assert d <= 1e-12, (k, d)
+        assert abs(sol.info.sigma_max - ref.sigma_max) <= 1e-12 * ref.sigma_max
+
+
+def test_full_size_solve_properties(oracle_lib, big):
+    lp = big
+    with lpg.Solver(lp, eps_rel=1e-4, max_iters=10**7, time_limit_s=90.0) as s:
+        sol = s.solve()
+    print(f"full-size solve: {sol.status}, {sol.info.iterations} iterations, {sol.info.solve_seconds:.2f}s, "
+          f"E_rel {sol.info.rel_kkt:.2e}, p {sol.info.primal_obj:.10g} vs p* {lp.p_star:.10g}")
+    if sol.status == "time_limit":
+        pytest.skip("did not reach 1e-4 within the time limit")
+    assert sol.status == "optimal"
+    chk = oracle.kkt(lp, sol.x, sol.y)
+    assert chk["erel"] <= 1e-4
+    assert abs(chk["erel"] - sol.info.rel_kkt) <= 1e-8 * chk["erel"]
+    assert abs(sol.info.primal_obj - lp.p_star) <= 1e-2 * (1 + abs(lp.p_star))
