@@ -78,6 +78,10 @@ def main(argv=None):
     ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-1e-4 measurement")
     ap.add_argument("--solve-time-limit", type=float, default=60.0)
     ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
+    ap.add_argument("--layout", type=int, default=0, help="0 panel-packed wave units, 1 row tiles")
+    ap.add_argument("--slice-bytes", type=int, default=0)
+    ap.add_argument("--units-per-cu", type=int, default=0)
+    ap.add_argument("--long-row-len", type=int, default=0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -99,7 +103,15 @@ def main(argv=None):
     print(f"[bench] generated {lp.name} in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     E = args.eval_every
-    solver = lpg.Solver(lp, eps_rel=0.0, max_iters=E * max(args.warmup, 1), eval_every=E)
+    tun = dict(spmv_layout=args.layout)
+    if args.slice_bytes:
+        tun["panel_slice_bytes"] = args.slice_bytes
+    if args.units_per_cu:
+        tun["units_per_cu"] = args.units_per_cu
+    if args.long_row_len:
+        tun["long_row_len"] = args.long_row_len
+    solver = lpg.Solver(lp, eps_rel=0.0, max_iters=E * max(args.warmup, 1), eval_every=E, **tun)
+    layout_info = solver.layout()
     sol = solver.solve()  # warmup (also captures the iteration graph)
     setup_s = sol.info.setup_seconds
     print(f"[bench] setup {setup_s:.2f}s, warmup {sol.info.iterations} iterations in {sol.info.solve_seconds:.3f}s",
@@ -147,7 +159,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": "single large LP, FP64: m=%d n=%d nnz=%d, power-law columns (exp 2.2, max 5000), "
                                "20%% free columns, 30%% two-sided rows, KKT-constructed" % (m, n, nnz),
-                   "m": m, "n": n, "nnz": nnz, "iters_per_step": E, "precision": "fp64", "scaling": "ruiz10+pc"},
+                   "m": m, "n": n, "nnz": nnz, "iters_per_step": E, "precision": "fp64", "scaling": "ruiz10+pc",
+                   "layout": layout_info},
         "roofline": {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom["kernel"],
                      "alg_bytes_per_launch": dom["bytes"], "avg_launch_ms": dom["ms"]},

@@ -83,6 +83,11 @@ typedef struct lp_options {
     void *hip_stream;      /* hipStream_t to run on; NULL: the library creates its own */
     int32_t device;        /* HIP device ordinal (default 0) */
     int32_t trace_cap;     /* number of evaluation records kept for lp_get_trace (default 4096) */
+    int32_t spmv_layout;   /* sparse-product layout: 0 panel-packed wave units (default), 1 row tiles */
+    int32_t long_row_len;  /* rows longer than this get a workgroup of their own (default 256) */
+    int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 8) */
+    int32_t pad0;
+    int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
 } lp_options;
@@ -171,7 +176,8 @@ int32_t lp_set_kernel_timing(lp_handle *h, int32_t enable);
 int32_t lp_get_kernel_times(lp_handle *h, double *primal_ms, double *dual_ms, int64_t *samples);
 
 /* Sizes the solver chose: sizes[0] = tiles of A, [1] = tiles of A^T, [2] = long rows of
- * A, [3] = long rows of A^T, [4] = device bytes held by the handle. */
+ * A, [3] = long rows of A^T, [4] = device bytes held by the handle, [5] = wave units of A,
+ * [6] = wave units of A^T, [7] = column panels of A, [8] = column panels of A^T. */
 int32_t lp_get_layout(lp_handle *h, int64_t *sizes, int32_t cap);
 
 #ifdef __cplusplus

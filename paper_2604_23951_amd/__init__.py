@@ -43,7 +43,8 @@ class lp_options(C.Structure):
         ("eval_every", C.c_int32), ("precision", C.c_int32), ("scaling", C.c_int32), ("ruiz_passes", C.c_int32),
         ("pow_iters", C.c_int32), ("restarts", C.c_int32), ("step_size", C.c_double), ("omega0", C.c_double),
         ("seed", C.c_uint64), ("hip_stream", C.c_void_p), ("device", C.c_int32), ("trace_cap", C.c_int32),
-        ("x0", C.c_void_p), ("y0", C.c_void_p),
+        ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32), ("pad0", C.c_int32),
+        ("panel_slice_bytes", C.c_int64), ("x0", C.c_void_p), ("y0", C.c_void_p),
     ]
 
 
@@ -196,10 +197,11 @@ def lp_get_kernel_times(h):
 
 
 def lp_get_layout(h):
-    out = np.zeros(5, np.int64)
-    _check(lib().lp_get_layout(h, _p(out), 5), h)
-    return dict(tiles_a=int(out[0]), tiles_at=int(out[1]), long_rows_a=int(out[2]), long_rows_at=int(out[3]),
-                device_bytes=int(out[4]))
+    out = np.zeros(9, np.int64)
+    _check(lib().lp_get_layout(h, _p(out), 9), h)
+    keys = ("tiles_a", "tiles_at", "long_rows_a", "long_rows_at", "device_bytes", "units_a", "units_at",
+            "panels_a", "panels_at")
+    return {k: int(v) for k, v in zip(keys, out)}
 
 
 # ---- convenience wrapper ---------------------------------------------------------------

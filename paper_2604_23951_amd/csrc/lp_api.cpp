@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "lp_device.h"
+#include "lp_layout.h"
 
 using namespace lpgpu;
 
@@ -71,6 +72,7 @@ struct lp_handle {
     int64_t nnz = 0;
     double c0 = 0.0;
     int64_t long_a = 0, long_at = 0;
+    int64_t units_a = 0, units_at = 0, panels_a = 0, panels_at = 0;
     char* arena = nullptr;
     size_t arena_bytes = 0;
     DevLP P{};
@@ -177,7 +179,8 @@ int32_t validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int
 
 int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
-        o.trace_cap < 0 || o.precision != LP_PREC_FP64 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
+        o.trace_cap < 0 || o.precision != LP_PREC_FP64 || o.spmv_layout < 0 || o.spmv_layout > 1 ||
+        o.long_row_len < 0 || o.units_per_cu < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s)) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
@@ -260,9 +263,30 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
                 perm[p] = e;
             }
     }
-    std::vector<int32_t> tA = build_tiles(m, rp, &h->long_a);
-    std::vector<int32_t> tAT = build_tiles(n, rpT.data(), &h->long_at);
+    int64_t dummy_long = 0;
+    std::vector<int32_t> tA = build_tiles(m, rp, &dummy_long);
+    std::vector<int32_t> tAT = build_tiles(n, rpT.data(), &dummy_long);
     const int32_t ntA = static_cast<int32_t>(tA.size()) - 1, ntAT = static_cast<int32_t>(tAT.size()) - 1;
+    // panel-packed layouts of A (gathers x) and A^T (gathers y)
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int target_units = cus * (o.units_per_cu > 0 ? o.units_per_cu : 8);
+    const int64_t slice = o.panel_slice_bytes > 0 ? o.panel_slice_bytes : (int64_t(1) << 20);
+    const int long_len = o.long_row_len > 0 ? o.long_row_len : 256;
+    const bool panels = o.spmv_layout == 0;
+    PanelLayoutHost LA, LAT;
+    if (panels) {
+        LA = build_panel_layout(m, n, rp, ci, nullptr, choose_panels(n, slice), long_len, target_units, kUnitRowCap);
+        LAT = build_panel_layout(n, m, rpT.data(), ciT.data(), perm.data(), choose_panels(m, slice), long_len,
+                                 target_units, kUnitRowCap);
+        h->long_a = static_cast<int64_t>(LA.long_rows.size());
+        h->long_at = static_cast<int64_t>(LAT.long_rows.size());
+        h->units_a = LA.units;
+        h->units_at = LAT.units;
+        h->panels_a = LA.panels;
+        h->panels_at = LAT.panels;
+    }
 
     int mx = m > n ? m : n;
     int nred = (mx + 1023) / 1024;
@@ -283,6 +307,20 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
     const size_t o_y = L.add(sm), o_ya = L.add(sm), o_yan = L.add(sm), o_ax = L.add(sm), o_axa = L.add(sm),
                  o_oy = L.add(sm);
     const size_t o_x0 = o.x0 ? L.add(sn) : 0, o_y0 = o.y0 ? L.add(sm) : 0;
+    auto add_layout = [&](const PanelLayoutHost& Q, size_t* off) {
+        off[0] = L.add(sizeof(int32_t) * Q.unit_row.size());
+        off[1] = L.add(sizeof(int32_t) * Q.unit_seg.size());
+        off[2] = L.add(sizeof(uint32_t) * Q.packed.size());
+        off[3] = L.add(sizeof(double) * Q.packed.size());
+        off[4] = L.add(sizeof(int32_t) * Q.src.size());
+        off[5] = L.add(sizeof(int32_t) * Q.long_rows.size());
+        off[6] = L.add(Q.is_long.size());
+    };
+    size_t offA[7] = {0}, offAT[7] = {0};
+    if (panels) {
+        add_layout(LA, offA);
+        add_layout(LAT, offAT);
+    }
     const size_t o_part = L.add(sizeof(double) * 2 * kNQ * kMaxRedBlocks), o_sc = L.add(sizeof(Scalars)),
                  o_tr = L.add(sizeof(double) * kTraceW * static_cast<size_t>(o.trace_cap > 0 ? o.trace_cap : 1));
     h->arena_bytes = L.off;
@@ -298,8 +336,22 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
     P.n = n;
     P.nnz = nnz;
     P.nred = nred;
-    P.A = Csr{m, ntA, I(o_arp), I(o_aci), D(o_av), I(o_at)};
-    P.AT = Csr{n, ntAT, I(o_trp), I(o_tci), D(o_tv), I(o_tt)};
+    P.A = Mat{};
+    P.AT = Mat{};
+    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), I(o_arp), I(o_aci), D(o_av), I(o_at), nullptr};
+    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), I(o_trp), I(o_tci), D(o_tv), I(o_tt), nullptr};
+    P.A.layout = P.AT.layout = panels ? 0 : 1;
+    auto bind_layout = [&](const PanelLayoutHost& Q, const size_t* off, Mat& M) {
+        M.pan = Panels{Q.units, Q.panels, Q.col_bits, static_cast<int>(Q.nnz_packed), I(off[0]), I(off[1]),
+                       reinterpret_cast<const unsigned*>(b + off[2]), D(off[3]),
+                       Q.is_long.empty() ? nullptr : reinterpret_cast<const unsigned char*>(b + off[6])};
+        M.nlong = static_cast<int>(Q.long_rows.size());
+        M.longrows = M.nlong ? I(off[5]) : nullptr;
+    };
+    if (panels) {
+        bind_layout(LA, offA, P.A);
+        bind_layout(LAT, offAT, P.AT);
+    }
     P.c = D(o_c);
     P.xl = D(o_xl);
     P.xu = D(o_xu);
@@ -348,6 +400,19 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
         HIP_TRY(h, H2D(D(o_bl), bl, sm));
         HIP_TRY(h, H2D(D(o_bu), bu, sm));
     }
+    auto upload_layout = [&](const PanelLayoutHost& Q, const size_t* off) -> hipError_t {
+        hipError_t e = H2D(b + off[0], Q.unit_row.data(), sizeof(int32_t) * Q.unit_row.size());
+        if (e == hipSuccess) e = H2D(b + off[1], Q.unit_seg.data(), sizeof(int32_t) * Q.unit_seg.size());
+        if (e == hipSuccess) e = H2D(b + off[2], Q.packed.data(), sizeof(uint32_t) * Q.packed.size());
+        if (e == hipSuccess) e = H2D(b + off[4], Q.src.data(), sizeof(int32_t) * Q.src.size());
+        if (e == hipSuccess) e = H2D(b + off[5], Q.long_rows.data(), sizeof(int32_t) * Q.long_rows.size());
+        if (e == hipSuccess) e = H2D(b + off[6], Q.is_long.data(), Q.is_long.size());
+        return e;
+    };
+    if (panels) {
+        HIP_TRY(h, upload_layout(LA, offA));
+        HIP_TRY(h, upload_layout(LAT, offAT));
+    }
     if (o.x0) HIP_TRY(h, H2D(h->d_x0, o.x0, sn));
     if (o.y0 && m > 0) HIP_TRY(h, H2D(h->d_y0, o.y0, sm));
     HIP_TRY(h, hipMemsetAsync(P.sc, 0, sizeof(Scalars), s));
@@ -361,6 +426,10 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
                               D(o_aty), pass == o.ruiz_passes ? 1 : 0, s);
     }
     launch_gather(h->d_perm, D(o_av), D(o_tv), nnz, s);
+    if (panels) {  // panel values in packed order, from the scaled A
+        launch_gather(I(offA[4]), D(o_av), D(offA[3]), LA.nnz_packed, s);
+        launch_gather(I(offAT[4]), D(o_av), D(offAT[3]), LAT.nnz_packed, s);
+    }
     launch_prepare(P, D(o_c), D(o_bl), D(o_bu), D(o_xl), D(o_xu), D(o_R), D(o_C), D(o_Ri), D(o_Ci), h->d_x0,
                    h->d_y0, s);
     // a3: ||A~||_2 by power iteration (x, A~x and A~^T y buffers are free at this point)
@@ -395,6 +464,10 @@ void lp_default_options(lp_options* o) {
     o->hip_stream = nullptr;
     o->device = 0;
     o->trace_cap = 4096;
+    o->spmv_layout = 0;
+    o->long_row_len = 256;
+    o->units_per_cu = 8;
+    o->panel_slice_bytes = int64_t(1) << 20;
     o->x0 = nullptr;
     o->y0 = nullptr;
 }
@@ -597,14 +670,14 @@ int32_t lp_get_scaled(lp_handle* h, double* vals, double* R, double* C, int32_t*
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const size_t nz = static_cast<size_t>(h->nnz);
-    if (vals && nz) HIP_TRY(h, hipMemcpyAsync(vals, h->P.A.v, sizeof(double) * nz, hipMemcpyDeviceToHost, s));
+    if (vals && nz) HIP_TRY(h, hipMemcpyAsync(vals, h->P.A.csr.v, sizeof(double) * nz, hipMemcpyDeviceToHost, s));
     if (R && h->m) HIP_TRY(h, hipMemcpyAsync(R, h->P.R, sizeof(double) * h->m, hipMemcpyDeviceToHost, s));
     if (C) HIP_TRY(h, hipMemcpyAsync(C, h->P.C, sizeof(double) * h->n, hipMemcpyDeviceToHost, s));
     if (t_row_ptr)
-        HIP_TRY(h, hipMemcpyAsync(t_row_ptr, h->P.AT.rp, sizeof(int32_t) * (h->n + 1), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipMemcpyAsync(t_row_ptr, h->P.AT.csr.rp, sizeof(int32_t) * (h->n + 1), hipMemcpyDeviceToHost, s));
     if (t_col_idx && nz)
-        HIP_TRY(h, hipMemcpyAsync(t_col_idx, h->P.AT.ci, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
-    if (t_vals && nz) HIP_TRY(h, hipMemcpyAsync(t_vals, h->P.AT.v, sizeof(double) * nz, hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipMemcpyAsync(t_col_idx, h->P.AT.csr.ci, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, s));
+    if (t_vals && nz) HIP_TRY(h, hipMemcpyAsync(t_vals, h->P.AT.csr.v, sizeof(double) * nz, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     return LP_OK;
 }
@@ -643,8 +716,9 @@ int32_t lp_get_kernel_times(lp_handle* h, double* primal_ms, double* dual_ms, in
 
 int32_t lp_get_layout(lp_handle* h, int64_t* sizes, int32_t cap) {
     if (!h || !sizes || cap < 0) return fail(h, LP_ERR_INVALID_ARG, "bad layout arguments");
-    const int64_t v[5] = {h->P.A.ntiles, h->P.AT.ntiles, h->long_a, h->long_at, static_cast<int64_t>(h->arena_bytes)};
-    for (int32_t i = 0; i < cap && i < 5; ++i) sizes[i] = v[i];
+    const int64_t v[9] = {h->P.A.csr.ntiles, h->P.AT.csr.ntiles, h->long_a, h->long_at,
+                          static_cast<int64_t>(h->arena_bytes), h->units_a, h->units_at, h->panels_a, h->panels_at};
+    for (int32_t i = 0; i < cap && i < 9; ++i) sizes[i] = v[i];
     return LP_OK;
 }
 

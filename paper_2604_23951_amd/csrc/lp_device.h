@@ -10,7 +10,7 @@ namespace lpgpu {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kTileNnz = 2048;    // nonzeros staged in LDS per SpMV tile
-constexpr int kTileRows = 1024;   // rows per SpMV tile at most
+constexpr int kTileRows = 512;    // rows per SpMV tile at most
 constexpr int kMaxRedBlocks = 512;
 constexpr int kNQ = 8;            // reduced quantities per candidate
 constexpr int kTraceW = 12;
@@ -35,21 +35,52 @@ struct Scalars {
     int pad;
 };
 
-// CSR matrix with its LDS tiling: tile b covers rows [tiles[b], tiles[b+1]).
+// CSR matrix with its LDS tiling: tile b covers rows [tiles[b], tiles[b+1]), or, when
+// rowlist is set, the single row rowlist[b].
 struct Csr {
     int rows;
     int ntiles;
+    int nnz;
     const int* rp;
     const int* ci;
     const double* v;
     const int* tiles;
+    const int* rowlist;
+};
+
+// Panel-packed layout (see lp_layout.h): unit u (one wave) owns rows
+// [unit_row[u], unit_row[u+1]) and the entries [unit_seg[u*(panels+1)], unit_seg[u*(panels+1)+panels]),
+// stored panel by panel. packed = (row inside the unit << col_bits) | column.
+struct Panels {
+    int units;
+    int panels;
+    int col_bits;
+    int nnz;
+    const int* unit_row;
+    const int* unit_seg;
+    const unsigned* pk;
+    const double* v;
+    const unsigned char* is_long;  // nullptr when the matrix has no long rows
+};
+
+constexpr int kUnitRowCap = 512;   // rows per wave unit at most
+constexpr int kUnitsPerBlock = 4;  // wave units per workgroup
+constexpr int kChunks = 2;         // 64-entry chunks a wave loads together
+
+// One sparse operand: CSR (scaling, inspection, long rows, row tiles) and its panel layout.
+struct Mat {
+    Csr csr;
+    Panels pan;
+    int nlong;
+    const int* longrows;
+    int layout;  // 0 panels, 1 row tiles
 };
 
 struct DevLP {
     int m, n;
     long long nnz;
     int nred;          // blocks of the fixed-grid reductions
-    Csr A, AT;
+    Mat A, AT;
     // scaled problem data
     const double *c, *bl, *bu, *xl, *xu;
     const double *R, *C, *Ri, *Ci;
@@ -79,7 +110,7 @@ void launch_finalize_setup(const DevLP& P, double eta_override, double omega_ove
 void launch_reset(const DevLP& P, double eps_rel, long long max_iters, int eval_every, int restarts_on,
                   long long trace_cap, hipStream_t s);
 void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s);
-void launch_spmv_store(const Csr& M, const double* xin, double* out, const Scalars* gate, hipStream_t s);
+void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scalars* gate, hipStream_t s);
 void launch_primal(const DevLP& P, int it, hipStream_t s);
 void launch_dual(const DevLP& P, int it, hipStream_t s);
 void launch_evaluate(const DevLP& P, int mode, hipStream_t s);  // mode 0 regular, 1 init, 2 final

@@ -89,49 +89,206 @@ inline unsigned grid_for(long long n, int per_block = kBlock) {
 
 // ------------------------------------------------------------------ SpMV with epilogues
 
-// One workgroup per tile. Short tiles: the tile's nonzeros are multiplied by the gathered
-// vector entries with coalesced loads and stored to LDS, then each thread forms the sum of
-// one row from LDS in CSR order and hands it to the epilogue. A tile that is a single row
-// longer than kTileNnz is reduced by the whole workgroup.
+// One workgroup per tile. Short tiles (at most kTileNnz nonzeros): every thread owns
+// kPerThread nonzeros of the tile; it first issues all their index and value loads, then all
+// the gathers of the vector entries, and stores the products to LDS, so each thread keeps
+// kPerThread independent memory requests in flight. The epilogue operands of the rows a
+// thread finishes are loaded before the barrier. After the barrier each thread forms the sum
+// of one row from LDS in CSR order and runs the epilogue. A tile that is a single row longer
+// than kTileNnz is reduced by the whole workgroup (fixed-shape tree).
+constexpr int kPerThread = kTileNnz / kBlock;
+constexpr int kRowsPerThread = kTileRows / kBlock;
+
 template <class Epi>
 __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double* __restrict__ xin, Epi epi) {
     __shared__ double prod[kTileNnz];
     __shared__ double red[kBlock / 64];
     if (!epi.begin()) return;
     const int b = blockIdx.x;
-    const int r0 = M.tiles[b], r1 = M.tiles[b + 1];
+    const int r0 = M.rowlist ? M.rowlist[b] : M.tiles[b];
+    const int r1 = M.rowlist ? r0 + 1 : M.tiles[b + 1];
     const int p0 = M.rp[r0], p1 = M.rp[r1];
     const int tid = threadIdx.x;
+    const int* __restrict__ ci = M.ci;
+    const double* __restrict__ av = M.v;
+    // Loads below are unconditional on clamped, in-bounds indices (every array holds at least
+    // one element) so that they issue back to back; out-of-range lanes are masked afterwards.
+    const int elast = M.nnz > 0 ? M.nnz - 1 : 0;
     if (p1 - p0 <= kTileNnz) {
-        for (int e = p0 + tid; e < p1; e += kBlock) prod[e - p0] = M.v[e] * xin[M.ci[e]];
+        int col[kPerThread];
+        double val[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int e = min(p0 + tid + k * kBlock, elast);
+            col[k] = __builtin_nontemporal_load(ci + e);
+            val[k] = __builtin_nontemporal_load(av + e);
+        }
+        typename Epi::Pre pre[kRowsPerThread];
+        int q0[kRowsPerThread], q1[kRowsPerThread];
+#pragma unroll
+        for (int j = 0; j < kRowsPerThread; ++j) {
+            const int r = min(r0 + tid + j * kBlock, r1 - 1);
+            q0[j] = M.rp[r] - p0;
+            q1[j] = M.rp[r + 1] - p0;
+            pre[j] = epi.load(r);
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+            if (p0 + tid + k * kBlock >= p1) col[k] = 0;
+        double xv[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) prod[tid + k * kBlock] = val[k] * xv[k];
         __syncthreads();
-        for (int r = r0 + tid; r < r1; r += kBlock) {
-            const int q0 = M.rp[r] - p0, q1 = M.rp[r + 1] - p0;
-            double s = 0.0;
-            for (int q = q0; q < q1; ++q) s += prod[q];
-            epi(r, s);
+#pragma unroll
+        for (int j = 0; j < kRowsPerThread; ++j) {
+            const int r = r0 + tid + j * kBlock;
+            if (r < r1) {
+                double s = 0.0;
+                int q = q0[j];
+                const int qe = q1[j];
+                for (; q + 4 <= qe; q += 4) {
+                    const double a0 = prod[q], a1 = prod[q + 1], a2 = prod[q + 2], a3 = prod[q + 3];
+                    s += a0;
+                    s += a1;
+                    s += a2;
+                    s += a3;
+                }
+                for (; q < qe; ++q) s += prod[q];
+                epi.finish(r, s, pre[j]);
+            }
         }
     } else {
+        const typename Epi::Pre pre = epi.load(r0);
         double s = 0.0;
-        for (int e = p0 + tid; e < p1; e += kBlock) {
-            const double pr = M.v[e] * xin[M.ci[e]];
-            s += pr;
+        for (int base = p0; base < p1; base += kTileNnz) {
+            int col[kPerThread];
+            double val[kPerThread];
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                const int e = min(base + tid + k * kBlock, elast);
+                col[k] = __builtin_nontemporal_load(ci + e);
+                val[k] = __builtin_nontemporal_load(av + e);
+            }
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k)
+                if (base + tid + k * kBlock >= p1) col[k] = 0;
+            double xv[kPerThread];
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                const double pr = val[k] * xv[k];
+                if (base + tid + k * kBlock < p1) s += pr;
+            }
         }
         s = block_sum(s, red);
-        if (tid == 0) epi(r0, s);
+        if (tid == 0) epi.finish(r0, s, pre);
     }
 }
 
+// Panel-packed SpMV, one wave64 per unit of rows. The wave walks its entries panel by panel
+// (all resident waves do, so the slice of the gathered vector for the current panel stays in
+// the L2 of each XCD). Inside a panel segment the entries are sorted by row, so a row's
+// entries in a 64-entry chunk form one run; the run's first lane adds the run's products,
+// in order, to the row's accumulator in wave-private LDS. Runs of a row in later chunks and
+// panels follow in column order, so every row sum is formed in CSR order. Loads and gathers
+// of kChunks chunks are issued together. After the last panel each lane finishes rows
+// lane, lane + 64, ... with the epilogue; rows listed as long are left to the long-row kernel.
+template <class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, const double* __restrict__ xin, Epi epi) {
+    __shared__ double acc_s[kUnitsPerBlock][kUnitRowCap];
+    __shared__ double prod_s[kUnitsPerBlock][kChunks * 64];
+    if (!epi.begin()) return;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int u = blockIdx.x * kUnitsPerBlock + w;
+    if (u >= M.units) return;  // the whole wave leaves; no workgroup barrier follows
+    const int r0 = M.unit_row[u], nr = M.unit_row[u + 1] - r0;
+    double* acc = acc_s[w];
+    double* prod = prod_s[w];
+    for (int r = lane; r < nr; r += 64) acc[r] = 0.0;
+    const int* seg = M.unit_seg + u * (M.panels + 1);
+    const unsigned cmask = (1u << M.col_bits) - 1u;
+    const int cb = M.col_bits;
+    const int last = M.nnz > 0 ? M.nnz - 1 : 0;
+    const unsigned* __restrict__ pkp = M.pk;
+    const double* __restrict__ pvp = M.v;
+    __builtin_amdgcn_wave_barrier();
+    for (int p = 0; p < M.panels; ++p) {
+        const int s = seg[p], e = seg[p + 1];
+        for (int base = s; base < e; base += kChunks * 64) {
+            unsigned pk[kChunks];
+            double val[kChunks];
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int idx = min(base + c * 64 + lane, last);
+                pk[c] = __builtin_nontemporal_load(pkp + idx);
+                val[c] = __builtin_nontemporal_load(pvp + idx);
+            }
+            double xv[kChunks];
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const unsigned col = (base + c * 64 + lane < e) ? (pk[c] & cmask) : 0u;
+                xv[c] = xin[col];
+            }
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) prod[c * 64 + lane] = val[c] * xv[c];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < kChunks; ++c) {
+                const int cbase = base + c * 64;
+                if (cbase >= e) break;
+                const int nvalid = min(64, e - cbase);
+                const int row = static_cast<int>(pk[c] >> cb);
+                const int prev = __shfl_up(row, 1, 64);
+                const bool head = lane < nvalid && (lane == 0 || prev != row);
+                const unsigned long long heads = __ballot(head);
+                if (head) {
+                    const unsigned long long rest = lane < 63 ? (heads >> (lane + 1)) : 0ull;
+                    const int end = rest ? lane + 1 + __builtin_ctzll(rest) : nvalid;
+                    double a = acc[row];
+                    for (int q = lane; q < end; ++q) a += prod[c * 64 + q];
+                    acc[row] = a;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int r = lane; r < nr; r += 4 * 64) {
+        typename Epi::Pre pre[4];
+        int rows[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            rows[k] = r0 + min(r + k * 64, nr - 1);
+            pre[k] = epi.load(rows[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int rl = r + k * 64;
+            if (rl < nr && !(M.is_long && M.is_long[rows[k]])) epi.finish(rows[k], acc[rl], pre[k]);
+        }
+    }
+}
+
+struct NoPre {};
+
 struct EpiStore {
+    using Pre = NoPre;
     double* out;
     const Scalars* gate;
     __device__ bool begin() const { return gate == nullptr || gate->status == kRunning; }
-    __device__ void operator()(int r, double s) const { out[r] = s; }
+    __device__ Pre load(int) const { return Pre{}; }
+    __device__ void finish(int r, double s, const Pre&) const { out[r] = s; }
 };
 
 // Primal step on column j of A (row j of A^T), s = (A~^T y)_j:
 //   x_j <- clamp(x_j - tau (c~_j - s), x~lo_j, x~hi_j);  running mean of x since the restart.
 struct EpiPrimal {
+    struct Pre {
+        double c, lo, hi, x, xa;
+    };
     const Scalars* sc;
     int it;
     const double *c, *xl, *xu;
@@ -146,12 +303,12 @@ struct EpiPrimal {
         wt = 1.0 / static_cast<double>(t);
         return true;
     }
-    __device__ void operator()(int j, double s) const {
-        const double g = c[j] - s;
-        const double xn = clampd(x[j] - tau * g, xl[j], xu[j]);
+    __device__ Pre load(int j) const { return Pre{c[j], xl[j], xu[j], x[j], xa[j]}; }
+    __device__ void finish(int j, double s, const Pre& p) const {
+        const double g = p.c - s;
+        const double xn = clampd(p.x - tau * g, p.lo, p.hi);
         x[j] = xn;
-        const double a = xa[j];
-        xa[j] = first ? xn : a + wt * (xn - a);
+        xa[j] = first ? xn : p.xa + wt * (xn - p.xa);
     }
 };
 
@@ -160,6 +317,9 @@ struct EpiPrimal {
 // (the closed-form proximal step of the row-bound term; it keeps y_i >= 0 where b_hi = +inf
 // and y_i <= 0 where b_lo = -inf), running mean of y, and A~x <- A~x+ for the next step.
 struct EpiDual {
+    struct Pre {
+        double y, bl, bu, ya, ax;
+    };
     const Scalars* sc;
     int it;
     const double *bl, *bu;
@@ -174,15 +334,15 @@ struct EpiDual {
         wt = 1.0 / static_cast<double>(t);
         return true;
     }
-    __device__ void operator()(int i, double s) const {
-        const double w = 2.0 * s - ax[i];
-        const double v = y[i] - sigma * w;
-        const double lo = v + sigma * bl[i];
-        const double hi = v + sigma * bu[i];
+    __device__ Pre load(int i) const { return Pre{y[i], bl[i], bu[i], ya[i], ax[i]}; }
+    __device__ void finish(int i, double s, const Pre& p) const {
+        const double w = 2.0 * s - p.ax;
+        const double v = p.y - sigma * w;
+        const double lo = v + sigma * p.bl;
+        const double hi = v + sigma * p.bu;
         const double yn = (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
         y[i] = yn;
-        const double a = ya[i];
-        ya[i] = first ? yn : a + wt * (yn - a);
+        ya[i] = first ? yn : p.ya + wt * (yn - p.ya);
         ax[i] = s;
     }
 };
@@ -191,6 +351,26 @@ template <class Epi>
 void launch_tiles(const Csr& M, const double* xin, const Epi& epi, hipStream_t s) {
     if (M.ntiles <= 0) return;
     hipLaunchKernelGGL(spmv_tiles_kernel<Epi>, dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
+}
+
+// One sparse product with its fused epilogue: the long rows (one workgroup each), then the
+// panel-packed rows; or the row tiles when that layout is selected.
+template <class Epi>
+void launch_spmv(const Mat& M, const double* xin, const Epi& epi, hipStream_t s) {
+    if (M.layout == 1) {
+        launch_tiles(M.csr, xin, epi, s);
+        return;
+    }
+    if (M.nlong > 0) {
+        Csr L = M.csr;
+        L.rowlist = M.longrows;
+        L.ntiles = M.nlong;
+        launch_tiles(L, xin, epi, s);
+    }
+    if (M.pan.units > 0) {
+        const unsigned g = (M.pan.units + kUnitsPerBlock - 1) / kUnitsPerBlock;
+        hipLaunchKernelGGL(spmv_panel_kernel<Epi>, dim3(g), dim3(kBlock), 0, s, M.pan, xin, epi);
+    }
 }
 
 // ------------------------------------------------------------------- setup kernels
@@ -788,9 +968,9 @@ void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipSt
     hipLaunchKernelGGL(init_state_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, x0, y0);
 }
 
-void launch_spmv_store(const Csr& M, const double* xin, double* out, const Scalars* gate, hipStream_t s) {
+void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scalars* gate, hipStream_t s) {
     EpiStore e{out, gate};
-    launch_tiles(M, xin, e, s);
+    launch_spmv(M, xin, e, s);
 }
 
 void launch_primal(const DevLP& P, int it, hipStream_t s) {
@@ -802,8 +982,8 @@ void launch_primal(const DevLP& P, int it, hipStream_t s) {
     e.xu = P.xu;
     e.x = P.x;
     e.xa = P.xa;
-    // with no rows every row of A^T is empty and the tiles still carry the primal update
-    launch_tiles(P.AT, P.y, e, s);
+    // with no rows every row of A^T is empty and the product still carries the primal update
+    launch_spmv(P.AT, P.y, e, s);
 }
 
 void launch_dual(const DevLP& P, int it, hipStream_t s) {
@@ -816,7 +996,7 @@ void launch_dual(const DevLP& P, int it, hipStream_t s) {
     e.y = P.y;
     e.ya = P.ya;
     e.ax = P.ax;
-    launch_tiles(P.A, P.x, e, s);
+    launch_spmv(P.A, P.x, e, s);
 }
 
 void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {

@@ -240,3 +240,32 @@ def test_torch_stream():
     ref = lpg.solve(lp, eps_rel=1e-4)
     assert sol.info.iterations == ref.info.iterations
     assert np.array_equal(sol.x, ref.x)
+
+
+LAYOUT_VARIANTS = {
+    "panels_default": dict(),
+    "row_tiles": dict(spmv_layout=1),
+    "tiny_panels_many_long_rows": dict(panel_slice_bytes=512, long_row_len=8, units_per_cu=1),
+    "one_unit_per_cu": dict(units_per_cu=1, panel_slice_bytes=4096),
+}
+
+
+@pytest.mark.parametrize("variant", sorted(LAYOUT_VARIANTS))
+@pytest.mark.parametrize("name", ["large_recipe_small", "transport"])
+def test_layout_variants_match_oracle(oracle_lib, variant, name):
+    """Every sparse-product layout (and extreme panel / unit / long-row settings) gives the
+    oracle's iterates: panel-packed rows are summed in CSR order like the oracle."""
+    lp = _case(name)
+    ks = [1, 2, 3, 64, 65, 130]
+    ref = oracle.solve(lp, eps_rel=0.0, max_iters=max(ks), snap_k=ks)
+    with lpg.Solver(lp, eps_rel=0.0, max_iters=1, **LAYOUT_VARIANTS[variant]) as s:
+        lay = s.layout()
+        if variant == "tiny_panels_many_long_rows":
+            assert lay["panels_a"] > 8
+            if name == "large_recipe_small":
+                assert lay["long_rows_at"] > 0
+        for i, k in enumerate(ks):
+            s.update(eps_rel=0.0, max_iters=k)
+            s.solve()
+            for a, b in zip(s.iterates(), oracle.split_snap(ref.snaps[i], lp.n, lp.m)):
+                assert _close(a, b) <= ITER_TOL, (variant, name, k)
