@@ -64,7 +64,12 @@ typedef enum {
 } lp_termination;
 
 typedef enum {
-    LP_PREC_FP64 = 0 /* matrix, iterates and all reductions in FP64 */
+    LP_PREC_FP64 = 0,        /* matrix, iterates and all reductions in FP64 */
+    LP_PREC_FP32_REFINED = 1 /* matrix and iterates stored and accumulated in FP32 around an FP64
+                                master point; KKT residuals, duality gap, restart, step-size and
+                                primal-weight decisions in FP64 on the FP64 matrix; at every
+                                restart the master moves to the restart point and the FP32
+                                correction data are recomputed in FP64 (iterative refinement) */
 } lp_precision;
 
 typedef struct lp_options {

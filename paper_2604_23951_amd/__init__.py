@@ -21,6 +21,8 @@ ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONS
           4: "LP_ERR_NAN_INPUT", 5: "LP_ERR_OUT_OF_MEMORY", 6: "LP_ERR_DEVICE", 7: "LP_ERR_NOT_SOLVED",
           8: "LP_ERR_INTERNAL"}
 STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_error"}
+LP_PREC_FP64 = 0
+LP_PREC_FP32_REFINED = 1
 TRACE_WIDTH = 12
 
 # names of every function include/lp.h declares

@@ -179,7 +179,7 @@ int32_t validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int
 
 int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
-        o.trace_cap < 0 || o.precision != LP_PREC_FP64 || o.spmv_layout < 0 || o.spmv_layout > 1 ||
+        o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 1 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s)) {
         *msg = "invalid option value";
@@ -307,6 +307,26 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
     const size_t o_y = L.add(sm), o_ya = L.add(sm), o_yan = L.add(sm), o_ax = L.add(sm), o_axa = L.add(sm),
                  o_oy = L.add(sm);
     const size_t o_x0 = o.x0 ? L.add(sn) : 0, o_y0 = o.y0 ? L.add(sm) : 0;
+    const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
+    const size_t fn = sizeof(float) * static_cast<size_t>(n), fm = sizeof(float) * static_cast<size_t>(m);
+    size_t o32[16] = {0};
+    if (fp32) {
+        o32[0] = L.add(fn);   // dx
+        o32[1] = L.add(fn);   // dxa
+        o32[2] = L.add(fm);   // dy
+        o32[3] = L.add(fm);   // dya
+        o32[4] = L.add(fm);   // adx
+        o32[5] = L.add(fn);   // d32
+        o32[6] = L.add(fn);   // lo32
+        o32[7] = L.add(fn);   // hi32
+        o32[8] = L.add(fm);   // rl32
+        o32[9] = L.add(fm);   // ru32
+        o32[10] = L.add(fm);  // yh32
+        o32[11] = L.add(sn);  // xh
+        o32[12] = L.add(sm);  // yh
+        o32[13] = L.add(sizeof(float) * static_cast<size_t>(nnz));  // A values
+        o32[14] = L.add(sizeof(float) * static_cast<size_t>(nnz));  // A^T values
+    }
     auto add_layout = [&](const PanelLayoutHost& Q, size_t* off) {
         off[0] = L.add(sizeof(int32_t) * Q.unit_row.size());
         off[1] = L.add(sizeof(int32_t) * Q.unit_seg.size());
@@ -316,10 +336,14 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
         off[5] = L.add(sizeof(int32_t) * Q.long_rows.size());
         off[6] = L.add(Q.is_long.size());
     };
-    size_t offA[7] = {0}, offAT[7] = {0};
+    size_t offA[7] = {0}, offAT[7] = {0}, offA32 = 0, offAT32 = 0;
     if (panels) {
         add_layout(LA, offA);
         add_layout(LAT, offAT);
+        if (fp32) {
+            offA32 = L.add(sizeof(float) * LA.packed.size());
+            offAT32 = L.add(sizeof(float) * LAT.packed.size());
+        }
     }
     const size_t o_part = L.add(sizeof(double) * 2 * kNQ * kMaxRedBlocks), o_sc = L.add(sizeof(Scalars)),
                  o_tr = L.add(sizeof(double) * kTraceW * static_cast<size_t>(o.trace_cap > 0 ? o.trace_cap : 1));
@@ -351,6 +375,29 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
     if (panels) {
         bind_layout(LA, offA, P.A);
         bind_layout(LAT, offAT, P.AT);
+    }
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(b + off); };
+    P.fp32 = fp32 ? 1 : 0;
+    if (fp32) {
+        P.dx = F(o32[0]);
+        P.dxa = F(o32[1]);
+        P.dy = F(o32[2]);
+        P.dya = F(o32[3]);
+        P.adx = F(o32[4]);
+        P.d32 = F(o32[5]);
+        P.lo32 = F(o32[6]);
+        P.hi32 = F(o32[7]);
+        P.rl32 = F(o32[8]);
+        P.ru32 = F(o32[9]);
+        P.yh32 = F(o32[10]);
+        P.xh = D(o32[11]);
+        P.yh = D(o32[12]);
+        P.A.csr.v32 = F(o32[13]);
+        P.AT.csr.v32 = F(o32[14]);
+        if (panels) {
+            P.A.pan.v32 = F(offA32);
+            P.AT.pan.v32 = F(offAT32);
+        }
     }
     P.c = D(o_c);
     P.xl = D(o_xl);
@@ -429,6 +476,14 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
     if (panels) {  // panel values in packed order, from the scaled A
         launch_gather(I(offA[4]), D(o_av), D(offA[3]), LA.nnz_packed, s);
         launch_gather(I(offAT[4]), D(o_av), D(offAT[3]), LAT.nnz_packed, s);
+    }
+    if (fp32) {  // FP32 copies of the scaled values (rounded to nearest)
+        launch_to_float(D(o_av), F(o32[13]), nnz, s);
+        launch_to_float(D(o_tv), F(o32[14]), nnz, s);
+        if (panels) {
+            launch_to_float(D(offA[3]), F(offA32), LA.nnz_packed, s);
+            launch_to_float(D(offAT[3]), F(offAT32), LAT.nnz_packed, s);
+        }
     }
     launch_prepare(P, D(o_c), D(o_bl), D(o_bu), D(o_xl), D(o_xu), D(o_R), D(o_C), D(o_Ri), D(o_Ci), h->d_x0,
                    h->d_y0, s);
@@ -654,6 +709,10 @@ int32_t lp_get_iterates(lp_handle* h, double* x, double* y, double* x_avg, doubl
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const size_t sn = sizeof(double) * h->n, sm = sizeof(double) * h->m;
+    if (h->P.fp32) {
+        launch_materialize(h->P, s);
+        if (int32_t rc = check_launch(h, "materialize")) return rc;
+    }
     if (x) HIP_TRY(h, hipMemcpyAsync(x, h->P.x, sn, hipMemcpyDeviceToHost, s));
     if (x_avg) HIP_TRY(h, hipMemcpyAsync(x_avg, h->P.xa, sn, hipMemcpyDeviceToHost, s));
     if (h->m > 0) {

@@ -46,6 +46,7 @@ struct Csr {
     const double* v;
     const int* tiles;
     const int* rowlist;
+    const float* v32;  // FP32 copy of v (FP32 storage form only)
 };
 
 // Panel-packed layout (see lp_layout.h): unit u (one wave) owns rows
@@ -61,6 +62,7 @@ struct Panels {
     const unsigned* pk;
     const double* v;
     const unsigned char* is_long;  // nullptr when the matrix has no long rows
+    const float* v32;              // FP32 copy of v (FP32 storage form only)
 };
 
 constexpr int kUnitRowCap = 512;   // rows per wave unit at most
@@ -92,6 +94,13 @@ struct DevLP {
     Scalars* sc;
     double* trace;
     double *out_x, *out_y, *out_z;
+    // FP32 storage form: the FP32 loop iterates on the correction (dx, dy) around the FP64
+    // master point (xh, yh); d32 = c~ - A~^T yh, lo32/hi32 = x~ bounds - xh,
+    // rl32/ru32 = b~ bounds - A~ xh and yh32 = yh, all computed in FP64 and rounded.
+    int fp32;
+    float *dx, *dxa, *dy, *dya, *adx;
+    float *d32, *lo32, *hi32, *rl32, *ru32, *yh32;
+    double *xh, *yh;
 };
 
 // ---- setup ------------------------------------------------------------------------
@@ -117,5 +126,7 @@ void launch_evaluate(const DevLP& P, int mode, hipStream_t s);  // mode 0 regula
 void launch_apply_restart(const DevLP& P, hipStream_t s);
 void launch_stop(const DevLP& P, int status, hipStream_t s);
 void launch_extract(const DevLP& P, hipStream_t s);
+void launch_to_float(const double* src, float* dst, long long n, hipStream_t s);
+void launch_materialize(const DevLP& P, hipStream_t s);
 
 }  // namespace lpgpu

@@ -99,9 +99,28 @@ inline unsigned grid_for(long long n, int per_block = kBlock) {
 constexpr int kPerThread = kTileNnz / kBlock;
 constexpr int kRowsPerThread = kTileRows / kBlock;
 
-template <class Epi>
-__global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double* __restrict__ xin, Epi epi) {
-    __shared__ double prod[kTileNnz];
+// Matrix values in the arithmetic type of a kernel instance.
+template <class T>
+__device__ inline const T* vals_of(const Csr& M);
+template <>
+__device__ inline const double* vals_of<double>(const Csr& M) { return M.v; }
+template <>
+__device__ inline const float* vals_of<float>(const Csr& M) { return M.v32; }
+template <class T>
+__device__ inline const T* vals_of(const Panels& M);
+template <>
+__device__ inline const double* vals_of<double>(const Panels& M) { return M.v; }
+template <>
+__device__ inline const float* vals_of<float>(const Panels& M) { return M.v32; }
+
+template <class T>
+__device__ inline T block_sum_t(T v, double* red) {
+    return static_cast<T>(block_sum(static_cast<double>(v), red));
+}
+
+template <class T, class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __restrict__ xin, Epi epi) {
+    __shared__ T prod[kTileNnz];
     __shared__ double red[kBlock / 64];
     if (!epi.begin()) return;
     const int b = blockIdx.x;
@@ -110,13 +129,13 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double*
     const int p0 = M.rp[r0], p1 = M.rp[r1];
     const int tid = threadIdx.x;
     const int* __restrict__ ci = M.ci;
-    const double* __restrict__ av = M.v;
+    const T* __restrict__ av = vals_of<T>(M);
     // Loads below are unconditional on clamped, in-bounds indices (every array holds at least
     // one element) so that they issue back to back; out-of-range lanes are masked afterwards.
     const int elast = M.nnz > 0 ? M.nnz - 1 : 0;
     if (p1 - p0 <= kTileNnz) {
         int col[kPerThread];
-        double val[kPerThread];
+        T val[kPerThread];
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) {
             const int e = min(p0 + tid + k * kBlock, elast);
@@ -135,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double*
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k)
             if (p0 + tid + k * kBlock >= p1) col[k] = 0;
-        double xv[kPerThread];
+        T xv[kPerThread];
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
 #pragma unroll
@@ -145,11 +164,11 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double*
         for (int j = 0; j < kRowsPerThread; ++j) {
             const int r = r0 + tid + j * kBlock;
             if (r < r1) {
-                double s = 0.0;
+                T s = 0;
                 int q = q0[j];
                 const int qe = q1[j];
                 for (; q + 4 <= qe; q += 4) {
-                    const double a0 = prod[q], a1 = prod[q + 1], a2 = prod[q + 2], a3 = prod[q + 3];
+                    const T a0 = prod[q], a1 = prod[q + 1], a2 = prod[q + 2], a3 = prod[q + 3];
                     s += a0;
                     s += a1;
                     s += a2;
@@ -161,10 +180,10 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double*
         }
     } else {
         const typename Epi::Pre pre = epi.load(r0);
-        double s = 0.0;
+        T s = 0;
         for (int base = p0; base < p1; base += kTileNnz) {
             int col[kPerThread];
-            double val[kPerThread];
+            T val[kPerThread];
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k) {
                 const int e = min(base + tid + k * kBlock, elast);
@@ -174,16 +193,16 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double*
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k)
                 if (base + tid + k * kBlock >= p1) col[k] = 0;
-            double xv[kPerThread];
+            T xv[kPerThread];
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k) {
-                const double pr = val[k] * xv[k];
+                const T pr = val[k] * xv[k];
                 if (base + tid + k * kBlock < p1) s += pr;
             }
         }
-        s = block_sum(s, red);
+        s = block_sum_t(s, red);
         if (tid == 0) epi.finish(r0, s, pre);
     }
 }
@@ -196,37 +215,37 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const double*
 // panels follow in column order, so every row sum is formed in CSR order. Loads and gathers
 // of kChunks chunks are issued together. After the last panel each lane finishes rows
 // lane, lane + 64, ... with the epilogue; rows listed as long are left to the long-row kernel.
-template <class Epi>
-__global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, const double* __restrict__ xin, Epi epi) {
-    __shared__ double acc_s[kUnitsPerBlock][kUnitRowCap];
-    __shared__ double prod_s[kUnitsPerBlock][kChunks * 64];
+template <class T, class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, const T* __restrict__ xin, Epi epi) {
+    __shared__ T acc_s[kUnitsPerBlock][kUnitRowCap];
+    __shared__ T prod_s[kUnitsPerBlock][kChunks * 64];
     if (!epi.begin()) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int u = blockIdx.x * kUnitsPerBlock + w;
     if (u >= M.units) return;  // the whole wave leaves; no workgroup barrier follows
     const int r0 = M.unit_row[u], nr = M.unit_row[u + 1] - r0;
-    double* acc = acc_s[w];
-    double* prod = prod_s[w];
-    for (int r = lane; r < nr; r += 64) acc[r] = 0.0;
+    T* acc = acc_s[w];
+    T* prod = prod_s[w];
+    for (int r = lane; r < nr; r += 64) acc[r] = 0;
     const int* seg = M.unit_seg + u * (M.panels + 1);
     const unsigned cmask = (1u << M.col_bits) - 1u;
     const int cb = M.col_bits;
     const int last = M.nnz > 0 ? M.nnz - 1 : 0;
     const unsigned* __restrict__ pkp = M.pk;
-    const double* __restrict__ pvp = M.v;
+    const T* __restrict__ pvp = vals_of<T>(M);
     __builtin_amdgcn_wave_barrier();
     for (int p = 0; p < M.panels; ++p) {
         const int s = seg[p], e = seg[p + 1];
         for (int base = s; base < e; base += kChunks * 64) {
             unsigned pk[kChunks];
-            double val[kChunks];
+            T val[kChunks];
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
                 const int idx = min(base + c * 64 + lane, last);
                 pk[c] = __builtin_nontemporal_load(pkp + idx);
                 val[c] = __builtin_nontemporal_load(pvp + idx);
             }
-            double xv[kChunks];
+            T xv[kChunks];
 #pragma unroll
             for (int c = 0; c < kChunks; ++c) {
                 const unsigned col = (base + c * 64 + lane < e) ? (pk[c] & cmask) : 0u;
@@ -247,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, const doub
                 if (head) {
                     const unsigned long long rest = lane < 63 ? (heads >> (lane + 1)) : 0ull;
                     const int end = rest ? lane + 1 + __builtin_ctzll(rest) : nvalid;
-                    double a = acc[row];
+                    T a = acc[row];
                     for (int q = lane; q < end; ++q) a += prod[c * 64 + q];
                     acc[row] = a;
                 }
@@ -347,16 +366,87 @@ struct EpiDual {
     }
 };
 
-template <class Epi>
-void launch_tiles(const Csr& M, const double* xin, const Epi& epi, hipStream_t s) {
+
+// FP32 storage form. The loop runs on the correction around the FP64 master (xh, yh):
+// x = xh + dx, y = yh + dy, which is the same PDHG in exact arithmetic; the data it needs
+// from the master (reduced cost, shifted bounds) are recomputed in FP64 at every restart.
+// Primal step on column j: dx_j <- clamp(dx_j - tau (d_j - (A~^T dy)_j), x~lo_j - xh_j, x~hi_j - xh_j).
+struct EpiPrimal32 {
+    struct Pre {
+        float d, lo, hi, x, xa;
+    };
+    const Scalars* sc;
+    int it;
+    const float *d, *lo, *hi;
+    float *x, *xa;
+    float tau, wt;
+    bool first;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it + 1;
+        tau = static_cast<float>(sc->tau);
+        first = (t == 1);
+        wt = static_cast<float>(1.0 / static_cast<double>(t));
+        return true;
+    }
+    __device__ Pre load(int j) const { return Pre{d[j], lo[j], hi[j], x[j], xa[j]}; }
+    __device__ void finish(int j, float s, const Pre& p) const {
+        const float g = p.d - s;
+        float xn = p.x - tau * g;
+        if (xn < p.lo) xn = p.lo;
+        if (xn > p.hi) xn = p.hi;
+        x[j] = xn;
+        xa[j] = first ? xn : p.xa + wt * (xn - p.xa);
+    }
+};
+
+// Dual step on row i, s = (A~ dx+)_i: v = dy_i - sigma (2 s - (A~ dx)_i) and, with
+// a = v + sigma (b~lo_i - (A~xh)_i), b = v + sigma (b~hi_i - (A~xh)_i), the proximal step of
+// y = yh + dy is yh + a if yh + a > 0, yh + b if yh + b < 0, and 0 otherwise.
+struct EpiDual32 {
+    struct Pre {
+        float y, rl, ru, yh, ya, ax;
+    };
+    const Scalars* sc;
+    int it;
+    const float *rl, *ru, *yh;
+    float *y, *ya, *ax;
+    float sigma, wt;
+    bool first;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it + 1;
+        sigma = static_cast<float>(sc->sigma);
+        first = (t == 1);
+        wt = static_cast<float>(1.0 / static_cast<double>(t));
+        return true;
+    }
+    __device__ Pre load(int i) const { return Pre{y[i], rl[i], ru[i], yh[i], ya[i], ax[i]}; }
+    __device__ void finish(int i, float s, const Pre& p) const {
+        const float w = 2.0f * s - p.ax;
+        const float v = p.y - sigma * w;
+        const float a = v + sigma * p.rl;
+        const float b = v + sigma * p.ru;
+        float yn;
+        if (a > -p.yh) yn = a;
+        else if (b < -p.yh) yn = b;
+        else yn = -p.yh;
+        y[i] = yn;
+        ya[i] = first ? yn : p.ya + wt * (yn - p.ya);
+        ax[i] = s;
+    }
+};
+
+template <class T, class Epi>
+void launch_tiles(const Csr& M, const T* xin, const Epi& epi, hipStream_t s) {
     if (M.ntiles <= 0) return;
-    hipLaunchKernelGGL(spmv_tiles_kernel<Epi>, dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
+    hipLaunchKernelGGL((spmv_tiles_kernel<T, Epi>), dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
 }
 
 // One sparse product with its fused epilogue: the long rows (one workgroup each), then the
 // panel-packed rows; or the row tiles when that layout is selected.
-template <class Epi>
-void launch_spmv(const Mat& M, const double* xin, const Epi& epi, hipStream_t s) {
+template <class T, class Epi>
+void launch_spmv(const Mat& M, const T* xin, const Epi& epi, hipStream_t s) {
     if (M.layout == 1) {
         launch_tiles(M.csr, xin, epi, s);
         return;
@@ -369,7 +459,7 @@ void launch_spmv(const Mat& M, const double* xin, const Epi& epi, hipStream_t s)
     }
     if (M.pan.units > 0) {
         const unsigned g = (M.pan.units + kUnitsPerBlock - 1) / kUnitsPerBlock;
-        hipLaunchKernelGGL(spmv_panel_kernel<Epi>, dim3(g), dim3(kBlock), 0, s, M.pan, xin, epi);
+        hipLaunchKernelGGL((spmv_panel_kernel<T, Epi>), dim3(g), dim3(kBlock), 0, s, M.pan, xin, epi);
     }
 }
 
@@ -893,6 +983,62 @@ __global__ void extract_kernel(DevLP P) {
     if (g < P.m) P.out_y[g] = ys[g] * P.R[g];
 }
 
+
+// FP64 values of the current and average iterate of the FP32 form: x = xh + dx, ...
+__global__ void materialize_kernel(DevLP P) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P.n) {
+        const double h = P.xh[g];
+        P.x[g] = h + static_cast<double>(P.dx[g]);
+        P.xa[g] = h + static_cast<double>(P.dxa[g]);
+    }
+    if (g < P.m) {
+        const double h = P.yh[g];
+        P.y[g] = h + static_cast<double>(P.dy[g]);
+        P.ya[g] = h + static_cast<double>(P.dya[g]);
+    }
+}
+
+// Refinement (FP32 form): after the initial evaluation (mode 1) or a restart decided by
+// the evaluation (mode 0: last_restart 1 current, 2 average), the chosen point becomes the
+// FP64 master and the anchor, and the correction data are recomputed in FP64 from the
+// products A~x, A~^T y that the evaluation just formed.
+__global__ void rebase_kernel(DevLP P, int mode) {
+    const int lr = mode == 1 ? 1 : P.sc->last_restart;
+    if (lr == 0) return;
+    if (mode == 1 && P.sc->status != kRunning) return;
+    const bool avg = lr == 2;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < P.n) {
+        const double xc = avg ? P.xa[g] : P.x[g];
+        const double at = avg ? P.atya[g] : P.aty[g];
+        P.xh[g] = xc;
+        P.xan[g] = xc;
+        P.d32[g] = static_cast<float>(P.c[g] - at);
+        P.lo32[g] = static_cast<float>(P.xl[g] - xc);
+        P.hi32[g] = static_cast<float>(P.xu[g] - xc);
+        P.dx[g] = 0.0f;
+        P.dxa[g] = 0.0f;
+    }
+    if (g < P.m) {
+        const double yc = avg ? P.ya[g] : P.y[g];
+        const double ax = avg ? P.axa[g] : P.ax[g];
+        P.yh[g] = yc;
+        P.yan[g] = yc;
+        P.yh32[g] = static_cast<float>(yc);
+        P.rl32[g] = static_cast<float>(P.bl[g] - ax);
+        P.ru32[g] = static_cast<float>(P.bu[g] - ax);
+        P.dy[g] = 0.0f;
+        P.dya[g] = 0.0f;
+        P.adx[g] = 0.0f;
+    }
+}
+
+__global__ void to_float_kernel(const double* src, float* dst, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = static_cast<float>(src[i]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------- launchers
@@ -974,6 +1120,18 @@ void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scala
 }
 
 void launch_primal(const DevLP& P, int it, hipStream_t s) {
+    if (P.fp32) {
+        EpiPrimal32 e{};
+        e.sc = P.sc;
+        e.it = it;
+        e.d = P.d32;
+        e.lo = P.lo32;
+        e.hi = P.hi32;
+        e.x = P.dx;
+        e.xa = P.dxa;
+        launch_spmv(P.AT, static_cast<const float*>(P.dy), e, s);
+        return;
+    }
     EpiPrimal e{};
     e.sc = P.sc;
     e.it = it;
@@ -988,6 +1146,19 @@ void launch_primal(const DevLP& P, int it, hipStream_t s) {
 
 void launch_dual(const DevLP& P, int it, hipStream_t s) {
     if (P.m == 0) return;
+    if (P.fp32) {
+        EpiDual32 e{};
+        e.sc = P.sc;
+        e.it = it;
+        e.rl = P.rl32;
+        e.ru = P.ru32;
+        e.yh = P.yh32;
+        e.y = P.dy;
+        e.ya = P.dya;
+        e.ax = P.adx;
+        launch_spmv(P.A, static_cast<const float*>(P.dx), e, s);
+        return;
+    }
     EpiDual e{};
     e.sc = P.sc;
     e.it = it;
@@ -999,7 +1170,26 @@ void launch_dual(const DevLP& P, int it, hipStream_t s) {
     launch_spmv(P.A, P.x, e, s);
 }
 
+void launch_materialize(const DevLP& P, hipStream_t s) {
+    const int mx = P.m > P.n ? P.m : P.n;
+    hipLaunchKernelGGL(materialize_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
 void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
+    if (P.fp32 && mode != 1) {
+        // FP64 iterates from the master and the FP32 correction, then FP64 products on A~
+        launch_materialize(P, s);
+        const Scalars* gate = mode == 2 ? nullptr : P.sc;
+        if (P.m > 0) launch_spmv_store(P.A, P.x, P.ax, gate, s);
+        launch_spmv_store(P.AT, P.y, P.aty, gate, s);
+        if (mode == 0) {
+            if (P.m > 0) launch_spmv_store(P.A, P.xa, P.axa, gate, s);
+            launch_spmv_store(P.AT, P.ya, P.atya, gate, s);
+        }
+        hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
+        hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
+        return;
+    }
     if (mode == 1) {
         if (P.m > 0) launch_spmv_store(P.A, P.x, P.ax, P.sc, s);
         launch_spmv_store(P.AT, P.y, P.aty, P.sc, s);
@@ -1012,11 +1202,26 @@ void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
     }
     hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
     hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
+    if (P.fp32 && mode == 1) {
+        const int mx = P.m > P.n ? P.m : P.n;
+        hipLaunchKernelGGL(rebase_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, 1);
+    }
 }
 
 void launch_apply_restart(const DevLP& P, hipStream_t s) {
     const int mx = P.m > P.n ? P.m : P.n;
+    if (P.fp32) {
+        hipLaunchKernelGGL(rebase_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, 0);
+        return;
+    }
     hipLaunchKernelGGL(apply_restart_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
+void launch_to_float(const double* src, float* dst, long long n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = grid_for(n);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(to_float_kernel, dim3(g), dim3(kBlock), 0, s, src, dst, n);
 }
 
 void launch_stop(const DevLP& P, int status, hipStream_t s) {
