@@ -75,10 +75,11 @@ def main(argv=None):
     ap.add_argument("--eval-every", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true", help="skip the solve-to-1e-4 measurement")
+    ap.add_argument("--solve", action="store_true", help="also solve the LP to E_rel 1e-4 (long)")
     ap.add_argument("--solve-time-limit", type=float, default=60.0)
     ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
     ap.add_argument("--layout", type=int, default=0, help="0 panel-packed wave units, 1 row tiles")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage form measurement")
     ap.add_argument("--slice-bytes", type=int, default=0)
     ap.add_argument("--units-per-cu", type=int, default=0)
     ap.add_argument("--long-row-len", type=int, default=0)
@@ -136,6 +137,28 @@ def main(argv=None):
     sol_g = solver.solve()
     dt_g = time.perf_counter() - t2
 
+    fp32_res = None
+    if not args.no_fp32:
+        # the FP32 storage form on the same LP (matrix and iterates FP32, FP64 evaluation,
+        # restart decisions and refinement), same step definition
+        s32 = lpg.Solver(lp, eps_rel=0.0, max_iters=E * max(args.warmup, 1), eval_every=E,
+                         precision=lpg.LP_PREC_FP32_REFINED, **tun)
+        s32.solve()
+        s32.update(eps_rel=0.0, max_iters=E * K, eval_every=E)
+        lpg.lp_set_kernel_timing(s32.h, True)
+        t5 = time.perf_counter()
+        s32.solve()
+        dt5 = time.perf_counter() - t5
+        p32, d32, n32 = lpg.lp_get_kernel_times(s32.h)
+        s32.close()
+        bp32, bd32 = algorithmic_bytes(m, n, nnz, sv=4)
+        fp32_res = {"workload": "same LP, FP32 storage form (FP64 evaluation / restarts / refinement)",
+                    "iters_per_s": E * K / dt5, "ms_per_step": dt5 / K * 1e3,
+                    "primal_ms": p32, "dual_ms": d32, "primal_alg_bytes": bp32, "dual_alg_bytes": bd32,
+                    "primal_gbs": bp32 / (p32 * 1e-3) / 1e9, "dual_gbs": bd32 / (d32 * 1e-3) / 1e9, "samples": n32}
+        print(f"[bench] fp32 form: {E * K / dt5:.1f} it/s; primal {p32 * 1e3:.1f} us, dual {d32 * 1e3:.1f} us",
+              file=sys.stderr, flush=True)
+
     bp, bd = algorithmic_bytes(m, n, nnz)
     gbs_p = bp / (p_ms * 1e-3) / 1e9
     gbs_d = bd / (d_ms * 1e-3) / 1e9
@@ -171,8 +194,9 @@ def main(argv=None):
         "graph_mode_iters_per_s": E * K / dt_g,
         "setup_s": setup_s,
         "generate_s": gen_s,
+        "fp32_form": fp32_res,
     }
-    if not args.no_solve:
+    if args.solve:
         solver.update(eps_rel=1e-4, max_iters=10**7, time_limit_s=args.solve_time_limit, eval_every=E)
         t3 = time.perf_counter()
         s4 = solver.solve()

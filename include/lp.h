@@ -91,7 +91,7 @@ typedef struct lp_options {
     int32_t spmv_layout;   /* sparse-product layout: 0 panel-packed wave units (default), 1 row tiles */
     int32_t long_row_len;  /* rows longer than this get a workgroup of their own (default 256) */
     int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 8) */
-    int32_t pad0;
+    int32_t batch_wg_per_cu; /* lp_solve_batch: workgroups per compute unit (default 3) */
     int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
@@ -137,6 +137,18 @@ int32_t lp_solve(lp_handle *h);
  * and restarts are taken from *opt; every other field of *opt is ignored (the problem
  * setup, the step size and the trace capacity are fixed at lp_create). */
 int32_t lp_update_options(lp_handle *h, const lp_options *opt);
+
+/* Batched form: solve the LPs of `count` handles (created on the same device) in one
+ * persistent launch. Each workgroup takes the next LP from a device work counter (largest
+ * nnz first) and runs that LP's whole restarted PDHG on chip: sparse products by row tiles
+ * with the fused updates, FP64 evaluations, restart and termination decisions. Each LP's
+ * result depends only on that LP (not on the other LPs or the workgroup that solved it),
+ * so it is the same alone and in any batch. The handles' precisions may differ.
+ * Solve-time options: batch_opt's eps_rel, max_iters, eval_every and restarts for every LP
+ * when batch_opt is given, each handle's own otherwise; batch_opt->batch_wg_per_cu sets the
+ * grid. Afterwards every handle is solved and lp_get_solution returns its result
+ * (info.solve_seconds is the batch time). Runs on the first handle's stream and waits. */
+int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
 
 /* Copy the returned point (original scale) to caller buffers x[n], y[m], z[n] and the run
  * record to *info. Any pointer may be NULL to skip it. LP_ERR_NOT_SOLVED before lp_solve. */

@@ -27,7 +27,7 @@ TRACE_WIDTH = 12
 
 # names of every function include/lp.h declares
 EXPORTS = (
-    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_solve_batch", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout",
 )
@@ -45,7 +45,8 @@ class lp_options(C.Structure):
         ("eval_every", C.c_int32), ("precision", C.c_int32), ("scaling", C.c_int32), ("ruiz_passes", C.c_int32),
         ("pow_iters", C.c_int32), ("restarts", C.c_int32), ("step_size", C.c_double), ("omega0", C.c_double),
         ("seed", C.c_uint64), ("hip_stream", C.c_void_p), ("device", C.c_int32), ("trace_cap", C.c_int32),
-        ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32), ("pad0", C.c_int32),
+        ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32),
+        ("batch_wg_per_cu", C.c_int32),
         ("panel_slice_bytes", C.c_int64), ("x0", C.c_void_p), ("y0", C.c_void_p),
     ]
 
@@ -95,6 +96,8 @@ def lib():
         L.lp_update_options.restype = I32
         L.lp_solve.argtypes = [P]
         L.lp_solve.restype = I32
+        L.lp_solve_batch.argtypes = [P, I32, P]
+        L.lp_solve_batch.restype = I32
         L.lp_get_solution.argtypes = [P, P, P, P, P]
         L.lp_get_solution.restype = I32
         L.lp_destroy.argtypes = [P]
@@ -152,6 +155,12 @@ def lp_update_options(h, opt: lp_options):
 
 def lp_solve(h):
     _check(lib().lp_solve(h), h)
+
+
+def lp_solve_batch(handles, opt: Optional[lp_options] = None):
+    arr = (C.c_void_p * max(len(handles), 1))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    rc = lib().lp_solve_batch(arr, len(handles), None if opt is None else C.byref(opt))
+    _check(rc)
 
 
 def lp_get_solution(h, x=None, y=None, z=None) -> lp_info:
@@ -312,6 +321,20 @@ class Solver:
 
     def layout(self):
         return lp_get_layout(self.h)
+
+
+def solve_batch(solvers, **options):
+    """Solve several Solver objects in one persistent launch; returns their Solutions."""
+    opt = make_options(**options) if options else None
+    lp_solve_batch([s.h for s in solvers], opt)
+    out = []
+    for s in solvers:
+        x = np.empty(s.n)
+        y = np.empty(max(s.m, 1))
+        z = np.empty(s.n)
+        info = lp_get_solution(s.h, x, y, z)
+        out.append(Solution(STATUS.get(info.status, str(info.status)), x, y[: s.m], z, info))
+    return out
 
 
 def solve(lp, **options) -> Solution:

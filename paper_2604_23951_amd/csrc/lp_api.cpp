@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -180,7 +181,7 @@ int32_t validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int
 int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 1 ||
-        o.long_row_len < 0 || o.units_per_cu < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
+        o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s)) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
@@ -216,6 +217,24 @@ void record_bundle(lp_handle* h, int timed_it) {
     }
     launch_evaluate(h->P, 0, h->stream);
     launch_apply_restart(h->P, h->stream);
+}
+
+void fill_info(lp_handle* h) {
+    const Scalars& sc = *h->h_sc;
+    lp_info& inf = h->info;
+    inf.status = sc.status;
+    inf.output_is_avg = sc.out_avg;
+    inf.iterations = sc.k;
+    inf.restarts = sc.restarts;
+    inf.primal_obj = sc.out_pobj;
+    inf.dual_obj = sc.out_dobj;
+    inf.rel_primal_res = sc.out_rel_p;
+    inf.rel_dual_res = sc.out_rel_d;
+    inf.rel_gap = sc.out_rel_gap;
+    inf.rel_kkt = sc.out_erel;
+    inf.sigma_max = sc.sigma_max;
+    inf.step_size = sc.eta;
+    inf.omega = sc.omega;
 }
 
 int32_t capture_graph(lp_handle* h) {
@@ -522,6 +541,7 @@ void lp_default_options(lp_options* o) {
     o->spmv_layout = 0;
     o->long_row_len = 256;
     o->units_per_cu = 8;
+    o->batch_wg_per_cu = 3;
     o->panel_slice_bytes = int64_t(1) << 20;
     o->x0 = nullptr;
     o->y0 = nullptr;
@@ -639,26 +659,86 @@ int32_t lp_solve(lp_handle* h) {
         if (int32_t rc = check_launch(h, "extract")) return rc;
         HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
-        const Scalars& sc = *h->h_sc;
-        lp_info& inf = h->info;
-        inf.status = sc.status;
-        inf.output_is_avg = sc.out_avg;
-        inf.iterations = sc.k;
-        inf.restarts = sc.restarts;
-        inf.primal_obj = sc.out_pobj;
-        inf.dual_obj = sc.out_dobj;
-        inf.rel_primal_res = sc.out_rel_p;
-        inf.rel_dual_res = sc.out_rel_d;
-        inf.rel_gap = sc.out_rel_gap;
-        inf.rel_kkt = sc.out_erel;
-        inf.sigma_max = sc.sigma_max;
-        inf.step_size = sc.eta;
-        inf.omega = sc.omega;
-        inf.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        fill_info(h);
+        h->info.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         h->solved = true;
         return LP_OK;
     } catch (...) {
         return fail(h, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo) {
+    if (count < 0 || (count > 0 && !hs)) return fail(nullptr, LP_ERR_INVALID_ARG, "bad batch arguments");
+    if (count == 0) return LP_OK;
+    try {
+        for (int32_t i = 0; i < count; ++i)
+            if (!hs[i]) return fail(nullptr, LP_ERR_INVALID_ARG, "NULL handle in batch");
+        const int dev = hs[0]->device;
+        for (int32_t i = 1; i < count; ++i)
+            if (hs[i]->device != dev) return fail(nullptr, LP_ERR_INVALID_ARG, "batch handles on different devices");
+        std::string msg;
+        if (bo && validate_options(*bo, &msg)) return fail(nullptr, LP_ERR_INVALID_ARG, msg);
+        lp_handle* h0 = hs[0];
+        HIP_TRY(h0, hipSetDevice(dev));
+        std::vector<BatchJob> jobs(static_cast<size_t>(count));
+        std::vector<int32_t> order(static_cast<size_t>(count));
+        for (int32_t i = 0; i < count; ++i) {
+            lp_handle* h = hs[i];
+            const lp_options& o = bo ? *bo : h->opt;
+            BatchJob& J = jobs[i];
+            J.P = h->P;
+            J.eps_rel = o.eps_rel;
+            J.max_iters = o.max_iters;
+            J.trace_cap = h->opt.trace_cap;
+            J.eval_every = o.eval_every;
+            J.restarts_on = o.restarts;
+            J.x0 = h->d_x0;
+            J.y0 = h->d_y0;
+            order[i] = i;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return hs[a]->nnz > hs[b]->nnz; });
+        int cus = 256;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
+        int grid = cus * wpc;
+        if (grid > count) grid = count;
+        const size_t bj = sizeof(BatchJob) * static_cast<size_t>(count), bo_ = sizeof(int32_t) * static_cast<size_t>(count);
+        char* buf = nullptr;
+        HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&buf), bj + bo_ + 256));
+        BatchJob* djobs = reinterpret_cast<BatchJob*>(buf);
+        int32_t* dorder = reinterpret_cast<int32_t*>(buf + bj);
+        int32_t* dcounter = reinterpret_cast<int32_t*>(buf + bj + bo_ + (256 - (bj + bo_) % 256) % 256);
+        hipStream_t s = h0->stream;
+        const auto t0 = std::chrono::steady_clock::now();
+        hipError_t e = hipMemcpyAsync(djobs, jobs.data(), bj, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dorder, order.data(), bo_, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, sizeof(int32_t), s);
+        if (e == hipSuccess) {
+            launch_batch(djobs, dorder, count, dcounter, grid, s);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        (void)hipFree(buf);
+        if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
+        for (int32_t i = 0; i < count; ++i) {
+            lp_handle* h = hs[i];
+            HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(h0, hipStreamSynchronize(s));
+        for (int32_t i = 0; i < count; ++i) {
+            lp_handle* h = hs[i];
+            fill_info(h);
+            h->info.solve_seconds = secs;
+            h->solved = true;
+        }
+        return LP_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, LP_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(nullptr, LP_ERR_INTERNAL, "unexpected exception");
     }
 }
 

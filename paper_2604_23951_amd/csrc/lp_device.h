@@ -103,6 +103,18 @@ struct DevLP {
     double *xh, *yh;
 };
 
+// One LP of a batched solve: its device problem and the solve-time options.
+struct BatchJob {
+    DevLP P;
+    double eps_rel;
+    long long max_iters;
+    long long trace_cap;
+    int eval_every;
+    int restarts_on;
+    const double* x0;
+    const double* y0;
+};
+
 // ---- setup ------------------------------------------------------------------------
 void launch_fill(double* p, long long n, double v, hipStream_t s);
 void launch_scale_pass(const DevLP& P, int* A_rp, int* A_ci, double* A_v, const int* AT_rp, const int* perm,
@@ -128,5 +140,8 @@ void launch_stop(const DevLP& P, int status, hipStream_t s);
 void launch_extract(const DevLP& P, hipStream_t s);
 void launch_to_float(const double* src, float* dst, long long n, hipStream_t s);
 void launch_materialize(const DevLP& P, hipStream_t s);
+// Batched form: `grid` workgroups take LPs jobs[order[0]], jobs[order[1]], ... from the
+// device counter (which must start at 0) and each solves one LP at a time, entirely on chip.
+void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s);
 
 }  // namespace lpgpu

@@ -119,11 +119,7 @@ __device__ inline T block_sum_t(T v, double* red) {
 }
 
 template <class T, class Epi>
-__global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __restrict__ xin, Epi epi) {
-    __shared__ T prod[kTileNnz];
-    __shared__ double red[kBlock / 64];
-    if (!epi.begin()) return;
-    const int b = blockIdx.x;
+__device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const Epi& epi, T* prod, double* red) {
     const int r0 = M.rowlist ? M.rowlist[b] : M.tiles[b];
     const int r1 = M.rowlist ? r0 + 1 : M.tiles[b + 1];
     const int p0 = M.rp[r0], p1 = M.rp[r1];
@@ -205,6 +201,14 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __re
         s = block_sum_t(s, red);
         if (tid == 0) epi.finish(r0, s, pre);
     }
+}
+
+template <class T, class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __restrict__ xin, Epi epi) {
+    __shared__ T prod[kTileNnz];
+    __shared__ double red[kBlock / 64];
+    if (!epi.begin()) return;
+    tile_body(M, static_cast<int>(blockIdx.x), xin, epi, prod, red);
 }
 
 // Panel-packed SpMV, one wave64 per unit of rows. The wave walks its entries panel by panel
@@ -661,8 +665,7 @@ __global__ void reset_kernel(Scalars* sc, double eps_rel, long long max_iters, i
     sc->kkt_prev = __builtin_inf();
 }
 
-__global__ void init_state_kernel(DevLP P, const double* x0, const double* y0) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void init_state_at(const DevLP& P, int g, const double* x0, const double* y0) {
     if (g < P.n) {
         const double v = clampd(x0 ? x0[g] : 0.0, P.xl[g], P.xu[g]);
         P.x[g] = v;
@@ -675,6 +678,10 @@ __global__ void init_state_kernel(DevLP P, const double* x0, const double* y0) {
         P.ya[g] = v;
         P.yan[g] = v;
     }
+}
+
+__global__ void init_state_kernel(DevLP P, const double* x0, const double* y0) {
+    init_state_at(P, blockIdx.x * blockDim.x + threadIdx.x, x0, y0);
 }
 
 // Residual and objective terms of one row for a candidate (A~x~, y~); see the evaluation
@@ -805,19 +812,9 @@ __device__ inline void set_output(Scalars* sc, const Kkt& K, int avg) {
 //  restart candidate = average if its KKT_w is strictly smaller; restart on
 //  (1) KKT_c <= 0.2 KKT_anchor, (2) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev,
 //  (3) t >= 0.36 k; on restart omega <- sqrt(omega dy / dx) when dx, dy > 1e-10.
-__global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) {
-    __shared__ double red[kBlock / 64];
-    __shared__ double tot[2 * kNQ];
-    Scalars* sc = P.sc;
-    if (mode != 2 && sc->status != kRunning) return;
-    const int nq = (mode == 0) ? 2 * kNQ : kNQ;
-    for (int q = 0; q < nq; ++q) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < P.nred; b += kBlock) v += P.partials[b * 2 * kNQ + q];
-        v = block_sum(v, red);
-        if (threadIdx.x == 0) tot[q] = v;
-    }
-    if (threadIdx.x != 0) return;
+// Thread-0 part of the evaluation: tot holds the summed KKT quantities of the current
+// iterate (0..7) and, in mode 0, of the average (8..15).
+__device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int mode) {
     const Kkt cur = make_kkt(tot, sc);
     if (mode == 2) {  // statistics of the current point after a host-side stop
         set_output(sc, cur, 0);
@@ -925,11 +922,24 @@ __global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) {
     sc->n_trace = nt + 1;
 }
 
+__global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) {
+    __shared__ double red[kBlock / 64];
+    __shared__ double tot[2 * kNQ];
+    Scalars* sc = P.sc;
+    if (mode != 2 && sc->status != kRunning) return;
+    const int nq = (mode == 0) ? 2 * kNQ : kNQ;
+    for (int q = 0; q < nq; ++q) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < P.nred; b += kBlock) v += P.partials[b * 2 * kNQ + q];
+        v = block_sum(v, red);
+        if (threadIdx.x == 0) tot[q] = v;
+    }
+    if (threadIdx.x != 0) return;
+    decide_logic(P, P.sc, tot, mode);
+}
+
 // Restart: the candidate becomes the iterate, the anchor and the average.
-__global__ void apply_restart_kernel(DevLP P) {
-    const int lr = P.sc->last_restart;
-    if (lr == 0) return;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
     if (g < P.n) {
         double v;
         if (lr == 2) {
@@ -955,6 +965,12 @@ __global__ void apply_restart_kernel(DevLP P) {
     }
 }
 
+__global__ void apply_restart_kernel(DevLP P) {
+    const int lr = P.sc->last_restart;
+    if (lr == 0) return;
+    apply_restart_at(P, lr, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __global__ void stop_kernel(Scalars* sc, int status) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && sc->status == kRunning) {
         sc->status = status;
@@ -964,12 +980,10 @@ __global__ void stop_kernel(Scalars* sc, int status) {
 }
 
 // Returned point on the original scale: x = C x~, y = R y~, z = projected reduced cost.
-__global__ void extract_kernel(DevLP P) {
-    const int avg = P.sc->out_avg;
+__device__ inline void extract_at(const DevLP& P, int avg, int g) {
     const double* xs = avg ? P.xa : P.x;
     const double* ys = avg ? P.ya : P.y;
     const double* at = avg ? P.atya : P.aty;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g < P.n) {
         P.out_x[g] = xs[g] * P.C[g];
         const double ls = P.c[g] - at[g];
@@ -983,10 +997,13 @@ __global__ void extract_kernel(DevLP P) {
     if (g < P.m) P.out_y[g] = ys[g] * P.R[g];
 }
 
+__global__ void extract_kernel(DevLP P) {
+    extract_at(P, P.sc->out_avg, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 
 // FP64 values of the current and average iterate of the FP32 form: x = xh + dx, ...
-__global__ void materialize_kernel(DevLP P) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void materialize_at(const DevLP& P, int g) {
     if (g < P.n) {
         const double h = P.xh[g];
         P.x[g] = h + static_cast<double>(P.dx[g]);
@@ -999,16 +1016,14 @@ __global__ void materialize_kernel(DevLP P) {
     }
 }
 
+__global__ void materialize_kernel(DevLP P) { materialize_at(P, blockIdx.x * blockDim.x + threadIdx.x); }
+
 // Refinement (FP32 form): after the initial evaluation (mode 1) or a restart decided by
 // the evaluation (mode 0: last_restart 1 current, 2 average), the chosen point becomes the
 // FP64 master and the anchor, and the correction data are recomputed in FP64 from the
 // products A~x, A~^T y that the evaluation just formed.
-__global__ void rebase_kernel(DevLP P, int mode) {
-    const int lr = mode == 1 ? 1 : P.sc->last_restart;
-    if (lr == 0) return;
-    if (mode == 1 && P.sc->status != kRunning) return;
+__device__ inline void rebase_at(const DevLP& P, int lr, int g) {
     const bool avg = lr == 2;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g < P.n) {
         const double xc = avg ? P.xa[g] : P.x[g];
         const double at = avg ? P.atya[g] : P.aty[g];
@@ -1034,9 +1049,195 @@ __global__ void rebase_kernel(DevLP P, int mode) {
     }
 }
 
+__global__ void rebase_kernel(DevLP P, int mode) {
+    const int lr = mode == 1 ? 1 : P.sc->last_restart;
+    if (lr == 0) return;
+    if (mode == 1 && P.sc->status != kRunning) return;
+    rebase_at(P, lr, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __global__ void to_float_kernel(const double* src, float* dst, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         dst[i] = static_cast<float>(src[i]);
+}
+
+
+// ------------------------------------------------------------------ batched form
+
+// Sparse product by one workgroup: every row tile of M in turn.
+template <class T, class Epi>
+__device__ void wg_spmv(const Csr& M, const T* xin, const Epi& epi, double* lds, double* red) {
+    T* prod = reinterpret_cast<T*>(lds);
+    for (int b = 0; b < M.ntiles; ++b) {
+        tile_body(M, b, xin, epi, prod, red);
+        __syncthreads();
+    }
+}
+
+// KKT quantities of the current iterate (and of the average in mode 0) summed over the
+// whole LP by one workgroup in a fixed order; tot[0..15] in LDS afterwards.
+__device__ void wg_kkt(const DevLP& P, int mode, double* tot, double* red16) {
+    double acc[2 * kNQ];
+#pragma unroll
+    for (int q = 0; q < 2 * kNQ; ++q) acc[q] = 0.0;
+    const bool both = mode == 0;
+    for (int i = threadIdx.x; i < P.m; i += kBlock) {
+        row_terms(P, i, P.ax, P.y, acc);
+        if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
+    }
+    for (int j = threadIdx.x; j < P.n; j += kBlock) {
+        col_terms(P, j, P.x, P.aty, acc);
+        if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 2 * kNQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red16[w * 2 * kNQ + q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kNQ) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / 64; ++k) t += red16[k * 2 * kNQ + threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// One LP solved by one workgroup: the same restarted, averaged PDHG as the multi-kernel
+// path (same kernels' epilogues, evaluation and decision logic), with the scalar state in
+// LDS and a workgroup barrier between the phases.
+__device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* red, double* red16, double* tot) {
+    const DevLP& P = J.P;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        *ssc = *P.sc;
+        ssc->omega = ssc->omega0;
+        ssc->tau = ssc->eta / ssc->omega;
+        ssc->sigma = ssc->eta * ssc->omega;
+        ssc->eps_rel = J.eps_rel;
+        ssc->max_iters = J.max_iters;
+        ssc->eval_every = J.eval_every;
+        ssc->restarts_on = J.restarts_on;
+        ssc->trace_cap = J.trace_cap;
+        ssc->k = 0;
+        ssc->t = 0;
+        ssc->restarts = 0;
+        ssc->n_trace = 0;
+        ssc->status = kRunning;
+        ssc->out_avg = 0;
+        ssc->last_restart = 0;
+        ssc->kkt_prev = __builtin_inf();
+    }
+    __syncthreads();
+    const int mx = P.m > P.n ? P.m : P.n;
+    for (int g = tid; g < mx; g += kBlock) init_state_at(P, g, J.x0, J.y0);
+    __syncthreads();
+    if (P.m > 0) wg_spmv(P.A.csr, static_cast<const double*>(P.x), EpiStore{P.ax, nullptr}, lds, red);
+    wg_spmv(P.AT.csr, static_cast<const double*>(P.y), EpiStore{P.aty, nullptr}, lds, red);
+    wg_kkt(P, 1, tot, red16);
+    if (tid == 0) decide_logic(P, ssc, tot, 1);
+    __syncthreads();
+    if (P.fp32 && ssc->status == kRunning) {
+        for (int g = tid; g < mx; g += kBlock) rebase_at(P, 1, g);
+        __syncthreads();
+    }
+    while (ssc->status == kRunning) {
+        const int E = ssc->eval_every;
+        for (int it = 0; it < E; ++it) {
+            if (ssc->k + it >= ssc->max_iters) break;
+            if (P.fp32) {
+                EpiPrimal32 ep{};
+                ep.sc = ssc;
+                ep.it = it;
+                ep.d = P.d32;
+                ep.lo = P.lo32;
+                ep.hi = P.hi32;
+                ep.x = P.dx;
+                ep.xa = P.dxa;
+                ep.begin();
+                wg_spmv(P.AT.csr, static_cast<const float*>(P.dy), ep, lds, red);
+                if (P.m > 0) {
+                    EpiDual32 ed{};
+                    ed.sc = ssc;
+                    ed.it = it;
+                    ed.rl = P.rl32;
+                    ed.ru = P.ru32;
+                    ed.yh = P.yh32;
+                    ed.y = P.dy;
+                    ed.ya = P.dya;
+                    ed.ax = P.adx;
+                    ed.begin();
+                    wg_spmv(P.A.csr, static_cast<const float*>(P.dx), ed, lds, red);
+                }
+            } else {
+                EpiPrimal ep{};
+                ep.sc = ssc;
+                ep.it = it;
+                ep.c = P.c;
+                ep.xl = P.xl;
+                ep.xu = P.xu;
+                ep.x = P.x;
+                ep.xa = P.xa;
+                ep.begin();
+                wg_spmv(P.AT.csr, static_cast<const double*>(P.y), ep, lds, red);
+                if (P.m > 0) {
+                    EpiDual ed{};
+                    ed.sc = ssc;
+                    ed.it = it;
+                    ed.bl = P.bl;
+                    ed.bu = P.bu;
+                    ed.y = P.y;
+                    ed.ya = P.ya;
+                    ed.ax = P.ax;
+                    ed.begin();
+                    wg_spmv(P.A.csr, static_cast<const double*>(P.x), ed, lds, red);
+                }
+            }
+        }
+        if (P.fp32) {
+            for (int g = tid; g < mx; g += kBlock) materialize_at(P, g);
+            __syncthreads();
+            if (P.m > 0) wg_spmv(P.A.csr, static_cast<const double*>(P.x), EpiStore{P.ax, nullptr}, lds, red);
+        }
+        wg_spmv(P.AT.csr, static_cast<const double*>(P.y), EpiStore{P.aty, nullptr}, lds, red);
+        if (P.m > 0) wg_spmv(P.A.csr, static_cast<const double*>(P.xa), EpiStore{P.axa, nullptr}, lds, red);
+        wg_spmv(P.AT.csr, static_cast<const double*>(P.ya), EpiStore{P.atya, nullptr}, lds, red);
+        wg_kkt(P, 0, tot, red16);
+        if (tid == 0) decide_logic(P, ssc, tot, 0);
+        __syncthreads();
+        const int lr = ssc->last_restart;
+        if (lr) {
+            for (int g = tid; g < mx; g += kBlock) {
+                if (P.fp32) rebase_at(P, lr, g);
+                else apply_restart_at(P, lr, g);
+            }
+            __syncthreads();
+        }
+    }
+    for (int g = tid; g < mx; g += kBlock) extract_at(P, ssc->out_avg, g);
+    __syncthreads();
+    if (tid == 0) *P.sc = *ssc;
+}
+
+// Persistent batched solve. Every workgroup loops: take the next LP from the counter,
+// solve it, until the counter passes `count`; then all of its waves return together.
+__global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, const int* order, int count,
+                                                        int* counter) {
+    __shared__ double lds[kTileNnz];
+    __shared__ double red[kBlock / 64];
+    __shared__ double red16[(kBlock / 64) * 2 * kNQ];
+    __shared__ double tot[2 * kNQ];
+    __shared__ Scalars ssc;
+    __shared__ int job;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) job = atomicAdd(counter, 1);
+        __syncthreads();
+        const int j = job;
+        if (j >= count) return;
+        wg_solve(jobs[order[j]], &ssc, lds, red, red16, tot);
+    }
 }
 
 }  // namespace
@@ -1215,6 +1416,11 @@ void launch_apply_restart(const DevLP& P, hipStream_t s) {
         return;
     }
     hipLaunchKernelGGL(apply_restart_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
+void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s) {
+    if (count <= 0 || grid <= 0) return;
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlock), 0, s, jobs, order, count, counter);
 }
 
 void launch_to_float(const double* src, float* dst, long long n, hipStream_t s) {

@@ -1,0 +1,108 @@
+"""Batched form: many LPs in one persistent launch, one workgroup per LP at a time.
+
+Bars: FP64 iterates of every LP in the batch match the oracle to 1e-12 relative; each
+LP's result in a batch is bit-identical to the same LP solved alone in a batch of one;
+FP32 and mixed-precision batches reach the requested E_rel (checked in FP64 by the oracle
+on the original data)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2604_23951_amd as lpg
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32 = lpg.LP_PREC_FP32_REFINED
+
+
+def _lps():
+    out = [synth.cfg0(0), synth.cfg0(1), synth.transportation(120, np.random.default_rng(5)),
+           synth.cfg1(0, m=400, n=800, nnz=4000), synth.cfg4_lp(2, m_hi=600)]
+    out += [synth.cfg3_lp(j, m_max=400) for j in range(4)]
+    return out
+
+
+def _solvers(lps, **kw):
+    return [lpg.Solver(lp, spmv_layout=1, **kw) for lp in lps]
+
+
+def test_batch_iterates_match_oracle(oracle_lib):
+    lps = _lps()
+    ks = [1, 2, 64, 65, 130]
+    refs = [oracle.solve(lp, eps_rel=0.0, max_iters=max(ks), snap_k=ks) for lp in lps]
+    solvers = _solvers(lps, eps_rel=0.0)
+    try:
+        for i, k in enumerate(ks):
+            lpg.solve_batch(solvers, eps_rel=0.0, max_iters=k)
+            for s, lp, ref in zip(solvers, lps, refs):
+                for a, b in zip(s.iterates(), oracle.split_snap(ref.snaps[i], lp.n, lp.m)):
+                    scale = max(1.0, float(np.max(np.abs(b)))) if b.size else 1.0
+                    assert float(np.max(np.abs(a - b), initial=0.0)) / scale <= 1e-12, (lp.name, k)
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_batch_solve_matches_oracle_and_single_path(oracle_lib):
+    lps = _lps()
+    solvers = _solvers(lps)
+    try:
+        sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=400000)
+    finally:
+        for s in solvers:
+            s.close()
+    for lp, sol in zip(lps, sols):
+        ref = oracle.solve(lp, eps_rel=1e-4, max_iters=400000)
+        assert sol.status == ref.status == "optimal", lp.name
+        assert sol.info.iterations == ref.iters, lp.name
+        assert abs(sol.info.primal_obj - ref.pobj) <= 1e-6 * max(1.0, abs(ref.pobj)), lp.name
+        chk = oracle.kkt(lp, sol.x, sol.y)
+        assert chk["erel"] <= 1e-4
+
+
+def test_batch_alone_equals_in_mix():
+    lps = _lps()
+    mix = _solvers(lps)
+    try:
+        in_mix = lpg.solve_batch(mix, eps_rel=1e-5, max_iters=400000)
+    finally:
+        for s in mix:
+            s.close()
+    for j in (0, 3, len(lps) - 1):
+        with lpg.Solver(lps[j], spmv_layout=1) as s:
+            alone = lpg.solve_batch([s], eps_rel=1e-5, max_iters=400000)[0]
+        a, b = alone, in_mix[j]
+        assert a.info.iterations == b.info.iterations
+        assert np.array_equal(a.x, b.x) and np.array_equal(a.y, b.y) and np.array_equal(a.z, b.z)
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-8])
+def test_batch_fp32_and_mixed_precision(oracle_lib, eps):
+    lps = _lps()
+    solvers = [lpg.Solver(lp, spmv_layout=1, precision=(FP32 if i % 3 else lpg.LP_PREC_FP64))
+               for i, lp in enumerate(lps)]
+    try:
+        sols = lpg.solve_batch(solvers, eps_rel=eps, max_iters=1_000_000)
+    finally:
+        for s in solvers:
+            s.close()
+    for lp, sol in zip(lps, sols):
+        assert sol.status == "optimal", (lp.name, sol.info.rel_kkt)
+        chk = oracle.kkt(lp, sol.x, sol.y)
+        assert chk["erel"] <= eps * (1 + 1e-9), lp.name
+
+
+def test_batched_workload_sample(oracle_lib):
+    """A stratified sample of the batched workload (random-sparse and transportation LPs,
+    rows capped for test time), FP32 form to 1e-4."""
+    lps = [synth.cfg3_lp(j, m_max=1500) for j in range(24)]
+    solvers = [lpg.Solver(lp, spmv_layout=1, precision=FP32) for lp in lps]
+    try:
+        sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=1_000_000)
+    finally:
+        for s in solvers:
+            s.close()
+    for lp, sol in zip(lps, sols):
+        assert sol.status == "optimal", (lp.name, sol.info.rel_kkt, sol.info.iterations)
+        assert oracle.kkt(lp, sol.x, sol.y)["erel"] <= 1e-4
