@@ -67,6 +67,69 @@ def run_cpu_baseline(lp, iters: int) -> dict:
                       f"{r.iter_s:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
 
 
+def run_batch(args) -> int:
+    """Batched workload: LPs j of the 4096-LP batch (m log-uniform in [50, 5000], n = 2m,
+    random-sparse with density U[0.5%, 5%] for even j, transportation for odd j), solved
+    to E_rel 1e-4 in one persistent launch in the FP32 storage form, against the plain
+    per-LP FP64 lp_solve loop on the same GPU (on a sub-sample)."""
+    import numpy as np
+
+    import paper_2604_23951_amd as lpg
+    import synth
+
+    total = 4096
+    stride = max(1, total // args.batch_count)
+    ids = list(range(0, total, stride))[: args.batch_count]
+    t0 = time.time()
+    lps = [synth.cfg3_lp(j) for j in ids]
+    gen_s = time.time() - t0
+    nnz = np.array([lp.nnz for lp in lps])
+    print(f"[bench] generated {len(lps)} LPs (nnz total {nnz.sum():.3e}, max {nnz.max()}) in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+    t1 = time.time()
+    solvers = [lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED) for lp in lps]
+    create_s = time.time() - t1
+    print(f"[bench] created {len(solvers)} handles in {create_s:.1f}s", file=sys.stderr, flush=True)
+    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64)  # warm-up launch
+    t2 = time.perf_counter()
+    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=args.batch_max_iters)
+    dt = time.perf_counter() - t2
+    ok = sum(s.status == "optimal" for s in sols)
+    iters = np.array([s.info.iterations for s in sols])
+    print(f"[bench] batch: {len(sols)} LPs in {dt:.2f}s ({len(sols) / dt:.1f} LPs/s), {ok} optimal, "
+          f"iterations median {int(np.median(iters))} max {iters.max()}", file=sys.stderr, flush=True)
+    for s in solvers:
+        s.close()
+    # plain per-LP FP64 loop on a sub-sample
+    sub = lps[:: max(1, len(lps) // args.loop_count)][: args.loop_count]
+    loop_t = 0.0
+    loop_ok = 0
+    for lp in sub:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters) as s1:
+            t3 = time.perf_counter()
+            r = s1.solve()
+            loop_t += time.perf_counter() - t3
+            loop_ok += r.status == "optimal"
+    loop_rate = len(sub) / loop_t
+    print(f"[bench] per-LP FP64 loop: {len(sub)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
+          file=sys.stderr, flush=True)
+    result = {
+        "metric": METRIC, "value": len(sols) / dt, "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batched LPs to E_rel 1e-4: stratified sample of the 4096-LP batch "
+                               "(m log-uniform [50,5000], n=2m, random-sparse density U[0.5%,5%] / transportation "
+                               "50/50), FP32 storage form with FP64 evaluation and refinement, one persistent launch",
+                   "lps": len(sols), "nnz_total": int(nnz.sum()), "optimal": ok,
+                   "iterations_median": int(np.median(iters)), "iterations_max": int(iters.max())},
+        "per_lp_fp64_loop": {"lps": len(sub), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok},
+        "speedup_vs_per_lp_loop": (len(sols) / dt) / loop_rate,
+        "create_s": create_s,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +143,10 @@ def main(argv=None):
     ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
     ap.add_argument("--layout", type=int, default=0, help="0 panel-packed wave units, 1 row tiles")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage form measurement")
+    ap.add_argument("--workload", default="large", choices=["large", "batch"])
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--loop-count", type=int, default=8)
+    ap.add_argument("--batch-max-iters", type=int, default=400000)
     ap.add_argument("--slice-bytes", type=int, default=0)
     ap.add_argument("--units-per-cu", type=int, default=0)
     ap.add_argument("--long-row-len", type=int, default=0)
@@ -88,6 +155,8 @@ def main(argv=None):
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU layout is a design note, not built", file=sys.stderr)
         return 2
+    if args.workload == "batch":
+        return run_batch(args)
 
     import numpy as np
 

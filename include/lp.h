@@ -93,6 +93,8 @@ typedef struct lp_options {
     int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 8) */
     int32_t batch_wg_per_cu; /* lp_solve_batch: workgroups per compute unit (default 3) */
     int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
+    int64_t batch_split_nnz;   /* lp_solve_batch: LPs with more nonzeros go to the block-diagonal
+                                  multi-LP launches, the rest to the persistent kernel (default 20000) */
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
 } lp_options;
@@ -138,15 +140,22 @@ int32_t lp_solve(lp_handle *h);
  * setup, the step size and the trace capacity are fixed at lp_create). */
 int32_t lp_update_options(lp_handle *h, const lp_options *opt);
 
-/* Batched form: solve the LPs of `count` handles (created on the same device) in one
- * persistent launch. Each workgroup takes the next LP from a device work counter (largest
- * nnz first) and runs that LP's whole restarted PDHG on chip: sparse products by row tiles
- * with the fused updates, FP64 evaluations, restart and termination decisions. Each LP's
- * result depends only on that LP (not on the other LPs or the workgroup that solved it),
- * so it is the same alone and in any batch. The handles' precisions may differ.
+/* Batched form: solve the LPs of `count` handles (created on the same device) together.
+ *  - LPs with at most batch_split_nnz nonzeros run in one persistent launch: each workgroup
+ *    takes the next LP from a device work counter (largest first) and runs that LP's whole
+ *    restarted PDHG on chip (row-tile sparse products with the fused updates, FP64
+ *    evaluations, restart and termination decisions).
+ *  - Larger LPs advance together as one block-diagonal problem: every launch covers the row
+ *    tiles of all of them, each LP with its own step sizes, restarts and termination;
+ *    evaluation periods are replayed as one hipGraph for the whole group until every LP
+ *    has stopped. Each such LP follows exactly the trajectory of its own lp_solve with the
+ *    row-tile layout.
+ * Each LP's result depends only on that LP (not on the other LPs or on where it ran), so it
+ * is the same alone and in any batch. The handles' precisions may differ.
  * Solve-time options: batch_opt's eps_rel, max_iters, eval_every and restarts for every LP
- * when batch_opt is given, each handle's own otherwise; batch_opt->batch_wg_per_cu sets the
- * grid. Afterwards every handle is solved and lp_get_solution returns its result
+ * when batch_opt is given, each handle's own otherwise (the LPs of the block-diagonal group
+ * must then share eval_every); batch_opt->batch_wg_per_cu and batch_split_nnz set the
+ * launches. Afterwards every handle is solved and lp_get_solution returns its result
  * (info.solve_seconds is the batch time). Runs on the first handle's stream and waits. */
 int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
 

@@ -47,7 +47,7 @@ class lp_options(C.Structure):
         ("seed", C.c_uint64), ("hip_stream", C.c_void_p), ("device", C.c_int32), ("trace_cap", C.c_int32),
         ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32),
         ("batch_wg_per_cu", C.c_int32),
-        ("panel_slice_bytes", C.c_int64), ("x0", C.c_void_p), ("y0", C.c_void_p),
+        ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("x0", C.c_void_p), ("y0", C.c_void_p),
     ]
 
 

@@ -181,7 +181,7 @@ int32_t validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int
 int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 1 ||
-        o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
+        o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s)) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
@@ -235,6 +235,191 @@ void fill_info(lp_handle* h) {
     inf.sigma_max = sc.sigma_max;
     inf.step_size = sc.eta;
     inf.omega = sc.omega;
+}
+
+
+BatchJob make_job(lp_handle* h, const lp_options* bo) {
+    const lp_options& o = bo ? *bo : h->opt;
+    BatchJob J{};
+    J.P = h->P;
+    J.eps_rel = o.eps_rel;
+    J.max_iters = o.max_iters;
+    J.trace_cap = h->opt.trace_cap;
+    J.eval_every = o.eval_every;
+    J.restarts_on = o.restarts;
+    J.x0 = h->d_x0;
+    J.y0 = h->d_y0;
+    return J;
+}
+
+int32_t finish_batch(const std::vector<lp_handle*>& hs, hipStream_t s) {
+    for (lp_handle* h : hs) HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hs[0], hipStreamSynchronize(s));
+    for (lp_handle* h : hs) {
+        fill_info(h);
+        h->solved = true;
+    }
+    return LP_OK;
+}
+
+// LPs solved one per workgroup in a single persistent launch.
+int32_t solve_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
+    const int count = static_cast<int>(hs.size());
+    lp_handle* h0 = hs[0];
+    std::vector<BatchJob> jobs(static_cast<size_t>(count));
+    std::vector<int32_t> order(static_cast<size_t>(count));
+    for (int i = 0; i < count; ++i) {
+        jobs[i] = make_job(hs[i], bo);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hs[a]->nnz > hs[b]->nnz; });
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h0->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
+    int grid = cus * wpc;
+    if (grid > count) grid = count;
+    const size_t bj = sizeof(BatchJob) * static_cast<size_t>(count), bo_ = sizeof(int32_t) * static_cast<size_t>(count);
+    const size_t oc = (bj + bo_ + 255) / 256 * 256;
+    char* buf = nullptr;
+    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&buf), oc + 256));
+    BatchJob* djobs = reinterpret_cast<BatchJob*>(buf);
+    int32_t* dorder = reinterpret_cast<int32_t*>(buf + bj);
+    int32_t* dcounter = reinterpret_cast<int32_t*>(buf + oc);
+    hipError_t e = hipMemcpyAsync(djobs, jobs.data(), bj, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dorder, order.data(), bo_, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) {
+        launch_batch(djobs, dorder, count, dcounter, grid, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
+    return finish_batch(hs, s);
+}
+
+// LPs advanced together as one block-diagonal problem, one launch per phase for all of
+// them, evaluation periods replayed as a hipGraph.
+int32_t solve_block_diagonal(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
+    const int count = static_cast<int>(hs.size());
+    lp_handle* h0 = hs[0];
+    std::vector<BatchJob> jobs(static_cast<size_t>(count));
+    std::vector<int2> ma, mat, mred, melem;
+    int E = 0;
+    for (int i = 0; i < count; ++i) {
+        lp_handle* h = hs[i];
+        jobs[i] = make_job(h, bo);
+        if (E == 0) E = jobs[i].eval_every;
+        if (jobs[i].eval_every != E)
+            return fail(h0, LP_ERR_INVALID_ARG, "block-diagonal batch LPs must share eval_every");
+        for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
+        for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
+        for (int b = 0; b < h->P.nred; ++b) mred.push_back(make_int2(i, b));
+        const int mx = h->m > h->n ? h->m : h->n;
+        for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
+    }
+    Arena L;
+    const size_t oj = L.add(sizeof(BatchJob) * jobs.size()), oa = L.add(sizeof(int2) * ma.size()),
+                 oat = L.add(sizeof(int2) * mat.size()), ored = L.add(sizeof(int2) * mred.size()),
+                 oel = L.add(sizeof(int2) * melem.size()), oact = L.add(sizeof(int));
+    char* buf = nullptr;
+    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&buf), L.off));
+    int* hact = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&hact), sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(buf);
+        return fail(h0, LP_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+    }
+    MultiMaps M{};
+    M.jobs = reinterpret_cast<const BatchJob*>(buf + oj);
+    M.count = count;
+    M.map_a = reinterpret_cast<const int2*>(buf + oa);
+    M.n_a = static_cast<int>(ma.size());
+    M.map_at = reinterpret_cast<const int2*>(buf + oat);
+    M.n_at = static_cast<int>(mat.size());
+    M.map_red = reinterpret_cast<const int2*>(buf + ored);
+    M.n_red = static_cast<int>(mred.size());
+    M.map_elem = reinterpret_cast<const int2*>(buf + oel);
+    M.n_elem = static_cast<int>(melem.size());
+    M.active = reinterpret_cast<int*>(buf + oact);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    auto cleanup = [&]() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipHostFree(hact);
+        (void)hipFree(buf);
+    };
+    auto H2D = [&](size_t off, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    hipError_t e = H2D(oj, jobs.data(), sizeof(BatchJob) * jobs.size());
+    if (e == hipSuccess) e = H2D(oa, ma.data(), sizeof(int2) * ma.size());
+    if (e == hipSuccess) e = H2D(oat, mat.data(), sizeof(int2) * mat.size());
+    if (e == hipSuccess) e = H2D(ored, mred.data(), sizeof(int2) * mred.size());
+    if (e == hipSuccess) e = H2D(oel, melem.data(), sizeof(int2) * melem.size());
+    if (e == hipSuccess) {
+        launch_multi(M, MULTI_RESET, 0, s);
+        launch_multi(M, MULTI_INIT, 0, s);
+        launch_multi(M, MULTI_AX_ALL, 0, s);
+        launch_multi(M, MULTI_ATY, 0, s);
+        launch_multi(M, MULTI_PARTIALS, 1, s);
+        launch_multi(M, MULTI_DECIDE, 1, s);
+        launch_multi(M, MULTI_REBASE_INIT, 0, s);
+        e = hipGetLastError();
+    }
+    auto bundle = [&]() {
+        for (int it = 0; it < E; ++it) {
+            launch_multi(M, MULTI_PRIMAL, it, s);
+            launch_multi(M, MULTI_DUAL, it, s);
+        }
+        launch_multi(M, MULTI_MATERIALIZE, 0, s);
+        launch_multi(M, MULTI_AX_FP32, 0, s);
+        launch_multi(M, MULTI_ATY, 0, s);
+        launch_multi(M, MULTI_AXA, 0, s);
+        launch_multi(M, MULTI_ATYA, 0, s);
+        launch_multi(M, MULTI_PARTIALS, 0, s);
+        launch_multi(M, MULTI_DECIDE, 0, s);
+        launch_multi(M, MULTI_APPLY, 0, s);
+        launch_multi(M, MULTI_ACTIVE, 0, s);
+    };
+    if (e == hipSuccess) {
+        hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (ce == hipSuccess) {
+            bundle();
+            ce = hipStreamEndCapture(s, &graph);
+        }
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+        if (ce != hipSuccess) {
+            (void)hipGetLastError();
+            if (graph) (void)hipGraphDestroy(graph);
+            graph = nullptr;
+            gexec = nullptr;
+        }
+    }
+    long long max_bundles = 0;
+    for (const BatchJob& J : jobs) {
+        const long long b = J.max_iters / E + 2;
+        if (b > max_bundles) max_bundles = b;
+    }
+    for (long long b = 0; e == hipSuccess && b < max_bundles; ++b) {
+        if (gexec) e = hipGraphLaunch(gexec, s);
+        else {
+            bundle();
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hact, M.active, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess && *hact == 0) break;
+    }
+    if (e == hipSuccess) {
+        launch_multi(M, MULTI_EXTRACT, 0, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("block-diagonal batch: ") + hipGetErrorString(e));
+    return finish_batch(hs, s);
 }
 
 int32_t capture_graph(lp_handle* h) {
@@ -542,6 +727,7 @@ void lp_default_options(lp_options* o) {
     o->long_row_len = 256;
     o->units_per_cu = 8;
     o->batch_wg_per_cu = 3;
+    o->batch_split_nnz = 20000;
     o->panel_slice_bytes = int64_t(1) << 20;
     o->x0 = nullptr;
     o->y0 = nullptr;
@@ -681,59 +867,18 @@ int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo
         if (bo && validate_options(*bo, &msg)) return fail(nullptr, LP_ERR_INVALID_ARG, msg);
         lp_handle* h0 = hs[0];
         HIP_TRY(h0, hipSetDevice(dev));
-        std::vector<BatchJob> jobs(static_cast<size_t>(count));
-        std::vector<int32_t> order(static_cast<size_t>(count));
-        for (int32_t i = 0; i < count; ++i) {
-            lp_handle* h = hs[i];
-            const lp_options& o = bo ? *bo : h->opt;
-            BatchJob& J = jobs[i];
-            J.P = h->P;
-            J.eps_rel = o.eps_rel;
-            J.max_iters = o.max_iters;
-            J.trace_cap = h->opt.trace_cap;
-            J.eval_every = o.eval_every;
-            J.restarts_on = o.restarts;
-            J.x0 = h->d_x0;
-            J.y0 = h->d_y0;
-            order[i] = i;
-        }
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return hs[a]->nnz > hs[b]->nnz; });
-        int cus = 256;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-        const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
-        int grid = cus * wpc;
-        if (grid > count) grid = count;
-        const size_t bj = sizeof(BatchJob) * static_cast<size_t>(count), bo_ = sizeof(int32_t) * static_cast<size_t>(count);
-        char* buf = nullptr;
-        HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&buf), bj + bo_ + 256));
-        BatchJob* djobs = reinterpret_cast<BatchJob*>(buf);
-        int32_t* dorder = reinterpret_cast<int32_t*>(buf + bj);
-        int32_t* dcounter = reinterpret_cast<int32_t*>(buf + bj + bo_ + (256 - (bj + bo_) % 256) % 256);
-        hipStream_t s = h0->stream;
+        const int64_t split = bo ? bo->batch_split_nnz : 20000;
+        std::vector<lp_handle*> big, small;
+        for (int32_t i = 0; i < count; ++i) (hs[i]->nnz > split ? big : small).push_back(hs[i]);
         const auto t0 = std::chrono::steady_clock::now();
-        hipError_t e = hipMemcpyAsync(djobs, jobs.data(), bj, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(dorder, order.data(), bo_, hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, sizeof(int32_t), s);
-        if (e == hipSuccess) {
-            launch_batch(djobs, dorder, count, dcounter, grid, s);
-            e = hipGetLastError();
+        if (!big.empty()) {
+            if (int32_t rc = solve_block_diagonal(big, bo, h0->stream)) return rc;
         }
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (!small.empty()) {
+            if (int32_t rc = solve_persistent(small, bo, h0->stream)) return rc;
+        }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        (void)hipFree(buf);
-        if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
-        for (int32_t i = 0; i < count; ++i) {
-            lp_handle* h = hs[i];
-            HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-        }
-        HIP_TRY(h0, hipStreamSynchronize(s));
-        for (int32_t i = 0; i < count; ++i) {
-            lp_handle* h = hs[i];
-            fill_info(h);
-            h->info.solve_seconds = secs;
-            h->solved = true;
-        }
+        for (int32_t i = 0; i < count; ++i) hs[i]->info.solve_seconds = secs;
         return LP_OK;
     } catch (const std::bad_alloc&) {
         return fail(nullptr, LP_ERR_OUT_OF_MEMORY, "host allocation failed");

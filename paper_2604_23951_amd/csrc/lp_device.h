@@ -115,6 +115,27 @@ struct BatchJob {
     const double* y0;
 };
 
+// Block maps of a block-diagonal batch: entry b of a map is (LP index, tile or block of it).
+struct MultiMaps {
+    const BatchJob* jobs;
+    int count;
+    const int2* map_a;    // row tiles of every A
+    int n_a;
+    const int2* map_at;   // row tiles of every A^T
+    int n_at;
+    const int2* map_red;  // reduction blocks (nred per LP)
+    int n_red;
+    const int2* map_elem; // vector blocks (ceil(max(m, n) / kBlock) per LP)
+    int n_elem;
+    int* active;          // number of LPs still running
+};
+
+enum MultiLaunch {
+    MULTI_PRIMAL = 0, MULTI_DUAL, MULTI_AX_ALL, MULTI_AX_FP32, MULTI_ATY, MULTI_AXA, MULTI_ATYA, MULTI_PARTIALS,
+    MULTI_DECIDE, MULTI_INIT, MULTI_REBASE_INIT, MULTI_MATERIALIZE, MULTI_APPLY, MULTI_EXTRACT, MULTI_RESET,
+    MULTI_ACTIVE
+};
+
 // ---- setup ------------------------------------------------------------------------
 void launch_fill(double* p, long long n, double v, hipStream_t s);
 void launch_scale_pass(const DevLP& P, int* A_rp, int* A_ci, double* A_v, const int* AT_rp, const int* perm,
@@ -143,5 +164,8 @@ void launch_materialize(const DevLP& P, hipStream_t s);
 // Batched form: `grid` workgroups take LPs jobs[order[0]], jobs[order[1]], ... from the
 // device counter (which must start at 0) and each solves one LP at a time, entirely on chip.
 void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s);
+// One launch of a block-diagonal batch; it_or_mode is the iteration inside the bundle for
+// MULTI_PRIMAL / MULTI_DUAL and the evaluation mode for MULTI_PARTIALS / MULTI_DECIDE.
+void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s);
 
 }  // namespace lpgpu

@@ -733,19 +733,19 @@ __device__ inline void col_terms(const DevLP& P, int j, const double* x, const d
 // Partial sums of the KKT quantities of the current iterate (slots 0..7) and of the running
 // average (slots 8..15). mode 1 (initial point) and mode 2 (final point after a stop)
 // evaluate the current iterate only; mode 2 runs whatever the status.
-__global__ __launch_bounds__(kBlock) void kkt_partials_kernel(DevLP P, int mode) {
+__device__ void kkt_partials_body(const DevLP& P, int mode, int blk, int nblk) {
     __shared__ double red[kBlock / 64][2 * kNQ];
     if (mode != 2 && P.sc->status != kRunning) return;
     double acc[2 * kNQ];
 #pragma unroll
     for (int q = 0; q < 2 * kNQ; ++q) acc[q] = 0.0;
     const bool both = (mode == 0);
-    const int stride = gridDim.x * blockDim.x;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < P.m; i += stride) {
+    const int stride = nblk * kBlock;
+    for (int i = blk * kBlock + threadIdx.x; i < P.m; i += stride) {
         row_terms(P, i, P.ax, P.y, acc);
         if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
     }
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P.n; j += stride) {
+    for (int j = blk * kBlock + threadIdx.x; j < P.n; j += stride) {
         col_terms(P, j, P.x, P.aty, acc);
         if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
     }
@@ -759,8 +759,12 @@ __global__ __launch_bounds__(kBlock) void kkt_partials_kernel(DevLP P, int mode)
     if (threadIdx.x < 2 * kNQ) {
         double t = 0.0;
         for (int k = 0; k < kBlock / 64; ++k) t += red[k][threadIdx.x];
-        P.partials[blockIdx.x * 2 * kNQ + threadIdx.x] = t;
+        P.partials[blk * 2 * kNQ + threadIdx.x] = t;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void kkt_partials_kernel(DevLP P, int mode) {
+    kkt_partials_body(P, mode, static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x));
 }
 
 struct Kkt {
@@ -922,7 +926,7 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
     sc->n_trace = nt + 1;
 }
 
-__global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) {
+__device__ void decide_body(const DevLP& P, int mode) {
     __shared__ double red[kBlock / 64];
     __shared__ double tot[2 * kNQ];
     Scalars* sc = P.sc;
@@ -937,6 +941,8 @@ __global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) {
     if (threadIdx.x != 0) return;
     decide_logic(P, P.sc, tot, mode);
 }
+
+__global__ __launch_bounds__(kBlock) void decide_kernel(DevLP P, int mode) { decide_body(P, mode); }
 
 // Restart: the candidate becomes the iterate, the anchor and the average.
 __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
@@ -1240,6 +1246,146 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, con
     }
 }
 
+
+// ------------------------------------------------ block-diagonal batch (many LPs per launch)
+// One launch covers the row tiles (or reduction blocks, or vector blocks) of every LP of a
+// batch; map[b] = (LP, tile-or-block of that LP). Each LP keeps its own scalars, so every
+// LP follows exactly the trajectory of its own single-LP solve, bundles are graph-captured
+// for the whole batch, and a converged LP's blocks return at once.
+enum MultiKind { MK_PRIMAL = 0, MK_DUAL, MK_AX_ALL, MK_AX_FP32, MK_ATY, MK_AXA, MK_ATYA };
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void multi_tiles_kernel(const BatchJob* jobs, const int2* map, int it) {
+    __shared__ double lds[kTileNnz];
+    __shared__ double red[kBlock / 64];
+    const int2 mt = map[blockIdx.x];
+    const DevLP& P = jobs[mt.x].P;
+    if (KIND == MK_PRIMAL) {
+        if (P.fp32) {
+            EpiPrimal32 e{};
+            e.sc = P.sc;
+            e.it = it;
+            e.d = P.d32;
+            e.lo = P.lo32;
+            e.hi = P.hi32;
+            e.x = P.dx;
+            e.xa = P.dxa;
+            if (!e.begin()) return;
+            tile_body(P.AT.csr, mt.y, static_cast<const float*>(P.dy), e, reinterpret_cast<float*>(lds), red);
+        } else {
+            EpiPrimal e{};
+            e.sc = P.sc;
+            e.it = it;
+            e.c = P.c;
+            e.xl = P.xl;
+            e.xu = P.xu;
+            e.x = P.x;
+            e.xa = P.xa;
+            if (!e.begin()) return;
+            tile_body(P.AT.csr, mt.y, static_cast<const double*>(P.y), e, lds, red);
+        }
+    } else if (KIND == MK_DUAL) {
+        if (P.fp32) {
+            EpiDual32 e{};
+            e.sc = P.sc;
+            e.it = it;
+            e.rl = P.rl32;
+            e.ru = P.ru32;
+            e.yh = P.yh32;
+            e.y = P.dy;
+            e.ya = P.dya;
+            e.ax = P.adx;
+            if (!e.begin()) return;
+            tile_body(P.A.csr, mt.y, static_cast<const float*>(P.dx), e, reinterpret_cast<float*>(lds), red);
+        } else {
+            EpiDual e{};
+            e.sc = P.sc;
+            e.it = it;
+            e.bl = P.bl;
+            e.bu = P.bu;
+            e.y = P.y;
+            e.ya = P.ya;
+            e.ax = P.ax;
+            if (!e.begin()) return;
+            tile_body(P.A.csr, mt.y, static_cast<const double*>(P.x), e, lds, red);
+        }
+    } else {
+        if (P.sc->status != kRunning) return;
+        if (KIND == MK_AX_FP32 && !P.fp32) return;
+        const bool onA = KIND == MK_AX_ALL || KIND == MK_AX_FP32 || KIND == MK_AXA;
+        const double* xin = KIND == MK_ATY ? P.y : KIND == MK_ATYA ? P.ya : KIND == MK_AXA ? P.xa : P.x;
+        double* out = KIND == MK_ATY ? P.aty : KIND == MK_ATYA ? P.atya : KIND == MK_AXA ? P.axa : P.ax;
+        tile_body(onA ? P.A.csr : P.AT.csr, mt.y, xin, EpiStore{out, nullptr}, lds, red);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void multi_partials_kernel(const BatchJob* jobs, const int2* map, int mode) {
+    const int2 mt = map[blockIdx.x];
+    const DevLP& P = jobs[mt.x].P;
+    kkt_partials_body(P, mode, mt.y, P.nred);
+}
+
+__global__ __launch_bounds__(kBlock) void multi_decide_kernel(const BatchJob* jobs, int mode) {
+    decide_body(jobs[blockIdx.x].P, mode);
+}
+
+enum ElemOp { EO_INIT = 0, EO_REBASE_INIT, EO_MATERIALIZE, EO_APPLY, EO_EXTRACT };
+
+template <int OP>
+__global__ __launch_bounds__(kBlock) void multi_elem_kernel(const BatchJob* jobs, const int2* map) {
+    const int2 mt = map[blockIdx.x];
+    const BatchJob& J = jobs[mt.x];
+    const DevLP& P = J.P;
+    const int g = mt.y * kBlock + threadIdx.x;
+    const Scalars* sc = P.sc;
+    if (OP == EO_INIT) {
+        init_state_at(P, g, J.x0, J.y0);
+    } else if (OP == EO_REBASE_INIT) {
+        if (P.fp32 && sc->status == kRunning) rebase_at(P, 1, g);
+    } else if (OP == EO_MATERIALIZE) {
+        if (P.fp32 && sc->status == kRunning) materialize_at(P, g);
+    } else if (OP == EO_APPLY) {
+        const int lr = sc->last_restart;
+        if (lr == 0) return;
+        if (P.fp32) rebase_at(P, lr, g);
+        else apply_restart_at(P, lr, g);
+    } else {
+        extract_at(P, sc->out_avg, g);
+    }
+}
+
+__global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const BatchJob& J = jobs[i];
+    Scalars* sc = J.P.sc;
+    sc->omega = sc->omega0;
+    sc->tau = sc->eta / sc->omega;
+    sc->sigma = sc->eta * sc->omega;
+    sc->eps_rel = J.eps_rel;
+    sc->max_iters = J.max_iters;
+    sc->eval_every = J.eval_every;
+    sc->restarts_on = J.restarts_on;
+    sc->trace_cap = J.trace_cap;
+    sc->k = 0;
+    sc->t = 0;
+    sc->restarts = 0;
+    sc->n_trace = 0;
+    sc->status = kRunning;
+    sc->out_avg = 0;
+    sc->last_restart = 0;
+    sc->kkt_prev = __builtin_inf();
+}
+
+// Number of LPs still running, summed by one workgroup in a fixed order.
+__global__ __launch_bounds__(kBlock) void multi_active_kernel(const BatchJob* jobs, int count, int* active) {
+    __shared__ double red[kBlock / 64];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) a += jobs[i].P.sc->status == kRunning ? 1.0 : 0.0;
+    a = block_sum(a, red);
+    if (threadIdx.x == 0) *active = static_cast<int>(a);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------- launchers
@@ -1416,6 +1562,42 @@ void launch_apply_restart(const DevLP& P, hipStream_t s) {
         return;
     }
     hipLaunchKernelGGL(apply_restart_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
+
+void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s) {
+    auto tiles = [&](auto kern, int n, const int2* map) {
+        if (n > 0) hipLaunchKernelGGL(kern, dim3(n), dim3(kBlock), 0, s, M.jobs, map, it_or_mode);
+    };
+    switch (kind) {
+        case MULTI_PRIMAL: tiles(multi_tiles_kernel<MK_PRIMAL>, M.n_at, M.map_at); break;
+        case MULTI_DUAL: tiles(multi_tiles_kernel<MK_DUAL>, M.n_a, M.map_a); break;
+        case MULTI_AX_ALL: tiles(multi_tiles_kernel<MK_AX_ALL>, M.n_a, M.map_a); break;
+        case MULTI_AX_FP32: tiles(multi_tiles_kernel<MK_AX_FP32>, M.n_a, M.map_a); break;
+        case MULTI_ATY: tiles(multi_tiles_kernel<MK_ATY>, M.n_at, M.map_at); break;
+        case MULTI_AXA: tiles(multi_tiles_kernel<MK_AXA>, M.n_a, M.map_a); break;
+        case MULTI_ATYA: tiles(multi_tiles_kernel<MK_ATYA>, M.n_at, M.map_at); break;
+        case MULTI_PARTIALS:
+            if (M.n_red > 0)
+                hipLaunchKernelGGL(multi_partials_kernel, dim3(M.n_red), dim3(kBlock), 0, s, M.jobs, M.map_red,
+                                   it_or_mode);
+            break;
+        case MULTI_DECIDE:
+            hipLaunchKernelGGL(multi_decide_kernel, dim3(M.count), dim3(kBlock), 0, s, M.jobs, it_or_mode);
+            break;
+        case MULTI_INIT: hipLaunchKernelGGL(multi_elem_kernel<EO_INIT>, dim3(M.n_elem), dim3(kBlock), 0, s, M.jobs, M.map_elem); break;
+        case MULTI_REBASE_INIT: hipLaunchKernelGGL(multi_elem_kernel<EO_REBASE_INIT>, dim3(M.n_elem), dim3(kBlock), 0, s, M.jobs, M.map_elem); break;
+        case MULTI_MATERIALIZE: hipLaunchKernelGGL(multi_elem_kernel<EO_MATERIALIZE>, dim3(M.n_elem), dim3(kBlock), 0, s, M.jobs, M.map_elem); break;
+        case MULTI_APPLY: hipLaunchKernelGGL(multi_elem_kernel<EO_APPLY>, dim3(M.n_elem), dim3(kBlock), 0, s, M.jobs, M.map_elem); break;
+        case MULTI_EXTRACT: hipLaunchKernelGGL(multi_elem_kernel<EO_EXTRACT>, dim3(M.n_elem), dim3(kBlock), 0, s, M.jobs, M.map_elem); break;
+        case MULTI_RESET:
+            hipLaunchKernelGGL(multi_reset_kernel, dim3((M.count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, M.jobs, M.count);
+            break;
+        case MULTI_ACTIVE:
+            hipLaunchKernelGGL(multi_active_kernel, dim3(1), dim3(kBlock), 0, s, M.jobs, M.count, M.active);
+            break;
+        default: break;
+    }
 }
 
 void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s) {

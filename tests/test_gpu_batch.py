@@ -106,3 +106,38 @@ def test_batched_workload_sample(oracle_lib):
     for lp, sol in zip(lps, sols):
         assert sol.status == "optimal", (lp.name, sol.info.rel_kkt, sol.info.iterations)
         assert oracle.kkt(lp, sol.x, sol.y)["erel"] <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [lpg.LP_PREC_FP64, FP32])
+def test_block_diagonal_equals_single_lp_solve(precision):
+    """LPs in the block-diagonal group follow their own lp_solve trajectory exactly."""
+    lps = _lps()
+    with_batch = [lpg.Solver(lp, spmv_layout=1, precision=precision) for lp in lps]
+    try:
+        sols = lpg.solve_batch(with_batch, eps_rel=1e-6, max_iters=400000, batch_split_nnz=0)
+    finally:
+        for s in with_batch:
+            s.close()
+    for lp, sb in zip(lps, sols):
+        with lpg.Solver(lp, spmv_layout=1, precision=precision, eps_rel=1e-6, max_iters=400000) as s1:
+            ss = s1.solve()
+        assert sb.status == ss.status and sb.info.iterations == ss.info.iterations, lp.name
+        assert np.array_equal(sb.x, ss.x) and np.array_equal(sb.y, ss.y) and np.array_equal(sb.z, ss.z), lp.name
+
+
+def test_block_diagonal_alone_equals_in_mix_and_split(oracle_lib):
+    lps = _lps()
+    mix = [lpg.Solver(lp, spmv_layout=1) for lp in lps]
+    try:
+        # a split that sends part of the batch to each path
+        split = int(np.median([lp.nnz for lp in lps]))
+        in_mix = lpg.solve_batch(mix, eps_rel=1e-5, max_iters=400000, batch_split_nnz=split)
+    finally:
+        for s in mix:
+            s.close()
+    for j, lp in enumerate(lps):
+        with lpg.Solver(lp, spmv_layout=1) as s:
+            alone = lpg.solve_batch([s], eps_rel=1e-5, max_iters=400000, batch_split_nnz=split)[0]
+        assert alone.info.iterations == in_mix[j].info.iterations, lp.name
+        assert np.array_equal(alone.x, in_mix[j].x) and np.array_equal(alone.y, in_mix[j].y), lp.name
+        assert oracle.kkt(lp, alone.x, alone.y)["erel"] <= 1e-5
