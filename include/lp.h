@@ -95,6 +95,10 @@ typedef struct lp_options {
     int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
     int64_t batch_split_nnz;   /* lp_solve_batch: LPs with more nonzeros go to the block-diagonal
                                   multi-LP launches, the rest to the persistent kernel (default 20000) */
+    int32_t deferred;      /* 1: lp_create validates and prepares on the host only; device memory is
+                              allocated (and the setup run) when the LP is first solved or admitted
+                              by a server, and released by the server when it completes (default 0) */
+    int32_t pad1;
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
 } lp_options;
@@ -158,6 +162,53 @@ int32_t lp_update_options(lp_handle *h, const lp_options *opt);
  * launches. Afterwards every handle is solved and lp_get_solution returns its result
  * (info.solve_seconds is the batch time). Runs on the first handle's stream and waits. */
 int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
+
+/* ---- serving form -------------------------------------------------------------------
+ * A server solves LPs as they arrive, with continuous batching: a worker thread keeps a
+ * running set of LPs on the device and advances all of them together, one evaluation
+ * period (eval_every iterations, evaluation, restart decision) per round of shared
+ * block-diagonal launches. Between rounds it retires the LPs that stopped (their result is
+ * copied to the host and their device memory released) and admits queued requests in
+ * arrival order while a slot is free and the request's device footprint fits the HBM
+ * budget. Every LP starts at its own iteration 0 and keeps its own step sizes, restarts and
+ * counters, so its result is the same as when it is solved alone.
+ * Handles submitted to a server must be created with opt->deferred = 1 (no device memory
+ * until admitted) and must not be used elsewhere until their ticket completes; afterwards
+ * lp_get_solution returns the result from the host copy. */
+typedef struct lp_server lp_server;
+
+typedef struct lp_server_stats {
+    int64_t submitted, admitted, completed, queued, running;
+    int64_t rounds;            /* evaluation periods run */
+    int64_t bytes_in_use;      /* device bytes of the admitted LPs */
+    int64_t peak_bytes;        /* largest bytes_in_use seen */
+    int64_t hbm_budget;
+} lp_server_stats;
+
+/* Start a server on `device` with a device-memory budget for admitted LPs and at most
+ * max_slots LPs in the running set. The solve-time fields of *opt (eps_rel, max_iters,
+ * eval_every, restarts) apply to every LP; opt may be NULL (defaults). */
+int32_t lp_server_create(lp_server **out, int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
+                         const lp_options *opt);
+
+/* Queue a deferred handle; returns at once with its ticket. LP_ERR_INVALID_ARG for a
+ * handle that is not deferred or whose footprint exceeds the whole budget. */
+int32_t lp_server_submit(lp_server *srv, lp_handle *h, uint64_t *ticket);
+
+/* Tickets completed since the last poll (each reported once), at most cap of them. For a
+ * completed ticket, times[0..2] of lp_server_ticket_times are the submit, admit and
+ * completion instants in seconds on the server's clock. Never blocks. */
+int32_t lp_server_poll(lp_server *srv, uint64_t *done_tickets, int32_t cap, int32_t *n_done);
+int32_t lp_server_ticket_times(lp_server *srv, uint64_t ticket, double *times);
+
+/* Block until nothing is queued or running, or until timeout_s seconds (<= 0: no limit);
+ * LP_ERR_INTERNAL on timeout. */
+int32_t lp_server_wait(lp_server *srv, double timeout_s);
+
+int32_t lp_server_stats_get(lp_server *srv, lp_server_stats *st);
+
+/* Stop the worker after the current round; queued and running LPs are left unsolved. */
+void lp_server_destroy(lp_server *srv);
 
 /* Copy the returned point (original scale) to caller buffers x[n], y[m], z[n] and the run
  * record to *info. Any pointer may be NULL to skip it. LP_ERR_NOT_SOLVED before lp_solve. */

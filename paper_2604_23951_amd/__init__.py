@@ -29,7 +29,8 @@ TRACE_WIDTH = 12
 EXPORTS = (
     "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_solve_batch", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
-    "lp_get_kernel_times", "lp_get_layout",
+    "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
+    "lp_server_ticket_times", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
 )
 
 
@@ -47,8 +48,14 @@ class lp_options(C.Structure):
         ("seed", C.c_uint64), ("hip_stream", C.c_void_p), ("device", C.c_int32), ("trace_cap", C.c_int32),
         ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32),
         ("batch_wg_per_cu", C.c_int32),
-        ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("x0", C.c_void_p), ("y0", C.c_void_p),
+        ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
+        ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p),
     ]
+
+
+class lp_server_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "admitted", "completed", "queued", "running", "rounds",
+                                           "bytes_in_use", "peak_bytes", "hbm_budget")]
 
 
 class lp_info(C.Structure):
@@ -118,6 +125,20 @@ def lib():
         L.lp_get_kernel_times.restype = I32
         L.lp_get_layout.argtypes = [P, P, I32]
         L.lp_get_layout.restype = I32
+        L.lp_server_create.argtypes = [P, I32, I64, I32, P]
+        L.lp_server_create.restype = I32
+        L.lp_server_submit.argtypes = [P, P, P]
+        L.lp_server_submit.restype = I32
+        L.lp_server_poll.argtypes = [P, P, I32, P]
+        L.lp_server_poll.restype = I32
+        L.lp_server_ticket_times.argtypes = [P, C.c_uint64, P]
+        L.lp_server_ticket_times.restype = I32
+        L.lp_server_wait.argtypes = [P, D]
+        L.lp_server_wait.restype = I32
+        L.lp_server_stats_get.argtypes = [P, P]
+        L.lp_server_stats_get.restype = I32
+        L.lp_server_destroy.argtypes = [P]
+        L.lp_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -335,6 +356,67 @@ def solve_batch(solvers, **options):
         info = lp_get_solution(s.h, x, y, z)
         out.append(Solution(STATUS.get(info.status, str(info.status)), x, y[: s.m], z, info))
     return out
+
+
+class Server:
+    """Serving form: continuous batching of deferred LPs (see include/lp.h, lp_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, device: int = 0, **options):
+        self.h = C.c_void_p()
+        o = make_options(**options) if options else None
+        _check(lib().lp_server_create(C.byref(self.h), device, int(hbm_budget_bytes), int(max_slots),
+                                      None if o is None else C.byref(o)))
+        self._by_ticket = {}
+
+    def submit(self, solver: "Solver") -> int:
+        t = C.c_uint64()
+        _check(lib().lp_server_submit(self.h, solver.h, C.byref(t)), solver.h)
+        self._by_ticket[t.value] = solver
+        return t.value
+
+    def poll(self, cap: int = 4096):
+        buf = (C.c_uint64 * max(cap, 1))()
+        n = C.c_int32()
+        _check(lib().lp_server_poll(self.h, buf, cap, C.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def times(self, ticket: int):
+        t = (C.c_double * 3)()
+        _check(lib().lp_server_ticket_times(self.h, C.c_uint64(ticket), t))
+        return tuple(t)
+
+    def wait(self, timeout_s: float = 0.0):
+        _check(lib().lp_server_wait(self.h, float(timeout_s)))
+
+    def stats(self) -> dict:
+        st = lp_server_stats()
+        _check(lib().lp_server_stats_get(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in lp_server_stats._fields_}
+
+    def result(self, ticket: int) -> Solution:
+        s = self._by_ticket[ticket]
+        x = np.empty(s.n)
+        y = np.empty(max(s.m, 1))
+        z = np.empty(s.n)
+        info = lp_get_solution(s.h, x, y, z)
+        return Solution(STATUS.get(info.status, str(info.status)), x, y[: s.m], z, info)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lp_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve(lp, **options) -> Solution:

@@ -7,6 +7,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -62,6 +67,30 @@ std::vector<int32_t> build_tiles(int32_t rows, const int32_t* rp, int64_t* n_lon
     return t;
 }
 
+// Host-side integer structure of an LP, built once at lp_create.
+struct Prep {
+    std::vector<int32_t> rpT, ciT, perm, tA, tAT;
+    PanelLayoutHost LA, LAT;
+    bool panels = false;
+    int nred = 1;
+    bool ready = false;
+};
+
+// Offsets of every device array inside a handle's allocation.
+struct Offsets {
+    size_t arp, aci, av, at, trp, tci, tv, tt, perm, c, xl, xu, C, Ci, bl, bu, R, Ri;
+    size_t x, xa, xan, aty, atya, ox, oz, y, ya, yan, ax, axa, oy, x0, y0;
+    size_t f32[15] = {0};
+    size_t pA[7] = {0}, pAT[7] = {0}, pA32 = 0, pAT32 = 0;
+    size_t part, sc, tr;
+};
+
+// Problem data kept on the host by a deferred handle until it is placed on the device.
+struct HostData {
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v, c, bl, bu, xl, xu, x0, y0;
+};
+
 }  // namespace
 
 struct lp_handle {
@@ -91,9 +120,17 @@ struct lp_handle {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     double sum_p_ms = 0.0, sum_d_ms = 0.0;
     int64_t samples = 0;
+    Prep prep;
+    HostData raw;
+    bool has_x0 = false, has_y0 = false;
+    bool deferred = false;
+    bool on_device = false;
+    std::vector<double> res_x, res_y, res_z;  // result kept on the host after the device copy is released
 };
 
 namespace {
+
+int32_t materialize(lp_handle* h);
 
 int32_t fail(lp_handle* h, int32_t code, const std::string& msg) {
     if (h) h->err = msg;
@@ -202,6 +239,34 @@ void destroy_device(lp_handle* h) {
     h->arena = nullptr;
     h->h_sc = nullptr;
     h->stream = nullptr;
+    for (auto& e : h->ev) e = nullptr;
+    h->on_device = false;
+}
+
+// Keep the result on the host and give the device memory back (the handle stays usable:
+// a later solve places it on the device again).
+int32_t release_device(lp_handle* h) {
+    if (!h->on_device) return LP_OK;
+    if (h->solved) {
+        h->res_x.resize(static_cast<size_t>(h->n));
+        h->res_y.resize(static_cast<size_t>(h->m));
+        h->res_z.resize(static_cast<size_t>(h->n));
+        HIP_TRY(h, hipMemcpyAsync(h->res_x.data(), h->P.out_x, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+        if (h->m > 0)
+            HIP_TRY(h, hipMemcpyAsync(h->res_y.data(), h->P.out_y, sizeof(double) * h->m, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(h->res_z.data(), h->P.out_z, sizeof(double) * h->n, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    h->graph_failed = false;
+    if (h->arena) (void)hipFree(h->arena);
+    h->arena = nullptr;
+    h->on_device = false;
+    if (!h->own_stream) h->stream = nullptr;  // a server's stream: not the handle's to keep
+    return LP_OK;
 }
 
 // One evaluation period: eval_every iterations of (primal, dual), the evaluation and the
@@ -266,6 +331,8 @@ int32_t finish_batch(const std::vector<lp_handle*>& hs, hipStream_t s) {
 int32_t solve_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
     const int count = static_cast<int>(hs.size());
     lp_handle* h0 = hs[0];
+    for (lp_handle* h : hs)
+        if (int32_t rc = materialize(h)) return rc;
     std::vector<BatchJob> jobs(static_cast<size_t>(count));
     std::vector<int32_t> order(static_cast<size_t>(count));
     for (int i = 0; i < count; ++i) {
@@ -304,6 +371,8 @@ int32_t solve_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo
 int32_t solve_block_diagonal(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
     const int count = static_cast<int>(hs.size());
     lp_handle* h0 = hs[0];
+    for (lp_handle* h : hs)
+        if (int32_t rc = materialize(h)) return rc;
     std::vector<BatchJob> jobs(static_cast<size_t>(count));
     std::vector<int2> ma, mat, mred, melem;
     int E = 0;
@@ -440,256 +509,293 @@ int32_t capture_graph(lp_handle* h) {
     return LP_OK;
 }
 
-int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* v, const double* c,
-              const double* bl, const double* bu, const double* xl, const double* xu) {
+// Host-side integer preparation (a1): transpose structure by a stable counting sort on the
+// column index (perm maps each entry of A^T to its entry of A so the values are moved on
+// the device), row tiles, panel layouts and the reduction grid.
+int32_t host_prep(lp_handle* h, const int32_t* rp, const int32_t* ci) {
     const int32_t m = h->m, n = h->n;
     const int64_t nnz = h->nnz;
     const lp_options& o = h->opt;
-    HIP_TRY(h, hipSetDevice(h->device));
-    if (o.hip_stream) {
-        h->stream = static_cast<hipStream_t>(o.hip_stream);
-    } else {
-        HIP_TRY(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-        h->own_stream = true;
-    }
-    // a1: transpose structure by a stable counting sort on the column index (integer work);
-    // perm maps each entry of A^T to its entry of A so the values are moved on the device.
-    std::vector<int32_t> rpT(static_cast<size_t>(n) + 1, 0), ciT(static_cast<size_t>(nnz)),
-        perm(static_cast<size_t>(nnz));
-    for (int64_t e = 0; e < nnz; ++e) rpT[ci[e] + 1]++;
-    for (int32_t j = 0; j < n; ++j) rpT[j + 1] += rpT[j];
+    Prep& Q = h->prep;
+    Q.rpT.assign(static_cast<size_t>(n) + 1, 0);
+    Q.ciT.resize(static_cast<size_t>(nnz));
+    Q.perm.resize(static_cast<size_t>(nnz));
+    for (int64_t e = 0; e < nnz; ++e) Q.rpT[ci[e] + 1]++;
+    for (int32_t j = 0; j < n; ++j) Q.rpT[j + 1] += Q.rpT[j];
     {
-        std::vector<int32_t> next(rpT.begin(), rpT.end() - 1);
+        std::vector<int32_t> next(Q.rpT.begin(), Q.rpT.end() - 1);
         for (int32_t i = 0; i < m; ++i)
             for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
                 const int32_t p = next[ci[e]]++;
-                ciT[p] = i;
-                perm[p] = e;
+                Q.ciT[p] = i;
+                Q.perm[p] = e;
             }
     }
     int64_t dummy_long = 0;
-    std::vector<int32_t> tA = build_tiles(m, rp, &dummy_long);
-    std::vector<int32_t> tAT = build_tiles(n, rpT.data(), &dummy_long);
-    const int32_t ntA = static_cast<int32_t>(tA.size()) - 1, ntAT = static_cast<int32_t>(tAT.size()) - 1;
-    // panel-packed layouts of A (gathers x) and A^T (gathers y)
+    Q.tA = build_tiles(m, rp, &dummy_long);
+    Q.tAT = build_tiles(n, Q.rpT.data(), &dummy_long);
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
     const int target_units = cus * (o.units_per_cu > 0 ? o.units_per_cu : 8);
     const int64_t slice = o.panel_slice_bytes > 0 ? o.panel_slice_bytes : (int64_t(1) << 20);
     const int long_len = o.long_row_len > 0 ? o.long_row_len : 256;
-    const bool panels = o.spmv_layout == 0;
-    PanelLayoutHost LA, LAT;
-    if (panels) {
-        LA = build_panel_layout(m, n, rp, ci, nullptr, choose_panels(n, slice), long_len, target_units, kUnitRowCap);
-        LAT = build_panel_layout(n, m, rpT.data(), ciT.data(), perm.data(), choose_panels(m, slice), long_len,
-                                 target_units, kUnitRowCap);
-        h->long_a = static_cast<int64_t>(LA.long_rows.size());
-        h->long_at = static_cast<int64_t>(LAT.long_rows.size());
-        h->units_a = LA.units;
-        h->units_at = LAT.units;
-        h->panels_a = LA.panels;
-        h->panels_at = LAT.panels;
+    Q.panels = o.spmv_layout == 0;
+    if (Q.panels) {
+        Q.LA = build_panel_layout(m, n, rp, ci, nullptr, choose_panels(n, slice), long_len, target_units, kUnitRowCap);
+        Q.LAT = build_panel_layout(n, m, Q.rpT.data(), Q.ciT.data(), Q.perm.data(), choose_panels(m, slice), long_len,
+                                   target_units, kUnitRowCap);
+        h->long_a = static_cast<int64_t>(Q.LA.long_rows.size());
+        h->long_at = static_cast<int64_t>(Q.LAT.long_rows.size());
+        h->units_a = Q.LA.units;
+        h->units_at = Q.LAT.units;
+        h->panels_a = Q.LA.panels;
+        h->panels_at = Q.LAT.panels;
     }
+    const int mx = m > n ? m : n;
+    Q.nred = (mx + 1023) / 1024;
+    if (Q.nred < 1) Q.nred = 1;
+    if (Q.nred > kMaxRedBlocks) Q.nred = kMaxRedBlocks;
+    Q.ready = true;
+    return LP_OK;
+}
 
-    int mx = m > n ? m : n;
-    int nred = (mx + 1023) / 1024;
-    if (nred < 1) nred = 1;
-    if (nred > kMaxRedBlocks) nred = kMaxRedBlocks;
-
+// Device layout of one handle: every array at a 256-byte aligned offset of one allocation.
+size_t arena_layout(const lp_handle* h, Offsets* O) {
+    const int32_t m = h->m, n = h->n;
+    const int64_t nnz = h->nnz;
+    const lp_options& o = h->opt;
+    const Prep& Q = h->prep;
     const size_t sm = sizeof(double) * static_cast<size_t>(m), sn = sizeof(double) * static_cast<size_t>(n);
     const size_t si_nnz = sizeof(int32_t) * static_cast<size_t>(nnz), sd_nnz = sizeof(double) * static_cast<size_t>(nnz);
     Arena L;
-    const size_t o_arp = L.add(sizeof(int32_t) * (m + 1)), o_aci = L.add(si_nnz), o_av = L.add(sd_nnz),
-                 o_at = L.add(sizeof(int32_t) * tA.size());
-    const size_t o_trp = L.add(sizeof(int32_t) * (n + 1)), o_tci = L.add(si_nnz), o_tv = L.add(sd_nnz),
-                 o_tt = L.add(sizeof(int32_t) * tAT.size()), o_perm = L.add(si_nnz);
-    const size_t o_c = L.add(sn), o_xl = L.add(sn), o_xu = L.add(sn), o_C = L.add(sn), o_Ci = L.add(sn);
-    const size_t o_bl = L.add(sm), o_bu = L.add(sm), o_R = L.add(sm), o_Ri = L.add(sm);
-    const size_t o_x = L.add(sn), o_xa = L.add(sn), o_xan = L.add(sn), o_aty = L.add(sn), o_atya = L.add(sn),
-                 o_ox = L.add(sn), o_oz = L.add(sn);
-    const size_t o_y = L.add(sm), o_ya = L.add(sm), o_yan = L.add(sm), o_ax = L.add(sm), o_axa = L.add(sm),
-                 o_oy = L.add(sm);
-    const size_t o_x0 = o.x0 ? L.add(sn) : 0, o_y0 = o.y0 ? L.add(sm) : 0;
+    O->arp = L.add(sizeof(int32_t) * (m + 1));
+    O->aci = L.add(si_nnz);
+    O->av = L.add(sd_nnz);
+    O->at = L.add(sizeof(int32_t) * Q.tA.size());
+    O->trp = L.add(sizeof(int32_t) * (n + 1));
+    O->tci = L.add(si_nnz);
+    O->tv = L.add(sd_nnz);
+    O->tt = L.add(sizeof(int32_t) * Q.tAT.size());
+    O->perm = L.add(si_nnz);
+    O->c = L.add(sn);
+    O->xl = L.add(sn);
+    O->xu = L.add(sn);
+    O->C = L.add(sn);
+    O->Ci = L.add(sn);
+    O->bl = L.add(sm);
+    O->bu = L.add(sm);
+    O->R = L.add(sm);
+    O->Ri = L.add(sm);
+    O->x = L.add(sn);
+    O->xa = L.add(sn);
+    O->xan = L.add(sn);
+    O->aty = L.add(sn);
+    O->atya = L.add(sn);
+    O->ox = L.add(sn);
+    O->oz = L.add(sn);
+    O->y = L.add(sm);
+    O->ya = L.add(sm);
+    O->yan = L.add(sm);
+    O->ax = L.add(sm);
+    O->axa = L.add(sm);
+    O->oy = L.add(sm);
+    O->x0 = h->has_x0 ? L.add(sn) : 0;
+    O->y0 = h->has_y0 ? L.add(sm) : 0;
     const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
     const size_t fn = sizeof(float) * static_cast<size_t>(n), fm = sizeof(float) * static_cast<size_t>(m);
-    size_t o32[16] = {0};
     if (fp32) {
-        o32[0] = L.add(fn);   // dx
-        o32[1] = L.add(fn);   // dxa
-        o32[2] = L.add(fm);   // dy
-        o32[3] = L.add(fm);   // dya
-        o32[4] = L.add(fm);   // adx
-        o32[5] = L.add(fn);   // d32
-        o32[6] = L.add(fn);   // lo32
-        o32[7] = L.add(fn);   // hi32
-        o32[8] = L.add(fm);   // rl32
-        o32[9] = L.add(fm);   // ru32
-        o32[10] = L.add(fm);  // yh32
-        o32[11] = L.add(sn);  // xh
-        o32[12] = L.add(sm);  // yh
-        o32[13] = L.add(sizeof(float) * static_cast<size_t>(nnz));  // A values
-        o32[14] = L.add(sizeof(float) * static_cast<size_t>(nnz));  // A^T values
+        const size_t sz[15] = {fn, fn, fm, fm, fm, fn, fn, fn, fm, fm, fm, sn, sm,
+                               sizeof(float) * static_cast<size_t>(nnz), sizeof(float) * static_cast<size_t>(nnz)};
+        for (int i = 0; i < 15; ++i) O->f32[i] = L.add(sz[i]);
     }
-    auto add_layout = [&](const PanelLayoutHost& Q, size_t* off) {
-        off[0] = L.add(sizeof(int32_t) * Q.unit_row.size());
-        off[1] = L.add(sizeof(int32_t) * Q.unit_seg.size());
-        off[2] = L.add(sizeof(uint32_t) * Q.packed.size());
-        off[3] = L.add(sizeof(double) * Q.packed.size());
-        off[4] = L.add(sizeof(int32_t) * Q.src.size());
-        off[5] = L.add(sizeof(int32_t) * Q.long_rows.size());
-        off[6] = L.add(Q.is_long.size());
+    auto add_layout = [&](const PanelLayoutHost& P, size_t* off) {
+        off[0] = L.add(sizeof(int32_t) * P.unit_row.size());
+        off[1] = L.add(sizeof(int32_t) * P.unit_seg.size());
+        off[2] = L.add(sizeof(uint32_t) * P.packed.size());
+        off[3] = L.add(sizeof(double) * P.packed.size());
+        off[4] = L.add(sizeof(int32_t) * P.src.size());
+        off[5] = L.add(sizeof(int32_t) * P.long_rows.size());
+        off[6] = L.add(P.is_long.size());
     };
-    size_t offA[7] = {0}, offAT[7] = {0}, offA32 = 0, offAT32 = 0;
-    if (panels) {
-        add_layout(LA, offA);
-        add_layout(LAT, offAT);
+    if (Q.panels) {
+        add_layout(Q.LA, O->pA);
+        add_layout(Q.LAT, O->pAT);
         if (fp32) {
-            offA32 = L.add(sizeof(float) * LA.packed.size());
-            offAT32 = L.add(sizeof(float) * LAT.packed.size());
+            O->pA32 = L.add(sizeof(float) * Q.LA.packed.size());
+            O->pAT32 = L.add(sizeof(float) * Q.LAT.packed.size());
         }
     }
-    const size_t o_part = L.add(sizeof(double) * 2 * kNQ * kMaxRedBlocks), o_sc = L.add(sizeof(Scalars)),
-                 o_tr = L.add(sizeof(double) * kTraceW * static_cast<size_t>(o.trace_cap > 0 ? o.trace_cap : 1));
-    h->arena_bytes = L.off;
+    O->part = L.add(sizeof(double) * 2 * kNQ * kMaxRedBlocks);
+    O->sc = L.add(sizeof(Scalars));
+    O->tr = L.add(sizeof(double) * kTraceW * static_cast<size_t>(o.trace_cap > 0 ? o.trace_cap : 1));
+    return L.off;
+}
+
+// Device part (a2, a3): allocate, bind, upload, scale, permute values, estimate ||A~||_2 and
+// the step size. Runs on the handle's stream and waits.
+int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* v, const double* c,
+                     const double* bl, const double* bu, const double* xl, const double* xu, const double* x0,
+                     const double* y0) {
+    const int32_t m = h->m, n = h->n;
+    const int64_t nnz = h->nnz;
+    const lp_options& o = h->opt;
+    const Prep& Q = h->prep;
+    HIP_TRY(h, hipSetDevice(h->device));
+    if (!h->stream) {
+        if (o.hip_stream) {
+            h->stream = static_cast<hipStream_t>(o.hip_stream);
+        } else {
+            HIP_TRY(h, hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            h->own_stream = true;
+        }
+    }
+    Offsets O;
+    h->arena_bytes = arena_layout(h, &O);
     HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&h->arena), h->arena_bytes));
-    HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->h_sc), sizeof(Scalars), hipHostMallocDefault));
-    std::memset(h->h_sc, 0, sizeof(Scalars));
+    if (!h->h_sc) {
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->h_sc), sizeof(Scalars), hipHostMallocDefault));
+        std::memset(h->h_sc, 0, sizeof(Scalars));
+    }
     char* b = h->arena;
     auto D = [&](size_t off) { return reinterpret_cast<double*>(b + off); };
     auto I = [&](size_t off) { return reinterpret_cast<int32_t*>(b + off); };
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(b + off); };
+    const int32_t ntA = static_cast<int32_t>(Q.tA.size()) - 1, ntAT = static_cast<int32_t>(Q.tAT.size()) - 1;
+    const bool panels = Q.panels;
+    const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
 
     DevLP& P = h->P;
+    P = DevLP{};
     P.m = m;
     P.n = n;
     P.nnz = nnz;
-    P.nred = nred;
-    P.A = Mat{};
-    P.AT = Mat{};
-    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), I(o_arp), I(o_aci), D(o_av), I(o_at), nullptr};
-    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), I(o_trp), I(o_tci), D(o_tv), I(o_tt), nullptr};
+    P.nred = Q.nred;
+    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), I(O.arp), I(O.aci), D(O.av), I(O.at), nullptr, nullptr};
+    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), I(O.trp), I(O.tci), D(O.tv), I(O.tt), nullptr, nullptr};
     P.A.layout = P.AT.layout = panels ? 0 : 1;
-    auto bind_layout = [&](const PanelLayoutHost& Q, const size_t* off, Mat& M) {
-        M.pan = Panels{Q.units, Q.panels, Q.col_bits, static_cast<int>(Q.nnz_packed), I(off[0]), I(off[1]),
+    auto bind_layout = [&](const PanelLayoutHost& L, const size_t* off, Mat& M) {
+        M.pan = Panels{L.units, L.panels, L.col_bits, static_cast<int>(L.nnz_packed), I(off[0]), I(off[1]),
                        reinterpret_cast<const unsigned*>(b + off[2]), D(off[3]),
-                       Q.is_long.empty() ? nullptr : reinterpret_cast<const unsigned char*>(b + off[6])};
-        M.nlong = static_cast<int>(Q.long_rows.size());
+                       L.is_long.empty() ? nullptr : reinterpret_cast<const unsigned char*>(b + off[6]), nullptr};
+        M.nlong = static_cast<int>(L.long_rows.size());
         M.longrows = M.nlong ? I(off[5]) : nullptr;
     };
     if (panels) {
-        bind_layout(LA, offA, P.A);
-        bind_layout(LAT, offAT, P.AT);
+        bind_layout(Q.LA, O.pA, P.A);
+        bind_layout(Q.LAT, O.pAT, P.AT);
     }
-    auto F = [&](size_t off) { return reinterpret_cast<float*>(b + off); };
     P.fp32 = fp32 ? 1 : 0;
     if (fp32) {
-        P.dx = F(o32[0]);
-        P.dxa = F(o32[1]);
-        P.dy = F(o32[2]);
-        P.dya = F(o32[3]);
-        P.adx = F(o32[4]);
-        P.d32 = F(o32[5]);
-        P.lo32 = F(o32[6]);
-        P.hi32 = F(o32[7]);
-        P.rl32 = F(o32[8]);
-        P.ru32 = F(o32[9]);
-        P.yh32 = F(o32[10]);
-        P.xh = D(o32[11]);
-        P.yh = D(o32[12]);
-        P.A.csr.v32 = F(o32[13]);
-        P.AT.csr.v32 = F(o32[14]);
+        P.dx = F(O.f32[0]);
+        P.dxa = F(O.f32[1]);
+        P.dy = F(O.f32[2]);
+        P.dya = F(O.f32[3]);
+        P.adx = F(O.f32[4]);
+        P.d32 = F(O.f32[5]);
+        P.lo32 = F(O.f32[6]);
+        P.hi32 = F(O.f32[7]);
+        P.rl32 = F(O.f32[8]);
+        P.ru32 = F(O.f32[9]);
+        P.yh32 = F(O.f32[10]);
+        P.xh = D(O.f32[11]);
+        P.yh = D(O.f32[12]);
+        P.A.csr.v32 = F(O.f32[13]);
+        P.AT.csr.v32 = F(O.f32[14]);
         if (panels) {
-            P.A.pan.v32 = F(offA32);
-            P.AT.pan.v32 = F(offAT32);
+            P.A.pan.v32 = F(O.pA32);
+            P.AT.pan.v32 = F(O.pAT32);
         }
     }
-    P.c = D(o_c);
-    P.xl = D(o_xl);
-    P.xu = D(o_xu);
-    P.C = D(o_C);
-    P.Ci = D(o_Ci);
-    P.bl = D(o_bl);
-    P.bu = D(o_bu);
-    P.R = D(o_R);
-    P.Ri = D(o_Ri);
-    P.x = D(o_x);
-    P.xa = D(o_xa);
-    P.xan = D(o_xan);
-    P.aty = D(o_aty);
-    P.atya = D(o_atya);
-    P.out_x = D(o_ox);
-    P.out_z = D(o_oz);
-    P.y = D(o_y);
-    P.ya = D(o_ya);
-    P.yan = D(o_yan);
-    P.ax = D(o_ax);
-    P.axa = D(o_axa);
-    P.out_y = D(o_oy);
-    P.partials = D(o_part);
-    P.sc = reinterpret_cast<Scalars*>(b + o_sc);
-    P.trace = o.trace_cap > 0 ? D(o_tr) : nullptr;
-    h->d_perm = I(o_perm);
-    h->d_x0 = o.x0 ? D(o_x0) : nullptr;
-    h->d_y0 = o.y0 ? D(o_y0) : nullptr;
+    P.c = D(O.c);
+    P.xl = D(O.xl);
+    P.xu = D(O.xu);
+    P.C = D(O.C);
+    P.Ci = D(O.Ci);
+    P.bl = D(O.bl);
+    P.bu = D(O.bu);
+    P.R = D(O.R);
+    P.Ri = D(O.Ri);
+    P.x = D(O.x);
+    P.xa = D(O.xa);
+    P.xan = D(O.xan);
+    P.aty = D(O.aty);
+    P.atya = D(O.atya);
+    P.out_x = D(O.ox);
+    P.out_z = D(O.oz);
+    P.y = D(O.y);
+    P.ya = D(O.ya);
+    P.yan = D(O.yan);
+    P.ax = D(O.ax);
+    P.axa = D(O.axa);
+    P.out_y = D(O.oy);
+    P.partials = D(O.part);
+    P.sc = reinterpret_cast<Scalars*>(b + O.sc);
+    P.trace = o.trace_cap > 0 ? D(O.tr) : nullptr;
+    h->d_perm = I(O.perm);
+    h->d_x0 = h->has_x0 ? D(O.x0) : nullptr;
+    h->d_y0 = h->has_y0 ? D(O.y0) : nullptr;
 
     hipStream_t s = h->stream;
+    const size_t sm = sizeof(double) * static_cast<size_t>(m), sn = sizeof(double) * static_cast<size_t>(n);
+    const size_t si_nnz = sizeof(int32_t) * static_cast<size_t>(nnz), sd_nnz = sizeof(double) * static_cast<size_t>(nnz);
     auto H2D = [&](void* dst, const void* src, size_t bytes) {
         return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
     };
-    HIP_TRY(h, H2D(I(o_arp), rp, sizeof(int32_t) * (m + 1)));
-    HIP_TRY(h, H2D(I(o_aci), ci, si_nnz));
-    HIP_TRY(h, H2D(D(o_av), v, sd_nnz));
-    HIP_TRY(h, H2D(I(o_at), tA.data(), sizeof(int32_t) * tA.size()));
-    HIP_TRY(h, H2D(I(o_trp), rpT.data(), sizeof(int32_t) * (n + 1)));
-    HIP_TRY(h, H2D(I(o_tci), ciT.data(), si_nnz));
-    HIP_TRY(h, H2D(I(o_tt), tAT.data(), sizeof(int32_t) * tAT.size()));
-    HIP_TRY(h, H2D(I(o_perm), perm.data(), si_nnz));
-    HIP_TRY(h, H2D(D(o_c), c, sn));
-    HIP_TRY(h, H2D(D(o_xl), xl, sn));
-    HIP_TRY(h, H2D(D(o_xu), xu, sn));
+    HIP_TRY(h, H2D(I(O.arp), rp, sizeof(int32_t) * (m + 1)));
+    HIP_TRY(h, H2D(I(O.aci), ci, si_nnz));
+    HIP_TRY(h, H2D(D(O.av), v, sd_nnz));
+    HIP_TRY(h, H2D(I(O.at), Q.tA.data(), sizeof(int32_t) * Q.tA.size()));
+    HIP_TRY(h, H2D(I(O.trp), Q.rpT.data(), sizeof(int32_t) * (n + 1)));
+    HIP_TRY(h, H2D(I(O.tci), Q.ciT.data(), si_nnz));
+    HIP_TRY(h, H2D(I(O.tt), Q.tAT.data(), sizeof(int32_t) * Q.tAT.size()));
+    HIP_TRY(h, H2D(I(O.perm), Q.perm.data(), si_nnz));
+    HIP_TRY(h, H2D(D(O.c), c, sn));
+    HIP_TRY(h, H2D(D(O.xl), xl, sn));
+    HIP_TRY(h, H2D(D(O.xu), xu, sn));
     if (m > 0) {
-        HIP_TRY(h, H2D(D(o_bl), bl, sm));
-        HIP_TRY(h, H2D(D(o_bu), bu, sm));
+        HIP_TRY(h, H2D(D(O.bl), bl, sm));
+        HIP_TRY(h, H2D(D(O.bu), bu, sm));
     }
-    auto upload_layout = [&](const PanelLayoutHost& Q, const size_t* off) -> hipError_t {
-        hipError_t e = H2D(b + off[0], Q.unit_row.data(), sizeof(int32_t) * Q.unit_row.size());
-        if (e == hipSuccess) e = H2D(b + off[1], Q.unit_seg.data(), sizeof(int32_t) * Q.unit_seg.size());
-        if (e == hipSuccess) e = H2D(b + off[2], Q.packed.data(), sizeof(uint32_t) * Q.packed.size());
-        if (e == hipSuccess) e = H2D(b + off[4], Q.src.data(), sizeof(int32_t) * Q.src.size());
-        if (e == hipSuccess) e = H2D(b + off[5], Q.long_rows.data(), sizeof(int32_t) * Q.long_rows.size());
-        if (e == hipSuccess) e = H2D(b + off[6], Q.is_long.data(), Q.is_long.size());
+    auto upload_layout = [&](const PanelLayoutHost& L, const size_t* off) -> hipError_t {
+        hipError_t e = H2D(b + off[0], L.unit_row.data(), sizeof(int32_t) * L.unit_row.size());
+        if (e == hipSuccess) e = H2D(b + off[1], L.unit_seg.data(), sizeof(int32_t) * L.unit_seg.size());
+        if (e == hipSuccess) e = H2D(b + off[2], L.packed.data(), sizeof(uint32_t) * L.packed.size());
+        if (e == hipSuccess) e = H2D(b + off[4], L.src.data(), sizeof(int32_t) * L.src.size());
+        if (e == hipSuccess) e = H2D(b + off[5], L.long_rows.data(), sizeof(int32_t) * L.long_rows.size());
+        if (e == hipSuccess) e = H2D(b + off[6], L.is_long.data(), L.is_long.size());
         return e;
     };
     if (panels) {
-        HIP_TRY(h, upload_layout(LA, offA));
-        HIP_TRY(h, upload_layout(LAT, offAT));
+        HIP_TRY(h, upload_layout(Q.LA, O.pA));
+        HIP_TRY(h, upload_layout(Q.LAT, O.pAT));
     }
-    if (o.x0) HIP_TRY(h, H2D(h->d_x0, o.x0, sn));
-    if (o.y0 && m > 0) HIP_TRY(h, H2D(h->d_y0, o.y0, sm));
+    if (h->has_x0) HIP_TRY(h, H2D(h->d_x0, x0, sn));
+    if (h->has_y0 && m > 0) HIP_TRY(h, H2D(h->d_y0, y0, sm));
     HIP_TRY(h, hipMemsetAsync(P.sc, 0, sizeof(Scalars), s));
 
     // a2: scaling, exact powers of two
-    launch_fill(D(o_R), m, 1.0, s);
-    launch_fill(D(o_C), n, 1.0, s);
+    launch_fill(D(O.R), m, 1.0, s);
+    launch_fill(D(O.C), n, 1.0, s);
     if (o.scaling) {
         for (int pass = 0; pass <= o.ruiz_passes; ++pass)
-            launch_scale_pass(P, I(o_arp), I(o_aci), D(o_av), I(o_trp), h->d_perm, D(o_R), D(o_C), D(o_ax),
-                              D(o_aty), pass == o.ruiz_passes ? 1 : 0, s);
+            launch_scale_pass(P, I(O.arp), I(O.aci), D(O.av), I(O.trp), h->d_perm, D(O.R), D(O.C), D(O.ax),
+                              D(O.aty), pass == o.ruiz_passes ? 1 : 0, s);
     }
-    launch_gather(h->d_perm, D(o_av), D(o_tv), nnz, s);
+    launch_gather(h->d_perm, D(O.av), D(O.tv), nnz, s);
     if (panels) {  // panel values in packed order, from the scaled A
-        launch_gather(I(offA[4]), D(o_av), D(offA[3]), LA.nnz_packed, s);
-        launch_gather(I(offAT[4]), D(o_av), D(offAT[3]), LAT.nnz_packed, s);
+        launch_gather(I(O.pA[4]), D(O.av), D(O.pA[3]), Q.LA.nnz_packed, s);
+        launch_gather(I(O.pAT[4]), D(O.av), D(O.pAT[3]), Q.LAT.nnz_packed, s);
     }
     if (fp32) {  // FP32 copies of the scaled values (rounded to nearest)
-        launch_to_float(D(o_av), F(o32[13]), nnz, s);
-        launch_to_float(D(o_tv), F(o32[14]), nnz, s);
+        launch_to_float(D(O.av), F(O.f32[13]), nnz, s);
+        launch_to_float(D(O.tv), F(O.f32[14]), nnz, s);
         if (panels) {
-            launch_to_float(D(offA[3]), F(offA32), LA.nnz_packed, s);
-            launch_to_float(D(offAT[3]), F(offAT32), LAT.nnz_packed, s);
+            launch_to_float(D(O.pA[3]), F(O.pA32), Q.LA.nnz_packed, s);
+            launch_to_float(D(O.pAT[3]), F(O.pAT32), Q.LAT.nnz_packed, s);
         }
     }
-    launch_prepare(P, D(o_c), D(o_bl), D(o_bu), D(o_xl), D(o_xu), D(o_R), D(o_C), D(o_Ri), D(o_Ci), h->d_x0,
+    launch_prepare(P, D(O.c), D(O.bl), D(O.bu), D(O.xl), D(O.xu), D(O.R), D(O.C), D(O.Ri), D(O.Ci), h->d_x0,
                    h->d_y0, s);
     // a3: ||A~||_2 by power iteration (x, A~x and A~^T y buffers are free at this point)
     if (!(o.step_size > 0.0)) launch_power_norm(P, o.pow_iters, o.seed, P.x, P.ax, P.aty, s);
@@ -697,10 +803,377 @@ int32_t setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* 
     if (int32_t rc = check_launch(h, "setup kernels")) return rc;
     HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
+    if (!h->ev[0])
+        for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
+    h->on_device = true;
     return LP_OK;
 }
 
+// Device memory of a deferred handle: allocate and set up from the kept host data.
+int32_t materialize(lp_handle* h) {
+    if (h->on_device) return LP_OK;
+    if (!h->deferred) return fail(h, LP_ERR_INTERNAL, "handle has no device data and no host copy");
+    const HostData& R = h->raw;
+    return device_setup(h, R.rp.data(), R.ci.data(), R.v.data(), R.c.data(), R.bl.data(), R.bu.data(), R.xl.data(),
+                        R.xu.data(), R.x0.data(), R.y0.data());
+}
+
+
+// ------------------------------------------------------------------ serving form
+
+// Device jobs table and block maps of a set of LPs (grown as needed, reused across rounds;
+// every round ends with a stream synchronisation before the next rebuild).
+struct DevMaps {
+    char* buf = nullptr;
+    size_t cap = 0;
+    int* hstatus = nullptr;  // pinned
+    int hcap = 0;
+    MultiMaps M{};
+    int E = 64;
+
+    int32_t build(const std::vector<lp_handle*>& hs, const lp_options* o, hipStream_t s, lp_handle* err_to) {
+        const int count = static_cast<int>(hs.size());
+        std::vector<BatchJob> jobs(static_cast<size_t>(count));
+        std::vector<int2> ma, mat, mred, melem;
+        for (int i = 0; i < count; ++i) {
+            lp_handle* h = hs[i];
+            jobs[i] = make_job(h, o);
+            for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
+            for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
+            for (int b = 0; b < h->P.nred; ++b) mred.push_back(make_int2(i, b));
+            const int mx = h->m > h->n ? h->m : h->n;
+            for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
+        }
+        E = o->eval_every;
+        Arena L;
+        const size_t oj = L.add(sizeof(BatchJob) * jobs.size()), oa = L.add(sizeof(int2) * ma.size()),
+                     oat = L.add(sizeof(int2) * mat.size()), ored = L.add(sizeof(int2) * mred.size()),
+                     oel = L.add(sizeof(int2) * melem.size()), ost = L.add(sizeof(int) * (count + 1));
+        if (L.off > cap) {
+            if (buf) (void)hipFree(buf);
+            buf = nullptr;
+            cap = 0;
+            const size_t want = L.off * 2;
+            HIP_TRY(err_to, hipMalloc(reinterpret_cast<void**>(&buf), want));
+            cap = want;
+        }
+        if (count + 1 > hcap) {
+            if (hstatus) (void)hipHostFree(hstatus);
+            hstatus = nullptr;
+            hcap = 0;
+            HIP_TRY(err_to, hipHostMalloc(reinterpret_cast<void**>(&hstatus), sizeof(int) * (count + 1) * 2,
+                                          hipHostMallocDefault));
+            hcap = (count + 1) * 2;
+        }
+        M = MultiMaps{};
+        M.jobs = reinterpret_cast<const BatchJob*>(buf + oj);
+        M.count = count;
+        M.map_a = reinterpret_cast<const int2*>(buf + oa);
+        M.n_a = static_cast<int>(ma.size());
+        M.map_at = reinterpret_cast<const int2*>(buf + oat);
+        M.n_at = static_cast<int>(mat.size());
+        M.map_red = reinterpret_cast<const int2*>(buf + ored);
+        M.n_red = static_cast<int>(mred.size());
+        M.map_elem = reinterpret_cast<const int2*>(buf + oel);
+        M.n_elem = static_cast<int>(melem.size());
+        M.active = reinterpret_cast<int*>(buf + ost);
+        auto H2D = [&](size_t off, const void* src, size_t bytes) {
+            return bytes ? hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+        };
+        HIP_TRY(err_to, H2D(oj, jobs.data(), sizeof(BatchJob) * jobs.size()));
+        HIP_TRY(err_to, H2D(oa, ma.data(), sizeof(int2) * ma.size()));
+        HIP_TRY(err_to, H2D(oat, mat.data(), sizeof(int2) * mat.size()));
+        HIP_TRY(err_to, H2D(ored, mred.data(), sizeof(int2) * mred.size()));
+        HIP_TRY(err_to, H2D(oel, melem.data(), sizeof(int2) * melem.size()));
+        return LP_OK;
+    }
+
+    void free_all() {
+        if (buf) (void)hipFree(buf);
+        if (hstatus) (void)hipHostFree(hstatus);
+        buf = nullptr;
+        hstatus = nullptr;
+        cap = 0;
+        hcap = 0;
+    }
+};
+
+struct Ticket {
+    uint64_t id;
+    lp_handle* h;
+    double t_submit, t_admit, t_done;
+};
+
+}  // namespace
+
+struct lp_server {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t budget = 0;
+    int max_slots = 1;
+    lp_options opt{};
+    std::chrono::steady_clock::time_point t0;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_idle;
+    std::deque<Ticket> queue;
+    std::vector<Ticket> running;
+    std::vector<uint64_t> done;
+    std::unordered_map<uint64_t, Ticket> finished;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    lp_server_stats st{};
+    lp_handle err_sink;  // receives error messages of the worker
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirty) {
+    hipStream_t s = S->stream;
+    // admission: arrival order, while a slot is free and the footprint fits the budget
+    std::vector<Ticket> newly;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        while (!S->queue.empty() && static_cast<int>(S->running.size() + newly.size()) < S->max_slots) {
+            Ticket& t = S->queue.front();
+            const int64_t fp = static_cast<int64_t>(t.h->arena_bytes);
+            if (S->st.bytes_in_use + fp > S->budget) break;
+            S->st.bytes_in_use += fp;
+            if (S->st.bytes_in_use > S->st.peak_bytes) S->st.peak_bytes = S->st.bytes_in_use;
+            t.t_admit = S->now();
+            newly.push_back(t);
+            S->queue.pop_front();
+            S->st.admitted++;
+            S->st.queued--;
+        }
+    }
+    std::vector<Ticket> failed;
+    std::vector<Ticket> ok;
+    for (Ticket& t : newly) {
+        t.h->stream = S->stream;
+        t.h->own_stream = false;
+        if (materialize(t.h) == LP_OK) ok.push_back(t);
+        else failed.push_back(t);
+    }
+    if (!ok.empty()) {
+        std::vector<lp_handle*> hs;
+        for (Ticket& t : ok) hs.push_back(t.h);
+        if (new_maps.build(hs, &S->opt, s, &S->err_sink) == LP_OK) {
+            const MultiMaps& M = new_maps.M;
+            launch_multi(M, MULTI_RESET, 0, s);
+            launch_multi(M, MULTI_INIT, 0, s);
+            launch_multi(M, MULTI_AX_ALL, 0, s);
+            launch_multi(M, MULTI_ATY, 0, s);
+            launch_multi(M, MULTI_PARTIALS, 1, s);
+            launch_multi(M, MULTI_DECIDE, 1, s);
+            launch_multi(M, MULTI_REBASE_INIT, 0, s);
+            (void)hipStreamSynchronize(s);
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (Ticket& t : ok) S->running.push_back(t);
+            S->st.running = static_cast<int64_t>(S->running.size());
+            dirty = true;
+        } else {
+            for (Ticket& t : ok) failed.push_back(t);
+        }
+    }
+    std::vector<Ticket> finished = failed;
+    if (!S->running.empty()) {
+        if (dirty) {
+            std::vector<lp_handle*> hs;
+            for (Ticket& t : S->running) hs.push_back(t.h);
+            if (run_maps.build(hs, &S->opt, s, &S->err_sink) != LP_OK) return;
+            dirty = false;
+        }
+        const MultiMaps& M = run_maps.M;
+        for (int it = 0; it < run_maps.E; ++it) {
+            launch_multi(M, MULTI_PRIMAL, it, s);
+            launch_multi(M, MULTI_DUAL, it, s);
+        }
+        launch_multi(M, MULTI_MATERIALIZE, 0, s);
+        launch_multi(M, MULTI_AX_FP32, 0, s);
+        launch_multi(M, MULTI_ATY, 0, s);
+        launch_multi(M, MULTI_AXA, 0, s);
+        launch_multi(M, MULTI_ATYA, 0, s);
+        launch_multi(M, MULTI_PARTIALS, 0, s);
+        launch_multi(M, MULTI_DECIDE, 0, s);
+        launch_multi(M, MULTI_APPLY, 0, s);
+        launch_multi(M, MULTI_STATUS, 0, s);
+        (void)hipMemcpyAsync(run_maps.hstatus, M.active, sizeof(int) * M.count, hipMemcpyDeviceToHost, s);
+        (void)hipStreamSynchronize(s);
+        S->st.rounds++;
+        std::vector<Ticket> still;
+        for (int i = 0; i < M.count; ++i) {
+            Ticket& t = S->running[i];
+            if (run_maps.hstatus[i] == kRunning) {
+                still.push_back(t);
+                continue;
+            }
+            launch_extract(t.h->P, s);
+            (void)hipMemcpyAsync(t.h->h_sc, t.h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s);
+            finished.push_back(t);
+        }
+        if (finished.size() > failed.size()) {
+            (void)hipStreamSynchronize(s);
+            for (size_t k = failed.size(); k < finished.size(); ++k) {
+                lp_handle* h = finished[k].h;
+                fill_info(h);
+                h->solved = true;
+            }
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->running = still;
+            S->st.running = static_cast<int64_t>(S->running.size());
+            dirty = true;
+        }
+    }
+    if (!finished.empty()) {
+        for (Ticket& t : finished) {
+            const int64_t fp = static_cast<int64_t>(t.h->arena_bytes);
+            (void)release_device(t.h);
+            t.t_done = S->now();
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->st.bytes_in_use -= fp;
+            S->st.completed++;
+            S->done.push_back(t.id);
+            S->finished[t.id] = t;
+        }
+        S->cv_idle.notify_all();
+    }
+}
+
+void server_loop(lp_server* S) {
+    (void)hipSetDevice(S->device);
+    DevMaps run_maps, new_maps;
+    bool dirty = true;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop) break;
+            if (S->queue.empty() && S->running.empty()) {
+                S->cv_idle.notify_all();
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+                continue;
+            }
+        }
+        server_round(S, run_maps, new_maps, dirty);
+    }
+    run_maps.free_all();
+    new_maps.free_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lp_server_create(lp_server** out, int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
+                         const lp_options* opt) {
+    if (!out || hbm_budget_bytes <= 0 || max_slots < 1) return fail(nullptr, LP_ERR_INVALID_ARG, "bad server arguments");
+    *out = nullptr;
+    try {
+        lp_options o;
+        lp_default_options(&o);
+        if (opt) o = *opt;
+        std::string msg;
+        if (int32_t rc = validate_options(o, &msg)) return fail(nullptr, rc, msg);
+        lp_server* S = new (std::nothrow) lp_server();
+        if (!S) return fail(nullptr, LP_ERR_OUT_OF_MEMORY, "host allocation failed");
+        S->device = device;
+        S->budget = hbm_budget_bytes;
+        S->max_slots = max_slots;
+        S->opt = o;
+        S->t0 = std::chrono::steady_clock::now();
+        S->st.hbm_budget = hbm_budget_bytes;
+        hipError_t e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete S;
+            return fail(nullptr, LP_ERR_DEVICE, std::string("server stream: ") + hipGetErrorString(e));
+        }
+        S->worker = std::thread(server_loop, S);
+        *out = S;
+        return LP_OK;
+    } catch (...) {
+        return fail(nullptr, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t lp_server_submit(lp_server* S, lp_handle* h, uint64_t* ticket) {
+    if (!S || !h || !ticket) return fail(nullptr, LP_ERR_INVALID_ARG, "bad submit arguments");
+    if (!h->deferred || h->on_device)
+        return fail(h, LP_ERR_INVALID_ARG, "a served handle must be deferred and hold no device data");
+    if (h->device != S->device) return fail(h, LP_ERR_INVALID_ARG, "handle and server on different devices");
+    if (static_cast<int64_t>(h->arena_bytes) > S->budget)
+        return fail(h, LP_ERR_INVALID_ARG, "footprint exceeds the server's HBM budget");
+    std::unique_lock<std::mutex> lk(S->mu);
+    Ticket t{S->next_ticket++, h, S->now(), 0.0, 0.0};
+    h->solved = false;
+    S->queue.push_back(t);
+    S->st.submitted++;
+    S->st.queued++;
+    *ticket = t.id;
+    S->cv_work.notify_one();
+    return LP_OK;
+}
+
+int32_t lp_server_poll(lp_server* S, uint64_t* done_tickets, int32_t cap, int32_t* n_done) {
+    if (!S || cap < 0 || (cap > 0 && !done_tickets) || !n_done) return fail(nullptr, LP_ERR_INVALID_ARG, "bad poll arguments");
+    std::unique_lock<std::mutex> lk(S->mu);
+    const int32_t k = static_cast<int32_t>(std::min<size_t>(S->done.size(), static_cast<size_t>(cap)));
+    for (int32_t i = 0; i < k; ++i) done_tickets[i] = S->done[i];
+    S->done.erase(S->done.begin(), S->done.begin() + k);
+    *n_done = k;
+    return LP_OK;
+}
+
+int32_t lp_server_ticket_times(lp_server* S, uint64_t ticket, double* times) {
+    if (!S || !times) return fail(nullptr, LP_ERR_INVALID_ARG, "bad arguments");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->finished.find(ticket);
+    if (it == S->finished.end()) return fail(nullptr, LP_ERR_NOT_SOLVED, "ticket not completed");
+    times[0] = it->second.t_submit;
+    times[1] = it->second.t_admit;
+    times[2] = it->second.t_done;
+    return LP_OK;
+}
+
+int32_t lp_server_wait(lp_server* S, double timeout_s) {
+    if (!S) return fail(nullptr, LP_ERR_INVALID_ARG, "server is NULL");
+    const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 1e9);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!(S->queue.empty() && S->running.empty())) {
+        if (S->cv_idle.wait_until(lk, deadline) == std::cv_status::timeout &&
+            !(S->queue.empty() && S->running.empty()))
+            return fail(nullptr, LP_ERR_INTERNAL, "server wait timed out");
+    }
+    return LP_OK;
+}
+
+int32_t lp_server_stats_get(lp_server* S, lp_server_stats* st) {
+    if (!S || !st) return fail(nullptr, LP_ERR_INVALID_ARG, "bad arguments");
+    std::unique_lock<std::mutex> lk(S->mu);
+    *st = S->st;
+    return LP_OK;
+}
+
+void lp_server_destroy(lp_server* S) {
+    if (!S) return;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    (void)hipSetDevice(S->device);
+    (void)hipStreamSynchronize(S->stream);
+    for (Ticket& t : S->running) (void)release_device(t.h);
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+}
+
+}  // extern "C"
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -778,15 +1251,38 @@ int32_t lp_create(lp_handle** out, int32_t m, int32_t n, int64_t nnz, const int3
         h->n = n;
         h->nnz = nnz;
         h->c0 = c0;
+        h->has_x0 = o.x0 != nullptr;
+        h->has_y0 = o.y0 != nullptr && m > 0;
+        h->deferred = o.deferred != 0;
         const auto t0 = std::chrono::steady_clock::now();
-        rc = setup(h, row_ptr, col_idx, vals, c, b_lo, b_hi, x_lo, x_hi);
+        rc = host_prep(h, row_ptr, col_idx);
+        if (!rc && h->deferred) {
+            HostData& R = h->raw;
+            R.rp.assign(row_ptr, row_ptr + m + 1);
+            R.ci.assign(col_idx, col_idx + nnz);
+            R.v.assign(vals, vals + nnz);
+            R.c.assign(c, c + n);
+            if (m > 0) {
+                R.bl.assign(b_lo, b_lo + m);
+                R.bu.assign(b_hi, b_hi + m);
+            }
+            R.xl.assign(x_lo, x_lo + n);
+            R.xu.assign(x_hi, x_hi + n);
+            if (h->has_x0) R.x0.assign(o.x0, o.x0 + n);
+            if (h->has_y0) R.y0.assign(o.y0, o.y0 + m);
+            Offsets O;
+            h->arena_bytes = arena_layout(h, &O);
+        } else if (!rc) {
+            rc = device_setup(h, row_ptr, col_idx, vals, c, b_lo, b_hi, x_lo, x_hi, o.x0, o.y0);
+            h->prep = Prep{};  // uploaded; the host copy is no longer needed
+        }
         if (rc) {
             g_last_error = h->err;
             destroy_device(h);
             delete h;
             return rc;
         }
-        h->opt.x0 = nullptr;  // copied to the device
+        h->opt.x0 = nullptr;  // copied
         h->opt.y0 = nullptr;
         h->info.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         *out = h;
@@ -802,6 +1298,7 @@ int32_t lp_solve(lp_handle* h) {
     if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
     try {
         HIP_TRY(h, hipSetDevice(h->device));
+        if (int32_t rc = materialize(h)) return rc;
         hipStream_t s = h->stream;
         const DevLP& P = h->P;
         const auto t0 = std::chrono::steady_clock::now();
@@ -911,6 +1408,13 @@ int32_t lp_update_options(lp_handle* h, const lp_options* opt) {
 int32_t lp_get_solution(lp_handle* h, double* x, double* y, double* z, lp_info* info) {
     if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
     if (!h->solved) return fail(h, LP_ERR_NOT_SOLVED, "lp_get_solution before lp_solve");
+    if (!h->on_device) {  // released by a server: the result was kept on the host
+        if (x) std::memcpy(x, h->res_x.data(), sizeof(double) * h->n);
+        if (y && h->m > 0) std::memcpy(y, h->res_y.data(), sizeof(double) * h->m);
+        if (z) std::memcpy(z, h->res_z.data(), sizeof(double) * h->n);
+        if (info) *info = h->info;
+        return LP_OK;
+    }
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = h->stream;
     if (x) HIP_TRY(h, hipMemcpyAsync(x, h->P.out_x, sizeof(double) * h->n, hipMemcpyDeviceToHost, s));
@@ -931,6 +1435,7 @@ void lp_destroy(lp_handle* h) {
 
 int32_t lp_get_iterates(lp_handle* h, double* x, double* y, double* x_avg, double* y_avg) {
     if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->on_device) return fail(h, LP_ERR_NOT_SOLVED, "the handle holds no device data");
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const size_t sn = sizeof(double) * h->n, sm = sizeof(double) * h->m;
@@ -951,6 +1456,7 @@ int32_t lp_get_iterates(lp_handle* h, double* x, double* y, double* x_avg, doubl
 int32_t lp_get_scaled(lp_handle* h, double* vals, double* R, double* C, int32_t* t_row_ptr, int32_t* t_col_idx,
                       double* t_vals) {
     if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->on_device) return fail(h, LP_ERR_NOT_SOLVED, "the handle holds no device data");
     HIP_TRY(h, hipSetDevice(h->device));
     hipStream_t s = h->stream;
     const size_t nz = static_cast<size_t>(h->nnz);
@@ -969,6 +1475,10 @@ int32_t lp_get_scaled(lp_handle* h, double* vals, double* R, double* C, int32_t*
 int32_t lp_get_trace(lp_handle* h, double* out, int32_t cap, int32_t* n_records) {
     if (!h || cap < 0 || (cap > 0 && !out)) return fail(h, LP_ERR_INVALID_ARG, "bad trace arguments");
     if (!h->solved) return fail(h, LP_ERR_NOT_SOLVED, "lp_get_trace before lp_solve");
+    if (!h->on_device || !h->h_sc) {
+        if (n_records) *n_records = 0;
+        return LP_OK;
+    }
     const long long avail = h->h_sc->n_trace < h->opt.trace_cap ? h->h_sc->n_trace : h->opt.trace_cap;
     const long long k = avail < cap ? avail : cap;
     if (k > 0 && h->P.trace) {

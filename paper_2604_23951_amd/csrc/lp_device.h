@@ -127,13 +127,13 @@ struct MultiMaps {
     int n_red;
     const int2* map_elem; // vector blocks (ceil(max(m, n) / kBlock) per LP)
     int n_elem;
-    int* active;          // number of LPs still running
+    int* active;          // number of LPs still running (MULTI_ACTIVE) or each LP's status (MULTI_STATUS)
 };
 
 enum MultiLaunch {
     MULTI_PRIMAL = 0, MULTI_DUAL, MULTI_AX_ALL, MULTI_AX_FP32, MULTI_ATY, MULTI_AXA, MULTI_ATYA, MULTI_PARTIALS,
     MULTI_DECIDE, MULTI_INIT, MULTI_REBASE_INIT, MULTI_MATERIALIZE, MULTI_APPLY, MULTI_EXTRACT, MULTI_RESET,
-    MULTI_ACTIVE
+    MULTI_ACTIVE, MULTI_STATUS
 };
 
 // ---- setup ------------------------------------------------------------------------

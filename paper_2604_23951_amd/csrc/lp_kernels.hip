@@ -1377,6 +1377,11 @@ __global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
     sc->kkt_prev = __builtin_inf();
 }
 
+__global__ void multi_status_kernel(const BatchJob* jobs, int count, int* status) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) status[i] = jobs[i].P.sc->status;
+}
+
 // Number of LPs still running, summed by one workgroup in a fixed order.
 __global__ __launch_bounds__(kBlock) void multi_active_kernel(const BatchJob* jobs, int count, int* active) {
     __shared__ double red[kBlock / 64];
@@ -1595,6 +1600,10 @@ void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s) {
             break;
         case MULTI_ACTIVE:
             hipLaunchKernelGGL(multi_active_kernel, dim3(1), dim3(kBlock), 0, s, M.jobs, M.count, M.active);
+            break;
+        case MULTI_STATUS:
+            hipLaunchKernelGGL(multi_status_kernel, dim3((M.count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, M.jobs,
+                               M.count, M.active);
             break;
         default: break;
     }

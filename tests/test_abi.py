@@ -125,3 +125,12 @@ def test_null_handle_calls():
     assert lpg.lib().lp_solve(None) == 1
     assert lpg.lib().lp_get_solution(None, None, None, None, None) == 1
     lpg.lib().lp_destroy(None)  # ignored
+
+
+def test_deferred_handle_needs_no_device():
+    """A deferred handle is validated and laid out on the host; its device footprint is
+    known before any device memory is touched."""
+    lp = synth.cfg0(0)
+    with lpg.Solver(lp, deferred=1, spmv_layout=1) as s:
+        fp = s.layout()["device_bytes"]
+    assert fp > 24 * lp.nnz
