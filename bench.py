@@ -130,6 +130,86 @@ def run_batch(args) -> int:
     return 0
 
 
+def run_serve(args) -> int:
+    """Serving workload: Poisson arrivals drawn from a pre-generated pool of LPs
+    (m log-uniform on [100, 2e5], n = 1.5m, 3-20 nonzeros per row, KKT-constructed),
+    FP32 storage form with FP64 evaluation and refinement, to E_rel 1e-4; continuous
+    batching with admission by device footprint."""
+    import random
+
+    import numpy as np
+
+    import paper_2604_23951_amd as lpg
+    import synth
+
+    t0 = time.time()
+    pool = [synth.cfg4_lp(j) for j in range(args.pool)]
+    nnz = np.array([lp.nnz for lp in pool])
+    tmpl = [lpg.Solver(lp, spmv_layout=1, deferred=1, precision=lpg.LP_PREC_FP32_REFINED) for lp in pool]
+    print(f"[bench] pool of {len(pool)} LPs (mean nnz {nnz.mean():.3g}, max {nnz.max()}) ready in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def phase(rate, seconds, seed):
+        rng = random.Random(seed)
+        srv = lpg.Server(args.hbm_budget_gb * 2**30, args.slots, eps_rel=1e-4, max_iters=args.batch_max_iters)
+        tickets = []
+        start = time.perf_counter()
+        t_next = 0.0
+        done = []
+        while True:
+            now = time.perf_counter() - start
+            if now >= seconds:
+                break
+            if now >= t_next:
+                tickets.append(srv.submit(tmpl[rng.randrange(len(tmpl))]))
+                t_next += rng.expovariate(rate)
+                continue
+            done += srv.poll()
+            time.sleep(min(0.0005, max(0.0, t_next - now)))
+        done += srv.poll()
+        st = srv.stats()
+        lat = []
+        wait = []
+        for t in done:
+            ts, ta, td = srv.times(t)
+            lat.append(td - ts)
+            wait.append(ta - ts)
+            srv.result(t)
+        srv.close()
+        lat = np.array(lat) if lat else np.array([np.nan])
+        wait = np.array(wait) if wait else np.array([np.nan])
+        return {"offered_lps_per_s": rate, "seconds": seconds, "submitted": len(tickets),
+                "completed": len(done), "lps_per_s": len(done) / seconds,
+                "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+                "admission_wait_p50_s": float(np.percentile(wait, 50)),
+                "backlog_at_end": st["queued"] + st["running"], "rounds": st["rounds"],
+                "peak_device_bytes": st["peak_bytes"]}
+
+    full = phase(args.rate, args.serve_seconds, 1)
+    print(f"[bench] offered {args.rate}/s: {full['lps_per_s']:.1f} LPs/s, p50 {full['latency_p50_s']:.3f}s, "
+          f"p99 {full['latency_p99_s']:.3f}s, backlog {full['backlog_at_end']}", file=sys.stderr, flush=True)
+    sub_rate = max(1.0, 0.7 * full["lps_per_s"])
+    sub = phase(sub_rate, args.sub_seconds, 2)
+    print(f"[bench] offered {sub_rate:.1f}/s: {sub['lps_per_s']:.1f} LPs/s, p50 {sub['latency_p50_s']:.3f}s, "
+          f"p99 {sub['latency_p99_s']:.3f}s, backlog {sub['backlog_at_end']}", file=sys.stderr, flush=True)
+    for t in tmpl:
+        t.close()
+    result = {
+        "metric": METRIC, "value": full["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": args.serve_seconds * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson arrivals at {args.rate}/s for {args.serve_seconds}s from a pool of "
+                               f"{len(pool)} LPs (m log-uniform [100, 2e5], n=1.5m, 3-20 nnz/row), FP32 storage "
+                               f"form + FP64 refinement to E_rel 1e-4, continuous batching, HBM budget "
+                               f"{args.hbm_budget_gb} GiB, {args.slots} slots",
+                   "pool_mean_nnz": float(nnz.mean())},
+        "latency_p50_s": full["latency_p50_s"], "latency_p99_s": full["latency_p99_s"],
+        "saturated": full, "sub_saturation": sub,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,7 +223,13 @@ def main(argv=None):
     ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
     ap.add_argument("--layout", type=int, default=0, help="0 panel-packed wave units, 1 row tiles")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage form measurement")
-    ap.add_argument("--workload", default="large", choices=["large", "batch"])
+    ap.add_argument("--workload", default="large", choices=["large", "batch", "serve"])
+    ap.add_argument("--pool", type=int, default=96)
+    ap.add_argument("--rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--sub-seconds", type=float, default=15.0)
+    ap.add_argument("--hbm-budget-gb", type=int, default=128)
+    ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--loop-count", type=int, default=8)
     ap.add_argument("--batch-max-iters", type=int, default=400000)
@@ -157,6 +243,8 @@ def main(argv=None):
         return 2
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
 

@@ -172,9 +172,11 @@ int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *ba
  * arrival order while a slot is free and the request's device footprint fits the HBM
  * budget. Every LP starts at its own iteration 0 and keeps its own step sizes, restarts and
  * counters, so its result is the same as when it is solved alone.
- * Handles submitted to a server must be created with opt->deferred = 1 (no device memory
- * until admitted) and must not be used elsewhere until their ticket completes; afterwards
- * lp_get_solution returns the result from the host copy. */
+ * A submitted handle is a template: it must be created with opt->deferred = 1, it is not
+ * modified, and it may be submitted any number of times, also while earlier submissions of
+ * it are queued or running; every submission is a request of its own, with device memory
+ * allocated at admission and released at completion. The result of a request is fetched
+ * once with lp_server_result. */
 typedef struct lp_server lp_server;
 
 typedef struct lp_server_stats {
@@ -191,9 +193,15 @@ typedef struct lp_server_stats {
 int32_t lp_server_create(lp_server **out, int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
                          const lp_options *opt);
 
-/* Queue a deferred handle; returns at once with its ticket. LP_ERR_INVALID_ARG for a
- * handle that is not deferred or whose footprint exceeds the whole budget. */
+/* Queue a request to solve the LP of a deferred handle; returns at once with its ticket.
+ * LP_ERR_INVALID_ARG for a handle that is not deferred or whose footprint exceeds the
+ * whole budget. The handle must outlive its requests' admission (its host data is shared). */
 int32_t lp_server_submit(lp_server *srv, lp_handle *h, uint64_t *ticket);
+
+/* Result of a completed request (original scale, as lp_get_solution) and its run record;
+ * any pointer may be NULL. The request's storage is released: a second call for the same
+ * ticket returns LP_ERR_NOT_SOLVED. */
+int32_t lp_server_result(lp_server *srv, uint64_t ticket, double *x, double *y, double *z, lp_info *info);
 
 /* Tickets completed since the last poll (each reported once), at most cap of them. For a
  * completed ticket, times[0..2] of lp_server_ticket_times are the submit, admit and
@@ -201,8 +209,8 @@ int32_t lp_server_submit(lp_server *srv, lp_handle *h, uint64_t *ticket);
 int32_t lp_server_poll(lp_server *srv, uint64_t *done_tickets, int32_t cap, int32_t *n_done);
 int32_t lp_server_ticket_times(lp_server *srv, uint64_t ticket, double *times);
 
-/* Block until nothing is queued or running, or until timeout_s seconds (<= 0: no limit);
- * LP_ERR_INTERNAL on timeout. */
+/* Block until every submitted request has completed, or until timeout_s seconds (<= 0: no
+ * limit); LP_ERR_INTERNAL on timeout. */
 int32_t lp_server_wait(lp_server *srv, double timeout_s);
 
 int32_t lp_server_stats_get(lp_server *srv, lp_server_stats *st);

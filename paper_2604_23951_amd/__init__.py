@@ -30,7 +30,7 @@ EXPORTS = (
     "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_solve_batch", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
-    "lp_server_ticket_times", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
+    "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
 )
 
 
@@ -133,6 +133,8 @@ def lib():
         L.lp_server_poll.restype = I32
         L.lp_server_ticket_times.argtypes = [P, C.c_uint64, P]
         L.lp_server_ticket_times.restype = I32
+        L.lp_server_result.argtypes = [P, C.c_uint64, P, P, P, P]
+        L.lp_server_result.restype = I32
         L.lp_server_wait.argtypes = [P, D]
         L.lp_server_wait.restype = I32
         L.lp_server_stats_get.argtypes = [P, P]
@@ -366,12 +368,13 @@ class Server:
         o = make_options(**options) if options else None
         _check(lib().lp_server_create(C.byref(self.h), device, int(hbm_budget_bytes), int(max_slots),
                                       None if o is None else C.byref(o)))
-        self._by_ticket = {}
+        self._dims = {}
 
     def submit(self, solver: "Solver") -> int:
+        """Queue a request for the solver's LP (a deferred Solver; may be submitted repeatedly)."""
         t = C.c_uint64()
         _check(lib().lp_server_submit(self.h, solver.h, C.byref(t)), solver.h)
-        self._by_ticket[t.value] = solver
+        self._dims[t.value] = (solver.n, solver.m)
         return t.value
 
     def poll(self, cap: int = 4096):
@@ -394,12 +397,13 @@ class Server:
         return {k: getattr(st, k) for k, _ in lp_server_stats._fields_}
 
     def result(self, ticket: int) -> Solution:
-        s = self._by_ticket[ticket]
-        x = np.empty(s.n)
-        y = np.empty(max(s.m, 1))
-        z = np.empty(s.n)
-        info = lp_get_solution(s.h, x, y, z)
-        return Solution(STATUS.get(info.status, str(info.status)), x, y[: s.m], z, info)
+        n, m = self._dims.pop(ticket)
+        x = np.empty(n)
+        y = np.empty(max(m, 1))
+        z = np.empty(n)
+        info = lp_info()
+        _check(lib().lp_server_result(self.h, C.c_uint64(ticket), _p(x), _p(y), _p(z), C.byref(info)))
+        return Solution(STATUS.get(info.status, str(info.status)), x, y[:m], z, info)
 
     def close(self):
         if getattr(self, "h", None):

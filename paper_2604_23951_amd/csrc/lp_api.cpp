@@ -8,7 +8,9 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <array>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -120,8 +122,8 @@ struct lp_handle {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     double sum_p_ms = 0.0, sum_d_ms = 0.0;
     int64_t samples = 0;
-    Prep prep;
-    HostData raw;
+    std::shared_ptr<Prep> prep;     // shared with the server's per-request clones
+    std::shared_ptr<HostData> raw;
     bool has_x0 = false, has_y0 = false;
     bool deferred = false;
     bool on_device = false;
@@ -516,7 +518,8 @@ int32_t host_prep(lp_handle* h, const int32_t* rp, const int32_t* ci) {
     const int32_t m = h->m, n = h->n;
     const int64_t nnz = h->nnz;
     const lp_options& o = h->opt;
-    Prep& Q = h->prep;
+    h->prep = std::make_shared<Prep>();
+    Prep& Q = *h->prep;
     Q.rpT.assign(static_cast<size_t>(n) + 1, 0);
     Q.ciT.resize(static_cast<size_t>(nnz));
     Q.perm.resize(static_cast<size_t>(nnz));
@@ -565,7 +568,7 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
     const int32_t m = h->m, n = h->n;
     const int64_t nnz = h->nnz;
     const lp_options& o = h->opt;
-    const Prep& Q = h->prep;
+    const Prep& Q = *h->prep;
     const size_t sm = sizeof(double) * static_cast<size_t>(m), sn = sizeof(double) * static_cast<size_t>(n);
     const size_t si_nnz = sizeof(int32_t) * static_cast<size_t>(nnz), sd_nnz = sizeof(double) * static_cast<size_t>(nnz);
     Arena L;
@@ -640,7 +643,7 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     const int32_t m = h->m, n = h->n;
     const int64_t nnz = h->nnz;
     const lp_options& o = h->opt;
-    const Prep& Q = h->prep;
+    const Prep& Q = *h->prep;
     HIP_TRY(h, hipSetDevice(h->device));
     if (!h->stream) {
         if (o.hip_stream) {
@@ -813,13 +816,39 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
 int32_t materialize(lp_handle* h) {
     if (h->on_device) return LP_OK;
     if (!h->deferred) return fail(h, LP_ERR_INTERNAL, "handle has no device data and no host copy");
-    const HostData& R = h->raw;
+    const HostData& R = *h->raw;
     return device_setup(h, R.rp.data(), R.ci.data(), R.v.data(), R.c.data(), R.bl.data(), R.bu.data(), R.xl.data(),
                         R.xu.data(), R.x0.data(), R.y0.data());
 }
 
 
 // ------------------------------------------------------------------ serving form
+
+// A request's private handle: the problem's host data and layout are shared with the
+// submitted handle (read-only), device state and result are its own.
+lp_handle* clone_for_request(const lp_handle* t) {
+    lp_handle* h = new lp_handle();
+    h->opt = t->opt;
+    h->opt.hip_stream = nullptr;
+    h->device = t->device;
+    h->m = t->m;
+    h->n = t->n;
+    h->nnz = t->nnz;
+    h->c0 = t->c0;
+    h->long_a = t->long_a;
+    h->long_at = t->long_at;
+    h->units_a = t->units_a;
+    h->units_at = t->units_at;
+    h->panels_a = t->panels_a;
+    h->panels_at = t->panels_at;
+    h->arena_bytes = t->arena_bytes;
+    h->prep = t->prep;
+    h->raw = t->raw;
+    h->has_x0 = t->has_x0;
+    h->has_y0 = t->has_y0;
+    h->deferred = true;
+    return h;
+}
 
 // Device jobs table and block maps of a set of LPs (grown as needed, reused across rounds;
 // every round ends with a stream synchronisation before the next rebuild).
@@ -919,7 +948,8 @@ struct lp_server {
     std::deque<Ticket> queue;
     std::vector<Ticket> running;
     std::vector<uint64_t> done;
-    std::unordered_map<uint64_t, Ticket> finished;
+    std::unordered_map<uint64_t, Ticket> finished;       // completed, result not fetched yet
+    std::unordered_map<uint64_t, std::array<double, 3>> times;  // submit, admit, done
     uint64_t next_ticket = 1;
     bool stop = false;
     lp_server_stats st{};
@@ -1037,6 +1067,7 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
             S->st.completed++;
             S->done.push_back(t.id);
             S->finished[t.id] = t;
+            S->times[t.id] = {t.t_submit, t.t_admit, t.t_done};
         }
         S->cv_idle.notify_all();
     }
@@ -1100,14 +1131,18 @@ int32_t lp_server_create(lp_server** out, int32_t device, int64_t hbm_budget_byt
 
 int32_t lp_server_submit(lp_server* S, lp_handle* h, uint64_t* ticket) {
     if (!S || !h || !ticket) return fail(nullptr, LP_ERR_INVALID_ARG, "bad submit arguments");
-    if (!h->deferred || h->on_device)
-        return fail(h, LP_ERR_INVALID_ARG, "a served handle must be deferred and hold no device data");
+    if (!h->deferred || !h->raw || !h->prep) return fail(h, LP_ERR_INVALID_ARG, "a served handle must be deferred");
     if (h->device != S->device) return fail(h, LP_ERR_INVALID_ARG, "handle and server on different devices");
     if (static_cast<int64_t>(h->arena_bytes) > S->budget)
         return fail(h, LP_ERR_INVALID_ARG, "footprint exceeds the server's HBM budget");
+    lp_handle* r = nullptr;
+    try {
+        r = clone_for_request(h);
+    } catch (...) {
+        return fail(h, LP_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
     std::unique_lock<std::mutex> lk(S->mu);
-    Ticket t{S->next_ticket++, h, S->now(), 0.0, 0.0};
-    h->solved = false;
+    Ticket t{S->next_ticket++, r, S->now(), 0.0, 0.0};
     S->queue.push_back(t);
     S->st.submitted++;
     S->st.queued++;
@@ -1129,21 +1164,39 @@ int32_t lp_server_poll(lp_server* S, uint64_t* done_tickets, int32_t cap, int32_
 int32_t lp_server_ticket_times(lp_server* S, uint64_t ticket, double* times) {
     if (!S || !times) return fail(nullptr, LP_ERR_INVALID_ARG, "bad arguments");
     std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->finished.find(ticket);
-    if (it == S->finished.end()) return fail(nullptr, LP_ERR_NOT_SOLVED, "ticket not completed");
-    times[0] = it->second.t_submit;
-    times[1] = it->second.t_admit;
-    times[2] = it->second.t_done;
+    auto it = S->times.find(ticket);
+    if (it == S->times.end()) return fail(nullptr, LP_ERR_NOT_SOLVED, "ticket not completed");
+    for (int k = 0; k < 3; ++k) times[k] = it->second[k];
     return LP_OK;
+}
+
+int32_t lp_server_result(lp_server* S, uint64_t ticket, double* x, double* y, double* z, lp_info* info) {
+    if (!S) return fail(nullptr, LP_ERR_INVALID_ARG, "server is NULL");
+    lp_handle* h = nullptr;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->finished.find(ticket);
+        if (it == S->finished.end()) return fail(nullptr, LP_ERR_NOT_SOLVED, "ticket not completed (or already fetched)");
+        h = it->second.h;
+        S->finished.erase(it);
+    }
+    int32_t rc = LP_OK;
+    if (h->solved) {
+        rc = lp_get_solution(h, x, y, z, info);
+    } else {
+        rc = fail(nullptr, LP_ERR_DEVICE, "the request failed to start on the device: " + h->err);
+    }
+    lp_destroy(h);
+    return rc;
 }
 
 int32_t lp_server_wait(lp_server* S, double timeout_s) {
     if (!S) return fail(nullptr, LP_ERR_INVALID_ARG, "server is NULL");
     const auto deadline = std::chrono::steady_clock::now() + std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 1e9);
     std::unique_lock<std::mutex> lk(S->mu);
-    while (!(S->queue.empty() && S->running.empty())) {
-        if (S->cv_idle.wait_until(lk, deadline) == std::cv_status::timeout &&
-            !(S->queue.empty() && S->running.empty()))
+    // every submitted request has reached the finished table
+    while (S->st.completed < S->st.submitted) {
+        if (S->cv_idle.wait_until(lk, deadline) == std::cv_status::timeout && S->st.completed < S->st.submitted)
             return fail(nullptr, LP_ERR_INTERNAL, "server wait timed out");
     }
     return LP_OK;
@@ -1166,7 +1219,9 @@ void lp_server_destroy(lp_server* S) {
     if (S->worker.joinable()) S->worker.join();
     (void)hipSetDevice(S->device);
     (void)hipStreamSynchronize(S->stream);
-    for (Ticket& t : S->running) (void)release_device(t.h);
+    for (Ticket& t : S->running) lp_destroy(t.h);
+    for (Ticket& t : S->queue) lp_destroy(t.h);
+    for (auto& kv : S->finished) lp_destroy(kv.second.h);
     (void)hipStreamDestroy(S->stream);
     delete S;
 }
@@ -1257,7 +1312,8 @@ int32_t lp_create(lp_handle** out, int32_t m, int32_t n, int64_t nnz, const int3
         const auto t0 = std::chrono::steady_clock::now();
         rc = host_prep(h, row_ptr, col_idx);
         if (!rc && h->deferred) {
-            HostData& R = h->raw;
+            h->raw = std::make_shared<HostData>();
+            HostData& R = *h->raw;
             R.rp.assign(row_ptr, row_ptr + m + 1);
             R.ci.assign(col_idx, col_idx + nnz);
             R.v.assign(vals, vals + nnz);
@@ -1274,7 +1330,7 @@ int32_t lp_create(lp_handle** out, int32_t m, int32_t n, int64_t nnz, const int3
             h->arena_bytes = arena_layout(h, &O);
         } else if (!rc) {
             rc = device_setup(h, row_ptr, col_idx, vals, c, b_lo, b_hi, x_lo, x_hi, o.x0, o.y0);
-            h->prep = Prep{};  // uploaded; the host copy is no longer needed
+            h->prep.reset();  // uploaded; the host copy is no longer needed
         }
         if (rc) {
             g_last_error = h->err;

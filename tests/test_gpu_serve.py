@@ -67,6 +67,17 @@ def test_served_results_equal_solo():
         s.close()
 
 
+def test_same_template_submitted_many_times():
+    lp = synth.cfg4_lp(3, m_hi=2000)
+    with lpg.Solver(lp, spmv_layout=1, deferred=1) as tmpl, lpg.Server(1 << 34, 8, **OPTS) as srv:
+        tickets = [srv.submit(tmpl) for _ in range(12)]
+        srv.wait(120.0)
+        sols = [srv.result(t) for t in tickets]
+    ref = _solo(lp)
+    for sol in sols:
+        assert sol.info.iterations == ref.info.iterations and np.array_equal(sol.x, ref.x)
+
+
 def test_admission_respects_hbm_budget():
     lps = _pool()
     fps = [lpg.Solver(lp, spmv_layout=1, deferred=1).layout()["device_bytes"] for lp in lps]
@@ -115,6 +126,7 @@ def test_fp32_served_and_handle_reuse(oracle_lib):
             assert oracle.kkt(lp, sol.x, sol.y)["erel"] <= 1e-5 * (1 + 1e-9)
     assert n_opt >= 4
     # a released handle is placed on the device again by lp_solve and gives the same result
+    solvers[0].update(**OPTS)
     again = solvers[0].solve()
     assert np.array_equal(again.x, sols[0].x)
     for s in solvers:
