@@ -210,6 +210,27 @@ def run_serve(args) -> int:
     return 0
 
 
+def run_copy_calibration(args) -> int:
+    """A plain device-to-device copy of known size (512 MiB read, 512 MiB written), the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    n = 64 * 2**20  # doubles
+    a = torch.empty(n, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 10
+    print(json.dumps({"copy_bytes_each_way": n * 8, "us_per_copy": dt * 1e6,
+                      "read_plus_write_gbs": 2 * n * 8 / dt / 1e9}), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,7 +244,7 @@ def main(argv=None):
     ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
     ap.add_argument("--layout", type=int, default=0, help="0 panel-packed wave units, 1 row tiles")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage form measurement")
-    ap.add_argument("--workload", default="large", choices=["large", "batch", "serve"])
+    ap.add_argument("--workload", default="large", choices=["large", "batch", "serve", "copy"])
     ap.add_argument("--pool", type=int, default=96)
     ap.add_argument("--rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
@@ -245,6 +266,8 @@ def main(argv=None):
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "copy":
+        return run_copy_calibration(args)
 
     import numpy as np
 
