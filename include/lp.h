@@ -90,7 +90,8 @@ typedef struct lp_options {
     int32_t trace_cap;     /* number of evaluation records kept for lp_get_trace (default 4096) */
     int32_t spmv_layout;   /* sparse-product layout: 0 panel-packed wave units (default), 1 row tiles */
     int32_t long_row_len;  /* rows longer than this get a workgroup of their own (default 256) */
-    int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 8) */
+    int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 4; one
+                              workgroup holds 4 units, so multiples of 4 fill every CU evenly) */
     int32_t batch_wg_per_cu; /* lp_solve_batch: workgroups per compute unit (default 3) */
     int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
     int64_t batch_split_nnz;   /* lp_solve_batch: LPs with more nonzeros go to the block-diagonal

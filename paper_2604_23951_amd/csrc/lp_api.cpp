@@ -540,7 +540,7 @@ int32_t host_prep(lp_handle* h, const int32_t* rp, const int32_t* ci) {
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
-    const int target_units = cus * (o.units_per_cu > 0 ? o.units_per_cu : 8);
+    const int target_units = cus * (o.units_per_cu > 0 ? o.units_per_cu : 4);
     const int64_t slice = o.panel_slice_bytes > 0 ? o.panel_slice_bytes : (int64_t(1) << 20);
     const int long_len = o.long_row_len > 0 ? o.long_row_len : 256;
     Q.panels = o.spmv_layout == 0;
@@ -678,7 +678,7 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), I(O.trp), I(O.tci), D(O.tv), I(O.tt), nullptr, nullptr};
     P.A.layout = P.AT.layout = panels ? 0 : 1;
     auto bind_layout = [&](const PanelLayoutHost& L, const size_t* off, Mat& M) {
-        M.pan = Panels{L.units, L.panels, L.col_bits, static_cast<int>(L.nnz_packed), I(off[0]), I(off[1]),
+        M.pan = Panels{L.units, L.panels, L.col_bits, static_cast<int>(L.nnz_packed), L.max_unit_rows, I(off[0]), I(off[1]),
                        reinterpret_cast<const unsigned*>(b + off[2]), D(off[3]),
                        L.is_long.empty() ? nullptr : reinterpret_cast<const unsigned char*>(b + off[6]), nullptr};
         M.nlong = static_cast<int>(L.long_rows.size());
@@ -1253,7 +1253,7 @@ void lp_default_options(lp_options* o) {
     o->trace_cap = 4096;
     o->spmv_layout = 0;
     o->long_row_len = 256;
-    o->units_per_cu = 8;
+    o->units_per_cu = 4;
     o->batch_wg_per_cu = 3;
     o->batch_split_nnz = 20000;
     o->panel_slice_bytes = int64_t(1) << 20;

@@ -57,6 +57,7 @@ struct Panels {
     int panels;
     int col_bits;
     int nnz;
+    int max_rows;  // rows of the largest unit (sizes the LDS accumulators)
     const int* unit_row;
     const int* unit_seg;
     const unsigned* pk;
@@ -65,9 +66,10 @@ struct Panels {
     const float* v32;              // FP32 copy of v (FP32 storage form only)
 };
 
-constexpr int kUnitRowCap = 512;   // rows per wave unit at most
+constexpr int kUnitRowCap = 2048;  // rows per wave unit at most
 constexpr int kUnitsPerBlock = 4;  // wave units per workgroup
-constexpr int kChunks = 2;         // 64-entry chunks a wave loads together
+constexpr int kChunks = 4;         // 64-entry chunks a wave loads together (one group)
+constexpr int kStreamDepth = 4;    // groups of matrix entries a wave keeps loaded or in flight
 
 // One sparse operand: CSR (scaling, inspection, long rows, row tiles) and its panel layout.
 struct Mat {

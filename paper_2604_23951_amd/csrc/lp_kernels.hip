@@ -118,10 +118,46 @@ __device__ inline T block_sum_t(T v, double* red) {
     return static_cast<T>(block_sum(static_cast<double>(v), red));
 }
 
+// Row r reduced by the whole workgroup: thread t adds the products of entries t, t + kBlock,
+// ... in order (kPerThread loads in flight per round), then a fixed-shape tree over the
+// workgroup. Called by every thread of the workgroup.
+template <class T, class Epi>
+__device__ void row_tree_body(const Csr& M, int r, const T* __restrict__ xin, const Epi& epi, double* red) {
+    const int p0 = M.rp[r], p1 = M.rp[r + 1];
+    const int tid = threadIdx.x;
+    const int* __restrict__ ci = M.ci;
+    const T* __restrict__ av = vals_of<T>(M);
+    const int elast = M.nnz > 0 ? M.nnz - 1 : 0;
+    const typename Epi::Pre pre = epi.load(r);
+    T s = 0;
+    for (int base = p0; base < p1; base += kTileNnz) {
+        int col[kPerThread];
+        T val[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const int e = min(base + tid + k * kBlock, elast);
+            col[k] = __builtin_nontemporal_load(ci + e);
+            val[k] = __builtin_nontemporal_load(av + e);
+        }
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+            if (base + tid + k * kBlock >= p1) col[k] = 0;
+        T xv[kPerThread];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const T pr = val[k] * xv[k];
+            if (base + tid + k * kBlock < p1) s += pr;
+        }
+    }
+    s = block_sum_t(s, red);
+    if (tid == 0) epi.finish(r, s, pre);
+}
+
 template <class T, class Epi>
 __device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const Epi& epi, T* prod, double* red) {
-    const int r0 = M.rowlist ? M.rowlist[b] : M.tiles[b];
-    const int r1 = M.rowlist ? r0 + 1 : M.tiles[b + 1];
+    const int r0 = M.tiles[b], r1 = M.tiles[b + 1];
     const int p0 = M.rp[r0], p1 = M.rp[r1];
     const int tid = threadIdx.x;
     const int* __restrict__ ci = M.ci;
@@ -175,31 +211,7 @@ __device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const 
             }
         }
     } else {
-        const typename Epi::Pre pre = epi.load(r0);
-        T s = 0;
-        for (int base = p0; base < p1; base += kTileNnz) {
-            int col[kPerThread];
-            T val[kPerThread];
-#pragma unroll
-            for (int k = 0; k < kPerThread; ++k) {
-                const int e = min(base + tid + k * kBlock, elast);
-                col[k] = __builtin_nontemporal_load(ci + e);
-                val[k] = __builtin_nontemporal_load(av + e);
-            }
-#pragma unroll
-            for (int k = 0; k < kPerThread; ++k)
-                if (base + tid + k * kBlock >= p1) col[k] = 0;
-            T xv[kPerThread];
-#pragma unroll
-            for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
-#pragma unroll
-            for (int k = 0; k < kPerThread; ++k) {
-                const T pr = val[k] * xv[k];
-                if (base + tid + k * kBlock < p1) s += pr;
-            }
-        }
-        s = block_sum_t(s, red);
-        if (tid == 0) epi.finish(r0, s, pre);
+        row_tree_body<T>(M, r0, xin, epi, red);
     }
 }
 
@@ -211,84 +223,195 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __re
     tile_body(M, static_cast<int>(blockIdx.x), xin, epi, prod, red);
 }
 
-// Panel-packed SpMV, one wave64 per unit of rows. The wave walks its entries panel by panel
-// (all resident waves do, so the slice of the gathered vector for the current panel stays in
-// the L2 of each XCD). Inside a panel segment the entries are sorted by row, so a row's
-// entries in a 64-entry chunk form one run; the run's first lane adds the run's products,
-// in order, to the row's accumulator in wave-private LDS. Runs of a row in later chunks and
-// panels follow in column order, so every row sum is formed in CSR order. Loads and gathers
-// of kChunks chunks are issued together. After the last panel each lane finishes rows
-// lane, lane + 64, ... with the epilogue; rows listed as long are left to the long-row kernel.
-template <class T, class Epi>
-__global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, const T* __restrict__ xin, Epi epi) {
-    __shared__ T acc_s[kUnitsPerBlock][kUnitRowCap];
-    __shared__ T prod_s[kUnitsPerBlock][kChunks * 64];
-    if (!epi.begin()) return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int u = blockIdx.x * kUnitsPerBlock + w;
-    if (u >= M.units) return;  // the whole wave leaves; no workgroup barrier follows
-    const int r0 = M.unit_row[u], nr = M.unit_row[u + 1] - r0;
-    T* acc = acc_s[w];
-    T* prod = prod_s[w];
-    for (int r = lane; r < nr; r += 64) acc[r] = 0;
-    const int* seg = M.unit_seg + u * (M.panels + 1);
-    const unsigned cmask = (1u << M.col_bits) - 1u;
-    const int cb = M.col_bits;
-    const int last = M.nnz > 0 ? M.nnz - 1 : 0;
-    const unsigned* __restrict__ pkp = M.pk;
-    const T* __restrict__ pvp = vals_of<T>(M);
+// Panel-packed SpMV, one wave64 per unit of rows. The wave walks its entries in packed order,
+// panel by panel (all resident waves do, so the slice of the gathered vector for the current
+// panel stays in the L2 of each XCD), in chunks of 64 consecutive entries. Inside a panel
+// segment the entries are sorted by row, so between two places where the row id drops (the
+// start of a later segment) the rows of a chunk ascend and each row forms one run. The run's
+// first lane adds the run's products, in order, to the row's accumulator in wave-private LDS;
+// a chunk with drops is handled piece by piece, in order. Later runs of a row (later chunks,
+// later panels) follow in column order, so every row sum is formed in CSR order. The loop is
+// software-pipelined (see PanelGroups). After the last chunk each lane finishes rows lane,
+// lane + 64, ... with the epilogue. Rows listed as long have no packed entries; workgroups
+// past the panel ones reduce them, one long row each (fixed-shape tree), in the same launch.
+//
+// Pipeline: the entries of kStreamDepth groups of kChunks chunks are loaded or in flight and
+// the gathers of two groups are in flight: while group g is summed, the gathers of groups
+// g + 1 and g + 2 and the entry loads of groups g + 3 and g + 4 are outstanding. Slots are
+// indexed at compile time (the loop is unrolled by 12 = lcm(4, 3) steps) so that every group
+// stays in registers.
+template <class T>
+struct PanelGroups {
+    unsigned pk[kStreamDepth][kChunks];
+    T val[kStreamDepth][kChunks];
+    T xv[3][kChunks];
+};
+
+struct PanelUnit {
+    int s, e, last, lane, cb;
+    unsigned cmask;
+    __device__ int chunk_start(int g, int c) const { return s + (g * kChunks + c) * 64; }
+};
+
+template <class T>
+__device__ inline void panel_load(PanelGroups<T>& G, int S, int g, const PanelUnit& U, const unsigned* __restrict__ pkp,
+                                  const T* __restrict__ pvp) {
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const int idx = min(U.chunk_start(g, c) + U.lane, U.last);
+        G.pk[S][c] = __builtin_nontemporal_load(pkp + idx);
+        G.val[S][c] = __builtin_nontemporal_load(pvp + idx);
+    }
+}
+
+template <class T>
+__device__ inline void panel_gather(PanelGroups<T>& G, int S, int X, int g, const PanelUnit& U,
+                                    const T* __restrict__ xin) {
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const unsigned col = U.chunk_start(g, c) + U.lane < U.e ? (G.pk[S][c] & U.cmask) : 0u;
+        G.xv[X][c] = xin[col];
+    }
+}
+
+// Row id of the previous lane (lane 0 gets -1): a DPP shift of the whole wave by one lane.
+__device__ inline int prev_lane_row(int row) {
+    return __builtin_amdgcn_update_dpp(-1, row, 0x138 /* wave_shr:1 */, 0xf, 0xf, false);
+}
+
+// Adds the run that starts at this (head) lane to its row's accumulator, in order.
+template <class T>
+__device__ inline void add_run(T* acc, const T* prodc, int row, T own, int lane, unsigned long long heads, int nvalid) {
+    const unsigned long long rest = lane < 63 ? (heads >> (lane + 1)) : 0ull;
+    const int end = rest ? lane + 1 + __builtin_ctzll(rest) : nvalid;
+    T a = acc[row] + own;
+    int q = lane + 1;
+    for (; q + 4 <= end; q += 4) {
+        const T a0 = prodc[q], a1 = prodc[q + 1], a2 = prodc[q + 2], a3 = prodc[q + 3];
+        a += a0;
+        a += a1;
+        a += a2;
+        a += a3;
+    }
+    for (; q < end; ++q) a += prodc[q];
+    acc[row] = a;
+}
+
+// Step K of the unrolled loop on group g (K = g mod 12): issue the gathers of group g + 2 and
+// the entry loads of group g + 4, then sum group g. Steps past the end of the unit see empty
+// chunks and do only masked work.
+template <class T, int K>
+__device__ inline void panel_step(PanelGroups<T>& G, int g, const PanelUnit& U, const unsigned* __restrict__ pkp,
+                                  const T* __restrict__ pvp, const T* __restrict__ xin, T* acc, T* prod) {
+    constexpr int S = K % kStreamDepth, X = K % 3;
+    constexpr int S2 = (K + 2) % kStreamDepth, X2 = (K + 2) % 3;
+    panel_gather(G, S2, X2, g + 2, U, xin);
+    int row[kChunks];
+    T v[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        row[c] = static_cast<int>(G.pk[S][c] >> U.cb);
+        v[c] = G.val[S][c];
+    }
+    panel_load(G, S, g + kStreamDepth, U, pkp, pvp);
+    T p[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        p[c] = v[c] * G.xv[X][c];
+        prod[c * 64 + U.lane] = p[c];
+    }
     __builtin_amdgcn_wave_barrier();
-    for (int p = 0; p < M.panels; ++p) {
-        const int s = seg[p], e = seg[p + 1];
-        for (int base = s; base < e; base += kChunks * 64) {
-            unsigned pk[kChunks];
-            T val[kChunks];
+    const int lane = U.lane;
 #pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const int idx = min(base + c * 64 + lane, last);
-                pk[c] = __builtin_nontemporal_load(pkp + idx);
-                val[c] = __builtin_nontemporal_load(pvp + idx);
-            }
-            T xv[kChunks];
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const unsigned col = (base + c * 64 + lane < e) ? (pk[c] & cmask) : 0u;
-                xv[c] = xin[col];
-            }
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) prod[c * 64 + lane] = val[c] * xv[c];
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int c = 0; c < kChunks; ++c) {
-                const int cbase = base + c * 64;
-                if (cbase >= e) break;
-                const int nvalid = min(64, e - cbase);
-                const int row = static_cast<int>(pk[c] >> cb);
-                const int prev = __shfl_up(row, 1, 64);
-                const bool head = lane < nvalid && (lane == 0 || prev != row);
-                const unsigned long long heads = __ballot(head);
-                if (head) {
-                    const unsigned long long rest = lane < 63 ? (heads >> (lane + 1)) : 0ull;
-                    const int end = rest ? lane + 1 + __builtin_ctzll(rest) : nvalid;
-                    T a = acc[row];
-                    for (int q = lane; q < end; ++q) a += prod[c * 64 + q];
-                    acc[row] = a;
-                }
+    for (int c = 0; c < kChunks; ++c) {
+        const int nvalid = min(64, U.e - U.chunk_start(g, c));
+        if (nvalid <= 0) break;
+        const int prev = prev_lane_row(row[c]);
+        const bool valid = lane < nvalid;
+        const bool head = valid && prev != row[c];
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long drops = __ballot(valid && prev > row[c]);
+        if (drops == 0) {
+            if (head) add_run(acc, prod + c * 64, row[c], p[c], lane, heads, nvalid);
+        } else {
+            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+            const int piece = __popcll(drops & upto);
+            const int npieces = __popcll(drops) + 1;
+            for (int j = 0; j < npieces; ++j) {
+                if (head && piece == j) add_run(acc, prod + c * 64, row[c], p[c], lane, heads, nvalid);
                 __builtin_amdgcn_wave_barrier();
             }
         }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <class T, class Epi>
+__global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, Csr L, int panel_blocks,
+                                                            const T* __restrict__ xin, Epi epi) {
+    extern __shared__ __align__(16) unsigned char panel_acc_lds[];  // kUnitsPerBlock x M.max_rows of T
+    __shared__ T prod_s[kUnitsPerBlock][kChunks * 64];
+    __shared__ double red[kBlock / 64];
+    if (!epi.begin()) return;
+    if (static_cast<int>(blockIdx.x) >= panel_blocks) {
+        const int r = L.rowlist[blockIdx.x - panel_blocks];
+        row_tree_body<T>(L, r, xin, epi, red);
+        return;
+    }
+    // The wave index is the same on every lane; saying so keeps the unit's bookkeeping in
+    // scalar registers and its branches scalar.
+    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int u = blockIdx.x * kUnitsPerBlock + w;
+    if (u >= M.units) return;  // the whole wave leaves; no workgroup barrier follows
+    const int r0 = M.unit_row[u], nr = M.unit_row[u + 1] - r0;
+    T* acc = reinterpret_cast<T*>(panel_acc_lds) + w * M.max_rows;
+    T* prod = prod_s[w];
+    for (int r = lane; r < nr; r += 64) acc[r] = 0;
+    PanelUnit U;
+    U.s = M.unit_seg[u * (M.panels + 1)];
+    U.e = M.unit_seg[u * (M.panels + 1) + M.panels];
+    U.last = M.nnz > 0 ? M.nnz - 1 : 0;
+    U.lane = lane;
+    U.cb = M.col_bits;
+    U.cmask = (1u << M.col_bits) - 1u;
+    const unsigned* __restrict__ pkp = M.pk;
+    const T* __restrict__ pvp = vals_of<T>(M);
+    const int ngroups = (U.e - U.s + kChunks * 64 - 1) / (kChunks * 64);
+    PanelGroups<T> G;
+#pragma unroll
+    for (int S = 0; S < kStreamDepth; ++S) panel_load(G, S, S, U, pkp, pvp);
+    panel_gather(G, 0, 0, 0, U, xin);
+    panel_gather(G, 1, 1, 1, U, xin);
+    __builtin_amdgcn_wave_barrier();
+    static_assert(kStreamDepth == 4, "the loop below is unrolled for four entry slots and three gather slots");
+    for (int g = 0; g < ngroups; g += 12) {
+        panel_step<T, 0>(G, g, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 1>(G, g + 1, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 2>(G, g + 2, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 3>(G, g + 3, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 4>(G, g + 4, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 5>(G, g + 5, U, pkp, pvp, xin, acc, prod);
+        if (g + 6 >= ngroups) break;
+        panel_step<T, 6>(G, g + 6, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 7>(G, g + 7, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 8>(G, g + 8, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 9>(G, g + 9, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 10>(G, g + 10, U, pkp, pvp, xin, acc, prod);
+        panel_step<T, 11>(G, g + 11, U, pkp, pvp, xin, acc, prod);
     }
     __builtin_amdgcn_wave_barrier();
-    for (int r = lane; r < nr; r += 4 * 64) {
-        typename Epi::Pre pre[4];
-        int rows[4];
+    constexpr int kEpiRows = 8;  // rows per lane whose epilogue operands are loaded together
+    for (int r = lane; r < nr; r += kEpiRows * 64) {
+        typename Epi::Pre pre[kEpiRows];
+        int rows[kEpiRows];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kEpiRows; ++k) {
             rows[k] = r0 + min(r + k * 64, nr - 1);
             pre[k] = epi.load(rows[k]);
         }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kEpiRows; ++k) {
             const int rl = r + k * 64;
             if (rl < nr && !(M.is_long && M.is_long[rows[k]])) epi.finish(rows[k], acc[rl], pre[k]);
         }
@@ -447,24 +570,29 @@ void launch_tiles(const Csr& M, const T* xin, const Epi& epi, hipStream_t s) {
     hipLaunchKernelGGL((spmv_tiles_kernel<T, Epi>), dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
 }
 
-// One sparse product with its fused epilogue: the long rows (one workgroup each), then the
-// panel-packed rows; or the row tiles when that layout is selected.
+// One sparse product with its fused epilogue: one launch holding the panel-packed units and,
+// after them, one workgroup per long row; or the row tiles when that layout is selected.
 template <class T, class Epi>
 void launch_spmv(const Mat& M, const T* xin, const Epi& epi, hipStream_t s) {
     if (M.layout == 1) {
         launch_tiles(M.csr, xin, epi, s);
         return;
     }
-    if (M.nlong > 0) {
-        Csr L = M.csr;
-        L.rowlist = M.longrows;
-        L.ntiles = M.nlong;
-        launch_tiles(L, xin, epi, s);
-    }
-    if (M.pan.units > 0) {
-        const unsigned g = (M.pan.units + kUnitsPerBlock - 1) / kUnitsPerBlock;
-        hipLaunchKernelGGL((spmv_panel_kernel<T, Epi>), dim3(g), dim3(kBlock), 0, s, M.pan, xin, epi);
-    }
+    Csr L = M.csr;
+    L.rowlist = M.longrows;
+    L.ntiles = M.nlong;
+    const int pb = (M.pan.units + kUnitsPerBlock - 1) / kUnitsPerBlock;
+    const int g = pb + M.nlong;
+    const size_t lds = static_cast<size_t>(kUnitsPerBlock) * (M.pan.max_rows > 0 ? M.pan.max_rows : 1) * sizeof(T);
+    // Allow the largest accumulator block once per kernel instance (thread-safe static init).
+    static const bool lds_attr = [] {
+        return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_panel_kernel<T, Epi>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   static_cast<int>(kUnitsPerBlock * kUnitRowCap * sizeof(T))) == hipSuccess;
+    }();
+    (void)lds_attr;
+    if (g > 0)
+        hipLaunchKernelGGL((spmv_panel_kernel<T, Epi>), dim3(g), dim3(kBlock), lds, s, M.pan, L, pb, xin, epi);
 }
 
 // ------------------------------------------------------------------- setup kernels

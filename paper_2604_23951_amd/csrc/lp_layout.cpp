@@ -64,6 +64,7 @@ PanelLayoutHost build_panel_layout(int rows, int cols, const int32_t* rp, const 
         }
     }
     L.units = static_cast<int>(L.unit_row.size()) - 1;
+    for (int u = 0; u < L.units; ++u) L.max_unit_rows = std::max(L.max_unit_rows, L.unit_row[u + 1] - L.unit_row[u]);
 
     // panel-major packing
     const int P = L.panels;

@@ -19,7 +19,7 @@
 namespace lpgpu {
 
 struct PanelLayoutHost {
-    int rows = 0, cols = 0, panels = 1, col_bits = 0, units = 0, unit_rows_cap = 0;
+    int rows = 0, cols = 0, panels = 1, col_bits = 0, units = 0, unit_rows_cap = 0, max_unit_rows = 0;
     int64_t nnz_packed = 0;
     std::vector<int32_t> unit_row;   // [units + 1] first row of each unit
     std::vector<int32_t> unit_seg;   // [units * (panels + 1)] entry offset of each (unit, panel) segment
