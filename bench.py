@@ -17,6 +17,7 @@ on the solver stream during the timed region (one sampled iteration per step).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -210,6 +211,30 @@ def run_serve(args) -> int:
     return 0
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "pdhg_large_lp_fp64_hbm_counters.md")
+
+
+def recorded_traffic(layout_info, kernel):
+    """HBM bytes per launch of `kernel` ("primal" or "dual") from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE figures, scaled by the copy calibration. None unless the kernel
+    sources still hash to the recorded value and the layout is the one the counters saw."""
+    try:
+        text = open(COUNTERS_FILE).read()
+        blk = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        h = hashlib.sha256()
+        for f in blk["source_files"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != blk["source_sha256"]:
+            return None
+        if any(layout_info.get(k) != v for k, v in blk["layout"].items()):
+            return None
+        c = blk[kernel]
+        return (c["fetch_kib"] * blk["fetch_scale"] + c["write_kib"] * blk["write_scale"]) * 1024.0
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
 def run_copy_calibration(args) -> int:
     """A plain device-to-device copy of known size (512 MiB read, 512 MiB written), the
     reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -343,9 +368,10 @@ def main(argv=None):
     gbs_p = bp / (p_ms * 1e-3) / 1e9
     gbs_d = bd / (d_ms * 1e-3) / 1e9
     if p_ms >= d_ms:
-        dom = dict(kernel="primal: A^T y + primal update", bytes=bp, ms=p_ms, gbs=gbs_p)
+        dom = dict(kernel="primal: A^T y + primal update", bytes=bp, ms=p_ms, gbs=gbs_p, key="primal")
     else:
-        dom = dict(kernel="dual: A x + dual update", bytes=bd, ms=d_ms, gbs=gbs_d)
+        dom = dict(kernel="dual: A x + dual update", bytes=bd, ms=d_ms, gbs=gbs_d, key="dual")
+    traffic = recorded_traffic(layout_info, dom["key"])
     iter_bytes = bp + bd
     result = {
         "metric": METRIC,
@@ -365,7 +391,7 @@ def main(argv=None):
                    "m": m, "n": n, "nnz": nnz, "iters_per_step": E, "precision": "fp64", "scaling": "ruiz10+pc",
                    "layout": layout_info},
         "roofline": {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": dom["kernel"],
+                     "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["kernel"],
                      "alg_bytes_per_launch": dom["bytes"], "avg_launch_ms": dom["ms"]},
         "kernels": {"primal_ms": p_ms, "primal_alg_bytes": bp, "primal_gbs": gbs_p,
                     "dual_ms": d_ms, "dual_alg_bytes": bd, "dual_gbs": gbs_d, "samples": samples},
