@@ -219,6 +219,75 @@ int32_t lp_server_stats_get(lp_server *srv, lp_server_stats *st);
 /* Stop the worker after the current round; queued and running LPs are left unsolved. */
 void lp_server_destroy(lp_server *srv);
 
+/* ---- presolve and postsolve (Section 3) -----------------------------------------------
+ * A lightweight host presolver built from the atomic reductions of Section 2.1 (fix a
+ * variable, remove a constraint, change bounds, substitute a variable that appears in a
+ * single equality row), driven by the fast explorers of Section 3.1 (Table 1): empty and singleton rows,
+ * redundant rows and row sides by minimum / maximum activity, empty and fixed columns,
+ * column singletons of equality rows and variable locks (Section 2.3). It runs sequentially
+ * on the CPU and touches no device. lp_presolve takes an LP of eq. 1 (same arguments and
+ * validation as lp_create) and keeps a reduced LP of the same form; lp_postsolve maps an
+ * (approximate) solution of the reduced LP to (x, y, z) of the original (eq. 2): y of a
+ * removed row and z of a removed column are recovered from the reductions in reverse order,
+ * z_k = c_k - a_k^T y for a fixed column (Section 2.1). Reductions never add nonzeros, so
+ * nnz(reduced) <= nnz. The presolver owns its memory until lp_presolve_destroy. */
+typedef struct lp_presolver lp_presolver;
+
+typedef enum {
+    LP_PRESOLVE_REDUCED = 0,    /* a reduced LP with at least one variable is available */
+    LP_PRESOLVE_SOLVED = 1,     /* every variable was fixed: the reduced LP is empty (m = n = 0);
+                                   lp_postsolve with empty inputs gives the solution */
+    LP_PRESOLVE_INFEASIBLE = 2, /* some row or bound is violated by every point */
+    LP_PRESOLVE_UNBOUNDED = 3   /* a variable whose cost favours an unlocked direction has no bound
+                                   there: the LP is unbounded or infeasible */
+} lp_presolve_status;
+
+typedef struct lp_presolve_options {
+    int32_t max_rounds;      /* rounds of all explorers at most (default 32) */
+    int32_t dual_reductions; /* 1: fixing by variable locks (default); 0: primal reductions only */
+    int32_t substitute;      /* 1: eliminate column singletons of equality rows (default) */
+    double feas_tol;         /* tolerance of the infeasibility tests (default 1e-9) */
+    double pivot_tol;        /* smallest |a_ik| / max_j |a_ij| accepted for a substitution (default 1e-3) */
+} lp_presolve_options;
+
+typedef struct lp_presolve_info {
+    int32_t status;          /* lp_presolve_status */
+    int32_t m, n;            /* reduced sizes */
+    int64_t nnz;             /* reduced nonzeros */
+    int32_t rounds;
+    int64_t empty_rows, singleton_rows, redundant_rows, dropped_sides;
+    int64_t empty_cols, fixed_cols, lock_fixed_cols, substituted_cols;
+    double seconds;          /* wall time of lp_presolve */
+} lp_presolve_info;
+
+void lp_presolve_default_options(lp_presolve_options *opt);
+
+/* Presolve the LP; opt may be NULL (defaults), info may be NULL. On LP_OK *out holds a
+ * presolver whatever the status in info (an infeasible or unbounded status leaves nothing
+ * to postsolve). Validation errors as for lp_create. */
+int32_t lp_presolve(lp_presolver **out, int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                    const int32_t *col_idx, const double *vals, const double *c, double c0,
+                    const double *b_lo, const double *b_hi, const double *x_lo, const double *x_hi,
+                    const lp_presolve_options *opt, lp_presolve_info *info);
+
+int32_t lp_presolve_get_info(const lp_presolver *p, lp_presolve_info *info);
+
+/* Copy the reduced LP into caller arrays sized by info (row_ptr[m+1], col_idx[nnz],
+ * vals[nnz], c[n], b_lo[m], b_hi[m], x_lo[n], x_hi[n]) and its objective offset to *c0.
+ * Rows and columns keep their original relative order. */
+int32_t lp_presolve_get_reduced(const lp_presolver *p, int32_t *row_ptr, int32_t *col_idx, double *vals,
+                                double *c, double *c0, double *b_lo, double *b_hi, double *x_lo, double *x_hi);
+
+/* Original index of each reduced row (row_map[m]) and column (col_map[n]). */
+int32_t lp_presolve_get_maps(const lp_presolver *p, int32_t *row_map, int32_t *col_map);
+
+/* Map a solution (x[n], y[m], z[n]) of the reduced LP to x_out[n0], y_out[m0], z_out[n0] of
+ * the original LP. The inputs may be NULL when the reduced size is 0. */
+int32_t lp_postsolve(const lp_presolver *p, const double *x, const double *y, const double *z,
+                     double *x_out, double *y_out, double *z_out);
+
+void lp_presolve_destroy(lp_presolver *p);
+
 /* Copy the returned point (original scale) to caller buffers x[n], y[m], z[n] and the run
  * record to *info. Any pointer may be NULL to skip it. LP_ERR_NOT_SOLVED before lp_solve. */
 int32_t lp_get_solution(lp_handle *h, double *x, double *y, double *z, lp_info *info);

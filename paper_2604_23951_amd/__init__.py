@@ -31,6 +31,8 @@ EXPORTS = (
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
     "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
+    "lp_presolve_default_options", "lp_presolve", "lp_presolve_get_info", "lp_presolve_get_reduced",
+    "lp_presolve_get_maps", "lp_postsolve", "lp_presolve_destroy",
 )
 
 
@@ -51,6 +53,19 @@ class lp_options(C.Structure):
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
         ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p),
     ]
+
+
+class lp_presolve_options(C.Structure):
+    _fields_ = [("max_rounds", C.c_int32), ("dual_reductions", C.c_int32), ("substitute", C.c_int32),
+                ("pad", C.c_int32), ("feas_tol", C.c_double), ("pivot_tol", C.c_double)]
+
+
+class lp_presolve_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("m", C.c_int32), ("n", C.c_int32), ("pad", C.c_int32), ("nnz", C.c_int64),
+                ("rounds", C.c_int32), ("pad2", C.c_int32)] + \
+               [(k, C.c_int64) for k in ("empty_rows", "singleton_rows", "redundant_rows", "dropped_sides",
+                                         "empty_cols", "fixed_cols", "lock_fixed_cols", "substituted_cols")] + \
+               [("seconds", C.c_double)]
 
 
 class lp_server_stats(C.Structure):
@@ -141,6 +156,20 @@ def lib():
         L.lp_server_stats_get.restype = I32
         L.lp_server_destroy.argtypes = [P]
         L.lp_server_destroy.restype = None
+        L.lp_presolve_default_options.argtypes = [P]
+        L.lp_presolve_default_options.restype = None
+        L.lp_presolve.argtypes = [P, I32, I32, I64, P, P, P, P, D, P, P, P, P, P, P]
+        L.lp_presolve.restype = I32
+        L.lp_presolve_get_info.argtypes = [P, P]
+        L.lp_presolve_get_info.restype = I32
+        L.lp_presolve_get_reduced.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        L.lp_presolve_get_reduced.restype = I32
+        L.lp_presolve_get_maps.argtypes = [P, P, P]
+        L.lp_presolve_get_maps.restype = I32
+        L.lp_postsolve.argtypes = [P, P, P, P, P, P, P]
+        L.lp_postsolve.restype = I32
+        L.lp_presolve_destroy.argtypes = [P]
+        L.lp_presolve_destroy.restype = None
         _lib = L
     return _lib
 
@@ -426,3 +455,149 @@ class Server:
 def solve(lp, **options) -> Solution:
     with Solver(lp, **options) as s:
         return s.solve()
+
+
+# ---- presolve / postsolve (host) -----------------------------------------------------
+
+PRESOLVE_STATUS = {0: "reduced", 1: "solved", 2: "infeasible", 3: "unbounded"}
+
+
+class ReducedLP:
+    """The reduced LP of a presolve, with the fields Solver expects."""
+
+    def __init__(self, m, n, row_ptr, col_idx, vals, c, c0, b_lo, b_hi, x_lo, x_hi):
+        self.m, self.n = m, n
+        self.row_ptr, self.col_idx, self.vals = row_ptr, col_idx, vals
+        self.c, self.c0 = c, c0
+        self.b_lo, self.b_hi, self.x_lo, self.x_hi = b_lo, b_hi, x_lo, x_hi
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[self.m])
+
+
+class Presolve:
+    """Owns one lp_presolver: `Presolve(lp, **options)` runs the presolve; `.reduced` is the
+    reduced LP, `.postsolve(x, y, z)` maps its solution back to the original LP."""
+
+    def __init__(self, lp, **options):
+        o = lp_presolve_options()
+        lib().lp_presolve_default_options(C.byref(o))
+        for k, v in options.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown presolve option {k}")
+            setattr(o, k, v)
+        self.m0, self.n0 = int(lp.m), int(lp.n)
+        rp = np.ascontiguousarray(lp.row_ptr, dtype=np.int32)
+        nnz = int(rp[self.m0])
+        ci = np.ascontiguousarray(lp.col_idx if nnz else np.zeros(1), dtype=np.int32)
+        v = np.ascontiguousarray(lp.vals if nnz else np.zeros(1), dtype=np.float64)
+        c = np.ascontiguousarray(lp.c, dtype=np.float64)
+        bl = np.ascontiguousarray(lp.b_lo, dtype=np.float64) if self.m0 else None
+        bu = np.ascontiguousarray(lp.b_hi, dtype=np.float64) if self.m0 else None
+        xl = np.ascontiguousarray(lp.x_lo, dtype=np.float64)
+        xu = np.ascontiguousarray(lp.x_hi, dtype=np.float64)
+        h = C.c_void_p()
+        info = lp_presolve_info()
+        _check(lib().lp_presolve(C.byref(h), self.m0, self.n0, nnz, _p(rp), _p(ci), _p(v), _p(c),
+                                 float(getattr(lp, "c0", 0.0)), _p(bl), _p(bu), _p(xl), _p(xu), C.byref(o),
+                                 C.byref(info)))
+        self.h = h
+        self.info = info
+        self.status = PRESOLVE_STATUS.get(info.status, str(info.status))
+        self.reduced = None
+        if info.status in (0, 1):
+            m, n, k = info.m, info.n, info.nnz
+            r = ReducedLP(m, n, np.zeros(m + 1, np.int32), np.zeros(max(k, 1), np.int32), np.zeros(max(k, 1)),
+                          np.zeros(max(n, 1)), 0.0, np.zeros(max(m, 1)), np.zeros(max(m, 1)), np.zeros(max(n, 1)),
+                          np.zeros(max(n, 1)))
+            c0 = C.c_double()
+            _check(lib().lp_presolve_get_reduced(self.h, _p(r.row_ptr), _p(r.col_idx), _p(r.vals), _p(r.c),
+                                                 C.byref(c0), _p(r.b_lo), _p(r.b_hi), _p(r.x_lo), _p(r.x_hi)))
+            r.c0 = c0.value
+            r.col_idx, r.vals = r.col_idx[:k], r.vals[:k]
+            r.c, r.x_lo, r.x_hi = r.c[:n], r.x_lo[:n], r.x_hi[:n]
+            r.b_lo, r.b_hi = r.b_lo[:m], r.b_hi[:m]
+            self.reduced = r
+
+    def stats(self) -> dict:
+        return {k: getattr(self.info, k) for k, _ in lp_presolve_info._fields_ if not k.startswith("pad")}
+
+    def maps(self):
+        rm = np.zeros(max(self.info.m, 1), np.int32)
+        cm = np.zeros(max(self.info.n, 1), np.int32)
+        _check(lib().lp_presolve_get_maps(self.h, _p(rm), _p(cm)))
+        return rm[: self.info.m], cm[: self.info.n]
+
+    def postsolve(self, x=None, y=None, z=None):
+        def arr(a, size):
+            if size == 0:
+                return None
+            return np.ascontiguousarray(a, dtype=np.float64)
+
+        xo, yo, zo = np.empty(self.n0), np.empty(max(self.m0, 1)), np.empty(self.n0)
+        _check(lib().lp_postsolve(self.h, _p(arr(x, self.info.n)), _p(arr(y, self.info.m)), _p(arr(z, self.info.n)),
+                                  _p(xo), _p(yo), _p(zo)))
+        return xo, yo[: self.m0], zo
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lp_presolve_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PresolvedSolution:
+    """Result of solve_presolved: the original LP's (x, y, z), the presolve record and the
+    reduced solve (None when presolve decided the LP on its own)."""
+
+    def __init__(self, status, x, y, z, presolve_stats, reduced, times):
+        self.status, self.x, self.y, self.z = status, x, y, z
+        self.presolve = presolve_stats
+        self.reduced = reduced
+        self.times = times
+
+
+def solve_presolved(lp, presolve_options=None, **options) -> PresolvedSolution:
+    """Presolve on the host, solve the reduced LP with the GPU solver, postsolve on the host."""
+    import time
+
+    t0 = time.perf_counter()
+    with Presolve(lp, **(presolve_options or {})) as P:
+        t1 = time.perf_counter()
+        stats = P.stats()
+        if P.status in ("infeasible", "unbounded"):
+            return PresolvedSolution(P.status, None, None, None, stats, None,
+                                     {"presolve_s": t1 - t0, "solve_s": 0.0, "postsolve_s": 0.0})
+        red = None
+        if P.info.n > 0:
+            with Solver(P.reduced, **options) as s:
+                red = s.solve()
+            t2 = time.perf_counter()
+            x, y, z = P.postsolve(red.x, red.y, red.z)
+            status = red.status
+        else:
+            t2 = time.perf_counter()
+            x, y, z = P.postsolve()
+            status = "optimal"
+        t3 = time.perf_counter()
+    return PresolvedSolution(status, x, y, z, stats, red,
+                             {"presolve_s": t1 - t0, "solve_s": t2 - t1, "postsolve_s": t3 - t2})
+
+
+def evaluate(lp, x, y, **options) -> lp_info:
+    """E_rel and its terms of the point (x, y) on `lp`, computed by the solver's own evaluation
+    (a handle warm-started at the point and run for zero iterations)."""
+    with Solver(lp, x0=x, y0=y, max_iters=0, eps_rel=0.0, **options) as s:
+        return s.solve().info

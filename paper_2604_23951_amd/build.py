@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "liblpgpu.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lp_kernels.hip", "lp_api.cpp", "lp_layout.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lp_kernels.hip", "lp_api.cpp", "lp_layout.cpp", "lp_presolve.cpp")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

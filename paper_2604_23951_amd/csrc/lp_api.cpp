@@ -23,6 +23,7 @@
 
 #include "lp_device.h"
 #include "lp_layout.h"
+#include "lp_check.h"
 
 using namespace lpgpu;
 
@@ -95,66 +96,9 @@ struct HostData {
 
 }  // namespace
 
-struct lp_handle {
-    lp_options opt{};
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int32_t m = 0, n = 0;
-    int64_t nnz = 0;
-    double c0 = 0.0;
-    int64_t long_a = 0, long_at = 0;
-    int64_t units_a = 0, units_at = 0, panels_a = 0, panels_at = 0;
-    char* arena = nullptr;
-    size_t arena_bytes = 0;
-    DevLP P{};
-    int* d_perm = nullptr;
-    double* d_x0 = nullptr;
-    double* d_y0 = nullptr;
-    Scalars* h_sc = nullptr;  // pinned host copy of the device scalars
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    bool graph_failed = false;
-    bool solved = false;
-    lp_info info{};
-    std::string err;
-    bool timing = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    double sum_p_ms = 0.0, sum_d_ms = 0.0;
-    int64_t samples = 0;
-    std::shared_ptr<Prep> prep;     // shared with the server's per-request clones
-    std::shared_ptr<HostData> raw;
-    bool has_x0 = false, has_y0 = false;
-    bool deferred = false;
-    bool on_device = false;
-    std::vector<double> res_x, res_y, res_z;  // result kept on the host after the device copy is released
-};
+namespace lpgpu {
 
-namespace {
-
-int32_t materialize(lp_handle* h);
-
-int32_t fail(lp_handle* h, int32_t code, const std::string& msg) {
-    if (h) h->err = msg;
-    g_last_error = msg;
-    return code;
-}
-
-#define HIP_TRY(h, call)                                                                         \
-    do {                                                                                         \
-        hipError_t e_ = (call);                                                                  \
-        if (e_ != hipSuccess)                                                                    \
-            return fail((h), e_ == hipErrorOutOfMemory ? LP_ERR_OUT_OF_MEMORY : LP_ERR_DEVICE,   \
-                        std::string(#call) + ": " + hipGetErrorString(e_));                     \
-    } while (0)
-
-int32_t check_launch(lp_handle* h, const char* what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(h, LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-    return LP_OK;
-}
-
-int32_t validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
+int32_t validate_lp(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
                  const double* c, double c0, const double* bl, const double* bu, const double* xl, const double* xu,
                  std::string* msg) {
     if (m < 0 || n < 1 || nnz < 0 || nnz > 0x7fffffffLL) {
@@ -216,6 +160,70 @@ int32_t validate(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int
     }
     return LP_OK;
 }
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace lpgpu
+
+struct lp_handle {
+    lp_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    double c0 = 0.0;
+    int64_t long_a = 0, long_at = 0;
+    int64_t units_a = 0, units_at = 0, panels_a = 0, panels_at = 0;
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    DevLP P{};
+    int* d_perm = nullptr;
+    double* d_x0 = nullptr;
+    double* d_y0 = nullptr;
+    Scalars* h_sc = nullptr;  // pinned host copy of the device scalars
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
+    bool solved = false;
+    lp_info info{};
+    std::string err;
+    bool timing = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    double sum_p_ms = 0.0, sum_d_ms = 0.0;
+    int64_t samples = 0;
+    std::shared_ptr<Prep> prep;     // shared with the server's per-request clones
+    std::shared_ptr<HostData> raw;
+    bool has_x0 = false, has_y0 = false;
+    bool deferred = false;
+    bool on_device = false;
+    std::vector<double> res_x, res_y, res_z;  // result kept on the host after the device copy is released
+};
+
+namespace {
+
+int32_t materialize(lp_handle* h);
+
+int32_t fail(lp_handle* h, int32_t code, const std::string& msg) {
+    if (h) h->err = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(h, call)                                                                         \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((h), e_ == hipErrorOutOfMemory ? LP_ERR_OUT_OF_MEMORY : LP_ERR_DEVICE,   \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                     \
+    } while (0)
+
+int32_t check_launch(lp_handle* h, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(h, LP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return LP_OK;
+}
+
 
 int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
@@ -1285,7 +1293,7 @@ int32_t lp_create(lp_handle** out, int32_t m, int32_t n, int64_t nnz, const int3
         if (!out) return fail(nullptr, LP_ERR_INVALID_ARG, "out is NULL");
         *out = nullptr;
         std::string msg;
-        int32_t rc = validate(m, n, nnz, row_ptr, col_idx, vals, c, c0, b_lo, b_hi, x_lo, x_hi, &msg);
+        int32_t rc = validate_lp(m, n, nnz, row_ptr, col_idx, vals, c, c0, b_lo, b_hi, x_lo, x_hi, &msg);
         if (rc) return fail(nullptr, rc, msg);
         lp_options o;
         lp_default_options(&o);

@@ -17,4 +17,6 @@ from .lpgen import (  # noqa: F401
     cfg4_lp,
     transportation,
     tiny_lp,
+    with_planted_reductions,
+    presolve_lp,
 )

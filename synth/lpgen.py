@@ -361,3 +361,163 @@ def tiny_lp(spec: dict) -> LP:
     return LP(m, n, row_ptr, col_idx, vals, vec(spec["c"]), vec(spec["b_lo"]), vec(spec["b_hi"]),
               vec(spec["x_lo"]), vec(spec["x_hi"]), c0=float(spec.get("c0", 0.0)),
               name=spec.get("name", ""))
+
+
+def with_planted_reductions(
+    base: LP,
+    rng: np.random.Generator,
+    *,
+    fixed_cols: int = 0,
+    empty_cols: int = 0,
+    lock_cols: int = 0,
+    singleton_rows: int = 0,
+    redundant_rows: int = 0,
+    free_singletons: int = 0,
+    empty_rows: int = 0,
+    name: str = "",
+) -> LP:
+    """Append structure that a presolver can remove to a KKT-constructed LP, keeping a known
+    optimum (the paper's Section 3 explorers: Table 1). All new rows and columns are shuffled
+    in with the old ones.
+
+    - fixed columns: x_lo = x_hi = v ~ U[0,10], 1-4 entries in existing rows whose bounds are
+      shifted by a*v (so Ax* moves with them); z* = c - a^T y* with c ~ N(0,1);
+    - empty columns: no entries, bounds [0,10], c ~ U(0,1], x* = 0, z* = c;
+    - lock columns: bounds [0,10], x* = 0, c ~ U(0,1], a single entry a > 0 in a new slack
+      "<=" row (y* = 0) that also holds 2-4 bounded old columns, so no row stops the column
+      from decreasing;
+    - singleton rows: a x_j >= a x*_j - U(0,1] on a bounded column (slack, y* = 0);
+    - redundant rows: 2-5 bounded columns, b_lo below the minimum activity over the bounds
+      by U(0,1], b_hi = +inf (y* = 0);
+    - free column singletons: a free column (x* ~ N(0,1)) in a new equality row with 2-4 old
+      columns; y* ~ N(0,1) on the row, the column's cost is a y* (z* = 0) and the old
+      columns' costs move by a_j y* so their z* is unchanged;
+    - empty rows: b_lo = -U(0,1], b_hi = U(0,1] (y* = 0).
+    """
+    if base.x_star is None:
+        raise ValueError("base LP must be KKT-constructed")
+    m0, n0 = base.m, base.n
+    rows0 = np.repeat(np.arange(m0), np.diff(base.row_ptr)).tolist()
+    R, Cc, V = list(rows0), base.col_idx.astype(np.int64).tolist(), base.vals.tolist()
+    c = base.c.tolist()
+    b_lo, b_hi = base.b_lo.tolist(), base.b_hi.tolist()
+    x_lo, x_hi = base.x_lo.tolist(), base.x_hi.tolist()
+    xs, ys, zs = base.x_star.tolist(), base.y_star.tolist(), base.z_star.tolist()
+    bounded = np.flatnonzero(np.isfinite(base.x_lo) & np.isfinite(base.x_hi))
+    m, n = m0, n0
+
+    def new_col(lo, hi, cost, x, z):
+        nonlocal n
+        x_lo.append(lo), x_hi.append(hi), c.append(cost), xs.append(x), zs.append(z)
+        n += 1
+        return n - 1
+
+    def new_row(lo, hi, y):
+        nonlocal m
+        b_lo.append(lo), b_hi.append(hi), ys.append(y)
+        m += 1
+        return m - 1
+
+    for _ in range(fixed_cols):
+        v = 10.0 * rng.random()
+        cost = rng.standard_normal()
+        k = new_col(v, v, cost, v, 0.0)
+        rr = rng.choice(m0, size=min(m0, int(rng.integers(1, 5))), replace=False)
+        zk = cost
+        for i in rr:
+            a = rng.standard_normal()
+            R.append(int(i)), Cc.append(k), V.append(a)
+            if math.isfinite(b_lo[i]):
+                b_lo[i] += a * v
+            if math.isfinite(b_hi[i]):
+                b_hi[i] += a * v
+            zk -= a * ys[i]
+        zs[k] = zk
+    for _ in range(empty_cols):
+        cost = 1.0 - rng.random()
+        new_col(0.0, 10.0, cost, 0.0, cost)
+    for _ in range(lock_cols):
+        cost = 1.0 - rng.random()
+        k = new_col(0.0, 10.0, cost, 0.0, cost)
+        js = rng.choice(bounded, size=min(len(bounded), int(rng.integers(2, 5))), replace=False)
+        a_k = 0.5 + rng.random()
+        act = 0.0
+        entries = [(k, a_k)]
+        for j in js:
+            a = rng.standard_normal()
+            entries.append((int(j), a))
+            act += a * xs[j]
+        i = new_row(-INF, act + (1.0 - rng.random()), 0.0)
+        for j, a in entries:
+            R.append(i), Cc.append(j), V.append(a)
+    for _ in range(singleton_rows):
+        j = int(rng.choice(bounded))
+        a = rng.standard_normal()
+        lo = a * xs[j] - (1.0 - rng.random())
+        i = new_row(lo, INF, 0.0)
+        R.append(i), Cc.append(j), V.append(a)
+    for _ in range(redundant_rows):
+        js = rng.choice(bounded, size=min(len(bounded), int(rng.integers(2, 6))), replace=False)
+        amin = 0.0
+        entries = []
+        for j in js:
+            a = rng.standard_normal()
+            entries.append((int(j), a))
+            amin += min(a * x_lo[j], a * x_hi[j])
+        i = new_row(amin - (1.0 - rng.random()), INF, 0.0)
+        for j, a in entries:
+            R.append(i), Cc.append(j), V.append(a)
+    for _ in range(free_singletons):
+        xk = rng.standard_normal()
+        a_k = np.sign(rng.standard_normal()) * (0.5 + rng.random())
+        yi = rng.standard_normal()
+        k = new_col(-INF, INF, a_k * yi, xk, 0.0)
+        js = rng.choice(n0, size=min(n0, int(rng.integers(2, 5))), replace=False)
+        b = a_k * xk
+        entries = [(k, a_k)]
+        for j in js:
+            a = rng.standard_normal()
+            entries.append((int(j), a))
+            b += a * xs[j]
+            c[j] += a * yi
+        i = new_row(b, b, yi)
+        for j, a in entries:
+            R.append(i), Cc.append(j), V.append(a)
+    for _ in range(empty_rows):
+        new_row(-(1.0 - rng.random()), 1.0 - rng.random(), 0.0)
+
+    # shuffle rows and columns
+    rp = rng.permutation(m)
+    cp = rng.permutation(n)
+    R = rp[np.asarray(R, dtype=np.int64)]
+    Cn = cp[np.asarray(Cc, dtype=np.int64)]
+    V = np.asarray(V)
+    keys = R * n + Cn
+    order = np.argsort(keys, kind="stable")
+    keys, V = keys[order], V[order]
+    if len(keys) and np.any(np.diff(keys) == 0):
+        raise AssertionError("duplicate entry in planted LP")
+    row_ptr, col_idx, vals = csr_from_keys(keys, m, n, V)
+
+    def perm(vec, p, size):
+        out = np.empty(size)
+        out[p] = np.asarray(vec, dtype=np.float64)
+        return out
+
+    lp = LP(m, n, row_ptr, col_idx, vals, perm(c, cp, n), perm(b_lo, rp, m), perm(b_hi, rp, m),
+            perm(x_lo, cp, n), perm(x_hi, cp, n), c0=base.c0, name=name or base.name + "+planted")
+    lp.x_star, lp.z_star, lp.y_star = perm(xs, cp, n), perm(zs, cp, n), perm(ys, rp, m)
+    lp.p_star = float(np.dot(lp.c, lp.x_star) + lp.c0)
+    return lp
+
+
+def presolve_lp(j: int = 0, *, m: int = 2000, n: int = 4000, density: float = 0.002, share: float = 0.1) -> LP:
+    """A KKT-constructed LP (small-LP recipe: 50% equality rows, bounds [0,10], 10% free
+    columns) with every planted reduction type at `share` of m (rows) or n (columns)."""
+    rng = np.random.default_rng([SEED_ROOT, 5, j])
+    base = kkt_constructed(m, n, random_sparse_pattern(m, n, density, rng), rng, free_frac=0.1, eq_frac=0.5,
+                           name=f"presolve[{j}]")
+    kr, kc = max(1, int(share * m)), max(1, int(share * n))
+    return with_planted_reductions(base, rng, fixed_cols=kc, empty_cols=kc // 4, lock_cols=kc // 2,
+                                   singleton_rows=kr, redundant_rows=kr, free_singletons=kr // 2,
+                                   empty_rows=kr // 4)
