@@ -27,7 +27,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _LOAD_PATH = os.environ.get("ORACLE_LIB_OVERRIDE", _LIB_PATH)
 
 TRACE_W = 12
-STATUS = {0: "optimal", 1: "iteration_limit", 2: "numerical_error"}
+STATUS = {0: "optimal", 1: "iteration_limit", 2: "numerical_error", 3: "primal_infeasible", 4: "dual_infeasible"}
 
 
 def compile_source(src: str, out: str) -> str:
@@ -63,7 +63,7 @@ class _OptsStruct(C.Structure):
         ("restarts", C.c_int32), ("pad0", C.c_int32), ("eta", C.c_double), ("omega0", C.c_double),
         ("seed", C.c_uint64), ("x0", C.c_void_p), ("y0", C.c_void_p),
         ("n_snap", C.c_int32), ("pad1", C.c_int32), ("snap_k", C.c_void_p), ("snap_out", C.c_void_p),
-        ("trace_cap", C.c_int32), ("pad2", C.c_int32), ("trace", C.c_void_p),
+        ("trace_cap", C.c_int32), ("pad2", C.c_int32), ("trace", C.c_void_p), ("eps_infeas", C.c_double),
     ]
 
 
@@ -222,7 +222,7 @@ class Result:
 def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int = 64, scaling: bool = True,
           ruiz_passes: int = 10, pow_iters: int = 200, restarts: bool = True, eta: float = 0.0,
           omega0: float = 0.0, seed: int = 0x5EED0C0FFEE, x0=None, y0=None,
-          snap_k: Sequence[int] = (), trace_cap: int = 4096) -> Result:
+          snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8) -> Result:
     """Run the oracle. `snap_k` lists iterations whose scaled-space state
     (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration."""
     b = _Bound(lp)
@@ -238,6 +238,7 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     o.eta = eta
     o.omega0 = omega0
     o.seed = seed
+    o.eps_infeas = eps_infeas
     keep = []
     if x0 is not None:
         x0 = np.ascontiguousarray(x0, dtype=np.float64)

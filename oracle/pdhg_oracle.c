@@ -40,6 +40,8 @@
 #define ORA_OPTIMAL 0
 #define ORA_ITERATION_LIMIT 1
 #define ORA_NUMERICAL_ERROR 2
+#define ORA_PRIMAL_INFEASIBLE 3 /* a dual ray certifies that no x satisfies the constraints */
+#define ORA_DUAL_INFEASIBLE 4   /* a primal ray certifies that the dual has no solution */
 
 #define ORA_TRACE_W 12
 
@@ -70,6 +72,7 @@ typedef struct {
     double *snap_out;    /* per snapshot: x~[n], y~[m], x~avg[n], y~avg[m] */
     int32_t trace_cap, pad2;
     double *trace;       /* trace_cap * ORA_TRACE_W */
+    double eps_infeas;   /* relative tolerance of the infeasibility certificates; 0: off */
 } ora_opts;
 
 typedef struct {
@@ -345,6 +348,77 @@ static double kkt_omega(const kkt_t *K, double omega) {
     return sqrt(w2 * K->rps2 + K->rds2 / w2 + g * g);
 }
 
+/* Infeasibility certificates (the sign remarks after eq. (2): an LP with no solution of
+ * eq. (2) is infeasible or unbounded). Reading: the candidate rays are the differences
+ * between the iterate at this evaluation and the one at the previous evaluation (after its
+ * restart decision), taken on the original scale:
+ *   dual ray   y^ = R (y~ - y~p), with lambda = -A^T y^ = -C^-1 (A~^T y~ - A~^T y~p) and
+ *              z^ = lambda projected onto the sign cone of eq. (2);
+ *              rd2 = ||lambda - z^||^2 + ||sign violations of y^||^2 (y^ > 0 where b_lo = -inf,
+ *              y^ < 0 where b_hi = +inf);
+ *              D = sum_i (b_lo,i y^_i^+ - b_hi,i y^_i^-) + sum_k (x_lo,k z^_k^+ - x_hi,k z^_k^-)
+ *              (finite bounds only). A ray with D > 0 and sqrt(rd2) <= eps * D certifies that
+ *              the constraints have no solution (Farkas).
+ *   primal ray x^ = C (x~ - x~p), A x^ = R^-1 (A~x~ - A~x~p);
+ *              rp2 = ||part of A x^ outside the recession cone of [b_lo, b_hi]||^2
+ *                  + ||part of x^ outside the recession cone of [x_lo, x_hi]||^2
+ *              (both bounds finite: the whole component; only the lower: its negative part;
+ *              only the upper: its positive part; none: nothing);
+ *              G = -c^T x^. A ray with G > 0 and sqrt(rp2) <= eps * G certifies that the
+ *              objective decreases without bound along a feasible direction, so the dual is
+ *              infeasible. */
+typedef struct {
+    double rd2, D, rp2, G;
+} ray_t;
+
+static void eval_rays(const prob *P, const double *x, const double *y, const double *ax, const double *aty,
+                      const double *xp, const double *yp, const double *axp, const double *atyp, ray_t *Rr,
+                      double *xray, double *yray, double *zray) {
+    double rd2 = 0, D = 0, rp2 = 0, G = 0;
+    for (int32_t i = 0; i < P->m; i++) {
+        double dy = (y[i] - yp[i]) * P->R[i];
+        double v = (ax[i] - axp[i]) * P->Ri[i];
+        int flo = isfinite(P->oblo[i]), fhi = isfinite(P->obhi[i]);
+        if (dy > 0.0 && flo) D += P->oblo[i] * dy;
+        if (dy < 0.0 && fhi) D += P->obhi[i] * dy;
+        double vs = 0.0;
+        if (!flo && dy > 0.0) vs += dy;
+        if (!fhi && dy < 0.0) vs -= dy;
+        rd2 += vs * vs;
+        double w = 0.0;
+        if (flo && fhi) w = v;
+        else if (flo) w = v < 0.0 ? v : 0.0;
+        else if (fhi) w = v > 0.0 ? v : 0.0;
+        rp2 += w * w;
+        if (yray) yray[i] = dy;
+    }
+    for (int32_t k = 0; k < P->n; k++) {
+        double lam = -(aty[k] - atyp[k]) * P->Ci[k];
+        int flo = isfinite(P->oxlo[k]), fhi = isfinite(P->oxhi[k]);
+        double zs = lam;
+        if (!flo && !fhi) zs = 0.0;
+        else if (flo && !fhi) zs = lam > 0.0 ? lam : 0.0;
+        else if (!flo && fhi) zs = lam < 0.0 ? lam : 0.0;
+        double r = lam - zs;
+        rd2 += r * r;
+        if (zs > 0.0) D += P->oxlo[k] * zs;
+        if (zs < 0.0) D += P->oxhi[k] * zs;
+        double xh = (x[k] - xp[k]) * P->C[k];
+        G -= P->oc[k] * xh;
+        double w = 0.0;
+        if (flo && fhi) w = xh;
+        else if (flo) w = xh < 0.0 ? xh : 0.0;
+        else if (fhi) w = xh > 0.0 ? xh : 0.0;
+        rp2 += w * w;
+        if (zray) zray[k] = zs;
+        if (xray) xray[k] = xh;
+    }
+    Rr->rd2 = rd2;
+    Rr->D = D;
+    Rr->rp2 = rp2;
+    Rr->G = G;
+}
+
 static double combined_bound_norm(int32_t m, const double *lo, const double *hi) {
     double s = 0.0;
     for (int32_t i = 0; i < m; i++) {
@@ -450,6 +524,7 @@ void ora_default_opts(ora_opts *o) {
     o->eta = 0.0;
     o->omega0 = 0.0;
     o->seed = 0x5EED0C0FFEEull;
+    o->eps_infeas = 1e-8;
 }
 
 /* Export the scaled problem: A~ values (in the caller's CSR order), R, C, and A~^T. */
@@ -535,6 +610,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     double *aty = (double *)malloc(nb), *atya = (double *)malloc(nb);
     double *y = (double *)malloc(mb), *ya = (double *)malloc(mb), *yan = (double *)malloc(mb);
     double *ax = (double *)malloc(mb), *axn = (double *)malloc(mb), *axa = (double *)malloc(mb);
+    /* point at the previous evaluation (after its restart decision), for the candidate rays */
+    double *xp = (double *)malloc(nb), *atyp = (double *)malloc(nb);
+    double *yp = (double *)malloc(mb), *axp = (double *)malloc(mb);
 
     /* a3 / O5: step size */
     double sig = 0.0;
@@ -567,6 +645,12 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
     kkt_t Kc, Ka, Kanc;
     eval_kkt(&P, x, y, ax, aty, &Kc, NULL);
+    memcpy(xp, x, nb);
+    memcpy(atyp, aty, nb);
+    memcpy(yp, y, sizeof(double) * (size_t)m);
+    memcpy(axp, ax, sizeof(double) * (size_t)m);
+    ray_t Rray;
+    memset(&Rray, 0, sizeof(Rray));
     Kanc = Kc;
     double kkt_anchor = kkt_omega(&Kanc, omega);
     double kkt_prev = INFINITY;
@@ -644,9 +728,16 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         } else if (Ka.erel <= o->eps_rel) {
             status = ORA_OPTIMAL;
             out_avg = 1;
-        } else if (k >= o->max_iters) {
-            status = ORA_ITERATION_LIMIT;
-            out_avg = Ka.erel < Kc.erel;
+        } else {
+            if (o->eps_infeas > 0.0) {
+                eval_rays(&P, x, y, ax, aty, xp, yp, axp, atyp, &Rray, NULL, NULL, NULL);
+                if (Rray.D > 0.0 && sqrt(Rray.rd2) <= o->eps_infeas * Rray.D) status = ORA_PRIMAL_INFEASIBLE;
+                else if (Rray.G > 0.0 && sqrt(Rray.rp2) <= o->eps_infeas * Rray.G) status = ORA_DUAL_INFEASIBLE;
+            }
+            if (status < 0 && k >= o->max_iters) {
+                status = ORA_ITERATION_LIMIT;
+                out_avg = Ka.erel < Kc.erel;
+            }
         }
         if (status >= 0) {
             rec[6] = out_avg;
@@ -700,6 +791,11 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         } else {
             kkt_prev = kcand;
         }
+        /* the point the next evaluation's rays start from */
+        memcpy(xp, x, nb);
+        memcpy(yp, y, sizeof(double) * (size_t)m);
+        memcpy(axp, ax, sizeof(double) * (size_t)m);
+        memcpy(atyp, (why && use_avg) ? atya : aty, nb);
         rec[8] = omega;
         if (o->trace && ntr < o->trace_cap) memcpy(o->trace + ntr * ORA_TRACE_W, rec, sizeof(rec));
         ntr++;
@@ -721,6 +817,25 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         for (int32_t j = 0; j < n; j++) x_out[j] = xo[j] * P.C[j];
     if (y_out)
         for (int32_t i = 0; i < m; i++) y_out[i] = yo[i] * P.R[i];
+    if (status == ORA_PRIMAL_INFEASIBLE || status == ORA_DUAL_INFEASIBLE) {
+        /* the certificate, normalised so that D = 1 (dual ray in y, z) or G = 1 (primal ray in x) */
+        double *xr = (double *)malloc(nb), *yr = (double *)malloc(mb), *zr = (double *)malloc(nb);
+        eval_rays(&P, x, y, ax, aty, xp, yp, axp, atyp, &Rray, xr, yr, zr);
+        if (status == ORA_PRIMAL_INFEASIBLE) {
+            double s = 1.0 / Rray.D;
+            if (y_out)
+                for (int32_t i = 0; i < m; i++) y_out[i] = yr[i] * s;
+            if (z_out)
+                for (int32_t j = 0; j < n; j++) z_out[j] = zr[j] * s;
+        } else {
+            double s = 1.0 / Rray.G;
+            if (x_out)
+                for (int32_t j = 0; j < n; j++) x_out[j] = xr[j] * s;
+        }
+        free(xr);
+        free(yr);
+        free(zr);
+    }
     info->status = status;
     info->output_is_avg = out_avg;
     info->iters = k;
@@ -735,6 +850,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     info->sigma_max = sig;
     info->eta = eta;
     info->omega = omega;
+    free(xp); free(yp); free(axp); free(atyp);
     free(x); free(xa); free(xan); free(aty); free(atya);
     free(y); free(ya); free(yan); free(ax); free(axn); free(axa);
     prob_free(&P);

@@ -28,6 +28,8 @@ MUTANTS = {
     "gap_denominator": ("K->rel_gap = fabs(p - d) / (1.0 + fabs(p) + fabs(d));",
                         "K->rel_gap = fabs(p - d) / (1.0 + fabs(p));"),
     "dual_residual_unscaled": ("double rdo = rds * P->Ci[k];", "double rdo = rds;"),
+    "ray_objective_sign": ("if (zs > 0.0) D += P->oxlo[k] * zs;", "if (zs > 0.0) D -= P->oxlo[k] * zs;"),
+    "ray_row_cone_side": ("else if (flo) w = v < 0.0 ? v : 0.0;", "else if (flo) w = v > 0.0 ? v : 0.0;"),
 }
 
 QUICK = [
@@ -36,6 +38,7 @@ QUICK = [
     "tests/test_oracle_exact.py::test_vertex_enumeration",
     "tests/test_oracle_exact.py::test_kkt_point_is_fixed_point",
     "tests/test_oracle_structure.py",
+    "tests/test_oracle_infeasible.py",
 ]
 
 
