@@ -58,9 +58,18 @@ typedef enum {
 
 typedef enum {
     LP_OPTIMAL = 0,         /* E_rel <= eps_rel */
-    LP_ITERATION_LIMIT = 1, /* max_iters reached (also the outcome for infeasible / unbounded LPs) */
+    LP_ITERATION_LIMIT = 1, /* max_iters reached */
     LP_TIME_LIMIT = 2,
-    LP_NUMERICAL_ERROR = 3  /* a NaN appeared in the residuals */
+    LP_NUMERICAL_ERROR = 3, /* a NaN appeared in the residuals */
+    LP_PRIMAL_INFEASIBLE = 4, /* no x satisfies the constraints: lp_get_solution returns in y a
+                                 dual ray and in z its projected reduced cost, with
+                                 A^T y + z = 0 up to eps_infeas and ray objective
+                                 sum_i (b_lo y_i^+ - b_hi y_i^-) + sum_k (x_lo z_k^+ - x_hi z_k^-) = 1;
+                                 x is the last iterate */
+    LP_DUAL_INFEASIBLE = 5    /* the dual has no solution (the LP is unbounded if it is feasible):
+                                 x is a primal ray with c^T x = -1 and A x, x inside the recession
+                                 cones of the row and variable bounds up to eps_infeas; y, z are
+                                 the last iterate's */
 } lp_termination;
 
 typedef enum {
@@ -102,6 +111,11 @@ typedef struct lp_options {
     int32_t pad1;
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
+    double eps_infeas;     /* relative tolerance of the infeasibility certificates (default 1e-8;
+                              0 turns the test off). At each evaluation after the first, the
+                              displacement of the iterate since the previous evaluation is
+                              tested as a dual ray (primal infeasibility) and as a primal ray
+                              (dual infeasibility); see LP_PRIMAL_INFEASIBLE / LP_DUAL_INFEASIBLE */
 } lp_options;
 
 typedef struct lp_info {

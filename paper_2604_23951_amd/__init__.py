@@ -20,7 +20,8 @@ LP_OK = 0
 ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONSISTENT_BOUNDS",
           4: "LP_ERR_NAN_INPUT", 5: "LP_ERR_OUT_OF_MEMORY", 6: "LP_ERR_DEVICE", 7: "LP_ERR_NOT_SOLVED",
           8: "LP_ERR_INTERNAL"}
-STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_error"}
+STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_error", 4: "primal_infeasible",
+          5: "dual_infeasible"}
 LP_PREC_FP64 = 0
 LP_PREC_FP32_REFINED = 1
 TRACE_WIDTH = 12
@@ -51,7 +52,7 @@ class lp_options(C.Structure):
         ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32),
         ("batch_wg_per_cu", C.c_int32),
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
-        ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p),
+        ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
     ]
 
 

@@ -83,6 +83,7 @@ struct Prep {
 struct Offsets {
     size_t arp, aci, av, at, trp, tci, tv, tt, perm, c, xl, xu, C, Ci, bl, bu, R, Ri;
     size_t x, xa, xan, aty, atya, ox, oz, y, ya, yan, ax, axa, oy, x0, y0;
+    size_t xp, atyp, yp, axp;
     size_t f32[15] = {0};
     size_t pA[7] = {0}, pAT[7] = {0}, pA32 = 0, pAT32 = 0;
     size_t part, sc, tr;
@@ -229,7 +230,7 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 1 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
-        std::isnan(o.time_limit_s)) {
+        std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0)) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
     }
@@ -318,6 +319,7 @@ BatchJob make_job(lp_handle* h, const lp_options* bo) {
     BatchJob J{};
     J.P = h->P;
     J.eps_rel = o.eps_rel;
+    J.eps_infeas = o.eps_infeas;
     J.max_iters = o.max_iters;
     J.trace_cap = h->opt.trace_cap;
     J.eval_every = o.eval_every;
@@ -611,6 +613,10 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
     O->ax = L.add(sm);
     O->axa = L.add(sm);
     O->oy = L.add(sm);
+    O->xp = L.add(sn);
+    O->atyp = L.add(sn);
+    O->yp = L.add(sm);
+    O->axp = L.add(sm);
     O->x0 = h->has_x0 ? L.add(sn) : 0;
     O->y0 = h->has_y0 ? L.add(sm) : 0;
     const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
@@ -637,7 +643,7 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
             O->pAT32 = L.add(sizeof(float) * Q.LAT.packed.size());
         }
     }
-    O->part = L.add(sizeof(double) * 2 * kNQ * kMaxRedBlocks);
+    O->part = L.add(sizeof(double) * kNT * kMaxRedBlocks);
     O->sc = L.add(sizeof(Scalars));
     O->tr = L.add(sizeof(double) * kTraceW * static_cast<size_t>(o.trace_cap > 0 ? o.trace_cap : 1));
     return L.off;
@@ -740,6 +746,10 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.ax = D(O.ax);
     P.axa = D(O.axa);
     P.out_y = D(O.oy);
+    P.xp = D(O.xp);
+    P.atyp = D(O.atyp);
+    P.yp = D(O.yp);
+    P.axp = D(O.axp);
     P.partials = D(O.part);
     P.sc = reinterpret_cast<Scalars*>(b + O.sc);
     P.trace = o.trace_cap > 0 ? D(O.tr) : nullptr;
@@ -1267,6 +1277,7 @@ void lp_default_options(lp_options* o) {
     o->panel_slice_bytes = int64_t(1) << 20;
     o->x0 = nullptr;
     o->y0 = nullptr;
+    o->eps_infeas = 1e-8;
 }
 
 const char* lp_error_string(int32_t code) {
@@ -1366,7 +1377,8 @@ int32_t lp_solve(lp_handle* h) {
         hipStream_t s = h->stream;
         const DevLP& P = h->P;
         const auto t0 = std::chrono::steady_clock::now();
-        launch_reset(P, h->opt.eps_rel, h->opt.max_iters, h->opt.eval_every, h->opt.restarts, h->opt.trace_cap, s);
+        launch_reset(P, h->opt.eps_rel, h->opt.eps_infeas, h->opt.max_iters, h->opt.eval_every, h->opt.restarts,
+                     h->opt.trace_cap, s);
         launch_init_state(P, h->d_x0, h->d_y0, s);
         launch_evaluate(P, 1, s);
         if (int32_t rc = check_launch(h, "initial evaluation")) return rc;

@@ -13,6 +13,8 @@ constexpr int kTileNnz = 2048;    // nonzeros staged in LDS per SpMV tile
 constexpr int kTileRows = 512;    // rows per SpMV tile at most
 constexpr int kMaxRedBlocks = 512;
 constexpr int kNQ = 8;            // reduced quantities per candidate
+constexpr int kNR = 4;            // reduced quantities of the candidate rays (infeasibility)
+constexpr int kNT = 2 * kNQ + kNR;  // all reduced quantities of one evaluation
 constexpr int kTraceW = 12;
 
 constexpr int kRunning = -1;
@@ -23,6 +25,7 @@ struct Scalars {
     double tau, sigma, omega, eta, omega0;
     double eps_rel, c0, qnorm, cnorm, sigma_max;
     double kkt_anchor, kkt_prev;
+    double eps_infeas, ray_scale;  // certificate tolerance (0: off); 1/D or 1/G of a certificate
     double anc_rps2, anc_rds2, anc_gap;
     // statistics of the returned point
     double out_pobj, out_dobj, out_rel_p, out_rel_d, out_rel_gap, out_erel;
@@ -92,7 +95,8 @@ struct DevLP {
     double *x, *y, *xa, *ya;          // current and running averages
     double *ax, *axa, *aty, *atya;    // A~x, A~x_avg, A~^T y, A~^T y_avg
     double *xan, *yan;                // anchor (start of the current restart cycle)
-    double *partials;                 // nred * 2 * kNQ
+    double *xp, *yp, *axp, *atyp;     // point of the previous evaluation (candidate rays)
+    double *partials;                 // nred * kNT
     Scalars* sc;
     double* trace;
     double *out_x, *out_y, *out_z;
@@ -109,6 +113,7 @@ struct DevLP {
 struct BatchJob {
     DevLP P;
     double eps_rel;
+    double eps_infeas;
     long long max_iters;
     long long trace_cap;
     int eval_every;
@@ -151,7 +156,7 @@ void launch_power_norm(const DevLP& P, int iters, unsigned long long seed, doubl
 void launch_finalize_setup(const DevLP& P, double eta_override, double omega_override, double c0, hipStream_t s);
 
 // ---- solve ------------------------------------------------------------------------
-void launch_reset(const DevLP& P, double eps_rel, long long max_iters, int eval_every, int restarts_on,
+void launch_reset(const DevLP& P, double eps_rel, double eps_infeas, long long max_iters, int eval_every, int restarts_on,
                   long long trace_cap, hipStream_t s);
 void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s);
 void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scalars* gate, hipStream_t s);

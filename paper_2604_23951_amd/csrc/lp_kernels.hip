@@ -772,13 +772,15 @@ __global__ __launch_bounds__(kBlock) void finalize_setup_kernel(DevLP P, int npa
 
 // ------------------------------------------------------------------- solve kernels
 
-__global__ void reset_kernel(Scalars* sc, double eps_rel, long long max_iters, int eval_every, int restarts_on,
-                             long long trace_cap) {
+__global__ void reset_kernel(Scalars* sc, double eps_rel, double eps_infeas, long long max_iters, int eval_every,
+                             int restarts_on, long long trace_cap) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     sc->omega = sc->omega0;
     sc->tau = sc->eta / sc->omega;
     sc->sigma = sc->eta * sc->omega;
     sc->eps_rel = eps_rel;
+    sc->eps_infeas = eps_infeas;
+    sc->ray_scale = 0.0;
     sc->max_iters = max_iters;
     sc->eval_every = eval_every;
     sc->restarts_on = restarts_on;
@@ -858,36 +860,86 @@ __device__ inline void col_terms(const DevLP& P, int j, const double* x, const d
     acc[6] += dx * dx;
 }
 
-// Partial sums of the KKT quantities of the current iterate (slots 0..7) and of the running
-// average (slots 8..15). mode 1 (initial point) and mode 2 (final point after a stop)
-// evaluate the current iterate only; mode 2 runs whatever the status.
+// Candidate rays for the infeasibility certificates: the displacement of the iterate since
+// the previous evaluation, on the original scale. acc: 0 rd2, 1 D, 2 rp2, 3 G, where
+//   dual ray y^ = R (y~ - y~p), lambda = -C^-1 (A~^T y~ - A~^T y~p), z^ = lambda projected on
+//   the sign cone of eq. 2: rd2 = ||lambda - z^||^2 + ||sign violations of y^||^2,
+//   D = sum_i (b_lo y^+ - b_hi y^-) + sum_k (x_lo z^+ - x_hi z^-) over finite bounds;
+//   primal ray x^ = C (x~ - x~p), A x^ = R^-1 (A~x~ - A~x~p): rp2 = squared parts of A x^ and
+//   x^ outside the recession cones of the row and variable bounds, G = -c^T x^.
+__device__ inline void row_ray_terms(const DevLP& P, int i, double* acc) {
+    const double dy = (P.y[i] - P.yp[i]) * P.R[i];
+    const double v = (P.ax[i] - P.axp[i]) * P.Ri[i];
+    const double bl = P.bl[i], bu = P.bu[i], Ri = P.Ri[i];
+    const bool flo = finite_d(bl), fhi = finite_d(bu);
+    if (dy > 0.0 && flo) acc[1] += (bl * Ri) * dy;
+    if (dy < 0.0 && fhi) acc[1] += (bu * Ri) * dy;
+    double vs = 0.0;
+    if (!flo && dy > 0.0) vs += dy;
+    if (!fhi && dy < 0.0) vs -= dy;
+    acc[0] += vs * vs;
+    double w = 0.0;
+    if (flo && fhi) w = v;
+    else if (flo) w = v < 0.0 ? v : 0.0;
+    else if (fhi) w = v > 0.0 ? v : 0.0;
+    acc[2] += w * w;
+}
+
+__device__ inline void col_ray_terms(const DevLP& P, int j, double* acc) {
+    const double lam = -(P.aty[j] - P.atyp[j]) * P.Ci[j];
+    const double lo = P.xl[j], hi = P.xu[j], Cj = P.C[j];
+    const bool flo = finite_d(lo), fhi = finite_d(hi);
+    double zs = lam;
+    if (!flo && !fhi) zs = 0.0;
+    else if (flo && !fhi) zs = lam > 0.0 ? lam : 0.0;
+    else if (!flo && fhi) zs = lam < 0.0 ? lam : 0.0;
+    const double r = lam - zs;
+    acc[0] += r * r;
+    if (zs > 0.0) acc[1] += (lo * Cj) * zs;
+    if (zs < 0.0) acc[1] += (hi * Cj) * zs;
+    const double xh = (P.x[j] - P.xp[j]) * Cj;
+    acc[3] -= (P.c[j] * P.Ci[j]) * xh;
+    double w = 0.0;
+    if (flo && fhi) w = xh;
+    else if (flo) w = xh < 0.0 ? xh : 0.0;
+    else if (fhi) w = xh > 0.0 ? xh : 0.0;
+    acc[2] += w * w;
+}
+
+// Partial sums of the KKT quantities of the current iterate (slots 0..7), of the running
+// average (slots 8..15) and of the candidate rays (16..19). mode 1 (initial point) and
+// mode 2 (final point after a stop) evaluate the current iterate only; mode 2 runs whatever
+// the status.
 __device__ void kkt_partials_body(const DevLP& P, int mode, int blk, int nblk) {
-    __shared__ double red[kBlock / 64][2 * kNQ];
+    __shared__ double red[kBlock / 64][kNT];
     if (mode != 2 && P.sc->status != kRunning) return;
-    double acc[2 * kNQ];
+    double acc[kNT];
 #pragma unroll
-    for (int q = 0; q < 2 * kNQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kNT; ++q) acc[q] = 0.0;
     const bool both = (mode == 0);
+    const bool rays = both && P.xp != nullptr;
     const int stride = nblk * kBlock;
     for (int i = blk * kBlock + threadIdx.x; i < P.m; i += stride) {
         row_terms(P, i, P.ax, P.y, acc);
         if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
+        if (rays) row_ray_terms(P, i, acc + 2 * kNQ);
     }
     for (int j = blk * kBlock + threadIdx.x; j < P.n; j += stride) {
         col_terms(P, j, P.x, P.aty, acc);
         if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
+        if (rays) col_ray_terms(P, j, acc + 2 * kNQ);
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 2 * kNQ; ++q) {
+    for (int q = 0; q < kNT; ++q) {
         const double v = wave_sum(acc[q]);
         if (lane == 0) red[w][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 2 * kNQ) {
+    if (threadIdx.x < kNT) {
         double t = 0.0;
         for (int k = 0; k < kBlock / 64; ++k) t += red[k][threadIdx.x];
-        P.partials[blk * 2 * kNQ + threadIdx.x] = t;
+        P.partials[blk * kNT + threadIdx.x] = t;
     }
 }
 
@@ -990,9 +1042,21 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
     } else if (avg.erel <= sc->eps_rel) {
         status = 0;
         out_avg = 1;
-    } else if (k >= sc->max_iters) {
-        status = 1;
-        out_avg = avg.erel < cur.erel;
+    } else {
+        if (sc->eps_infeas > 0.0 && P.xp != nullptr) {
+            const double* ray = tot + 2 * kNQ;  // rd2, D, rp2, G
+            if (ray[1] > 0.0 && sqrt(ray[0]) <= sc->eps_infeas * ray[1]) {
+                status = 4;
+                sc->ray_scale = 1.0 / ray[1];
+            } else if (ray[3] > 0.0 && sqrt(ray[2]) <= sc->eps_infeas * ray[3]) {
+                status = 5;
+                sc->ray_scale = 1.0 / ray[3];
+            }
+        }
+        if (status == kRunning && k >= sc->max_iters) {
+            status = 1;
+            out_avg = avg.erel < cur.erel;
+        }
     }
     sc->k = k;
     if (status != kRunning) {
@@ -1056,13 +1120,13 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
 
 __device__ void decide_body(const DevLP& P, int mode) {
     __shared__ double red[kBlock / 64];
-    __shared__ double tot[2 * kNQ];
+    __shared__ double tot[kNT];
     Scalars* sc = P.sc;
     if (mode != 2 && sc->status != kRunning) return;
-    const int nq = (mode == 0) ? 2 * kNQ : kNQ;
+    const int nq = (mode == 0) ? kNT : kNQ;
     for (int q = 0; q < nq; ++q) {
         double v = 0.0;
-        for (int b = threadIdx.x; b < P.nred; b += kBlock) v += P.partials[b * 2 * kNQ + q];
+        for (int b = threadIdx.x; b < P.nred; b += kBlock) v += P.partials[b * kNT + q];
         v = block_sum(v, red);
         if (threadIdx.x == 0) tot[q] = v;
     }
@@ -1099,6 +1163,26 @@ __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
     }
 }
 
+// The point the next evaluation's rays start from: the current iterate, or the average when
+// this evaluation restarts there (lr == 2).
+__device__ inline void save_prev_at(const DevLP& P, int lr, int g) {
+    if (P.xp == nullptr) return;
+    const bool avg = lr == 2;
+    if (g < P.n) {
+        P.xp[g] = avg ? P.xa[g] : P.x[g];
+        P.atyp[g] = avg ? P.atya[g] : P.aty[g];
+    }
+    if (g < P.m) {
+        P.yp[g] = avg ? P.ya[g] : P.y[g];
+        P.axp[g] = avg ? P.axa[g] : P.ax[g];
+    }
+}
+
+__global__ void save_prev_kernel(DevLP P) {
+    if (P.sc->status != kRunning) return;
+    save_prev_at(P, P.sc->last_restart, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 __global__ void apply_restart_kernel(DevLP P) {
     const int lr = P.sc->last_restart;
     if (lr == 0) return;
@@ -1114,25 +1198,38 @@ __global__ void stop_kernel(Scalars* sc, int status) {
 }
 
 // Returned point on the original scale: x = C x~, y = R y~, z = projected reduced cost.
-__device__ inline void extract_at(const DevLP& P, int avg, int g) {
+// With a certificate (status 4: primal infeasible, 5: dual infeasible) the ray replaces the
+// dual pair (y, z) or the primal x, scaled by `scale` so that its ray objective is 1.
+__device__ inline void extract_at(const DevLP& P, int avg, int status, double scale, int g) {
     const double* xs = avg ? P.xa : P.x;
     const double* ys = avg ? P.ya : P.y;
     const double* at = avg ? P.atya : P.aty;
+    const bool dual_ray = status == 4 && P.xp != nullptr;
+    const bool primal_ray = status == 5 && P.xp != nullptr;
     if (g < P.n) {
-        P.out_x[g] = xs[g] * P.C[g];
-        const double ls = P.c[g] - at[g];
+        P.out_x[g] = primal_ray ? ((P.x[g] - P.xp[g]) * P.C[g]) * scale : xs[g] * P.C[g];
         const bool flo = finite_d(P.xl[g]), fhi = finite_d(P.xu[g]);
-        double zs = ls;
-        if (!flo && !fhi) zs = 0.0;
-        else if (flo && !fhi) zs = ls > 0.0 ? ls : 0.0;
-        else if (!flo && fhi) zs = ls < 0.0 ? ls : 0.0;
-        P.out_z[g] = zs * P.Ci[g];
+        if (dual_ray) {
+            const double lam = -(P.aty[g] - P.atyp[g]) * P.Ci[g];
+            double zs = lam;
+            if (!flo && !fhi) zs = 0.0;
+            else if (flo && !fhi) zs = lam > 0.0 ? lam : 0.0;
+            else if (!flo && fhi) zs = lam < 0.0 ? lam : 0.0;
+            P.out_z[g] = zs * scale;
+        } else {
+            const double ls = P.c[g] - at[g];
+            double zs = ls;
+            if (!flo && !fhi) zs = 0.0;
+            else if (flo && !fhi) zs = ls > 0.0 ? ls : 0.0;
+            else if (!flo && fhi) zs = ls < 0.0 ? ls : 0.0;
+            P.out_z[g] = zs * P.Ci[g];
+        }
     }
-    if (g < P.m) P.out_y[g] = ys[g] * P.R[g];
+    if (g < P.m) P.out_y[g] = dual_ray ? ((P.y[g] - P.yp[g]) * P.R[g]) * scale : ys[g] * P.R[g];
 }
 
 __global__ void extract_kernel(DevLP P) {
-    extract_at(P, P.sc->out_avg, blockIdx.x * blockDim.x + threadIdx.x);
+    extract_at(P, P.sc->out_avg, P.sc->status, P.sc->ray_scale, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 
@@ -1211,28 +1308,31 @@ __device__ void wg_spmv(const Csr& M, const T* xin, const Epi& epi, double* lds,
 // KKT quantities of the current iterate (and of the average in mode 0) summed over the
 // whole LP by one workgroup in a fixed order; tot[0..15] in LDS afterwards.
 __device__ void wg_kkt(const DevLP& P, int mode, double* tot, double* red16) {
-    double acc[2 * kNQ];
+    double acc[kNT];
 #pragma unroll
-    for (int q = 0; q < 2 * kNQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kNT; ++q) acc[q] = 0.0;
     const bool both = mode == 0;
+    const bool rays = both && P.xp != nullptr;
     for (int i = threadIdx.x; i < P.m; i += kBlock) {
         row_terms(P, i, P.ax, P.y, acc);
         if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
+        if (rays) row_ray_terms(P, i, acc + 2 * kNQ);
     }
     for (int j = threadIdx.x; j < P.n; j += kBlock) {
         col_terms(P, j, P.x, P.aty, acc);
         if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
+        if (rays) col_ray_terms(P, j, acc + 2 * kNQ);
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < 2 * kNQ; ++q) {
+    for (int q = 0; q < kNT; ++q) {
         const double v = wave_sum(acc[q]);
-        if (lane == 0) red16[w * 2 * kNQ + q] = v;
+        if (lane == 0) red16[w * kNT + q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 2 * kNQ) {
+    if (threadIdx.x < kNT) {
         double t = 0.0;
-        for (int k = 0; k < kBlock / 64; ++k) t += red16[k * 2 * kNQ + threadIdx.x];
+        for (int k = 0; k < kBlock / 64; ++k) t += red16[k * kNT + threadIdx.x];
         tot[threadIdx.x] = t;
     }
     __syncthreads();
@@ -1250,6 +1350,7 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
         ssc->tau = ssc->eta / ssc->omega;
         ssc->sigma = ssc->eta * ssc->omega;
         ssc->eps_rel = J.eps_rel;
+        ssc->eps_infeas = J.eps_infeas;
         ssc->max_iters = J.max_iters;
         ssc->eval_every = J.eval_every;
         ssc->restarts_on = J.restarts_on;
@@ -1272,6 +1373,10 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
     wg_kkt(P, 1, tot, red16);
     if (tid == 0) decide_logic(P, ssc, tot, 1);
     __syncthreads();
+    if (ssc->status == kRunning) {
+        for (int g = tid; g < mx; g += kBlock) save_prev_at(P, 0, g);
+        __syncthreads();
+    }
     if (P.fp32 && ssc->status == kRunning) {
         for (int g = tid; g < mx; g += kBlock) rebase_at(P, 1, g);
         __syncthreads();
@@ -1341,6 +1446,10 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
         if (tid == 0) decide_logic(P, ssc, tot, 0);
         __syncthreads();
         const int lr = ssc->last_restart;
+        if (ssc->status == kRunning) {
+            for (int g = tid; g < mx; g += kBlock) save_prev_at(P, lr, g);
+            __syncthreads();
+        }
         if (lr) {
             for (int g = tid; g < mx; g += kBlock) {
                 if (P.fp32) rebase_at(P, lr, g);
@@ -1349,7 +1458,7 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
             __syncthreads();
         }
     }
-    for (int g = tid; g < mx; g += kBlock) extract_at(P, ssc->out_avg, g);
+    for (int g = tid; g < mx; g += kBlock) extract_at(P, ssc->out_avg, ssc->status, ssc->ray_scale, g);
     __syncthreads();
     if (tid == 0) *P.sc = *ssc;
 }
@@ -1360,8 +1469,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, con
                                                         int* counter) {
     __shared__ double lds[kTileNnz];
     __shared__ double red[kBlock / 64];
-    __shared__ double red16[(kBlock / 64) * 2 * kNQ];
-    __shared__ double tot[2 * kNQ];
+    __shared__ double red16[(kBlock / 64) * kNT];
+    __shared__ double tot[kNT];
     __shared__ Scalars ssc;
     __shared__ int job;
     for (;;) {
@@ -1469,16 +1578,20 @@ __global__ __launch_bounds__(kBlock) void multi_elem_kernel(const BatchJob* jobs
     if (OP == EO_INIT) {
         init_state_at(P, g, J.x0, J.y0);
     } else if (OP == EO_REBASE_INIT) {
-        if (P.fp32 && sc->status == kRunning) rebase_at(P, 1, g);
+        if (sc->status != kRunning) return;
+        save_prev_at(P, 0, g);
+        if (P.fp32) rebase_at(P, 1, g);
     } else if (OP == EO_MATERIALIZE) {
         if (P.fp32 && sc->status == kRunning) materialize_at(P, g);
     } else if (OP == EO_APPLY) {
+        if (sc->status != kRunning) return;
         const int lr = sc->last_restart;
+        save_prev_at(P, lr, g);
         if (lr == 0) return;
         if (P.fp32) rebase_at(P, lr, g);
         else apply_restart_at(P, lr, g);
     } else {
-        extract_at(P, sc->out_avg, g);
+        extract_at(P, sc->out_avg, sc->status, sc->ray_scale, g);
     }
 }
 
@@ -1491,6 +1604,7 @@ __global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
     sc->tau = sc->eta / sc->omega;
     sc->sigma = sc->eta * sc->omega;
     sc->eps_rel = J.eps_rel;
+    sc->eps_infeas = J.eps_infeas;
     sc->max_iters = J.max_iters;
     sc->eval_every = J.eval_every;
     sc->restarts_on = J.restarts_on;
@@ -1583,10 +1697,10 @@ void launch_finalize_setup(const DevLP& P, double eta_override, double omega_ove
                        c0);
 }
 
-void launch_reset(const DevLP& P, double eps_rel, long long max_iters, int eval_every, int restarts_on,
-                  long long trace_cap, hipStream_t s) {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, P.sc, eps_rel, max_iters, eval_every, restarts_on,
-                       trace_cap);
+void launch_reset(const DevLP& P, double eps_rel, double eps_infeas, long long max_iters, int eval_every,
+                  int restarts_on, long long trace_cap, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, P.sc, eps_rel, eps_infeas, max_iters, eval_every,
+                       restarts_on, trace_cap);
 }
 
 void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s) {
@@ -1668,6 +1782,10 @@ void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
         }
         hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
         hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
+        if (mode == 0 && P.xp) {
+            const int mx = P.m > P.n ? P.m : P.n;
+            hipLaunchKernelGGL(save_prev_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+        }
         return;
     }
     if (mode == 1) {
@@ -1682,6 +1800,10 @@ void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
     }
     hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
     hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
+    if (mode != 2 && P.xp) {
+        const int mx = P.m > P.n ? P.m : P.n;
+        hipLaunchKernelGGL(save_prev_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+    }
     if (P.fp32 && mode == 1) {
         const int mx = P.m > P.n ? P.m : P.n;
         hipLaunchKernelGGL(rebase_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, 1);

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import paper_2604_23951_amd as lpg
+from test_oracle_infeasible import check_primal_ray
 import synth
 from conftest import golden_lps
 
@@ -94,17 +95,24 @@ def test_admission_respects_hbm_budget():
         s.close()
 
 
-def test_failure_is_isolated():
+@pytest.mark.parametrize("eps_infeas", [1e-8, 0.0])
+def test_failure_is_isolated(eps_infeas):
+    """An unbounded request among feasible ones: with certificates on it ends with a primal
+    ray, with them off at the iteration limit; the others get their solo results either way."""
     lps = _pool()[:5]
     bad, _ = golden_lps()["T3"]
-    bad.x_hi = np.array([np.inf, 4.0])  # unbounded: never converges
+    bad.x_hi = np.array([np.inf, 4.0])  # unbounded
     mix = lps[:2] + [bad] + lps[2:]
     solvers = [lpg.Solver(lp, spmv_layout=1, deferred=1) for lp in mix]
-    with lpg.Server(1 << 34, 16, eps_rel=1e-5, max_iters=20000) as srv:
+    with lpg.Server(1 << 34, 16, eps_rel=1e-5, max_iters=20000, eps_infeas=eps_infeas) as srv:
         tickets = [srv.submit(s) for s in solvers]
         srv.wait(120.0)
         sols = [srv.result(t) for t in tickets]
-    assert sols[2].status == "iteration_limit"
+    if eps_infeas > 0:
+        assert sols[2].status == "dual_infeasible"
+        check_primal_ray(bad, sols[2].x, 2 * eps_infeas)
+    else:
+        assert sols[2].status == "iteration_limit"
     for lp, sol in zip(lps, sols[:2] + sols[3:]):
         with lpg.Solver(lp, spmv_layout=1, eps_rel=1e-5, max_iters=20000) as s1:
             ref = s1.solve()
