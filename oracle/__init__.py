@@ -64,6 +64,7 @@ class _OptsStruct(C.Structure):
         ("seed", C.c_uint64), ("x0", C.c_void_p), ("y0", C.c_void_p),
         ("n_snap", C.c_int32), ("pad1", C.c_int32), ("snap_k", C.c_void_p), ("snap_out", C.c_void_p),
         ("trace_cap", C.c_int32), ("pad2", C.c_int32), ("trace", C.c_void_p), ("eps_infeas", C.c_double),
+        ("method", C.c_int32), ("pad3", C.c_int32), ("reflection", C.c_double),
     ]
 
 
@@ -222,7 +223,8 @@ class Result:
 def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int = 64, scaling: bool = True,
           ruiz_passes: int = 10, pow_iters: int = 200, restarts: bool = True, eta: float = 0.0,
           omega0: float = 0.0, seed: int = 0x5EED0C0FFEE, x0=None, y0=None,
-          snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8) -> Result:
+          snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8, method: int = 0,
+          reflection: float = 1.0) -> Result:
     """Run the oracle. `snap_k` lists iterations whose scaled-space state
     (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration."""
     b = _Bound(lp)
@@ -239,6 +241,8 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     o.omega0 = omega0
     o.seed = seed
     o.eps_infeas = eps_infeas
+    o.method = method
+    o.reflection = reflection
     keep = []
     if x0 is not None:
         x0 = np.ascontiguousarray(x0, dtype=np.float64)

@@ -73,6 +73,9 @@ typedef struct {
     int32_t trace_cap, pad2;
     double *trace;       /* trace_cap * ORA_TRACE_W */
     double eps_infeas;   /* relative tolerance of the infeasibility certificates; 0: off */
+    int32_t method;      /* 0: averaged PDHG; 1: reflected Halpern PDHG */
+    int32_t pad3;
+    double reflection;   /* rho of the Halpern form, in [0, 1] */
 } ora_opts;
 
 typedef struct {
@@ -525,6 +528,8 @@ void ora_default_opts(ora_opts *o) {
     o->omega0 = 0.0;
     o->seed = 0x5EED0C0FFEEull;
     o->eps_infeas = 1e-8;
+    o->method = 0;
+    o->reflection = 1.0;
 }
 
 /* Export the scaled problem: A~ values (in the caller's CSR order), R, C, and A~^T. */
@@ -590,7 +595,12 @@ int ora_kkt(const ora_lp *lp, const double *x, const double *y, double *out, dou
  *     (iii) t >= 0.36 k.
  * O11 on restart omega <- sqrt(omega * dy / dx) when dx, dy > 1e-10 (the theta = 1/2 smoothing
  *     of log omega toward log(dy/dx)), the candidate becomes iterate, anchor and average.
- * O12 x = C x~, y = R y~, z = projected reduced cost. */
+ * O12 x = C x~, y = R y~, z = projected reduced cost.
+ *
+ * Halpern form (method 1, a reading of the newer cuPDLPx-family iteration the paper names):
+ * the iterate is z <- w ((1 + rho) T(z) - rho z) + (1 - w) z_anchor with T the map of O7,
+ * w = (t + 1) / (t + 2); no averages; O8-O11 act on T(z) (the only candidate), a restart
+ * moves the iterate and the anchor to T(z). */
 int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out, double *z_out,
               ora_info *info) {
     double t0 = now_s();
@@ -613,6 +623,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     /* point at the previous evaluation (after its restart decision), for the candidate rays */
     double *xp = (double *)malloc(nb), *atyp = (double *)malloc(nb);
     double *yp = (double *)malloc(mb), *axp = (double *)malloc(mb);
+    double *axan = (double *)malloc(mb); /* A~ x~ of the anchor (Halpern form) */
+    const int halpern = o->method == 1;
+    const double rho = o->reflection;
 
     /* a3 / O5: step size */
     double sig = 0.0;
@@ -643,6 +656,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     }
     csr_mv(m, P.rp, P.ci, P.av, x, ax);
     csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
+    memcpy(axan, ax, sizeof(double) * (size_t)m);
+    memcpy(axa, ax, sizeof(double) * (size_t)m);
+    memcpy(atya, aty, nb);
     kkt_t Kc, Ka, Kanc;
     eval_kkt(&P, x, y, ax, aty, &Kc, NULL);
     memcpy(xp, x, nb);
@@ -665,6 +681,37 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     else if (o->max_iters <= 0) status = ORA_ITERATION_LIMIT;
 
     while (status < 0) {
+        if (halpern) {
+            /* Reflected Halpern PDHG (a reading; the paper names cuPDLPx's family but does not
+             * print its iteration): with T the PDHG map of O7 and the anchor z0 of the current
+             * restart cycle, z <- w ((1 + rho) T(z) - rho z) + (1 - w) z0, w = (t + 1) / (t + 2),
+             * t the iterations since the restart. xa, ya hold T(z) (bounded and sign-feasible),
+             * axa = A~ xa; A~x of the Halpern iterate follows by linearity. */
+            csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
+            for (int32_t j = 0; j < n; j++) {
+                double g = P.c[j] - aty[j];
+                double xn = x[j] - tau * g;
+                xa[j] = clampd(xn, P.xlo[j], P.xhi[j]);
+            }
+            csr_mv(m, P.rp, P.ci, P.av, xa, axa);
+            for (int32_t i = 0; i < m; i++) {
+                double w = 2.0 * axa[i] - ax[i];
+                double v = y[i] - sigma * w;
+                double lo = v + sigma * P.blo[i];
+                double hi = v + sigma * P.bhi[i];
+                ya[i] = (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
+            }
+            double wk = (double)(t + 1) / (double)(t + 2);
+            double wa = 1.0 - wk;
+            double r1 = 1.0 + rho;
+            for (int32_t j = 0; j < n; j++) x[j] = wk * (r1 * xa[j] - rho * x[j]) + wa * xan[j];
+            for (int32_t i = 0; i < m; i++) {
+                y[i] = wk * (r1 * ya[i] - rho * y[i]) + wa * yan[i];
+                ax[i] = wk * (r1 * axa[i] - rho * ax[i]) + wa * axan[i];
+            }
+            k++;
+            t++;
+        } else {
         /* O7: primal step (A~^T y computed for the current y) */
         csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
         for (int32_t j = 0; j < n; j++) {
@@ -692,6 +739,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             for (int32_t j = 0; j < n; j++) xa[j] = xa[j] + wt * (x[j] - xa[j]);
             for (int32_t i = 0; i < m; i++) ya[i] = ya[i] + wt * (y[i] - ya[i]);
         }
+        }
         while (snap_i < o->n_snap && o->snap_k[snap_i] < k) snap_i++;
         if (snap_i < o->n_snap && o->snap_k[snap_i] == k) {
             double *s = o->snap_out + (size_t)snap_i * (2 * (size_t)n + 2 * (size_t)m);
@@ -703,12 +751,21 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         }
         if (!(k % o->eval_every == 0 || k >= o->max_iters)) continue;
 
-        /* O8 */
+        /* O8 (Halpern form: the only candidate is T(z) = (xa, ya), whose A~x is axa) */
+        if (halpern) {
+            csr_mv(n, P.rpT, P.ciT, P.avT, ya, atya);
+            eval_kkt(&P, xa, ya, axa, atya, &Kc, NULL);
+            Ka = Kc;
+        } else {
         csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
         csr_mv(m, P.rp, P.ci, P.av, xa, axa);
         csr_mv(n, P.rpT, P.ciT, P.avT, ya, atya);
         eval_kkt(&P, x, y, ax, aty, &Kc, NULL);
         eval_kkt(&P, xa, ya, axa, atya, &Ka, NULL);
+        }
+        /* the point each evaluation looks at: (x, y) or, in the Halpern form, T(z) */
+        const double *ex = halpern ? xa : x, *ey = halpern ? ya : y;
+        const double *eax = halpern ? axa : ax, *eaty = halpern ? atya : aty;
         double kc = kkt_omega(&Kc, omega), ka = kkt_omega(&Ka, omega);
         double rec[ORA_TRACE_W];
         memset(rec, 0, sizeof(rec));
@@ -725,21 +782,23 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             status = ORA_NUMERICAL_ERROR;
         } else if (Kc.erel <= o->eps_rel) {
             status = ORA_OPTIMAL;
+            out_avg = halpern;
         } else if (Ka.erel <= o->eps_rel) {
             status = ORA_OPTIMAL;
             out_avg = 1;
         } else {
             if (o->eps_infeas > 0.0) {
-                eval_rays(&P, x, y, ax, aty, xp, yp, axp, atyp, &Rray, NULL, NULL, NULL);
+                eval_rays(&P, ex, ey, eax, eaty, xp, yp, axp, atyp, &Rray, NULL, NULL, NULL);
                 if (Rray.D > 0.0 && sqrt(Rray.rd2) <= o->eps_infeas * Rray.D) status = ORA_PRIMAL_INFEASIBLE;
                 else if (Rray.G > 0.0 && sqrt(Rray.rp2) <= o->eps_infeas * Rray.G) status = ORA_DUAL_INFEASIBLE;
             }
             if (status < 0 && k >= o->max_iters) {
                 status = ORA_ITERATION_LIMIT;
-                out_avg = Ka.erel < Kc.erel;
+                out_avg = halpern ? 1 : Ka.erel < Kc.erel;
             }
         }
         if (status >= 0) {
+            if (status == ORA_PRIMAL_INFEASIBLE || status == ORA_DUAL_INFEASIBLE) out_avg = halpern;
             rec[6] = out_avg;
             rec[8] = omega;
             rec[11] = INFINITY;
@@ -748,7 +807,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             break;
         }
         /* O10 */
-        int use_avg = ka < kc;
+        int use_avg = halpern ? 1 : ka < kc;
         double kcand = use_avg ? ka : kc;
         double margin = fabs(ka - kc) / fmax(fmax(ka, kc), 1e-300);
         int why = 0;
@@ -776,6 +835,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
                 memcpy(x, xa, nb);
                 memcpy(y, ya, sizeof(double) * (size_t)m);
                 memcpy(ax, axa, sizeof(double) * (size_t)m);
+                memcpy(axan, axa, sizeof(double) * (size_t)m);
                 Kanc = Ka;
             } else {
                 memcpy(xa, x, nb);
@@ -792,10 +852,17 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             kkt_prev = kcand;
         }
         /* the point the next evaluation's rays start from */
-        memcpy(xp, x, nb);
-        memcpy(yp, y, sizeof(double) * (size_t)m);
-        memcpy(axp, ax, sizeof(double) * (size_t)m);
-        memcpy(atyp, (why && use_avg) ? atya : aty, nb);
+        if (halpern) {
+            memcpy(xp, xa, nb);
+            memcpy(yp, ya, sizeof(double) * (size_t)m);
+            memcpy(axp, axa, sizeof(double) * (size_t)m);
+            memcpy(atyp, atya, nb);
+        } else {
+            memcpy(xp, x, nb);
+            memcpy(yp, y, sizeof(double) * (size_t)m);
+            memcpy(axp, ax, sizeof(double) * (size_t)m);
+            memcpy(atyp, (why && use_avg) ? atya : aty, nb);
+        }
         rec[8] = omega;
         if (o->trace && ntr < o->trace_cap) memcpy(o->trace + ntr * ORA_TRACE_W, rec, sizeof(rec));
         ntr++;
@@ -820,7 +887,8 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     if (status == ORA_PRIMAL_INFEASIBLE || status == ORA_DUAL_INFEASIBLE) {
         /* the certificate, normalised so that D = 1 (dual ray in y, z) or G = 1 (primal ray in x) */
         double *xr = (double *)malloc(nb), *yr = (double *)malloc(mb), *zr = (double *)malloc(nb);
-        eval_rays(&P, x, y, ax, aty, xp, yp, axp, atyp, &Rray, xr, yr, zr);
+        if (halpern) eval_rays(&P, xa, ya, axa, atya, xp, yp, axp, atyp, &Rray, xr, yr, zr);
+        else eval_rays(&P, x, y, ax, aty, xp, yp, axp, atyp, &Rray, xr, yr, zr);
         if (status == ORA_PRIMAL_INFEASIBLE) {
             double s = 1.0 / Rray.D;
             if (y_out)
@@ -850,7 +918,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     info->sigma_max = sig;
     info->eta = eta;
     info->omega = omega;
-    free(xp); free(yp); free(axp); free(atyp);
+    free(xp); free(yp); free(axp); free(atyp); free(axan);
     free(x); free(xa); free(xan); free(aty); free(atya);
     free(y); free(ya); free(yan); free(ax); free(axn); free(axa);
     prob_free(&P);

@@ -51,11 +51,12 @@ def check_primal_ray(lp, x, tol):
     assert np.linalg.norm(viol(v, lp.b_lo, lp.b_hi)) ** 2 + np.linalg.norm(viol(x, lp.x_lo, lp.x_hi)) ** 2 <= tol ** 2
 
 
+@pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("name", ["I1", "I2", "U1", "U2"])
-def test_hand_built_infeasible_lps(oracle_lib, name):
+def test_hand_built_infeasible_lps(oracle_lib, name, method):
     lp, spec = infeasible_lps()[name]
     assert highs(lp)["status"] == ("infeasible" if spec["status"] == "primal_infeasible" else "unbounded")
-    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=20000, eps_infeas=EPS)
+    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=20000, eps_infeas=EPS, method=method)
     assert r.status == spec["status"], (r.status, r.iters)
     if r.status == "primal_infeasible":
         check_dual_ray(lp, r.y, r.z, 2 * EPS)
@@ -103,31 +104,34 @@ def _free_descent_column(base, rng):
     return synth.tiny_lp(spec)
 
 
+@pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("j", range(3))
-def test_random_primal_infeasible(oracle_lib, j):
+def test_random_primal_infeasible(oracle_lib, j, method):
     rng = np.random.default_rng([synth.SEED_ROOT, 6, j])
     base = synth.kkt_constructed(40, 80, synth.random_sparse_pattern(40, 80, 0.08, rng), rng, eq_frac=0.5)
     lp = _contradicting_rows(base, rng, 1 + j)
     assert highs(lp)["status"] == "infeasible"
-    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=100000, eps_infeas=EPS)
+    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=100000, eps_infeas=EPS, method=method)
     assert r.status == "primal_infeasible", (r.status, r.iters)
     check_dual_ray(lp, r.y, r.z, 2 * EPS)
 
 
+@pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("j", range(3))
-def test_random_unbounded(oracle_lib, j):
+def test_random_unbounded(oracle_lib, j, method):
     rng = np.random.default_rng([synth.SEED_ROOT, 7, j])
     base = synth.kkt_constructed(40, 80, synth.random_sparse_pattern(40, 80, 0.08, rng), rng, eq_frac=0.3)
     lp = _free_descent_column(base, rng)
     assert highs(lp)["status"] == "unbounded"
-    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=100000, eps_infeas=EPS)
+    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=100000, eps_infeas=EPS, method=method)
     assert r.status == "dual_infeasible", (r.status, r.iters)
     check_primal_ray(lp, r.x, 2 * EPS)
 
 
+@pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("j", range(4))
-def test_no_false_certificate_on_feasible_lps(oracle_lib, j):
+def test_no_false_certificate_on_feasible_lps(oracle_lib, j, method):
     """Feasible, bounded LPs solved to a tight tolerance never report a certificate."""
     lp = synth.cfg0(j) if j < 2 else synth.transportation(40 + 20 * j, np.random.default_rng(j))
-    r = oracle_lib.solve(lp, eps_rel=1e-7, max_iters=200000, eps_infeas=EPS)
+    r = oracle_lib.solve(lp, eps_rel=1e-7, max_iters=200000, eps_infeas=EPS, method=method)
     assert r.status == "optimal"

@@ -30,6 +30,10 @@ MUTANTS = {
     "dual_residual_unscaled": ("double rdo = rds * P->Ci[k];", "double rdo = rds;"),
     "ray_objective_sign": ("if (zs > 0.0) D += P->oxlo[k] * zs;", "if (zs > 0.0) D -= P->oxlo[k] * zs;"),
     "ray_row_cone_side": ("else if (flo) w = v < 0.0 ? v : 0.0;", "else if (flo) w = v > 0.0 ? v : 0.0;"),
+    "halpern_anchor_weight": ("double wk = (double)(t + 1) / (double)(t + 2);",
+                              "double wk = (double)(t + 1) / (double)(t + 3);"),
+    "halpern_reflection_sign": ("x[j] = wk * (r1 * xa[j] - rho * x[j]) + wa * xan[j];",
+                                "x[j] = wk * (r1 * xa[j] + rho * x[j]) + wa * xan[j];"),
 }
 
 QUICK = [
@@ -39,6 +43,7 @@ QUICK = [
     "tests/test_oracle_exact.py::test_kkt_point_is_fixed_point",
     "tests/test_oracle_structure.py",
     "tests/test_oracle_infeasible.py",
+    "tests/test_oracle_halpern.py",
 ]
 
 
