@@ -579,6 +579,23 @@ int ora_kkt(const ora_lp *lp, const double *x, const double *y, double *out, dou
 
 /* ------------------------------------------------------------------ O4 - O12 */
 
+/* O7, primal half of the PDHG map: x+ = clamp(x - tau (c~ - A~^T y)) for one column. */
+static double primal_step(double x, double c, double aty, double tau, double lo, double hi) {
+    double g = c - aty;
+    double xn = x - tau * g;
+    return clampd(xn, lo, hi);
+}
+
+/* O7, dual half: v = y - sigma (2 A~x+ - A~x), y+ = max(v + sigma b~lo, 0) + min(v + sigma b~hi, 0)
+ * (the closed-form prox of the row bounds) for one row. */
+static double dual_step(double y, double axn, double ax, double sigma, double blo, double bhi) {
+    double w = 2.0 * axn - ax;
+    double v = y - sigma * w;
+    double lo = v + sigma * blo;
+    double hi = v + sigma * bhi;
+    return (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
+}
+
 /* Restarted, averaged PDHG (primal step first) on the scaled problem.
  *
  * O4  omega0 = ||c~|| / ||q~|| when both exceed 1e-10, else 1 (q: combined bounds).
@@ -688,19 +705,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
              * t the iterations since the restart. xa, ya hold T(z) (bounded and sign-feasible),
              * axa = A~ xa; A~x of the Halpern iterate follows by linearity. */
             csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
-            for (int32_t j = 0; j < n; j++) {
-                double g = P.c[j] - aty[j];
-                double xn = x[j] - tau * g;
-                xa[j] = clampd(xn, P.xlo[j], P.xhi[j]);
-            }
+            for (int32_t j = 0; j < n; j++) xa[j] = primal_step(x[j], P.c[j], aty[j], tau, P.xlo[j], P.xhi[j]);
             csr_mv(m, P.rp, P.ci, P.av, xa, axa);
-            for (int32_t i = 0; i < m; i++) {
-                double w = 2.0 * axa[i] - ax[i];
-                double v = y[i] - sigma * w;
-                double lo = v + sigma * P.blo[i];
-                double hi = v + sigma * P.bhi[i];
-                ya[i] = (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
-            }
+            for (int32_t i = 0; i < m; i++) ya[i] = dual_step(y[i], axa[i], ax[i], sigma, P.blo[i], P.bhi[i]);
             double wk = (double)(t + 1) / (double)(t + 2);
             double wa = 1.0 - wk;
             double r1 = 1.0 + rho;
@@ -714,19 +721,11 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         } else {
         /* O7: primal step (A~^T y computed for the current y) */
         csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
-        for (int32_t j = 0; j < n; j++) {
-            double g = P.c[j] - aty[j];
-            double xn = x[j] - tau * g;
-            x[j] = clampd(xn, P.xlo[j], P.xhi[j]);
-        }
+        for (int32_t j = 0; j < n; j++) x[j] = primal_step(x[j], P.c[j], aty[j], tau, P.xlo[j], P.xhi[j]);
         /* O7: dual step with the extrapolation 2 A~x+ - A~x */
         csr_mv(m, P.rp, P.ci, P.av, x, axn);
         for (int32_t i = 0; i < m; i++) {
-            double w = 2.0 * axn[i] - ax[i];
-            double v = y[i] - sigma * w;
-            double lo = v + sigma * P.blo[i];
-            double hi = v + sigma * P.bhi[i];
-            y[i] = (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
+            y[i] = dual_step(y[i], axn[i], ax[i], sigma, P.blo[i], P.bhi[i]);
             ax[i] = axn[i];
         }
         k++;

@@ -13,9 +13,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "pdhg_oracle.c")
 
 MUTANTS = {
-    "primal_step_sign": ("double xn = x[j] - tau * g;", "double xn = x[j] + tau * g;"),
-    "no_extrapolation": ("double w = 2.0 * axn[i] - ax[i];", "double w = axn[i];"),
-    "dual_prox_sign": ("double lo = v + sigma * P.blo[i];", "double lo = v - sigma * P.blo[i];"),
+    "primal_step_sign": ("double xn = x - tau * g;", "double xn = x + tau * g;"),
+    "no_extrapolation": ("double w = 2.0 * axn - ax;", "double w = axn;"),
+    "dual_prox_sign": ("double lo = v + sigma * blo;", "double lo = v - sigma * blo;"),
     "swapped_sign_cone": ("else if (flo && !fhi) zs = ls > 0.0 ? ls : 0.0;",
                           "else if (flo && !fhi) zs = ls < 0.0 ? ls : 0.0;"),
     "dropped_dual_bound_term": ("if (zo > 0.0) dobj += P->oxlo[k] * zo;", "if (zo > 0.0) dobj += 0.0;"),
