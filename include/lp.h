@@ -81,6 +81,17 @@ typedef enum {
                                 correction data are recomputed in FP64 (iterative refinement) */
 } lp_precision;
 
+typedef enum {
+    LP_METHOD_AVERAGED = 0, /* restarted PDHG with running averages (PDLP family): the averages
+                               and the iterate are the candidates of every evaluation */
+    LP_METHOD_HALPERN = 1   /* reflected Halpern PDHG: z <- w ((1 + rho) T(z) - rho z) + (1 - w) z0
+                               with T the PDHG map, z0 the anchor of the restart cycle and
+                               w = (t + 1) / (t + 2) after t iterations of the cycle; the PDHG
+                               output T(z) is the only candidate (termination, restarts,
+                               certificates and the returned point), a restart moves the iterate
+                               and the anchor to it (the newer cuPDLPx-family form) */
+} lp_method;
+
 typedef struct lp_options {
     double eps_rel;        /* relative tolerance on E_rel (default 1e-4) */
     int64_t max_iters;     /* iteration limit (default 100000) */
@@ -116,6 +127,9 @@ typedef struct lp_options {
                               displacement of the iterate since the previous evaluation is
                               tested as a dual ray (primal infeasibility) and as a primal ray
                               (dual infeasibility); see LP_PRIMAL_INFEASIBLE / LP_DUAL_INFEASIBLE */
+    int32_t method;        /* lp_method (default LP_METHOD_AVERAGED) */
+    int32_t pad2;
+    double reflection;     /* rho of LP_METHOD_HALPERN, in [0, 1] (default 1) */
 } lp_options;
 
 typedef struct lp_info {

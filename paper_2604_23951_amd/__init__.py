@@ -22,6 +22,8 @@ ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONS
           8: "LP_ERR_INTERNAL"}
 STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_error", 4: "primal_infeasible",
           5: "dual_infeasible"}
+LP_METHOD_AVERAGED = 0
+LP_METHOD_HALPERN = 1
 LP_PREC_FP64 = 0
 LP_PREC_FP32_REFINED = 1
 TRACE_WIDTH = 12
@@ -53,6 +55,7 @@ class lp_options(C.Structure):
         ("batch_wg_per_cu", C.c_int32),
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
         ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
+        ("method", C.c_int32), ("pad2", C.c_int32), ("reflection", C.c_double),
     ]
 
 

@@ -83,7 +83,7 @@ struct Prep {
 struct Offsets {
     size_t arp, aci, av, at, trp, tci, tv, tt, perm, c, xl, xu, C, Ci, bl, bu, R, Ri;
     size_t x, xa, xan, aty, atya, ox, oz, y, ya, yan, ax, axa, oy, x0, y0;
-    size_t xp, atyp, yp, axp;
+    size_t xp, atyp, yp, axp, axan;
     size_t f32[15] = {0};
     size_t pA[7] = {0}, pAT[7] = {0}, pA32 = 0, pAT32 = 0;
     size_t part, sc, tr;
@@ -230,7 +230,8 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 1 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
-        std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0)) {
+        std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
+        o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0)) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
     }
@@ -320,6 +321,8 @@ BatchJob make_job(lp_handle* h, const lp_options* bo) {
     J.P = h->P;
     J.eps_rel = o.eps_rel;
     J.eps_infeas = o.eps_infeas;
+    J.P.method = o.method;
+    J.P.rho = o.reflection;
     J.max_iters = o.max_iters;
     J.trace_cap = h->opt.trace_cap;
     J.eval_every = o.eval_every;
@@ -443,7 +446,7 @@ int32_t solve_block_diagonal(const std::vector<lp_handle*>& hs, const lp_options
         launch_multi(M, MULTI_RESET, 0, s);
         launch_multi(M, MULTI_INIT, 0, s);
         launch_multi(M, MULTI_AX_ALL, 0, s);
-        launch_multi(M, MULTI_ATY, 0, s);
+        launch_multi(M, MULTI_ATY, 1, s);  // 1: products of the initial point
         launch_multi(M, MULTI_PARTIALS, 1, s);
         launch_multi(M, MULTI_DECIDE, 1, s);
         launch_multi(M, MULTI_REBASE_INIT, 0, s);
@@ -617,6 +620,7 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
     O->atyp = L.add(sn);
     O->yp = L.add(sm);
     O->axp = L.add(sm);
+    O->axan = L.add(sm);
     O->x0 = h->has_x0 ? L.add(sn) : 0;
     O->y0 = h->has_y0 ? L.add(sm) : 0;
     const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
@@ -750,6 +754,7 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.atyp = D(O.atyp);
     P.yp = D(O.yp);
     P.axp = D(O.axp);
+    P.axan = D(O.axan);
     P.partials = D(O.part);
     P.sc = reinterpret_cast<Scalars*>(b + O.sc);
     P.trace = o.trace_cap > 0 ? D(O.tr) : nullptr;
@@ -1013,7 +1018,7 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
             launch_multi(M, MULTI_RESET, 0, s);
             launch_multi(M, MULTI_INIT, 0, s);
             launch_multi(M, MULTI_AX_ALL, 0, s);
-            launch_multi(M, MULTI_ATY, 0, s);
+            launch_multi(M, MULTI_ATY, 1, s);  // 1: products of the initial point
             launch_multi(M, MULTI_PARTIALS, 1, s);
             launch_multi(M, MULTI_DECIDE, 1, s);
             launch_multi(M, MULTI_REBASE_INIT, 0, s);
@@ -1278,6 +1283,8 @@ void lp_default_options(lp_options* o) {
     o->x0 = nullptr;
     o->y0 = nullptr;
     o->eps_infeas = 1e-8;
+    o->method = LP_METHOD_AVERAGED;
+    o->reflection = 1.0;
 }
 
 const char* lp_error_string(int32_t code) {
@@ -1374,6 +1381,8 @@ int32_t lp_solve(lp_handle* h) {
     try {
         HIP_TRY(h, hipSetDevice(h->device));
         if (int32_t rc = materialize(h)) return rc;
+        h->P.method = h->opt.method;
+        h->P.rho = h->opt.reflection;
         hipStream_t s = h->stream;
         const DevLP& P = h->P;
         const auto t0 = std::chrono::steady_clock::now();

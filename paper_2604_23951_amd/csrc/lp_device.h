@@ -96,6 +96,12 @@ struct DevLP {
     double *ax, *axa, *aty, *atya;    // A~x, A~x_avg, A~^T y, A~^T y_avg
     double *xan, *yan;                // anchor (start of the current restart cycle)
     double *xp, *yp, *axp, *atyp;     // point of the previous evaluation (candidate rays)
+    double *axan;                     // A~x of the anchor (Halpern form)
+    // iteration form of the current solve: 0 averaged PDHG, 1 reflected Halpern PDHG with
+    // reflection rho. In the Halpern form (x, y, ax) is the Halpern iterate and (xa, ya, axa)
+    // the PDHG output T(z), the only candidate of the evaluations.
+    int method;
+    double rho;
     double *partials;                 // nred * kNT
     Scalars* sc;
     double* trace;

@@ -564,6 +564,236 @@ struct EpiDual32 {
     }
 };
 
+// Reflected Halpern form (a reading of the newer cuPDLPx-family iteration): with T the PDHG map
+// above and the anchor z0 of the restart cycle, z <- w ((1 + rho) T(z) - rho z) + (1 - w) z0,
+// w = (t + 1) / (t + 2), t the iterations of the cycle before this one. The primal half on
+// column j, s = (A~^T y)_j: x+ = clamp(x - tau (c~ - s)), x <- w ((1 + rho) x+ - rho x) +
+// (1 - w) x0, and x+ is kept in xa for the dual half and the evaluations.
+struct EpiPrimalH {
+    struct Pre {
+        double c, lo, hi, x, xan;
+    };
+    const Scalars* sc;
+    int it;
+    const double *c, *xl, *xu, *xan;
+    double *x, *xa;
+    double tau, w, wa, r1, rho;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it;
+        tau = sc->tau;
+        w = static_cast<double>(t + 1) / static_cast<double>(t + 2);
+        wa = 1.0 - w;
+        r1 = 1.0 + rho;
+        return true;
+    }
+    __device__ Pre load(int j) const { return Pre{c[j], xl[j], xu[j], x[j], xan[j]}; }
+    __device__ void finish(int j, double s, const Pre& p) const {
+        const double g = p.c - s;
+        const double xp = clampd(p.x - tau * g, p.lo, p.hi);
+        x[j] = w * (r1 * xp - rho * p.x) + wa * p.xan;
+        xa[j] = xp;
+    }
+};
+
+// Dual half on row i, s = (A~ x+)_i: y+ = prox of y - sigma (2 s - (A~x)_i) as in EpiDual;
+// y <- w ((1 + rho) y+ - rho y) + (1 - w) y0, ya <- y+, axa <- s, and A~x of the new Halpern
+// iterate by linearity: ax <- w ((1 + rho) s - rho ax) + (1 - w) A~x0.
+struct EpiDualH {
+    struct Pre {
+        double y, bl, bu, ax, yan, axan;
+    };
+    const Scalars* sc;
+    int it;
+    const double *bl, *bu, *yan, *axan;
+    double *y, *ya, *ax, *axa;
+    double sigma, w, wa, r1, rho;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it;
+        sigma = sc->sigma;
+        w = static_cast<double>(t + 1) / static_cast<double>(t + 2);
+        wa = 1.0 - w;
+        r1 = 1.0 + rho;
+        return true;
+    }
+    __device__ Pre load(int i) const { return Pre{y[i], bl[i], bu[i], ax[i], yan[i], axan[i]}; }
+    __device__ void finish(int i, double s, const Pre& p) const {
+        const double w2 = 2.0 * s - p.ax;
+        const double v = p.y - sigma * w2;
+        const double lo = v + sigma * p.bl;
+        const double hi = v + sigma * p.bu;
+        const double yp = (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
+        y[i] = w * (r1 * yp - rho * p.y) + wa * p.yan;
+        ya[i] = yp;
+        axa[i] = s;
+        ax[i] = w * (r1 * s - rho * p.ax) + wa * p.axan;
+    }
+};
+
+// Halpern form in the FP32 storage form: the anchor is the FP64 master point, so in correction
+// space it is zero and the update is dz <- w ((1 + rho) T(dz) - rho dz).
+struct EpiPrimal32H {
+    struct Pre {
+        float d, lo, hi, x;
+    };
+    const Scalars* sc;
+    int it;
+    const float *d, *lo, *hi;
+    float *x, *xa;
+    float tau, w, r1, rho;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it;
+        tau = static_cast<float>(sc->tau);
+        w = static_cast<float>(static_cast<double>(t + 1) / static_cast<double>(t + 2));
+        r1 = 1.0f + rho;
+        return true;
+    }
+    __device__ Pre load(int j) const { return Pre{d[j], lo[j], hi[j], x[j]}; }
+    __device__ void finish(int j, float s, const Pre& p) const {
+        const float g = p.d - s;
+        float xp = p.x - tau * g;
+        if (xp < p.lo) xp = p.lo;
+        if (xp > p.hi) xp = p.hi;
+        x[j] = w * (r1 * xp - rho * p.x);
+        xa[j] = xp;
+    }
+};
+
+struct EpiDual32H {
+    struct Pre {
+        float y, rl, ru, yh, ax;
+    };
+    const Scalars* sc;
+    int it;
+    const float *rl, *ru, *yh;
+    float *y, *ya, *ax;
+    float sigma, w, r1, rho;
+    __device__ bool begin() {
+        if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
+        const long long t = sc->t + it;
+        sigma = static_cast<float>(sc->sigma);
+        w = static_cast<float>(static_cast<double>(t + 1) / static_cast<double>(t + 2));
+        r1 = 1.0f + rho;
+        return true;
+    }
+    __device__ Pre load(int i) const { return Pre{y[i], rl[i], ru[i], yh[i], ax[i]}; }
+    __device__ void finish(int i, float s, const Pre& p) const {
+        const float w2 = 2.0f * s - p.ax;
+        const float v = p.y - sigma * w2;
+        const float a = v + sigma * p.rl;
+        const float b = v + sigma * p.ru;
+        float yp;
+        if (a > -p.yh) yp = a;
+        else if (b < -p.yh) yp = b;
+        else yp = -p.yh;
+        y[i] = w * (r1 * yp - rho * p.y);
+        ya[i] = yp;
+        ax[i] = w * (r1 * s - rho * p.ax);
+    }
+};
+
+// Epilogues of the primal and dual halves for a solve's form and precision.
+__host__ __device__ inline EpiPrimal epi_primal(const DevLP& P, const Scalars* sc, int it) {
+    EpiPrimal e{};
+    e.sc = sc;
+    e.it = it;
+    e.c = P.c;
+    e.xl = P.xl;
+    e.xu = P.xu;
+    e.x = P.x;
+    e.xa = P.xa;
+    return e;
+}
+__host__ __device__ inline EpiDual epi_dual(const DevLP& P, const Scalars* sc, int it) {
+    EpiDual e{};
+    e.sc = sc;
+    e.it = it;
+    e.bl = P.bl;
+    e.bu = P.bu;
+    e.y = P.y;
+    e.ya = P.ya;
+    e.ax = P.ax;
+    return e;
+}
+__host__ __device__ inline EpiPrimal32 epi_primal32(const DevLP& P, const Scalars* sc, int it) {
+    EpiPrimal32 e{};
+    e.sc = sc;
+    e.it = it;
+    e.d = P.d32;
+    e.lo = P.lo32;
+    e.hi = P.hi32;
+    e.x = P.dx;
+    e.xa = P.dxa;
+    return e;
+}
+__host__ __device__ inline EpiDual32 epi_dual32(const DevLP& P, const Scalars* sc, int it) {
+    EpiDual32 e{};
+    e.sc = sc;
+    e.it = it;
+    e.rl = P.rl32;
+    e.ru = P.ru32;
+    e.yh = P.yh32;
+    e.y = P.dy;
+    e.ya = P.dya;
+    e.ax = P.adx;
+    return e;
+}
+__host__ __device__ inline EpiPrimalH epi_primal_h(const DevLP& P, const Scalars* sc, int it) {
+    EpiPrimalH e{};
+    e.sc = sc;
+    e.it = it;
+    e.c = P.c;
+    e.xl = P.xl;
+    e.xu = P.xu;
+    e.xan = P.xan;
+    e.x = P.x;
+    e.xa = P.xa;
+    e.rho = P.rho;
+    return e;
+}
+__host__ __device__ inline EpiDualH epi_dual_h(const DevLP& P, const Scalars* sc, int it) {
+    EpiDualH e{};
+    e.sc = sc;
+    e.it = it;
+    e.bl = P.bl;
+    e.bu = P.bu;
+    e.yan = P.yan;
+    e.axan = P.axan;
+    e.y = P.y;
+    e.ya = P.ya;
+    e.ax = P.ax;
+    e.axa = P.axa;
+    e.rho = P.rho;
+    return e;
+}
+__host__ __device__ inline EpiPrimal32H epi_primal32_h(const DevLP& P, const Scalars* sc, int it) {
+    EpiPrimal32H e{};
+    e.sc = sc;
+    e.it = it;
+    e.d = P.d32;
+    e.lo = P.lo32;
+    e.hi = P.hi32;
+    e.x = P.dx;
+    e.xa = P.dxa;
+    e.rho = static_cast<float>(P.rho);
+    return e;
+}
+__host__ __device__ inline EpiDual32H epi_dual32_h(const DevLP& P, const Scalars* sc, int it) {
+    EpiDual32H e{};
+    e.sc = sc;
+    e.it = it;
+    e.rl = P.rl32;
+    e.ru = P.ru32;
+    e.yh = P.yh32;
+    e.y = P.dy;
+    e.ya = P.dya;
+    e.ax = P.adx;
+    e.rho = static_cast<float>(P.rho);
+    return e;
+}
+
 template <class T, class Epi>
 void launch_tiles(const Csr& M, const T* xin, const Epi& epi, hipStream_t s) {
     if (M.ntiles <= 0) return;
@@ -867,9 +1097,9 @@ __device__ inline void col_terms(const DevLP& P, int j, const double* x, const d
 //   D = sum_i (b_lo y^+ - b_hi y^-) + sum_k (x_lo z^+ - x_hi z^-) over finite bounds;
 //   primal ray x^ = C (x~ - x~p), A x^ = R^-1 (A~x~ - A~x~p): rp2 = squared parts of A x^ and
 //   x^ outside the recession cones of the row and variable bounds, G = -c^T x^.
-__device__ inline void row_ray_terms(const DevLP& P, int i, double* acc) {
-    const double dy = (P.y[i] - P.yp[i]) * P.R[i];
-    const double v = (P.ax[i] - P.axp[i]) * P.Ri[i];
+__device__ inline void row_ray_terms(const DevLP& P, int i, const double* y, const double* ax, double* acc) {
+    const double dy = (y[i] - P.yp[i]) * P.R[i];
+    const double v = (ax[i] - P.axp[i]) * P.Ri[i];
     const double bl = P.bl[i], bu = P.bu[i], Ri = P.Ri[i];
     const bool flo = finite_d(bl), fhi = finite_d(bu);
     if (dy > 0.0 && flo) acc[1] += (bl * Ri) * dy;
@@ -885,8 +1115,8 @@ __device__ inline void row_ray_terms(const DevLP& P, int i, double* acc) {
     acc[2] += w * w;
 }
 
-__device__ inline void col_ray_terms(const DevLP& P, int j, double* acc) {
-    const double lam = -(P.aty[j] - P.atyp[j]) * P.Ci[j];
+__device__ inline void col_ray_terms(const DevLP& P, int j, const double* x, const double* aty, double* acc) {
+    const double lam = -(aty[j] - P.atyp[j]) * P.Ci[j];
     const double lo = P.xl[j], hi = P.xu[j], Cj = P.C[j];
     const bool flo = finite_d(lo), fhi = finite_d(hi);
     double zs = lam;
@@ -897,7 +1127,7 @@ __device__ inline void col_ray_terms(const DevLP& P, int j, double* acc) {
     acc[0] += r * r;
     if (zs > 0.0) acc[1] += (lo * Cj) * zs;
     if (zs < 0.0) acc[1] += (hi * Cj) * zs;
-    const double xh = (P.x[j] - P.xp[j]) * Cj;
+    const double xh = (x[j] - P.xp[j]) * Cj;
     acc[3] -= (P.c[j] * P.Ci[j]) * xh;
     double w = 0.0;
     if (flo && fhi) w = xh;
@@ -906,8 +1136,31 @@ __device__ inline void col_ray_terms(const DevLP& P, int j, double* acc) {
     acc[2] += w * w;
 }
 
-// Partial sums of the KKT quantities of the current iterate (slots 0..7), of the running
-// average (slots 8..15) and of the candidate rays (16..19). mode 1 (initial point) and
+// Per-thread sums of one evaluation over rows and columns start, start + stride, ...
+// Averaged form, mode 0: the current iterate (slots 0..7), the running average (8..15) and the
+// candidate rays of the current iterate (16..19). Halpern form, mode 0: the PDHG output
+// (xa, ya) in slots 0..7 and its rays. Modes 1 and 2: the current iterate only.
+__device__ inline void eval_terms(const DevLP& P, int mode, int start, int stride, double* acc) {
+    const bool both = mode == 0 && !P.method;
+    const bool cand = (mode == 0 || mode == 2) && P.method;
+    const bool rays = mode == 0 && P.xp != nullptr;
+    const double* ex = cand ? P.xa : P.x;
+    const double* ey = cand ? P.ya : P.y;
+    const double* eax = cand ? P.axa : P.ax;
+    const double* eaty = cand ? P.atya : P.aty;
+    for (int i = start; i < P.m; i += stride) {
+        row_terms(P, i, eax, ey, acc);
+        if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
+        if (rays) row_ray_terms(P, i, ey, eax, acc + 2 * kNQ);
+    }
+    for (int j = start; j < P.n; j += stride) {
+        col_terms(P, j, ex, eaty, acc);
+        if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
+        if (rays) col_ray_terms(P, j, ex, eaty, acc + 2 * kNQ);
+    }
+}
+
+// Partial sums of the evaluation quantities (see eval_terms) of one block. mode 1 (initial point) and
 // mode 2 (final point after a stop) evaluate the current iterate only; mode 2 runs whatever
 // the status.
 __device__ void kkt_partials_body(const DevLP& P, int mode, int blk, int nblk) {
@@ -916,19 +1169,7 @@ __device__ void kkt_partials_body(const DevLP& P, int mode, int blk, int nblk) {
     double acc[kNT];
 #pragma unroll
     for (int q = 0; q < kNT; ++q) acc[q] = 0.0;
-    const bool both = (mode == 0);
-    const bool rays = both && P.xp != nullptr;
-    const int stride = nblk * kBlock;
-    for (int i = blk * kBlock + threadIdx.x; i < P.m; i += stride) {
-        row_terms(P, i, P.ax, P.y, acc);
-        if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
-        if (rays) row_ray_terms(P, i, acc + 2 * kNQ);
-    }
-    for (int j = blk * kBlock + threadIdx.x; j < P.n; j += stride) {
-        col_terms(P, j, P.x, P.aty, acc);
-        if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
-        if (rays) col_ray_terms(P, j, acc + 2 * kNQ);
-    }
+    eval_terms(P, mode, blk * kBlock + threadIdx.x, nblk * kBlock, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < kNT; ++q) {
@@ -1000,8 +1241,8 @@ __device__ inline void set_output(Scalars* sc, const Kkt& K, int avg) {
 // iterate (0..7) and, in mode 0, of the average (8..15).
 __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int mode) {
     const Kkt cur = make_kkt(tot, sc);
-    if (mode == 2) {  // statistics of the current point after a host-side stop
-        set_output(sc, cur, 0);
+    if (mode == 2) {  // statistics of the returned point after a host-side stop
+        set_output(sc, cur, P.method ? 1 : 0);
         return;
     }
     if (mode == 1) {
@@ -1016,7 +1257,9 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         if (sc->status != kRunning) set_output(sc, cur, 0);
         return;
     }
-    const Kkt avg = make_kkt(tot + kNQ, sc);
+    // Halpern form: the PDHG output is the only candidate (slots 0..7), returned as "average"
+    const bool halpern = P.method != 0;
+    const Kkt avg = halpern ? cur : make_kkt(tot + kNQ, sc);
     long long ex = sc->max_iters - sc->k;
     if (ex > sc->eval_every) ex = sc->eval_every;
     const long long k = sc->k + ex;
@@ -1039,6 +1282,7 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         status = 3;
     } else if (cur.erel <= sc->eps_rel) {
         status = 0;
+        out_avg = halpern;
     } else if (avg.erel <= sc->eps_rel) {
         status = 0;
         out_avg = 1;
@@ -1053,9 +1297,10 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
                 sc->ray_scale = 1.0 / ray[3];
             }
         }
+        if (status != kRunning) out_avg = halpern;
         if (status == kRunning && k >= sc->max_iters) {
             status = 1;
-            out_avg = avg.erel < cur.erel;
+            out_avg = halpern ? 1 : avg.erel < cur.erel;
         }
     }
     sc->k = k;
@@ -1068,7 +1313,7 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         rec[8] = omega;
         rec[11] = __builtin_inf();
     } else {
-        const int use_avg = ka < kc;
+        const int use_avg = halpern ? 1 : ka < kc;
         const double kcand = use_avg ? ka : kc;
         const double anc = sc->kkt_anchor, prev = sc->kkt_prev;
         double margin = fabs(ka - kc) / fmax(fmax(ka, kc), 1e-300);
@@ -1155,6 +1400,7 @@ __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
             v = P.ya[g];
             P.y[g] = v;
             P.ax[g] = P.axa[g];
+            if (P.method) P.axan[g] = P.axa[g];
         } else {
             v = P.y[g];
             P.ya[g] = v;
@@ -1165,9 +1411,19 @@ __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
 
 // The point the next evaluation's rays start from: the current iterate, or the average when
 // this evaluation restarts there (lr == 2).
-__device__ inline void save_prev_at(const DevLP& P, int lr, int g) {
+// In the Halpern form the evaluated point is always the PDHG output; after the initial
+// evaluation (init) it equals the start, whose products A~x, A~^T y also seed axa, atya and
+// the anchor's A~x.
+__device__ inline void save_prev_at(const DevLP& P, int lr, bool init, int g) {
+    if (init && P.method) {
+        if (g < P.n) P.atya[g] = P.aty[g];
+        if (g < P.m) {
+            P.axa[g] = P.ax[g];
+            P.axan[g] = P.ax[g];
+        }
+    }
     if (P.xp == nullptr) return;
-    const bool avg = lr == 2;
+    const bool avg = lr == 2 || (P.method && !init);
     if (g < P.n) {
         P.xp[g] = avg ? P.xa[g] : P.x[g];
         P.atyp[g] = avg ? P.atya[g] : P.aty[g];
@@ -1178,9 +1434,9 @@ __device__ inline void save_prev_at(const DevLP& P, int lr, int g) {
     }
 }
 
-__global__ void save_prev_kernel(DevLP P) {
+__global__ void save_prev_kernel(DevLP P, int init) {
     if (P.sc->status != kRunning) return;
-    save_prev_at(P, P.sc->last_restart, blockIdx.x * blockDim.x + threadIdx.x);
+    save_prev_at(P, init ? 0 : P.sc->last_restart, init != 0, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 __global__ void apply_restart_kernel(DevLP P) {
@@ -1206,11 +1462,15 @@ __device__ inline void extract_at(const DevLP& P, int avg, int status, double sc
     const double* at = avg ? P.atya : P.aty;
     const bool dual_ray = status == 4 && P.xp != nullptr;
     const bool primal_ray = status == 5 && P.xp != nullptr;
+    // the rays start at the evaluated point: (x, y) or, in the Halpern form, the PDHG output
+    const double* rx = P.method ? P.xa : P.x;
+    const double* ry = P.method ? P.ya : P.y;
+    const double* raty = P.method ? P.atya : P.aty;
     if (g < P.n) {
-        P.out_x[g] = primal_ray ? ((P.x[g] - P.xp[g]) * P.C[g]) * scale : xs[g] * P.C[g];
+        P.out_x[g] = primal_ray ? ((rx[g] - P.xp[g]) * P.C[g]) * scale : xs[g] * P.C[g];
         const bool flo = finite_d(P.xl[g]), fhi = finite_d(P.xu[g]);
         if (dual_ray) {
-            const double lam = -(P.aty[g] - P.atyp[g]) * P.Ci[g];
+            const double lam = -(raty[g] - P.atyp[g]) * P.Ci[g];
             double zs = lam;
             if (!flo && !fhi) zs = 0.0;
             else if (flo && !fhi) zs = lam > 0.0 ? lam : 0.0;
@@ -1225,7 +1485,7 @@ __device__ inline void extract_at(const DevLP& P, int avg, int status, double sc
             P.out_z[g] = zs * P.Ci[g];
         }
     }
-    if (g < P.m) P.out_y[g] = dual_ray ? ((P.y[g] - P.yp[g]) * P.R[g]) * scale : ys[g] * P.R[g];
+    if (g < P.m) P.out_y[g] = dual_ray ? ((ry[g] - P.yp[g]) * P.R[g]) * scale : ys[g] * P.R[g];
 }
 
 __global__ void extract_kernel(DevLP P) {
@@ -1305,24 +1565,21 @@ __device__ void wg_spmv(const Csr& M, const T* xin, const Epi& epi, double* lds,
     }
 }
 
-// KKT quantities of the current iterate (and of the average in mode 0) summed over the
-// whole LP by one workgroup in a fixed order; tot[0..15] in LDS afterwards.
+// One half-iteration by one workgroup: the epilogue's begin() sets its scalars (it always
+// runs here: the workgroup only iterates while the LP is running below max_iters).
+template <class T, class Epi>
+__device__ void wg_step(const Csr& M, const T* xin, Epi e, double* lds, double* red) {
+    e.begin();
+    wg_spmv(M, xin, e, lds, red);
+}
+
+// KKT quantities of the current iterate (and of the average in mode 0, of the candidate rays
+// in mode 0) summed over the whole LP by one workgroup in a fixed order; tot[] in LDS afterwards.
 __device__ void wg_kkt(const DevLP& P, int mode, double* tot, double* red16) {
     double acc[kNT];
 #pragma unroll
     for (int q = 0; q < kNT; ++q) acc[q] = 0.0;
-    const bool both = mode == 0;
-    const bool rays = both && P.xp != nullptr;
-    for (int i = threadIdx.x; i < P.m; i += kBlock) {
-        row_terms(P, i, P.ax, P.y, acc);
-        if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
-        if (rays) row_ray_terms(P, i, acc + 2 * kNQ);
-    }
-    for (int j = threadIdx.x; j < P.n; j += kBlock) {
-        col_terms(P, j, P.x, P.aty, acc);
-        if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
-        if (rays) col_ray_terms(P, j, acc + 2 * kNQ);
-    }
+    eval_terms(P, mode, threadIdx.x, kBlock, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < kNT; ++q) {
@@ -1374,7 +1631,7 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
     if (tid == 0) decide_logic(P, ssc, tot, 1);
     __syncthreads();
     if (ssc->status == kRunning) {
-        for (int g = tid; g < mx; g += kBlock) save_prev_at(P, 0, g);
+        for (int g = tid; g < mx; g += kBlock) save_prev_at(P, 0, true, g);
         __syncthreads();
     }
     if (P.fp32 && ssc->status == kRunning) {
@@ -1386,68 +1643,38 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
         for (int it = 0; it < E; ++it) {
             if (ssc->k + it >= ssc->max_iters) break;
             if (P.fp32) {
-                EpiPrimal32 ep{};
-                ep.sc = ssc;
-                ep.it = it;
-                ep.d = P.d32;
-                ep.lo = P.lo32;
-                ep.hi = P.hi32;
-                ep.x = P.dx;
-                ep.xa = P.dxa;
-                ep.begin();
-                wg_spmv(P.AT.csr, static_cast<const float*>(P.dy), ep, lds, red);
+                const float* dy = static_cast<const float*>(P.dy);
+                if (P.method) wg_step(P.AT.csr, dy, epi_primal32_h(P, ssc, it), lds, red);
+                else wg_step(P.AT.csr, dy, epi_primal32(P, ssc, it), lds, red);
                 if (P.m > 0) {
-                    EpiDual32 ed{};
-                    ed.sc = ssc;
-                    ed.it = it;
-                    ed.rl = P.rl32;
-                    ed.ru = P.ru32;
-                    ed.yh = P.yh32;
-                    ed.y = P.dy;
-                    ed.ya = P.dya;
-                    ed.ax = P.adx;
-                    ed.begin();
-                    wg_spmv(P.A.csr, static_cast<const float*>(P.dx), ed, lds, red);
+                    if (P.method) wg_step(P.A.csr, static_cast<const float*>(P.dxa), epi_dual32_h(P, ssc, it), lds, red);
+                    else wg_step(P.A.csr, static_cast<const float*>(P.dx), epi_dual32(P, ssc, it), lds, red);
                 }
             } else {
-                EpiPrimal ep{};
-                ep.sc = ssc;
-                ep.it = it;
-                ep.c = P.c;
-                ep.xl = P.xl;
-                ep.xu = P.xu;
-                ep.x = P.x;
-                ep.xa = P.xa;
-                ep.begin();
-                wg_spmv(P.AT.csr, static_cast<const double*>(P.y), ep, lds, red);
+                const double* y = static_cast<const double*>(P.y);
+                if (P.method) wg_step(P.AT.csr, y, epi_primal_h(P, ssc, it), lds, red);
+                else wg_step(P.AT.csr, y, epi_primal(P, ssc, it), lds, red);
                 if (P.m > 0) {
-                    EpiDual ed{};
-                    ed.sc = ssc;
-                    ed.it = it;
-                    ed.bl = P.bl;
-                    ed.bu = P.bu;
-                    ed.y = P.y;
-                    ed.ya = P.ya;
-                    ed.ax = P.ax;
-                    ed.begin();
-                    wg_spmv(P.A.csr, static_cast<const double*>(P.x), ed, lds, red);
+                    if (P.method) wg_step(P.A.csr, static_cast<const double*>(P.xa), epi_dual_h(P, ssc, it), lds, red);
+                    else wg_step(P.A.csr, static_cast<const double*>(P.x), epi_dual(P, ssc, it), lds, red);
                 }
             }
         }
         if (P.fp32) {
             for (int g = tid; g < mx; g += kBlock) materialize_at(P, g);
             __syncthreads();
-            if (P.m > 0) wg_spmv(P.A.csr, static_cast<const double*>(P.x), EpiStore{P.ax, nullptr}, lds, red);
+            if (P.m > 0 && !P.method) wg_spmv(P.A.csr, static_cast<const double*>(P.x), EpiStore{P.ax, nullptr}, lds, red);
         }
-        wg_spmv(P.AT.csr, static_cast<const double*>(P.y), EpiStore{P.aty, nullptr}, lds, red);
-        if (P.m > 0) wg_spmv(P.A.csr, static_cast<const double*>(P.xa), EpiStore{P.axa, nullptr}, lds, red);
+        if (!P.method) wg_spmv(P.AT.csr, static_cast<const double*>(P.y), EpiStore{P.aty, nullptr}, lds, red);
+        if (P.m > 0 && (!P.method || P.fp32))
+            wg_spmv(P.A.csr, static_cast<const double*>(P.xa), EpiStore{P.axa, nullptr}, lds, red);
         wg_spmv(P.AT.csr, static_cast<const double*>(P.ya), EpiStore{P.atya, nullptr}, lds, red);
         wg_kkt(P, 0, tot, red16);
         if (tid == 0) decide_logic(P, ssc, tot, 0);
         __syncthreads();
         const int lr = ssc->last_restart;
         if (ssc->status == kRunning) {
-            for (int g = tid; g < mx; g += kBlock) save_prev_at(P, lr, g);
+            for (int g = tid; g < mx; g += kBlock) save_prev_at(P, lr, false, g);
             __syncthreads();
         }
         if (lr) {
@@ -1491,64 +1718,45 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, con
 // for the whole batch, and a converged LP's blocks return at once.
 enum MultiKind { MK_PRIMAL = 0, MK_DUAL, MK_AX_ALL, MK_AX_FP32, MK_ATY, MK_AXA, MK_ATYA };
 
+// One row tile with an epilogue whose begin() may decline the work (LP stopped).
+template <class T, class Epi>
+__device__ inline void run_tile(const Csr& M, int b, const T* xin, Epi e, T* prod, double* red) {
+    if (!e.begin()) return;
+    tile_body(M, b, xin, e, prod, red);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void multi_tiles_kernel(const BatchJob* jobs, const int2* map, int it) {
     __shared__ double lds[kTileNnz];
     __shared__ double red[kBlock / 64];
     const int2 mt = map[blockIdx.x];
     const DevLP& P = jobs[mt.x].P;
+    float* lds32 = reinterpret_cast<float*>(lds);
     if (KIND == MK_PRIMAL) {
         if (P.fp32) {
-            EpiPrimal32 e{};
-            e.sc = P.sc;
-            e.it = it;
-            e.d = P.d32;
-            e.lo = P.lo32;
-            e.hi = P.hi32;
-            e.x = P.dx;
-            e.xa = P.dxa;
-            if (!e.begin()) return;
-            tile_body(P.AT.csr, mt.y, static_cast<const float*>(P.dy), e, reinterpret_cast<float*>(lds), red);
+            if (P.method) run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32_h(P, P.sc, it), lds32, red);
+            else run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32(P, P.sc, it), lds32, red);
+        } else if (P.method) {
+            run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal_h(P, P.sc, it), lds, red);
         } else {
-            EpiPrimal e{};
-            e.sc = P.sc;
-            e.it = it;
-            e.c = P.c;
-            e.xl = P.xl;
-            e.xu = P.xu;
-            e.x = P.x;
-            e.xa = P.xa;
-            if (!e.begin()) return;
-            tile_body(P.AT.csr, mt.y, static_cast<const double*>(P.y), e, lds, red);
+            run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal(P, P.sc, it), lds, red);
         }
     } else if (KIND == MK_DUAL) {
         if (P.fp32) {
-            EpiDual32 e{};
-            e.sc = P.sc;
-            e.it = it;
-            e.rl = P.rl32;
-            e.ru = P.ru32;
-            e.yh = P.yh32;
-            e.y = P.dy;
-            e.ya = P.dya;
-            e.ax = P.adx;
-            if (!e.begin()) return;
-            tile_body(P.A.csr, mt.y, static_cast<const float*>(P.dx), e, reinterpret_cast<float*>(lds), red);
+            if (P.method) run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dxa), epi_dual32_h(P, P.sc, it), lds32, red);
+            else run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dx), epi_dual32(P, P.sc, it), lds32, red);
+        } else if (P.method) {
+            run_tile(P.A.csr, mt.y, static_cast<const double*>(P.xa), epi_dual_h(P, P.sc, it), lds, red);
         } else {
-            EpiDual e{};
-            e.sc = P.sc;
-            e.it = it;
-            e.bl = P.bl;
-            e.bu = P.bu;
-            e.y = P.y;
-            e.ya = P.ya;
-            e.ax = P.ax;
-            if (!e.begin()) return;
-            tile_body(P.A.csr, mt.y, static_cast<const double*>(P.x), e, lds, red);
+            run_tile(P.A.csr, mt.y, static_cast<const double*>(P.x), epi_dual(P, P.sc, it), lds, red);
         }
     } else {
         if (P.sc->status != kRunning) return;
-        if (KIND == MK_AX_FP32 && !P.fp32) return;
+        if (KIND == MK_AX_FP32 && (!P.fp32 || P.method)) return;
+        // the Halpern form evaluates only T(z): no A~^T y of the iterate, and in FP64 the
+        // dual half already left A~ xa in axa
+        if (KIND == MK_ATY && P.method && it == 0) return;  // it == 1: the initial point
+        if (KIND == MK_AXA && P.method && !P.fp32) return;
         const bool onA = KIND == MK_AX_ALL || KIND == MK_AX_FP32 || KIND == MK_AXA;
         const double* xin = KIND == MK_ATY ? P.y : KIND == MK_ATYA ? P.ya : KIND == MK_AXA ? P.xa : P.x;
         double* out = KIND == MK_ATY ? P.aty : KIND == MK_ATYA ? P.atya : KIND == MK_AXA ? P.axa : P.ax;
@@ -1579,14 +1787,14 @@ __global__ __launch_bounds__(kBlock) void multi_elem_kernel(const BatchJob* jobs
         init_state_at(P, g, J.x0, J.y0);
     } else if (OP == EO_REBASE_INIT) {
         if (sc->status != kRunning) return;
-        save_prev_at(P, 0, g);
+        save_prev_at(P, 0, true, g);
         if (P.fp32) rebase_at(P, 1, g);
     } else if (OP == EO_MATERIALIZE) {
         if (P.fp32 && sc->status == kRunning) materialize_at(P, g);
     } else if (OP == EO_APPLY) {
         if (sc->status != kRunning) return;
         const int lr = sc->last_restart;
-        save_prev_at(P, lr, g);
+        save_prev_at(P, lr, false, g);
         if (lr == 0) return;
         if (P.fp32) rebase_at(P, lr, g);
         else apply_restart_at(P, lr, g);
@@ -1713,55 +1921,30 @@ void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scala
     launch_spmv(M, xin, e, s);
 }
 
+// With no rows every row of A^T is empty and the product still carries the primal update.
 void launch_primal(const DevLP& P, int it, hipStream_t s) {
+    const float* dy = static_cast<const float*>(P.dy);
     if (P.fp32) {
-        EpiPrimal32 e{};
-        e.sc = P.sc;
-        e.it = it;
-        e.d = P.d32;
-        e.lo = P.lo32;
-        e.hi = P.hi32;
-        e.x = P.dx;
-        e.xa = P.dxa;
-        launch_spmv(P.AT, static_cast<const float*>(P.dy), e, s);
-        return;
+        if (P.method) launch_spmv(P.AT, dy, epi_primal32_h(P, P.sc, it), s);
+        else launch_spmv(P.AT, dy, epi_primal32(P, P.sc, it), s);
+    } else if (P.method) {
+        launch_spmv(P.AT, static_cast<const double*>(P.y), epi_primal_h(P, P.sc, it), s);
+    } else {
+        launch_spmv(P.AT, static_cast<const double*>(P.y), epi_primal(P, P.sc, it), s);
     }
-    EpiPrimal e{};
-    e.sc = P.sc;
-    e.it = it;
-    e.c = P.c;
-    e.xl = P.xl;
-    e.xu = P.xu;
-    e.x = P.x;
-    e.xa = P.xa;
-    // with no rows every row of A^T is empty and the product still carries the primal update
-    launch_spmv(P.AT, P.y, e, s);
 }
 
+// The dual half gathers x+ : the updated x (averaged form) or the PDHG output xa (Halpern).
 void launch_dual(const DevLP& P, int it, hipStream_t s) {
     if (P.m == 0) return;
     if (P.fp32) {
-        EpiDual32 e{};
-        e.sc = P.sc;
-        e.it = it;
-        e.rl = P.rl32;
-        e.ru = P.ru32;
-        e.yh = P.yh32;
-        e.y = P.dy;
-        e.ya = P.dya;
-        e.ax = P.adx;
-        launch_spmv(P.A, static_cast<const float*>(P.dx), e, s);
-        return;
+        if (P.method) launch_spmv(P.A, static_cast<const float*>(P.dxa), epi_dual32_h(P, P.sc, it), s);
+        else launch_spmv(P.A, static_cast<const float*>(P.dx), epi_dual32(P, P.sc, it), s);
+    } else if (P.method) {
+        launch_spmv(P.A, static_cast<const double*>(P.xa), epi_dual_h(P, P.sc, it), s);
+    } else {
+        launch_spmv(P.A, static_cast<const double*>(P.x), epi_dual(P, P.sc, it), s);
     }
-    EpiDual e{};
-    e.sc = P.sc;
-    e.it = it;
-    e.bl = P.bl;
-    e.bu = P.bu;
-    e.y = P.y;
-    e.ya = P.ya;
-    e.ax = P.ax;
-    launch_spmv(P.A, P.x, e, s);
 }
 
 void launch_materialize(const DevLP& P, hipStream_t s) {
@@ -1769,28 +1952,32 @@ void launch_materialize(const DevLP& P, hipStream_t s) {
     hipLaunchKernelGGL(materialize_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
 }
 
+// Evaluation (mode 0 periodic, 1 initial point, 2 final point after a host-side stop): the
+// products the evaluated point needs, the fixed-order reductions, the decision, and the point
+// the next evaluation's rays start from. The Halpern form evaluates the PDHG output only.
 void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
+    const int mx = P.m > P.n ? P.m : P.n;
+    const Scalars* gate = mode == 2 ? nullptr : P.sc;
+    const bool cand = P.method && mode != 1;
     if (P.fp32 && mode != 1) {
         // FP64 iterates from the master and the FP32 correction, then FP64 products on A~
         launch_materialize(P, s);
-        const Scalars* gate = mode == 2 ? nullptr : P.sc;
-        if (P.m > 0) launch_spmv_store(P.A, P.x, P.ax, gate, s);
-        launch_spmv_store(P.AT, P.y, P.aty, gate, s);
-        if (mode == 0) {
+        if (cand) {
             if (P.m > 0) launch_spmv_store(P.A, P.xa, P.axa, gate, s);
             launch_spmv_store(P.AT, P.ya, P.atya, gate, s);
+        } else {
+            if (P.m > 0) launch_spmv_store(P.A, P.x, P.ax, gate, s);
+            launch_spmv_store(P.AT, P.y, P.aty, gate, s);
+            if (mode == 0) {
+                if (P.m > 0) launch_spmv_store(P.A, P.xa, P.axa, gate, s);
+                launch_spmv_store(P.AT, P.ya, P.atya, gate, s);
+            }
         }
-        hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
-        hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
-        if (mode == 0 && P.xp) {
-            const int mx = P.m > P.n ? P.m : P.n;
-            hipLaunchKernelGGL(save_prev_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
-        }
-        return;
-    }
-    if (mode == 1) {
+    } else if (mode == 1) {
         if (P.m > 0) launch_spmv_store(P.A, P.x, P.ax, P.sc, s);
         launch_spmv_store(P.AT, P.y, P.aty, P.sc, s);
+    } else if (cand) {
+        launch_spmv_store(P.AT, P.ya, P.atya, gate, s);  // A~ xa is left in axa by the dual half
     } else if (mode == 0) {
         launch_spmv_store(P.AT, P.y, P.aty, P.sc, s);
         if (P.m > 0) launch_spmv_store(P.A, P.xa, P.axa, P.sc, s);
@@ -1800,14 +1987,8 @@ void launch_evaluate(const DevLP& P, int mode, hipStream_t s) {
     }
     hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, mode);
     hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, mode);
-    if (mode != 2 && P.xp) {
-        const int mx = P.m > P.n ? P.m : P.n;
-        hipLaunchKernelGGL(save_prev_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
-    }
-    if (P.fp32 && mode == 1) {
-        const int mx = P.m > P.n ? P.m : P.n;
-        hipLaunchKernelGGL(rebase_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, 1);
-    }
+    if (mode != 2) hipLaunchKernelGGL(save_prev_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, mode == 1 ? 1 : 0);
+    if (P.fp32 && mode == 1) hipLaunchKernelGGL(rebase_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P, 1);
 }
 
 void launch_apply_restart(const DevLP& P, hipStream_t s) {
