@@ -32,17 +32,26 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "PDHG iters/s & HBM GB/s vs roofline; batched LPs/s to 1e-4 KKT, p50/p99"
 
 
-def algorithmic_bytes(m: int, n: int, nnz: int, sv: int = 8):
+def algorithmic_bytes(m: int, n: int, nnz: int, sv: int = 8, halpern: bool = False):
     """Bytes the method must move per launch (int32 indices, sv-byte values).
 
     primal kernel: A^T values + indices, A^T row pointers, one gather of y, read x, c,
-                   x_lo, x_hi, x_avg and write x, x_avg.
+                   x_lo, x_hi, x_avg (Halpern form: the anchor x0) and write x, x_avg (T(z)).
     dual kernel:   A values + indices, A row pointers, one gather of x, read y, b_lo, b_hi,
-                   y_avg, A x and write y, y_avg, A x.
+                   y_avg, A x and write y, y_avg, A x; the Halpern form reads the anchor y0
+                   and its A x0 instead of y_avg and also writes A T(z).
     """
     primal = (sv + 4) * nnz + 4 * (n + 1) + sv * (7 * n + m)
-    dual = (sv + 4) * nnz + 4 * (m + 1) + sv * (n + 8 * m)
+    dual = (sv + 4) * nnz + 4 * (m + 1) + sv * (n + (10 if halpern else 8) * m)
     return primal, dual
+
+
+METHODS = {"averaged": 0, "halpern": 1}
+
+
+def method_of(args, default: str) -> int:
+    """The PDHG form a workload runs: --method, else the workload's default."""
+    return METHODS[args.method or default]
 
 
 def cpu_model() -> str:
@@ -88,12 +97,13 @@ def run_batch(args) -> int:
     print(f"[bench] generated {len(lps)} LPs (nnz total {nnz.sum():.3e}, max {nnz.max()}) in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
     t1 = time.time()
-    solvers = [lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED) for lp in lps]
+    meth = method_of(args, "halpern")
+    solvers = [lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED, method=meth) for lp in lps]
     create_s = time.time() - t1
     print(f"[bench] created {len(solvers)} handles in {create_s:.1f}s", file=sys.stderr, flush=True)
-    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64)  # warm-up launch
+    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64, method=meth)  # warm-up launch
     t2 = time.perf_counter()
-    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=args.batch_max_iters)
+    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth)
     dt = time.perf_counter() - t2
     ok = sum(s.status == "optimal" for s in sols)
     iters = np.array([s.info.iterations for s in sols])
@@ -106,7 +116,7 @@ def run_batch(args) -> int:
     loop_t = 0.0
     loop_ok = 0
     for lp in sub:
-        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters) as s1:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth) as s1:
             t3 = time.perf_counter()
             r = s1.solve()
             loop_t += time.perf_counter() - t3
@@ -121,9 +131,11 @@ def run_batch(args) -> int:
         "config": {"workload": "batched LPs to E_rel 1e-4: stratified sample of the 4096-LP batch "
                                "(m log-uniform [50,5000], n=2m, random-sparse density U[0.5%,5%] / transportation "
                                "50/50), FP32 storage form with FP64 evaluation and refinement, one persistent launch",
+                   "method": {v: k for k, v in METHODS.items()}[meth],
                    "lps": len(sols), "nnz_total": int(nnz.sum()), "optimal": ok,
                    "iterations_median": int(np.median(iters)), "iterations_max": int(iters.max())},
-        "per_lp_fp64_loop": {"lps": len(sub), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok},
+        "per_lp_fp64_loop": {"lps": len(sub), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok,
+                             "method": "same as the batch"},
         "speedup_vs_per_lp_loop": (len(sols) / dt) / loop_rate,
         "create_s": create_s,
     }
@@ -146,13 +158,15 @@ def run_serve(args) -> int:
     t0 = time.time()
     pool = [synth.cfg4_lp(j) for j in range(args.pool)]
     nnz = np.array([lp.nnz for lp in pool])
-    tmpl = [lpg.Solver(lp, spmv_layout=1, deferred=1, precision=lpg.LP_PREC_FP32_REFINED) for lp in pool]
+    meth = method_of(args, "halpern")
+    tmpl = [lpg.Solver(lp, spmv_layout=1, deferred=1, precision=lpg.LP_PREC_FP32_REFINED, method=meth) for lp in pool]
     print(f"[bench] pool of {len(pool)} LPs (mean nnz {nnz.mean():.3g}, max {nnz.max()}) ready in "
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     def phase(rate, seconds, seed):
         rng = random.Random(seed)
-        srv = lpg.Server(args.hbm_budget_gb * 2**30, args.slots, eps_rel=1e-4, max_iters=args.batch_max_iters)
+        srv = lpg.Server(args.hbm_budget_gb * 2**30, args.slots, eps_rel=1e-4, max_iters=args.batch_max_iters,
+                         method=meth)
         tickets = []
         start = time.perf_counter()
         t_next = 0.0
@@ -203,7 +217,7 @@ def run_serve(args) -> int:
                                f"{len(pool)} LPs (m log-uniform [100, 2e5], n=1.5m, 3-20 nnz/row), FP32 storage "
                                f"form + FP64 refinement to E_rel 1e-4, continuous batching, HBM budget "
                                f"{args.hbm_budget_gb} GiB, {args.slots} slots",
-                   "pool_mean_nnz": float(nnz.mean())},
+                   "pool_mean_nnz": float(nnz.mean()), "method": {v: k for k, v in METHODS.items()}[meth]},
         "latency_p50_s": full["latency_p50_s"], "latency_p99_s": full["latency_p99_s"],
         "saturated": full, "sub_saturation": sub,
     }
@@ -224,7 +238,7 @@ def run_presolve(args) -> int:
     lp = synth.presolve_lp(0, m=m, n=2 * m, density=args.presolve_density)
     print(f"[bench] presolve workload m={lp.m} n={lp.n} nnz={lp.nnz} generated in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    opts = dict(eps_rel=1e-4, max_iters=args.batch_max_iters)
+    opts = dict(eps_rel=1e-4, max_iters=args.batch_max_iters, method=method_of(args, "halpern"))
     lpg.solve_presolved(synth.presolve_lp(1, m=200, n=400, density=0.02), **opts)  # warm-up
     t1 = time.perf_counter()
     with lpg.Solver(lp, **opts) as s:
@@ -244,7 +258,8 @@ def run_presolve(args) -> int:
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"presolve + solve to E_rel 1e-4 vs solve alone: KKT-constructed LP m={lp.m} "
                                f"n={lp.n} nnz={lp.nnz} with planted reducible structure (10% of rows / columns "
-                               f"per type)", "m": lp.m, "n": lp.n, "nnz": lp.nnz},
+                               f"per type)", "m": lp.m, "n": lp.n, "nnz": lp.nnz,
+                   "method": {v: k for k, v in METHODS.items()}[opts["method"]]},
         "presolve": r.presolve, "times": r.times,
         "reduced": {"status": r.reduced.status, "iterations": int(r.reduced.info.iterations),
                     "rel_kkt": r.reduced.info.rel_kkt},
@@ -315,6 +330,10 @@ def main(argv=None):
     ap.add_argument("--size", default="full", help="full, or m,n,nnz for a reduced instance")
     ap.add_argument("--layout", type=int, default=0, help="0 panel-packed wave units, 1 row tiles")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 storage form measurement")
+    ap.add_argument("--method", choices=sorted(METHODS), default=None,
+                    help="PDHG form (default: averaged for the large-LP iteration rate, halpern for the "
+                         "workloads measured to a tolerance)")
+    ap.add_argument("--no-halpern-leg", action="store_true")
     ap.add_argument("--workload", default="large", choices=["large", "batch", "serve", "copy", "presolve"])
     ap.add_argument("--presolve-m", type=int, default=20000)
     ap.add_argument("--presolve-density", type=float, default=0.0003)
@@ -414,6 +433,27 @@ def main(argv=None):
         print(f"[bench] fp32 form: {E * K / dt5:.1f} it/s; primal {p32 * 1e3:.1f} us, dual {d32 * 1e3:.1f} us",
               file=sys.stderr, flush=True)
 
+    halpern_res = None
+    if not args.no_halpern_leg:
+        # the reflected Halpern form on the same LP (FP64), same step definition
+        sh = lpg.Solver(lp, eps_rel=0.0, max_iters=E * max(args.warmup, 1), eval_every=E,
+                        method=lpg.LP_METHOD_HALPERN, **tun)
+        sh.solve()
+        sh.update(eps_rel=0.0, max_iters=E * K, eval_every=E, method=lpg.LP_METHOD_HALPERN)
+        lpg.lp_set_kernel_timing(sh.h, True)
+        t6 = time.perf_counter()
+        sh.solve()
+        dt6 = time.perf_counter() - t6
+        ph, dh, nh = lpg.lp_get_kernel_times(sh.h)
+        sh.close()
+        bph, bdh = algorithmic_bytes(m, n, nnz, halpern=True)
+        halpern_res = {"workload": "same LP, reflected Halpern form (FP64)",
+                       "iters_per_s": E * K / dt6, "ms_per_step": dt6 / K * 1e3,
+                       "primal_ms": ph, "dual_ms": dh, "primal_alg_bytes": bph, "dual_alg_bytes": bdh,
+                       "primal_gbs": bph / (ph * 1e-3) / 1e9, "dual_gbs": bdh / (dh * 1e-3) / 1e9, "samples": nh}
+        print(f"[bench] halpern form: {E * K / dt6:.1f} it/s; primal {ph * 1e3:.1f} us, dual {dh * 1e3:.1f} us",
+              file=sys.stderr, flush=True)
+
     bp, bd = algorithmic_bytes(m, n, nnz)
     gbs_p = bp / (p_ms * 1e-3) / 1e9
     gbs_d = bd / (d_ms * 1e-3) / 1e9
@@ -451,6 +491,7 @@ def main(argv=None):
         "setup_s": setup_s,
         "generate_s": gen_s,
         "fp32_form": fp32_res,
+        "halpern_form": halpern_res,
     }
     if args.solve:
         solver.update(eps_rel=1e-4, max_iters=10**7, time_limit_s=args.solve_time_limit, eval_every=E)

@@ -164,13 +164,14 @@ int32_t lp_create(lp_handle **out, int32_t m, int32_t n, int64_t nnz, const int3
                   const double *b_lo, const double *b_hi, const double *x_lo, const double *x_hi,
                   const lp_options *opt);
 
-/* Run restarted, averaged PDHG from the start point until E_rel <= eps_rel or a limit.
- * Every call starts again from x0, y0 (the handle keeps the problem, not the iterates). */
+/* Run restarted PDHG (the form of opt->method) from the start point until E_rel <= eps_rel,
+ * a certificate or a limit. Every call starts again from x0, y0 (the handle keeps the
+ * problem, not the iterates). */
 int32_t lp_solve(lp_handle *h);
 
-/* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every
- * and restarts are taken from *opt; every other field of *opt is ignored (the problem
- * setup, the step size and the trace capacity are fixed at lp_create). */
+/* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every,
+ * restarts, eps_infeas, method and reflection are taken from *opt; every other field of *opt
+ * is ignored (the problem setup, the step size and the trace capacity are fixed at lp_create). */
 int32_t lp_update_options(lp_handle *h, const lp_options *opt);
 
 /* Batched form: solve the LPs of `count` handles (created on the same device) together.

@@ -350,7 +350,8 @@ class Solver:
         self.close()
 
     def update(self, **options):
-        """Change solve-time options (eps_rel, max_iters, time_limit_s, eval_every, restarts)."""
+        """Change solve-time options (eps_rel, max_iters, time_limit_s, eval_every, restarts,
+        eps_infeas, method, reflection); the ones not given take their defaults."""
         lp_update_options(self.h, make_options(**options))
 
     def solve(self, with_trace: bool = False) -> Solution:

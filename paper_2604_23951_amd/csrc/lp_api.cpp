@@ -1477,9 +1477,13 @@ int32_t lp_update_options(lp_handle* h, const lp_options* opt) {
     o.time_limit_s = opt->time_limit_s;
     o.eval_every = opt->eval_every;
     o.restarts = opt->restarts;
+    o.eps_infeas = opt->eps_infeas;
+    o.method = opt->method;
+    o.reflection = opt->reflection;
     std::string msg;
     if (int32_t rc = validate_options(o, &msg)) return fail(h, rc, msg);
-    if (o.eval_every != h->opt.eval_every) {
+    // the captured iteration bundle bakes in the period, the form and its reflection
+    if (o.eval_every != h->opt.eval_every || o.method != h->opt.method || o.reflection != h->opt.reflection) {
         if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
         if (h->graph) (void)hipGraphDestroy(h->graph);
         h->gexec = nullptr;

@@ -112,3 +112,20 @@ def test_time_limit_returns_pdhg_output():
     assert np.all(sol.x >= lp.x_lo) and np.all(sol.x <= lp.x_hi)
     chk = oracle.kkt(lp, sol.x, sol.y)
     assert abs(chk["erel"] - sol.info.rel_kkt) <= 1e-9 * max(chk["erel"], 1e-12)
+
+
+def test_update_switches_form():
+    """lp_update_options changes the form of a handle (and drops its captured bundle)."""
+    lp = _case("cfg0")
+    opts = dict(eps_rel=1e-4, max_iters=200000)
+    with lpg.Solver(lp, **opts) as s:
+        a = s.solve()
+        s.update(**opts, **H)
+        h = s.solve()
+        s.update(**opts)
+        a2 = s.solve()
+    with lpg.Solver(lp, **opts, **H) as s2:
+        h2 = s2.solve()
+    assert h.info.iterations == h2.info.iterations != a.info.iterations
+    assert np.array_equal(h.x, h2.x)
+    assert a.info.iterations == a2.info.iterations and np.array_equal(a.x, a2.x)
