@@ -116,7 +116,8 @@ def run_batch(args) -> int:
     loop_t = 0.0
     loop_ok = 0
     for lp in sub:
-        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth) as s1:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth,
+                        spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
             t3 = time.perf_counter()
             r = s1.solve()
             loop_t += time.perf_counter() - t3
@@ -128,14 +129,15 @@ def run_batch(args) -> int:
         "metric": METRIC, "value": len(sols) / dt, "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "batched LPs to E_rel 1e-4: stratified sample of the 4096-LP batch "
+        "config": {"workload": ("batched LPs to E_rel 1e-4: the 4096-LP batch " if len(lps) == total else
+                                f"batched LPs to E_rel 1e-4: every {stride}th LP of the 4096-LP batch ") +
                                "(m log-uniform [50,5000], n=2m, random-sparse density U[0.5%,5%] / transportation "
                                "50/50), FP32 storage form with FP64 evaluation and refinement, one persistent launch",
                    "method": {v: k for k, v in METHODS.items()}[meth],
                    "lps": len(sols), "nnz_total": int(nnz.sum()), "optimal": ok,
                    "iterations_median": int(np.median(iters)), "iterations_max": int(iters.max())},
         "per_lp_fp64_loop": {"lps": len(sub), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok,
-                             "method": "same as the batch"},
+                             "method": "same as the batch", "layout": "tuned per LP"},
         "speedup_vs_per_lp_loop": (len(sols) / dt) / loop_rate,
         "create_s": create_s,
     }
@@ -163,7 +165,10 @@ def run_serve(args) -> int:
     print(f"[bench] pool of {len(pool)} LPs (mean nnz {nnz.mean():.3g}, max {nnz.max()}) ready in "
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
-    def phase(rate, seconds, seed):
+    def phase(rate, seconds, seed, drain):
+        """Poisson arrivals at `rate` for `seconds`; with `drain`, keep serving (no new
+        arrivals) until every request submitted in the window has completed, at most
+        args.drain_seconds more, so that latency covers the whole window."""
         rng = random.Random(seed)
         srv = lpg.Server(args.hbm_budget_gb * 2**30, args.slots, eps_rel=1e-4, max_iters=args.batch_max_iters,
                          method=meth)
@@ -182,6 +187,13 @@ def run_serve(args) -> int:
             done += srv.poll()
             time.sleep(min(0.0005, max(0.0, t_next - now)))
         done += srv.poll()
+        in_window = len(done)
+        st_window = srv.stats()
+        if drain:
+            while len(done) < len(tickets) and time.perf_counter() - start < seconds + args.drain_seconds:
+                time.sleep(0.002)
+                done += srv.poll()
+        span = time.perf_counter() - start
         st = srv.stats()
         lat = []
         wait = []
@@ -193,22 +205,47 @@ def run_serve(args) -> int:
         srv.close()
         lat = np.array(lat) if lat else np.array([np.nan])
         wait = np.array(wait) if wait else np.array([np.nan])
+        # work: PDHG iterations x nnz(A) run by the server; with FP32 storage both products
+        # stream 8 bytes (value + index) per nonzero, a lower bound on the traffic
+        wsec = st_window["nnz_iterations"] / seconds
         return {"offered_lps_per_s": rate, "seconds": seconds, "submitted": len(tickets),
-                "completed": len(done), "lps_per_s": len(done) / seconds,
+                "completed_in_window": in_window, "lps_per_s": in_window / seconds,
+                "completed": len(done), "drained": bool(drain and len(done) == len(tickets)),
+                "span_s": span,
                 "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
                 "admission_wait_p50_s": float(np.percentile(wait, 50)),
-                "backlog_at_end": st["queued"] + st["running"], "rounds": st["rounds"],
-                "peak_device_bytes": st["peak_bytes"]}
+                "backlog_at_window_end": st_window["queued"] + st_window["running"], "rounds": st["rounds"],
+                "peak_device_bytes": st["peak_bytes"],
+                "nnz_iterations_per_s": wsec, "matrix_stream_GBps": 16 * wsec / 1e9,
+                "lp_iterations_per_s": st_window["lp_iterations"] / seconds}
 
-    full = phase(args.rate, args.serve_seconds, 1)
+    full = phase(args.rate, args.serve_seconds, 1, False)
     print(f"[bench] offered {args.rate}/s: {full['lps_per_s']:.1f} LPs/s, p50 {full['latency_p50_s']:.3f}s, "
-          f"p99 {full['latency_p99_s']:.3f}s, backlog {full['backlog_at_end']}", file=sys.stderr, flush=True)
-    sub_rate = max(1.0, 0.7 * full["lps_per_s"])
-    sub = phase(sub_rate, args.sub_seconds, 2)
-    print(f"[bench] offered {sub_rate:.1f}/s: {sub['lps_per_s']:.1f} LPs/s, p50 {sub['latency_p50_s']:.3f}s, "
-          f"p99 {sub['latency_p99_s']:.3f}s, backlog {sub['backlog_at_end']}", file=sys.stderr, flush=True)
+          f"p99 {full['latency_p99_s']:.3f}s, backlog {full['backlog_at_window_end']}, "
+          f"{full['nnz_iterations_per_s']:.3g} nnz-it/s ({full['matrix_stream_GBps']:.0f} GB/s of A)",
+          file=sys.stderr, flush=True)
+    sub_rate = max(0.5, 0.5 * full["lps_per_s"])
+    sub = phase(sub_rate, args.sub_seconds, 2, True)
+    print(f"[bench] offered {sub_rate:.2f}/s: {sub['completed']}/{sub['submitted']} completed (drained "
+          f"{sub['drained']}), p50 {sub['latency_p50_s']:.3f}s, p99 {sub['latency_p99_s']:.3f}s, "
+          f"{sub['nnz_iterations_per_s']:.3g} nnz-it/s", file=sys.stderr, flush=True)
     for t in tmpl:
         t.close()
+    # plain per-LP FP64 loop: every 12th LP of the pool (the pool is drawn at random), same
+    # method and tolerance, lp_solve one after another on the same GPU
+    sub_lps = pool[::12][: args.loop_count]
+    loop_t = 0.0
+    loop_ok = 0
+    for lp in sub_lps:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth,
+                        spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
+            t3 = time.perf_counter()
+            r = s1.solve()
+            loop_t += time.perf_counter() - t3
+            loop_ok += r.status == "optimal"
+    loop_rate = len(sub_lps) / loop_t
+    print(f"[bench] per-LP FP64 loop: {len(sub_lps)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
+          file=sys.stderr, flush=True)
     result = {
         "metric": METRIC, "value": full["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": args.serve_seconds * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -218,8 +255,15 @@ def run_serve(args) -> int:
                                f"form + FP64 refinement to E_rel 1e-4, continuous batching, HBM budget "
                                f"{args.hbm_budget_gb} GiB, {args.slots} slots",
                    "pool_mean_nnz": float(nnz.mean()), "method": {v: k for k, v in METHODS.items()}[meth]},
-        "latency_p50_s": full["latency_p50_s"], "latency_p99_s": full["latency_p99_s"],
+        # latency of every request of the half-load window (drained); under saturation the
+        # queue grows without bound and only early, small requests complete in the window
+        "latency_p50_s": sub["latency_p50_s"], "latency_p99_s": sub["latency_p99_s"],
+        "latency_phase": f"offered {sub_rate:.2f}/s (half the saturated rate), all requests of a "
+                         f"{args.sub_seconds}s window",
         "saturated": full, "sub_saturation": sub,
+        "per_lp_fp64_loop": {"lps": len(sub_lps), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok,
+                             "method": "same as the server", "layout": "tuned per LP"},
+        "speedup_vs_per_lp_loop": full["lps_per_s"] / loop_rate,
     }
     print(json.dumps(result), flush=True)
     return 0
@@ -339,11 +383,12 @@ def main(argv=None):
     ap.add_argument("--presolve-density", type=float, default=0.0003)
     ap.add_argument("--pool", type=int, default=96)
     ap.add_argument("--rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=20.0)
-    ap.add_argument("--sub-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--sub-seconds", type=float, default=20.0)
+    ap.add_argument("--drain-seconds", type=float, default=60.0)
     ap.add_argument("--hbm-budget-gb", type=int, default=128)
     ap.add_argument("--slots", type=int, default=256)
-    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--loop-count", type=int, default=8)
     ap.add_argument("--batch-max-iters", type=int, default=400000)
     ap.add_argument("--slice-bytes", type=int, default=0)

@@ -92,6 +92,12 @@ typedef enum {
                                and the anchor to it (the newer cuPDLPx-family form) */
 } lp_method;
 
+typedef enum lp_layout {
+    LP_LAYOUT_PANELS = 0, /* panel-packed wave units */
+    LP_LAYOUT_TILES = 1,  /* row tiles of up to a fixed number of nonzeros per workgroup */
+    LP_LAYOUT_TUNED = 2   /* the faster of the two on the device, measured at set-up */
+} lp_layout;
+
 typedef struct lp_options {
     double eps_rel;        /* relative tolerance on E_rel (default 1e-4) */
     int64_t max_iters;     /* iteration limit (default 100000) */
@@ -108,7 +114,11 @@ typedef struct lp_options {
     void *hip_stream;      /* hipStream_t to run on; NULL: the library creates its own */
     int32_t device;        /* HIP device ordinal (default 0) */
     int32_t trace_cap;     /* number of evaluation records kept for lp_get_trace (default 4096) */
-    int32_t spmv_layout;   /* sparse-product layout: 0 panel-packed wave units (default), 1 row tiles */
+    int32_t spmv_layout;   /* sparse-product layout: 0 panel-packed wave units (default), 1 row tiles,
+                            * 2 tuned: both are built and timed on the device at set-up (a few
+                            * products each, on scratch buffers) and the faster one is kept; the
+                            * choice depends on the measurement, so two handles of one LP may
+                            * differ in rounding (deferred clones share their template's choice) */
     int32_t long_row_len;  /* rows longer than this get a workgroup of their own (default 256) */
     int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 4; one
                               workgroup holds 4 units, so multiples of 4 fill every CU evenly) */
@@ -215,6 +225,8 @@ typedef struct lp_server_stats {
     int64_t bytes_in_use;      /* device bytes of the admitted LPs */
     int64_t peak_bytes;        /* largest bytes_in_use seen */
     int64_t hbm_budget;
+    int64_t lp_iterations;     /* PDHG iterations run, summed over the served LPs */
+    double nnz_iterations;     /* sum over those iterations of the LP's nnz(A) (work done) */
 } lp_server_stats;
 
 /* Start a server on `device` with a device-memory budget for admitted LPs and at most
@@ -361,7 +373,10 @@ int32_t lp_get_kernel_times(lp_handle *h, double *primal_ms, double *dual_ms, in
 
 /* Sizes the solver chose: sizes[0] = tiles of A, [1] = tiles of A^T, [2] = long rows of
  * A, [3] = long rows of A^T, [4] = device bytes held by the handle, [5] = wave units of A,
- * [6] = wave units of A^T, [7] = column panels of A, [8] = column panels of A^T. */
+ * [6] = wave units of A^T, [7] = column panels of A, [8] = column panels of A^T,
+ * [9] = layout of the products (0 panels, 1 row tiles; -1 before the handle is on the
+ * device), [10] / [11] = the layout tuner's time in nanoseconds of one A x + A^T y pair in
+ * panels / row tiles (0 unless spmv_layout is 2). */
 int32_t lp_get_layout(lp_handle *h, int64_t *sizes, int32_t cap);
 
 #ifdef __cplusplus

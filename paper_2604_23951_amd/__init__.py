@@ -24,6 +24,9 @@ STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_err
           5: "dual_infeasible"}
 LP_METHOD_AVERAGED = 0
 LP_METHOD_HALPERN = 1
+LP_LAYOUT_PANELS = 0
+LP_LAYOUT_TILES = 1
+LP_LAYOUT_TUNED = 2
 LP_PREC_FP64 = 0
 LP_PREC_FP32_REFINED = 1
 TRACE_WIDTH = 12
@@ -74,7 +77,8 @@ class lp_presolve_info(C.Structure):
 
 class lp_server_stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("submitted", "admitted", "completed", "queued", "running", "rounds",
-                                           "bytes_in_use", "peak_bytes", "hbm_budget")]
+                                           "bytes_in_use", "peak_bytes", "hbm_budget", "lp_iterations")]
+    _fields_ += [("nnz_iterations", C.c_double)]
 
 
 class lp_info(C.Structure):
@@ -264,10 +268,10 @@ def lp_get_kernel_times(h):
 
 
 def lp_get_layout(h):
-    out = np.zeros(9, np.int64)
-    _check(lib().lp_get_layout(h, _p(out), 9), h)
+    out = np.zeros(12, np.int64)
+    _check(lib().lp_get_layout(h, _p(out), 12), h)
     keys = ("tiles_a", "tiles_at", "long_rows_a", "long_rows_at", "device_bytes", "units_a", "units_at",
-            "panels_a", "panels_at")
+            "panels_a", "panels_at", "layout", "trial_ns_panels", "trial_ns_tiles")
     return {k: int(v) for k, v in zip(keys, out)}
 
 

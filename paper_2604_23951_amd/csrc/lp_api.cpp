@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <array>
@@ -77,6 +78,11 @@ struct Prep {
     bool panels = false;
     int nred = 1;
     bool ready = false;
+    // layout tuner (spmv_layout 2): the chosen layout (-1 before the first trial) and the
+    // mean time in microseconds of one A x + A^T y pair in each layout; shared by the
+    // clones of a deferred handle, which take the first trial's choice
+    std::atomic<int> tuned{-1};
+    double trial_us[2] = {0.0, 0.0};
 };
 
 // Offsets of every device array inside a handle's allocation.
@@ -176,6 +182,7 @@ struct lp_handle {
     double c0 = 0.0;
     int64_t long_a = 0, long_at = 0;
     int64_t units_a = 0, units_at = 0, panels_a = 0, panels_at = 0;
+    double trial_us[2] = {0.0, 0.0};  // layout tuner's times (panels, row tiles)
     char* arena = nullptr;
     size_t arena_bytes = 0;
     DevLP P{};
@@ -228,7 +235,7 @@ int32_t check_launch(lp_handle* h, const char* what) {
 
 int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
-        o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 1 ||
+        o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 2 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
         o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0)) {
@@ -556,7 +563,7 @@ int32_t host_prep(lp_handle* h, const int32_t* rp, const int32_t* ci) {
     const int target_units = cus * (o.units_per_cu > 0 ? o.units_per_cu : 4);
     const int64_t slice = o.panel_slice_bytes > 0 ? o.panel_slice_bytes : (int64_t(1) << 20);
     const int long_len = o.long_row_len > 0 ? o.long_row_len : 256;
-    Q.panels = o.spmv_layout == 0;
+    Q.panels = o.spmv_layout == 0 || o.spmv_layout == 2;
     if (Q.panels) {
         Q.LA = build_panel_layout(m, n, rp, ci, nullptr, choose_panels(n, slice), long_len, target_units, kUnitRowCap);
         Q.LAT = build_panel_layout(n, m, Q.rpT.data(), Q.ciT.data(), Q.perm.data(), choose_panels(m, slice), long_len,
@@ -655,6 +662,49 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
 
 // Device part (a2, a3): allocate, bind, upload, scale, permute values, estimate ||A~||_2 and
 // the step size. Runs on the handle's stream and waits.
+// Times reps pairs of products in each layout, twice in alternation, keeps the smaller
+// time of each and records the faster layout in the shared host structure.
+int32_t tune_layout(lp_handle* h, hipStream_t s) {
+    Prep& Q = *h->prep;
+    const DevLP& P = h->P;
+    constexpr int kReps = 8;
+    if (P.fp32) {
+        HIP_TRY(h, hipMemsetAsync(P.dx, 0, sizeof(float) * static_cast<size_t>(P.n), s));
+        if (P.m > 0) HIP_TRY(h, hipMemsetAsync(P.dy, 0, sizeof(float) * static_cast<size_t>(P.m), s));
+    } else {
+        HIP_TRY(h, hipMemsetAsync(P.x, 0, sizeof(double) * static_cast<size_t>(P.n), s));
+        if (P.m > 0) HIP_TRY(h, hipMemsetAsync(P.y, 0, sizeof(double) * static_cast<size_t>(P.m), s));
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(h, LP_ERR_DEVICE, "event creation failed");
+    }
+    float best[2] = {1e30f, 1e30f};
+    hipError_t e = hipSuccess;
+    for (int round = 0; round < 2 && e == hipSuccess; ++round)
+        for (int L = 0; L < 2 && e == hipSuccess; ++L) {
+            launch_layout_trial(P, L, 2, s);  // warm-up: caches and code
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) launch_layout_trial(P, L, kReps, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best[L]) best[L] = ms;
+        }
+    if (e == hipSuccess) e = hipGetLastError();
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(h, LP_ERR_DEVICE, std::string("layout trial: ") + hipGetErrorString(e));
+    Q.trial_us[0] = 1e3 * best[0] / kReps;
+    Q.trial_us[1] = 1e3 * best[1] / kReps;
+    int expect = -1;
+    (void)Q.tuned.compare_exchange_strong(expect, best[1] < best[0] ? 1 : 0);
+    return LP_OK;
+}
+
 int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const double* v, const double* c,
                      const double* bl, const double* bu, const double* xl, const double* xu, const double* x0,
                      const double* y0) {
@@ -823,6 +873,16 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     }
     launch_prepare(P, D(O.c), D(O.bl), D(O.bu), D(O.xl), D(O.xu), D(O.R), D(O.C), D(O.Ri), D(O.Ci), h->d_x0,
                    h->d_y0, s);
+    // layout tuner: time both product layouts on this device and keep the faster one for
+    // every product of the solve, the power iteration below included
+    if (o.spmv_layout == 2) {
+        if (Q.tuned.load() < 0) {
+            if (int32_t rc = tune_layout(h, s)) return rc;
+        }
+        P.A.layout = P.AT.layout = Q.tuned.load();
+        h->trial_us[0] = Q.trial_us[0];
+        h->trial_us[1] = Q.trial_us[1];
+    }
     // a3: ||A~||_2 by power iteration (x, A~x and A~^T y buffers are free at this point)
     if (!(o.step_size > 0.0)) launch_power_norm(P, o.pow_iters, o.seed, P.x, P.ax, P.aty, s);
     launch_finalize_setup(P, o.step_size, o.omega0, h->c0, s);
@@ -882,8 +942,24 @@ struct DevMaps {
     int hcap = 0;
     MultiMaps M{};
     int E = 64;
+    // The round's launches as a graph, captured once the same set has run one round
+    // uncaptured (a set that changes every round is not worth an instantiation).
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int stable_rounds = 0;
+    bool graph_failed = false;
+
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        stable_rounds = 0;
+        graph_failed = false;
+    }
 
     int32_t build(const std::vector<lp_handle*>& hs, const lp_options* o, hipStream_t s, lp_handle* err_to) {
+        drop_graph();
         const int count = static_cast<int>(hs.size());
         std::vector<BatchJob> jobs(static_cast<size_t>(count));
         std::vector<int2> ma, mat, mred, melem;
@@ -941,6 +1017,7 @@ struct DevMaps {
     }
 
     void free_all() {
+        drop_graph();
         if (buf) (void)hipFree(buf);
         if (hstatus) (void)hipHostFree(hstatus);
         buf = nullptr;
@@ -954,6 +1031,7 @@ struct Ticket {
     uint64_t id;
     lp_handle* h;
     double t_submit, t_admit, t_done;
+    int64_t counted;  // iterations already added to the server's work counters
 };
 
 }  // namespace
@@ -1040,26 +1118,51 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
             dirty = false;
         }
         const MultiMaps& M = run_maps.M;
-        for (int it = 0; it < run_maps.E; ++it) {
-            launch_multi(M, MULTI_PRIMAL, it, s);
-            launch_multi(M, MULTI_DUAL, it, s);
+        auto round = [&]() {
+            for (int it = 0; it < run_maps.E; ++it) {
+                launch_multi(M, MULTI_PRIMAL, it, s);
+                launch_multi(M, MULTI_DUAL, it, s);
+            }
+            launch_multi(M, MULTI_MATERIALIZE, 0, s);
+            launch_multi(M, MULTI_AX_FP32, 0, s);
+            launch_multi(M, MULTI_ATY, 0, s);
+            launch_multi(M, MULTI_AXA, 0, s);
+            launch_multi(M, MULTI_ATYA, 0, s);
+            launch_multi(M, MULTI_PARTIALS, 0, s);
+            launch_multi(M, MULTI_DECIDE, 0, s);
+            launch_multi(M, MULTI_APPLY, 0, s);
+            launch_multi(M, MULTI_STATUS, 0, s);
+        };
+        if (!run_maps.gexec && !run_maps.graph_failed && run_maps.stable_rounds >= 1) {
+            hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (ce == hipSuccess) {
+                round();
+                ce = hipStreamEndCapture(s, &run_maps.graph);
+            }
+            if (ce == hipSuccess) ce = hipGraphInstantiate(&run_maps.gexec, run_maps.graph, nullptr, nullptr, 0);
+            if (ce != hipSuccess) {  // stay with direct launches for this set
+                (void)hipGetLastError();
+                if (run_maps.graph) (void)hipGraphDestroy(run_maps.graph);
+                run_maps.graph = nullptr;
+                run_maps.gexec = nullptr;
+                run_maps.graph_failed = true;
+            }
         }
-        launch_multi(M, MULTI_MATERIALIZE, 0, s);
-        launch_multi(M, MULTI_AX_FP32, 0, s);
-        launch_multi(M, MULTI_ATY, 0, s);
-        launch_multi(M, MULTI_AXA, 0, s);
-        launch_multi(M, MULTI_ATYA, 0, s);
-        launch_multi(M, MULTI_PARTIALS, 0, s);
-        launch_multi(M, MULTI_DECIDE, 0, s);
-        launch_multi(M, MULTI_APPLY, 0, s);
-        launch_multi(M, MULTI_STATUS, 0, s);
+        if (run_maps.gexec) (void)hipGraphLaunch(run_maps.gexec, s);
+        else round();
+        run_maps.stable_rounds++;
         (void)hipMemcpyAsync(run_maps.hstatus, M.active, sizeof(int) * M.count, hipMemcpyDeviceToHost, s);
         (void)hipStreamSynchronize(s);
         S->st.rounds++;
         std::vector<Ticket> still;
+        int64_t work_it = 0;
+        double work_nnz = 0.0;
         for (int i = 0; i < M.count; ++i) {
             Ticket& t = S->running[i];
             if (run_maps.hstatus[i] == kRunning) {
+                t.counted += run_maps.E;
+                work_it += run_maps.E;
+                work_nnz += static_cast<double>(run_maps.E) * static_cast<double>(t.h->nnz);
                 still.push_back(t);
                 continue;
             }
@@ -1073,11 +1176,20 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
                 lp_handle* h = finished[k].h;
                 fill_info(h);
                 h->solved = true;
+                const int64_t extra = h->info.iterations - finished[k].counted;
+                work_it += extra;
+                work_nnz += static_cast<double>(extra) * static_cast<double>(h->nnz);
             }
             std::unique_lock<std::mutex> lk(S->mu);
+            S->st.lp_iterations += work_it;
+            S->st.nnz_iterations += work_nnz;
             S->running = still;
             S->st.running = static_cast<int64_t>(S->running.size());
             dirty = true;
+        } else {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->st.lp_iterations += work_it;
+            S->st.nnz_iterations += work_nnz;
         }
     }
     if (!finished.empty()) {
@@ -1165,7 +1277,7 @@ int32_t lp_server_submit(lp_server* S, lp_handle* h, uint64_t* ticket) {
         return fail(h, LP_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
     std::unique_lock<std::mutex> lk(S->mu);
-    Ticket t{S->next_ticket++, r, S->now(), 0.0, 0.0};
+    Ticket t{S->next_ticket++, r, S->now(), 0.0, 0.0, 0};
     S->queue.push_back(t);
     S->st.submitted++;
     S->st.queued++;
@@ -1599,9 +1711,11 @@ int32_t lp_get_kernel_times(lp_handle* h, double* primal_ms, double* dual_ms, in
 
 int32_t lp_get_layout(lp_handle* h, int64_t* sizes, int32_t cap) {
     if (!h || !sizes || cap < 0) return fail(h, LP_ERR_INVALID_ARG, "bad layout arguments");
-    const int64_t v[9] = {h->P.A.csr.ntiles, h->P.AT.csr.ntiles, h->long_a, h->long_at,
-                          static_cast<int64_t>(h->arena_bytes), h->units_a, h->units_at, h->panels_a, h->panels_at};
-    for (int32_t i = 0; i < cap && i < 9; ++i) sizes[i] = v[i];
+    const int64_t v[12] = {h->P.A.csr.ntiles, h->P.AT.csr.ntiles, h->long_a, h->long_at,
+                           static_cast<int64_t>(h->arena_bytes), h->units_a, h->units_at, h->panels_a, h->panels_at,
+                           h->on_device ? h->P.A.layout : -1,
+                           static_cast<int64_t>(h->trial_us[0] * 1e3), static_cast<int64_t>(h->trial_us[1] * 1e3)};
+    for (int32_t i = 0; i < cap && i < 12; ++i) sizes[i] = v[i];
     return LP_OK;
 }
 

@@ -166,6 +166,9 @@ void launch_reset(const DevLP& P, double eps_rel, double eps_infeas, long long m
                   long long trace_cap, hipStream_t s);
 void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s);
 void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scalars* gate, hipStream_t s);
+// reps pairs of products (A~ x, then A~^T y) in the given layout (0 panels, 1 row tiles) in the
+// precision of the solve, stored to the A~x and A~^T y buffers: the trial of the layout tuner.
+void launch_layout_trial(const DevLP& P, int layout, int reps, hipStream_t s);
 void launch_primal(const DevLP& P, int it, hipStream_t s);
 void launch_dual(const DevLP& P, int it, hipStream_t s);
 void launch_evaluate(const DevLP& P, int mode, hipStream_t s);  // mode 0 regular, 1 init, 2 final

@@ -1921,6 +1921,20 @@ void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scala
     launch_spmv(M, xin, e, s);
 }
 
+void launch_layout_trial(const DevLP& P, int layout, int reps, hipStream_t s) {
+    Mat A = P.A, AT = P.AT;
+    A.layout = AT.layout = layout;
+    for (int r = 0; r < reps; ++r) {
+        if (P.fp32) {
+            if (P.m > 0) launch_spmv(A, static_cast<const float*>(P.dx), EpiStore{P.ax, nullptr}, s);
+            launch_spmv(AT, static_cast<const float*>(P.dy), EpiStore{P.aty, nullptr}, s);
+        } else {
+            if (P.m > 0) launch_spmv(A, static_cast<const double*>(P.x), EpiStore{P.ax, nullptr}, s);
+            launch_spmv(AT, static_cast<const double*>(P.y), EpiStore{P.aty, nullptr}, s);
+        }
+    }
+}
+
 // With no rows every row of A^T is empty and the product still carries the primal update.
 void launch_primal(const DevLP& P, int it, hipStream_t s) {
     const float* dy = static_cast<const float*>(P.dy);

@@ -61,7 +61,7 @@ def _create_code(**a):
     ("lo_gt_hi_row", 3), ("lo_gt_hi_col", 3), ("lo_plus_inf", 3), ("hi_minus_inf", 3),
     ("unsorted_row", 2), ("duplicate_col", 2), ("col_out_of_range", 2), ("row_ptr_decreasing", 2),
     ("row_ptr_bad_end", 2), ("negative_m", 1), ("zero_n", 1), ("null_cost", 1), ("bad_eval_every", 1),
-    ("nan_c0", 4),
+    ("nan_c0", 4), ("bad_layout", 1),
 ])
 def test_invalid_input_codes(case, code):
     lp = synth.cfg0(0)
@@ -107,6 +107,8 @@ def test_invalid_input_codes(case, code):
         a["opt"] = lpg.make_options(eval_every=0)
     elif case == "nan_c0":
         a["c0"] = math.nan
+    elif case == "bad_layout":
+        a["opt"] = lpg.make_options(spmv_layout=3)
     assert _create_code(**a) == code
     assert lpg.lp_last_error()  # a message is recorded
 
@@ -134,3 +136,16 @@ def test_deferred_handle_needs_no_device():
     with lpg.Solver(lp, deferred=1, spmv_layout=1) as s:
         fp = s.layout()["device_bytes"]
     assert fp > 24 * lp.nnz
+
+
+def test_tuned_layout_builds_both_on_the_host():
+    """spmv_layout 2 lays out both product forms (panels and row tiles) at create; the
+    choice between them is made on the device, so a deferred handle reports none yet."""
+    lp = synth.cfg0(0)
+    with lpg.Solver(lp, deferred=1, spmv_layout=lpg.LP_LAYOUT_TUNED) as s:
+        L = s.layout()
+    with lpg.Solver(lp, deferred=1, spmv_layout=lpg.LP_LAYOUT_TILES) as s:
+        T = s.layout()
+    assert L["units_a"] > 0 and L["units_at"] > 0 and L["tiles_a"] == T["tiles_a"]
+    assert T["units_a"] == 0 and L["device_bytes"] > T["device_bytes"]
+    assert L["layout"] == -1 and L["trial_ns_panels"] == 0 and L["trial_ns_tiles"] == 0
