@@ -25,6 +25,8 @@ MUTANTS = {
                                 "double rs = ax[i] - clampd(ax[i], P->bhi[i], P->blo[i]);"),
     "scaling_exponent_sign": ("return ldexp(1.0, -h);", "return ldexp(1.0, h);"),
     "power_iteration_transposed_operand": ("csr_mv(n, rpT, ciT, vT, u, w);", "csr_mv(n, rp, ci, v, u, w);"),
+    "power_iteration_fixed_count": ("if ((it + 1) % iters == 0 && sigma - prev <= 1e-8 * sigma) break;",
+                                    "if ((it + 1) % iters == 0) break;"),
     "gap_denominator": ("K->rel_gap = fabs(p - d) / (1.0 + fabs(p) + fabs(d));",
                         "K->rel_gap = fabs(p - d) / (1.0 + fabs(p));"),
     "dual_residual_unscaled": ("double rdo = rds * P->Ci[k];", "double rdo = rds;"),

@@ -104,3 +104,40 @@ def test_validation_codes(oracle_lib):
     bad.x_lo = bad.x_lo.copy()
     bad.x_lo[3] = 11.0
     assert oracle_lib.validate(bad) == 3
+
+
+def _csr_of_dense(D):
+    import scipy.sparse as sp
+    S = sp.csr_matrix(D)
+    S.sort_indices()
+    return S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64)
+
+
+def test_power_norm_close_top_singular_values(oracle_lib):
+    """Two leading singular values 0.1% apart: 200 fixed steps leave sigma_hat about 3e-4
+    low, which would break the PDHG step condition eta ||A~|| < 1 at eta = 0.998 / sigma_hat
+    once combined with a slightly larger gap; the chunked iteration runs until the estimate
+    stops rising and lands within 2e-5 (the singular values are set, so the norm is known)."""
+    rng = np.random.default_rng(11)
+    m, n = 40, 60
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.concatenate([[2.0, 2.0 * 0.999], np.linspace(1.5, 0.1, m - 2)])
+    D = (U * s) @ V[:, :m].T
+    rp, ci, v = _csr_of_dense(D)
+    est = oracle_lib.power_norm(m, n, rp, ci, v, iters=200)
+    assert est <= 2.0 * (1 + 1e-13)
+    assert est >= 2.0 * (1 - 2e-5), est
+
+
+def test_power_norm_small_lp_with_close_gap(oracle_lib):
+    """A small LP of the batched recipe whose scaled matrix has its two largest singular
+    values 0.4% apart: the estimate is within 1e-4 of LAPACK's norm, so eta = 0.998 /
+    sigma_hat keeps eta ||A~|| below 1."""
+    lp = synth.cfg3_lp(2564)
+    av, R, Cc, *_ = oracle_lib.scaled_problem(lp)
+    import scipy.sparse as sp
+    true = np.linalg.norm(sp.csr_matrix((av, lp.col_idx, lp.row_ptr), shape=(lp.m, lp.n)).toarray(), 2)
+    est = oracle_lib.power_norm(lp.m, lp.n, lp.row_ptr, lp.col_idx, av, iters=200)
+    assert true * (1 - 1e-4) <= est <= true * (1 + 1e-13)
+    assert 0.998 / est * true < 1.0
