@@ -106,7 +106,9 @@ typedef struct lp_options {
     int32_t precision;     /* lp_precision (default LP_PREC_FP64) */
     int32_t scaling;       /* 1: power-of-two Ruiz + Pock-Chambolle scaling (default), 0: none */
     int32_t ruiz_passes;   /* number of infinity-norm Ruiz passes (default 10) */
-    int32_t pow_iters;     /* power-iteration steps for ||A~||_2 (default 200) */
+    int32_t pow_iters;     /* power-iteration chunk for ||A~||_2 (default 200): after each chunk of
+                            * this many steps the iteration stops when its last step raised the
+                            * estimate by at most 1e-8 of it; at most 25 chunks */
     int32_t restarts;      /* 1: adaptive restarts and primal-weight updates (default), 0: off */
     double step_size;      /* eta; <= 0 selects 0.998 / ||A~||_2 (default 0) */
     double omega0;         /* initial primal weight; <= 0 selects ||c~|| / ||q~|| (default 0) */

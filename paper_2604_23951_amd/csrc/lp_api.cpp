@@ -883,8 +883,21 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
         h->trial_us[0] = Q.trial_us[0];
         h->trial_us[1] = Q.trial_us[1];
     }
-    // a3: ||A~||_2 by power iteration (x, A~x and A~^T y buffers are free at this point)
-    if (!(o.step_size > 0.0)) launch_power_norm(P, o.pow_iters, o.seed, P.x, P.ax, P.aty, s);
+    // a3: ||A~||_2 by power iteration (x, A~x and A~^T y buffers are free at this point), in
+    // chunks of pow_iters steps until a chunk's last step raises the estimate by at most
+    // 1e-8 of it (it approaches ||A~||_2 from below and eta = 0.998 / estimate must keep
+    // eta ||A~||_2 < 1), at most 25 chunks
+    if (!(o.step_size > 0.0)) {
+        launch_power_start(P, o.seed, P.x, s);
+        for (int chunk = 0; chunk < 25; ++chunk) {
+            launch_power_steps(P, o.pow_iters, P.x, P.ax, P.aty, s);
+            if (chunk == 24) break;
+            double sg[2];
+            HIP_TRY(h, hipMemcpyAsync(sg, &P.sc->sigma_max, sizeof(sg), hipMemcpyDeviceToHost, s));
+            HIP_TRY(h, hipStreamSynchronize(s));
+            if (sg[0] - sg[1] <= 1e-8 * sg[0]) break;
+        }
+    }
     launch_finalize_setup(P, o.step_size, o.omega0, h->c0, s);
     if (int32_t rc = check_launch(h, "setup kernels")) return rc;
     HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));

@@ -23,7 +23,7 @@ constexpr int kRunning = -1;
 // single-workgroup decision kernels write it.
 struct Scalars {
     double tau, sigma, omega, eta, omega0;
-    double eps_rel, c0, qnorm, cnorm, sigma_max;
+    double eps_rel, c0, qnorm, cnorm, sigma_max, sigma_prev;  // sigma_prev: the power step before
     double kkt_anchor, kkt_prev;
     double eps_infeas, ray_scale;  // certificate tolerance (0: off); 1/D or 1/G of a certificate
     double anc_rps2, anc_rds2, anc_gap;
@@ -157,8 +157,10 @@ void launch_gather(const int* perm, const double* src, double* dst, long long nn
 void launch_prepare(const DevLP& P, double* c, double* bl, double* bu, double* xl, double* xu, double* R, double* C,
                     double* Ri, double* Ci, double* x0, double* y0, hipStream_t s);
 void launch_norms(const DevLP& P, hipStream_t s);
-void launch_power_norm(const DevLP& P, int iters, unsigned long long seed, double* v, double* u, double* w,
-                       hipStream_t s);
+// Power iteration on A~^T A~: the start vector (normalised into v, sigma_max and sigma_prev
+// cleared), then `iters` steps (u = A~ v, w = A~^T u, sigma_max = ||u||, v = w / ||w||).
+void launch_power_start(const DevLP& P, unsigned long long seed, double* v, hipStream_t s);
+void launch_power_steps(const DevLP& P, int iters, double* v, double* u, double* w, hipStream_t s);
 void launch_finalize_setup(const DevLP& P, double eta_override, double omega_override, double c0, hipStream_t s);
 
 // ---- solve ------------------------------------------------------------------------

@@ -971,7 +971,10 @@ __global__ __launch_bounds__(kBlock) void normalize_kernel(const double* src, do
         s0 = block_sum_all(s0, red);
     }
     const double nrm = sqrt(s);
-    if (sc && blockIdx.x == 0 && threadIdx.x == 0) sc->sigma_max = sqrt(s0);
+    if (sc && blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->sigma_prev = sc->sigma_max;
+        sc->sigma_max = sqrt(s0);
+    }
     if (!(nrm > 0.0)) return;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) dst[k] = src[k] / nrm;
 }
@@ -1881,15 +1884,21 @@ void launch_norms(const DevLP& P, hipStream_t s) {
     hipLaunchKernelGGL(norms_kernel, dim3(P.nred), dim3(kBlock), 0, s, P);
 }
 
-void launch_power_norm(const DevLP& P, int iters, unsigned long long seed, double* v, double* u, double* w,
-                       hipStream_t s) {
+void launch_power_start(const DevLP& P, unsigned long long seed, double* v, hipStream_t s) {
     hipLaunchKernelGGL(power_init_kernel, dim3(grid_for(P.n)), dim3(kBlock), 0, s, P.n, seed, v);
     hipLaunchKernelGGL(sumsq2_kernel, dim3(P.nred), dim3(kBlock), 0, s, v, P.n, v, 0, P.partials);
     unsigned gn = grid_for(P.n);
     if (gn > 2048) gn = 2048;
     hipLaunchKernelGGL(normalize_kernel, dim3(gn), dim3(kBlock), 0, s, v, v, P.n, P.partials, P.nred, 0,
                        (Scalars*)nullptr);
-    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(1), 0, s, &P.sc->sigma_max, 1LL, 0.0);
+    static_assert(offsetof(Scalars, sigma_prev) == offsetof(Scalars, sigma_max) + sizeof(double),
+                  "sigma_max and sigma_prev are cleared together");
+    hipLaunchKernelGGL(fill_kernel, dim3(1), dim3(2), 0, s, &P.sc->sigma_max, 2LL, 0.0);
+}
+
+void launch_power_steps(const DevLP& P, int iters, double* v, double* u, double* w, hipStream_t s) {
+    unsigned gn = grid_for(P.n);
+    if (gn > 2048) gn = 2048;
     for (int it = 0; it < iters; ++it) {
         if (P.m > 0) launch_spmv_store(P.A, v, u, nullptr, s);
         if (P.m > 0) launch_spmv_store(P.AT, u, w, nullptr, s);

@@ -129,3 +129,22 @@ def test_update_switches_form():
     assert h.info.iterations == h2.info.iterations != a.info.iterations
     assert np.array_equal(h.x, h2.x)
     assert a.info.iterations == a2.info.iterations and np.array_equal(a.x, a2.x)
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_close_gap_lp_step_condition(oracle_lib, layout):
+    """A 90-row LP of the batched recipe whose two largest singular values are 0.4% apart:
+    the power iteration goes past its first chunk on the device as in the oracle (same
+    estimate to 1e-12), eta ||A~|| stays below 1, and the reflected Halpern form solves it
+    with the oracle's iteration count."""
+    lp = synth.cfg3_lp(2564)
+    ref = oracle_lib.solve(lp, eps_rel=1e-4, max_iters=20000, method=1)
+    assert ref.status == "optimal"
+    with lpg.Solver(lp, spmv_layout=layout, eps_rel=1e-4, max_iters=20000, method=1) as s:
+        sol = s.solve()
+    assert abs(sol.info.sigma_max - ref.sigma_max) <= 1e-12 * ref.sigma_max
+    assert sol.status == "optimal" and sol.info.iterations == ref.iters
+    # the batched FP32 form reaches the tolerance too (it hit the iteration limit before)
+    with lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED, method=1) as s:
+        (b,) = lpg.solve_batch([s], eps_rel=1e-4, max_iters=20000, method=1)
+    assert b.status == "optimal"
