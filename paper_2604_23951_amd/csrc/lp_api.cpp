@@ -349,118 +349,109 @@ int32_t finish_batch(const std::vector<lp_handle*>& hs, hipStream_t s) {
     return LP_OK;
 }
 
-// LPs solved one per workgroup in a single persistent launch.
-int32_t solve_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
-    const int count = static_cast<int>(hs.size());
-    lp_handle* h0 = hs[0];
-    for (lp_handle* h : hs)
-        if (int32_t rc = materialize(h)) return rc;
-    std::vector<BatchJob> jobs(static_cast<size_t>(count));
-    std::vector<int32_t> order(static_cast<size_t>(count));
-    for (int i = 0; i < count; ++i) {
-        jobs[i] = make_job(hs[i], bo);
-        order[i] = i;
-    }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hs[a]->nnz > hs[b]->nnz; });
-    int cus = 256;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h0->device) != hipSuccess || cus < 1)
-        cus = 256;
-    const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
-    int grid = cus * wpc;
-    if (grid > count) grid = count;
-    const size_t bj = sizeof(BatchJob) * static_cast<size_t>(count), bo_ = sizeof(int32_t) * static_cast<size_t>(count);
-    const size_t oc = (bj + bo_ + 255) / 256 * 256;
+// Device jobs table and block maps of a set of LPs (grown as needed, reused across rounds;
+// every round ends with a stream synchronisation before the next rebuild).
+struct DevMaps {
     char* buf = nullptr;
-    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&buf), oc + 256));
-    BatchJob* djobs = reinterpret_cast<BatchJob*>(buf);
-    int32_t* dorder = reinterpret_cast<int32_t*>(buf + bj);
-    int32_t* dcounter = reinterpret_cast<int32_t*>(buf + oc);
-    hipError_t e = hipMemcpyAsync(djobs, jobs.data(), bj, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dorder, order.data(), bo_, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, sizeof(int32_t), s);
-    if (e == hipSuccess) {
-        launch_batch(djobs, dorder, count, dcounter, grid, s);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(buf);
-    if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
-    return finish_batch(hs, s);
-}
-
-// LPs advanced together as one block-diagonal problem, one launch per phase for all of
-// them, evaluation periods replayed as a hipGraph.
-int32_t solve_block_diagonal(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
-    const int count = static_cast<int>(hs.size());
-    lp_handle* h0 = hs[0];
-    for (lp_handle* h : hs)
-        if (int32_t rc = materialize(h)) return rc;
-    std::vector<BatchJob> jobs(static_cast<size_t>(count));
-    std::vector<int2> ma, mat, mred, melem;
-    int E = 0;
-    for (int i = 0; i < count; ++i) {
-        lp_handle* h = hs[i];
-        jobs[i] = make_job(h, bo);
-        if (E == 0) E = jobs[i].eval_every;
-        if (jobs[i].eval_every != E)
-            return fail(h0, LP_ERR_INVALID_ARG, "block-diagonal batch LPs must share eval_every");
-        for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
-        for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
-        for (int b = 0; b < h->P.nred; ++b) mred.push_back(make_int2(i, b));
-        const int mx = h->m > h->n ? h->m : h->n;
-        for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
-    }
-    Arena L;
-    const size_t oj = L.add(sizeof(BatchJob) * jobs.size()), oa = L.add(sizeof(int2) * ma.size()),
-                 oat = L.add(sizeof(int2) * mat.size()), ored = L.add(sizeof(int2) * mred.size()),
-                 oel = L.add(sizeof(int2) * melem.size()), oact = L.add(sizeof(int));
-    char* buf = nullptr;
-    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&buf), L.off));
-    int* hact = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void**>(&hact), sizeof(int), hipHostMallocDefault) != hipSuccess) {
-        (void)hipFree(buf);
-        return fail(h0, LP_ERR_OUT_OF_MEMORY, "pinned allocation failed");
-    }
+    size_t cap = 0;
+    int* hstatus = nullptr;  // pinned
+    int hcap = 0;
     MultiMaps M{};
-    M.jobs = reinterpret_cast<const BatchJob*>(buf + oj);
-    M.count = count;
-    M.map_a = reinterpret_cast<const int2*>(buf + oa);
-    M.n_a = static_cast<int>(ma.size());
-    M.map_at = reinterpret_cast<const int2*>(buf + oat);
-    M.n_at = static_cast<int>(mat.size());
-    M.map_red = reinterpret_cast<const int2*>(buf + ored);
-    M.n_red = static_cast<int>(mred.size());
-    M.map_elem = reinterpret_cast<const int2*>(buf + oel);
-    M.n_elem = static_cast<int>(melem.size());
-    M.active = reinterpret_cast<int*>(buf + oact);
+    int E = 64;
+    // The round's launches as a graph, captured once the same set has run one round
+    // uncaptured (a set that changes every round is not worth an instantiation).
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    auto cleanup = [&]() {
+    int stable_rounds = 0;
+    bool graph_failed = false;
+
+    void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
-        (void)hipHostFree(hact);
-        (void)hipFree(buf);
-    };
-    auto H2D = [&](size_t off, const void* src, size_t bytes) {
-        return bytes ? hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
-    };
-    hipError_t e = H2D(oj, jobs.data(), sizeof(BatchJob) * jobs.size());
-    if (e == hipSuccess) e = H2D(oa, ma.data(), sizeof(int2) * ma.size());
-    if (e == hipSuccess) e = H2D(oat, mat.data(), sizeof(int2) * mat.size());
-    if (e == hipSuccess) e = H2D(ored, mred.data(), sizeof(int2) * mred.size());
-    if (e == hipSuccess) e = H2D(oel, melem.data(), sizeof(int2) * melem.size());
-    if (e == hipSuccess) {
-        launch_multi(M, MULTI_RESET, 0, s);
-        launch_multi(M, MULTI_INIT, 0, s);
-        launch_multi(M, MULTI_AX_ALL, 0, s);
-        launch_multi(M, MULTI_ATY, 1, s);  // 1: products of the initial point
-        launch_multi(M, MULTI_PARTIALS, 1, s);
-        launch_multi(M, MULTI_DECIDE, 1, s);
-        launch_multi(M, MULTI_REBASE_INIT, 0, s);
-        e = hipGetLastError();
+        gexec = nullptr;
+        graph = nullptr;
+        stable_rounds = 0;
+        graph_failed = false;
     }
-    auto bundle = [&]() {
-        for (int it = 0; it < E; ++it) {
+
+    int32_t build(const std::vector<lp_handle*>& hs, const lp_options* o, hipStream_t s, lp_handle* err_to) {
+        drop_graph();
+        const int count = static_cast<int>(hs.size());
+        std::vector<BatchJob> jobs(static_cast<size_t>(count));
+        std::vector<int2> ma, mat, mred, melem;
+        for (int i = 0; i < count; ++i) {
+            lp_handle* h = hs[i];
+            jobs[i] = make_job(h, o);
+            for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
+            for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
+            for (int b = 0; b < h->P.nred; ++b) mred.push_back(make_int2(i, b));
+            const int mx = h->m > h->n ? h->m : h->n;
+            for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
+        }
+        E = count > 0 ? jobs[0].eval_every : 64;
+        for (const BatchJob& J : jobs)
+            if (J.eval_every != E) return fail(err_to, LP_ERR_INVALID_ARG, "block-diagonal LPs must share eval_every");
+        Arena L;
+        const size_t oj = L.add(sizeof(BatchJob) * jobs.size()), oa = L.add(sizeof(int2) * ma.size()),
+                     oat = L.add(sizeof(int2) * mat.size()), ored = L.add(sizeof(int2) * mred.size()),
+                     oel = L.add(sizeof(int2) * melem.size()), ost = L.add(sizeof(int) * (count + 1));
+        if (L.off > cap) {
+            if (buf) (void)hipFree(buf);
+            buf = nullptr;
+            cap = 0;
+            const size_t want = L.off * 2;
+            HIP_TRY(err_to, hipMalloc(reinterpret_cast<void**>(&buf), want));
+            cap = want;
+        }
+        if (count + 1 > hcap) {
+            if (hstatus) (void)hipHostFree(hstatus);
+            hstatus = nullptr;
+            hcap = 0;
+            HIP_TRY(err_to, hipHostMalloc(reinterpret_cast<void**>(&hstatus), sizeof(int) * (count + 1) * 2,
+                                          hipHostMallocDefault));
+            hcap = (count + 1) * 2;
+        }
+        M = MultiMaps{};
+        M.jobs = reinterpret_cast<const BatchJob*>(buf + oj);
+        M.count = count;
+        M.map_a = reinterpret_cast<const int2*>(buf + oa);
+        M.n_a = static_cast<int>(ma.size());
+        M.map_at = reinterpret_cast<const int2*>(buf + oat);
+        M.n_at = static_cast<int>(mat.size());
+        M.map_red = reinterpret_cast<const int2*>(buf + ored);
+        M.n_red = static_cast<int>(mred.size());
+        M.map_elem = reinterpret_cast<const int2*>(buf + oel);
+        M.n_elem = static_cast<int>(melem.size());
+        M.active = reinterpret_cast<int*>(buf + ost);
+        auto H2D = [&](size_t off, const void* src, size_t bytes) {
+            return bytes ? hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+        };
+        HIP_TRY(err_to, H2D(oj, jobs.data(), sizeof(BatchJob) * jobs.size()));
+        HIP_TRY(err_to, H2D(oa, ma.data(), sizeof(int2) * ma.size()));
+        HIP_TRY(err_to, H2D(oat, mat.data(), sizeof(int2) * mat.size()));
+        HIP_TRY(err_to, H2D(ored, mred.data(), sizeof(int2) * mred.size()));
+        HIP_TRY(err_to, H2D(oel, melem.data(), sizeof(int2) * melem.size()));
+        return LP_OK;
+    }
+
+    void free_all() {
+        drop_graph();
+        if (buf) (void)hipFree(buf);
+        if (hstatus) (void)hipHostFree(hstatus);
+        buf = nullptr;
+        hstatus = nullptr;
+        cap = 0;
+        hcap = 0;
+    }
+};
+
+// One evaluation period of every LP of D: eval_every (primal, dual) launches, the
+// evaluation, the decision, the restart and each LP's status into D.M.active[i]. Replayed
+// as a hipGraph once the same set has run `capture_after` rounds uncaptured.
+void run_round(DevMaps& D, hipStream_t s, int capture_after) {
+    const MultiMaps& M = D.M;
+    auto round = [&]() {
+        for (int it = 0; it < D.E; ++it) {
             launch_multi(M, MULTI_PRIMAL, it, s);
             launch_multi(M, MULTI_DUAL, it, s);
         }
@@ -472,44 +463,140 @@ int32_t solve_block_diagonal(const std::vector<lp_handle*>& hs, const lp_options
         launch_multi(M, MULTI_PARTIALS, 0, s);
         launch_multi(M, MULTI_DECIDE, 0, s);
         launch_multi(M, MULTI_APPLY, 0, s);
-        launch_multi(M, MULTI_ACTIVE, 0, s);
+        launch_multi(M, MULTI_STATUS, 0, s);
     };
-    if (e == hipSuccess) {
+    if (!D.gexec && !D.graph_failed && D.stable_rounds >= capture_after) {
         hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (ce == hipSuccess) {
-            bundle();
-            ce = hipStreamEndCapture(s, &graph);
+            round();
+            ce = hipStreamEndCapture(s, &D.graph);
         }
-        if (ce == hipSuccess) ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
-        if (ce != hipSuccess) {
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&D.gexec, D.graph, nullptr, nullptr, 0);
+        if (ce != hipSuccess) {  // stay with direct launches for this set
             (void)hipGetLastError();
-            if (graph) (void)hipGraphDestroy(graph);
-            graph = nullptr;
-            gexec = nullptr;
+            if (D.graph) (void)hipGraphDestroy(D.graph);
+            D.graph = nullptr;
+            D.gexec = nullptr;
+            D.graph_failed = true;
         }
     }
-    long long max_bundles = 0;
-    for (const BatchJob& J : jobs) {
-        const long long b = J.max_iters / E + 2;
-        if (b > max_bundles) max_bundles = b;
+    if (D.gexec) (void)hipGraphLaunch(D.gexec, s);
+    else round();
+    D.stable_rounds++;
+}
+
+// LPs solved one per workgroup in a single persistent launch, started on its own stream
+// so that it runs beside the block-diagonal launches of the larger LPs. The host arrays
+// stay alive until finish_persistent.
+struct PersistentRun {
+    std::vector<BatchJob> jobs;
+    std::vector<int32_t> order;
+    char* buf = nullptr;
+    hipStream_t s = nullptr;
+};
+
+int32_t start_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo, PersistentRun& R) {
+    const int count = static_cast<int>(hs.size());
+    lp_handle* h0 = hs[0];
+    for (lp_handle* h : hs)
+        if (int32_t rc = materialize(h)) return rc;
+    R.jobs.resize(static_cast<size_t>(count));
+    R.order.resize(static_cast<size_t>(count));
+    for (int i = 0; i < count; ++i) {
+        R.jobs[i] = make_job(hs[i], bo);
+        R.order[i] = i;
     }
-    for (long long b = 0; e == hipSuccess && b < max_bundles; ++b) {
-        if (gexec) e = hipGraphLaunch(gexec, s);
-        else {
-            bundle();
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = hipMemcpyAsync(hact, M.active, sizeof(int), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess && *hact == 0) break;
-    }
+    std::stable_sort(R.order.begin(), R.order.end(), [&](int32_t a, int32_t b) { return hs[a]->nnz > hs[b]->nnz; });
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h0->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
+    int grid = cus * wpc;
+    if (grid > count) grid = count;
+    const size_t bj = sizeof(BatchJob) * static_cast<size_t>(count), bo_ = sizeof(int32_t) * static_cast<size_t>(count);
+    const size_t oc = (bj + bo_ + 255) / 256 * 256;
+    HIP_TRY(h0, hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
+    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&R.buf), oc + 256));
+    BatchJob* djobs = reinterpret_cast<BatchJob*>(R.buf);
+    int32_t* dorder = reinterpret_cast<int32_t*>(R.buf + bj);
+    int32_t* dcounter = reinterpret_cast<int32_t*>(R.buf + oc);
+    hipError_t e = hipMemcpyAsync(djobs, R.jobs.data(), bj, hipMemcpyHostToDevice, R.s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dorder, R.order.data(), bo_, hipMemcpyHostToDevice, R.s);
+    if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, sizeof(int32_t), R.s);
     if (e == hipSuccess) {
-        launch_multi(M, MULTI_EXTRACT, 0, s);
+        launch_batch(djobs, dorder, count, dcounter, grid, R.s);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    cleanup();
-    if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("block-diagonal batch: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
+    return LP_OK;
+}
+
+// Waits for the persistent launch (also after an error elsewhere: its kernels must have
+// ended before their memory goes) and collects the results when `collect`.
+int32_t finish_persistent(const std::vector<lp_handle*>& hs, PersistentRun& R, bool collect) {
+    hipError_t e = R.s ? hipStreamSynchronize(R.s) : hipSuccess;
+    if (R.buf) (void)hipFree(R.buf);
+    R.buf = nullptr;
+    int32_t rc = LP_OK;
+    if (e != hipSuccess) rc = fail(hs[0], LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
+    else if (collect) rc = finish_batch(hs, R.s);
+    if (R.s) (void)hipStreamDestroy(R.s);
+    R.s = nullptr;
+    return rc;
+}
+
+// LPs advanced together as one block-diagonal problem, one launch per phase for all of
+// them, evaluation periods replayed as a hipGraph. When a quarter of the mapped LPs have
+// stopped, the maps are rebuilt over the running ones, so finished LPs cost no more
+// workgroups (each LP's trajectory does not depend on the others in the map).
+int32_t solve_block_diagonal(const std::vector<lp_handle*>& hs, const lp_options* bo, hipStream_t s) {
+    lp_handle* h0 = hs[0];
+    for (lp_handle* h : hs)
+        if (int32_t rc = materialize(h)) return rc;
+    DevMaps all, run;
+    struct Release {
+        DevMaps &a, &b;
+        ~Release() {
+            a.free_all();
+            b.free_all();
+        }
+    } release{all, run};
+    if (int32_t rc = all.build(hs, bo, s, h0)) return rc;
+    {
+        const MultiMaps& M = all.M;
+        launch_multi(M, MULTI_RESET, 0, s);
+        launch_multi(M, MULTI_INIT, 0, s);
+        launch_multi(M, MULTI_AX_ALL, 0, s);
+        launch_multi(M, MULTI_ATY, 1, s);  // 1: products of the initial point
+        launch_multi(M, MULTI_PARTIALS, 1, s);
+        launch_multi(M, MULTI_DECIDE, 1, s);
+        launch_multi(M, MULTI_REBASE_INIT, 0, s);
+        HIP_TRY(h0, hipGetLastError());
+    }
+    long long max_bundles = 0;
+    for (lp_handle* h : hs) {
+        const long long b = make_job(h, bo).max_iters / all.E + 2;
+        if (b > max_bundles) max_bundles = b;
+    }
+    std::vector<lp_handle*> cur = hs;
+    if (int32_t rc = run.build(cur, bo, s, h0)) return rc;
+    for (long long b = 0; b < max_bundles; ++b) {
+        run_round(run, s, 0);
+        HIP_TRY(h0, hipGetLastError());
+        HIP_TRY(h0, hipMemcpyAsync(run.hstatus, run.M.active, sizeof(int) * run.M.count, hipMemcpyDeviceToHost, s));
+        HIP_TRY(h0, hipStreamSynchronize(s));
+        std::vector<lp_handle*> still;
+        for (int i = 0; i < run.M.count; ++i)
+            if (run.hstatus[i] == kRunning) still.push_back(cur[i]);
+        if (still.empty()) break;
+        if (4 * still.size() <= 3 * cur.size()) {
+            cur.swap(still);
+            if (int32_t rc = run.build(cur, bo, s, h0)) return rc;
+        }
+    }
+    launch_multi(all.M, MULTI_EXTRACT, 0, s);
+    HIP_TRY(h0, hipGetLastError());
+    HIP_TRY(h0, hipStreamSynchronize(s));
     return finish_batch(hs, s);
 }
 
@@ -946,100 +1033,6 @@ lp_handle* clone_for_request(const lp_handle* t) {
     return h;
 }
 
-// Device jobs table and block maps of a set of LPs (grown as needed, reused across rounds;
-// every round ends with a stream synchronisation before the next rebuild).
-struct DevMaps {
-    char* buf = nullptr;
-    size_t cap = 0;
-    int* hstatus = nullptr;  // pinned
-    int hcap = 0;
-    MultiMaps M{};
-    int E = 64;
-    // The round's launches as a graph, captured once the same set has run one round
-    // uncaptured (a set that changes every round is not worth an instantiation).
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int stable_rounds = 0;
-    bool graph_failed = false;
-
-    void drop_graph() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
-        gexec = nullptr;
-        graph = nullptr;
-        stable_rounds = 0;
-        graph_failed = false;
-    }
-
-    int32_t build(const std::vector<lp_handle*>& hs, const lp_options* o, hipStream_t s, lp_handle* err_to) {
-        drop_graph();
-        const int count = static_cast<int>(hs.size());
-        std::vector<BatchJob> jobs(static_cast<size_t>(count));
-        std::vector<int2> ma, mat, mred, melem;
-        for (int i = 0; i < count; ++i) {
-            lp_handle* h = hs[i];
-            jobs[i] = make_job(h, o);
-            for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
-            for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
-            for (int b = 0; b < h->P.nred; ++b) mred.push_back(make_int2(i, b));
-            const int mx = h->m > h->n ? h->m : h->n;
-            for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
-        }
-        E = o->eval_every;
-        Arena L;
-        const size_t oj = L.add(sizeof(BatchJob) * jobs.size()), oa = L.add(sizeof(int2) * ma.size()),
-                     oat = L.add(sizeof(int2) * mat.size()), ored = L.add(sizeof(int2) * mred.size()),
-                     oel = L.add(sizeof(int2) * melem.size()), ost = L.add(sizeof(int) * (count + 1));
-        if (L.off > cap) {
-            if (buf) (void)hipFree(buf);
-            buf = nullptr;
-            cap = 0;
-            const size_t want = L.off * 2;
-            HIP_TRY(err_to, hipMalloc(reinterpret_cast<void**>(&buf), want));
-            cap = want;
-        }
-        if (count + 1 > hcap) {
-            if (hstatus) (void)hipHostFree(hstatus);
-            hstatus = nullptr;
-            hcap = 0;
-            HIP_TRY(err_to, hipHostMalloc(reinterpret_cast<void**>(&hstatus), sizeof(int) * (count + 1) * 2,
-                                          hipHostMallocDefault));
-            hcap = (count + 1) * 2;
-        }
-        M = MultiMaps{};
-        M.jobs = reinterpret_cast<const BatchJob*>(buf + oj);
-        M.count = count;
-        M.map_a = reinterpret_cast<const int2*>(buf + oa);
-        M.n_a = static_cast<int>(ma.size());
-        M.map_at = reinterpret_cast<const int2*>(buf + oat);
-        M.n_at = static_cast<int>(mat.size());
-        M.map_red = reinterpret_cast<const int2*>(buf + ored);
-        M.n_red = static_cast<int>(mred.size());
-        M.map_elem = reinterpret_cast<const int2*>(buf + oel);
-        M.n_elem = static_cast<int>(melem.size());
-        M.active = reinterpret_cast<int*>(buf + ost);
-        auto H2D = [&](size_t off, const void* src, size_t bytes) {
-            return bytes ? hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
-        };
-        HIP_TRY(err_to, H2D(oj, jobs.data(), sizeof(BatchJob) * jobs.size()));
-        HIP_TRY(err_to, H2D(oa, ma.data(), sizeof(int2) * ma.size()));
-        HIP_TRY(err_to, H2D(oat, mat.data(), sizeof(int2) * mat.size()));
-        HIP_TRY(err_to, H2D(ored, mred.data(), sizeof(int2) * mred.size()));
-        HIP_TRY(err_to, H2D(oel, melem.data(), sizeof(int2) * melem.size()));
-        return LP_OK;
-    }
-
-    void free_all() {
-        drop_graph();
-        if (buf) (void)hipFree(buf);
-        if (hstatus) (void)hipHostFree(hstatus);
-        buf = nullptr;
-        hstatus = nullptr;
-        cap = 0;
-        hcap = 0;
-    }
-};
-
 struct Ticket {
     uint64_t id;
     lp_handle* h;
@@ -1131,39 +1124,7 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
             dirty = false;
         }
         const MultiMaps& M = run_maps.M;
-        auto round = [&]() {
-            for (int it = 0; it < run_maps.E; ++it) {
-                launch_multi(M, MULTI_PRIMAL, it, s);
-                launch_multi(M, MULTI_DUAL, it, s);
-            }
-            launch_multi(M, MULTI_MATERIALIZE, 0, s);
-            launch_multi(M, MULTI_AX_FP32, 0, s);
-            launch_multi(M, MULTI_ATY, 0, s);
-            launch_multi(M, MULTI_AXA, 0, s);
-            launch_multi(M, MULTI_ATYA, 0, s);
-            launch_multi(M, MULTI_PARTIALS, 0, s);
-            launch_multi(M, MULTI_DECIDE, 0, s);
-            launch_multi(M, MULTI_APPLY, 0, s);
-            launch_multi(M, MULTI_STATUS, 0, s);
-        };
-        if (!run_maps.gexec && !run_maps.graph_failed && run_maps.stable_rounds >= 1) {
-            hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-            if (ce == hipSuccess) {
-                round();
-                ce = hipStreamEndCapture(s, &run_maps.graph);
-            }
-            if (ce == hipSuccess) ce = hipGraphInstantiate(&run_maps.gexec, run_maps.graph, nullptr, nullptr, 0);
-            if (ce != hipSuccess) {  // stay with direct launches for this set
-                (void)hipGetLastError();
-                if (run_maps.graph) (void)hipGraphDestroy(run_maps.graph);
-                run_maps.graph = nullptr;
-                run_maps.gexec = nullptr;
-                run_maps.graph_failed = true;
-            }
-        }
-        if (run_maps.gexec) (void)hipGraphLaunch(run_maps.gexec, s);
-        else round();
-        run_maps.stable_rounds++;
+        run_round(run_maps, s, 1);
         (void)hipMemcpyAsync(run_maps.hstatus, M.active, sizeof(int) * M.count, hipMemcpyDeviceToHost, s);
         (void)hipStreamSynchronize(s);
         S->st.rounds++;
@@ -1578,11 +1539,21 @@ int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo
         std::vector<lp_handle*> big, small;
         for (int32_t i = 0; i < count; ++i) (hs[i]->nnz > split ? big : small).push_back(hs[i]);
         const auto t0 = std::chrono::steady_clock::now();
+        PersistentRun pr;
+        if (!small.empty()) {
+            if (int32_t rc = start_persistent(small, bo, pr)) {
+                (void)finish_persistent(small, pr, false);
+                return rc;
+            }
+        }
         if (!big.empty()) {
-            if (int32_t rc = solve_block_diagonal(big, bo, h0->stream)) return rc;
+            if (int32_t rc = solve_block_diagonal(big, bo, h0->stream)) {
+                if (!small.empty()) (void)finish_persistent(small, pr, false);
+                return rc;
+            }
         }
         if (!small.empty()) {
-            if (int32_t rc = solve_persistent(small, bo, h0->stream)) return rc;
+            if (int32_t rc = finish_persistent(small, pr, true)) return rc;
         }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         for (int32_t i = 0; i < count; ++i) hs[i]->info.solve_seconds = secs;
