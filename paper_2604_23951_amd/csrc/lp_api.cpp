@@ -379,11 +379,22 @@ struct DevMaps {
         const int count = static_cast<int>(hs.size());
         std::vector<BatchJob> jobs(static_cast<size_t>(count));
         std::vector<int2> ma, mat, mred, melem;
+        int off_a[4], cnt_a[4], off_at[4], cnt_at[4];
+        for (int i = 0; i < count; ++i) jobs[i] = make_job(hs[i], o);
+        for (int v = 0; v < 4; ++v) {  // tile maps grouped by form
+            off_a[v] = static_cast<int>(ma.size());
+            off_at[v] = static_cast<int>(mat.size());
+            for (int i = 0; i < count; ++i) {
+                const lp_handle* h = hs[i];
+                if ((jobs[i].P.fp32 ? 2 : 0) + (jobs[i].P.method ? 1 : 0) != v) continue;
+                for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
+                for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
+            }
+            cnt_a[v] = static_cast<int>(ma.size()) - off_a[v];
+            cnt_at[v] = static_cast<int>(mat.size()) - off_at[v];
+        }
         for (int i = 0; i < count; ++i) {
-            lp_handle* h = hs[i];
-            jobs[i] = make_job(h, o);
-            for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
-            for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
+            const lp_handle* h = hs[i];
             for (int b = 0; b < h->P.nred; ++b) mred.push_back(make_int2(i, b));
             const int mx = h->m > h->n ? h->m : h->n;
             for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
@@ -418,6 +429,12 @@ struct DevMaps {
         M.n_a = static_cast<int>(ma.size());
         M.map_at = reinterpret_cast<const int2*>(buf + oat);
         M.n_at = static_cast<int>(mat.size());
+        for (int v = 0; v < 4; ++v) {
+            M.off_a[v] = off_a[v];
+            M.cnt_a[v] = cnt_a[v];
+            M.off_at[v] = off_at[v];
+            M.cnt_at[v] = cnt_at[v];
+        }
         M.map_red = reinterpret_cast<const int2*>(buf + ored);
         M.n_red = static_cast<int>(mred.size());
         M.map_elem = reinterpret_cast<const int2*>(buf + oel);

@@ -141,6 +141,10 @@ struct MultiMaps {
     const int2* map_elem; // vector blocks (ceil(max(m, n) / kBlock) per LP)
     int n_elem;
     int* active;          // number of LPs still running (MULTI_ACTIVE) or each LP's status (MULTI_STATUS)
+    // The tile maps are grouped by form v = 2 * fp32 + method (FP64 / FP32 storage, averaged /
+    // Halpern): the tiles of form v are entries [off_a[v], off_a[v] + cnt_a[v]) of map_a (and
+    // likewise of map_at), so the iteration launches one kernel specialised per form present.
+    int off_a[4], cnt_a[4], off_at[4], cnt_at[4];
 };
 
 enum MultiLaunch {

@@ -1728,31 +1728,26 @@ __device__ inline void run_tile(const Csr& M, int b, const T* xin, Epi e, T* pro
     tile_body(M, b, xin, e, prod, red);
 }
 
-template <int KIND>
+// FORM = 2 * fp32 + method for the iteration kinds (one instance per form: the four fused
+// epilogues in one kernel would hold the registers of the largest and halve occupancy), -1
+// for the evaluation products.
+template <int KIND, int FORM>
 __global__ __launch_bounds__(kBlock) void multi_tiles_kernel(const BatchJob* jobs, const int2* map, int it) {
     __shared__ double lds[kTileNnz];
     __shared__ double red[kBlock / 64];
     const int2 mt = map[blockIdx.x];
     const DevLP& P = jobs[mt.x].P;
     float* lds32 = reinterpret_cast<float*>(lds);
-    if (KIND == MK_PRIMAL) {
-        if (P.fp32) {
-            if (P.method) run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32_h(P, P.sc, it), lds32, red);
-            else run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32(P, P.sc, it), lds32, red);
-        } else if (P.method) {
-            run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal_h(P, P.sc, it), lds, red);
-        } else {
-            run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal(P, P.sc, it), lds, red);
-        }
-    } else if (KIND == MK_DUAL) {
-        if (P.fp32) {
-            if (P.method) run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dxa), epi_dual32_h(P, P.sc, it), lds32, red);
-            else run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dx), epi_dual32(P, P.sc, it), lds32, red);
-        } else if (P.method) {
-            run_tile(P.A.csr, mt.y, static_cast<const double*>(P.xa), epi_dual_h(P, P.sc, it), lds, red);
-        } else {
-            run_tile(P.A.csr, mt.y, static_cast<const double*>(P.x), epi_dual(P, P.sc, it), lds, red);
-        }
+    if constexpr (KIND == MK_PRIMAL) {
+        if constexpr (FORM == 3) run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32_h(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 2) run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 1) run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal_h(P, P.sc, it), lds, red);
+        else run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal(P, P.sc, it), lds, red);
+    } else if constexpr (KIND == MK_DUAL) {
+        if constexpr (FORM == 3) run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dxa), epi_dual32_h(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 2) run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dx), epi_dual32(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 1) run_tile(P.A.csr, mt.y, static_cast<const double*>(P.xa), epi_dual_h(P, P.sc, it), lds, red);
+        else run_tile(P.A.csr, mt.y, static_cast<const double*>(P.x), epi_dual(P, P.sc, it), lds, red);
     } else {
         if (P.sc->status != kRunning) return;
         if (KIND == MK_AX_FP32 && (!P.fp32 || P.method)) return;
@@ -2029,13 +2024,23 @@ void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s) {
         if (n > 0) hipLaunchKernelGGL(kern, dim3(n), dim3(kBlock), 0, s, M.jobs, map, it_or_mode);
     };
     switch (kind) {
-        case MULTI_PRIMAL: tiles(multi_tiles_kernel<MK_PRIMAL>, M.n_at, M.map_at); break;
-        case MULTI_DUAL: tiles(multi_tiles_kernel<MK_DUAL>, M.n_a, M.map_a); break;
-        case MULTI_AX_ALL: tiles(multi_tiles_kernel<MK_AX_ALL>, M.n_a, M.map_a); break;
-        case MULTI_AX_FP32: tiles(multi_tiles_kernel<MK_AX_FP32>, M.n_a, M.map_a); break;
-        case MULTI_ATY: tiles(multi_tiles_kernel<MK_ATY>, M.n_at, M.map_at); break;
-        case MULTI_AXA: tiles(multi_tiles_kernel<MK_AXA>, M.n_a, M.map_a); break;
-        case MULTI_ATYA: tiles(multi_tiles_kernel<MK_ATYA>, M.n_at, M.map_at); break;
+        case MULTI_PRIMAL:
+            tiles(multi_tiles_kernel<MK_PRIMAL, 0>, M.cnt_at[0], M.map_at + M.off_at[0]);
+            tiles(multi_tiles_kernel<MK_PRIMAL, 1>, M.cnt_at[1], M.map_at + M.off_at[1]);
+            tiles(multi_tiles_kernel<MK_PRIMAL, 2>, M.cnt_at[2], M.map_at + M.off_at[2]);
+            tiles(multi_tiles_kernel<MK_PRIMAL, 3>, M.cnt_at[3], M.map_at + M.off_at[3]);
+            break;
+        case MULTI_DUAL:
+            tiles(multi_tiles_kernel<MK_DUAL, 0>, M.cnt_a[0], M.map_a + M.off_a[0]);
+            tiles(multi_tiles_kernel<MK_DUAL, 1>, M.cnt_a[1], M.map_a + M.off_a[1]);
+            tiles(multi_tiles_kernel<MK_DUAL, 2>, M.cnt_a[2], M.map_a + M.off_a[2]);
+            tiles(multi_tiles_kernel<MK_DUAL, 3>, M.cnt_a[3], M.map_a + M.off_a[3]);
+            break;
+        case MULTI_AX_ALL: tiles(multi_tiles_kernel<MK_AX_ALL, -1>, M.n_a, M.map_a); break;
+        case MULTI_AX_FP32: tiles(multi_tiles_kernel<MK_AX_FP32, -1>, M.n_a, M.map_a); break;
+        case MULTI_ATY: tiles(multi_tiles_kernel<MK_ATY, -1>, M.n_at, M.map_at); break;
+        case MULTI_AXA: tiles(multi_tiles_kernel<MK_AXA, -1>, M.n_a, M.map_a); break;
+        case MULTI_ATYA: tiles(multi_tiles_kernel<MK_ATYA, -1>, M.n_at, M.map_at); break;
         case MULTI_PARTIALS:
             if (M.n_red > 0)
                 hipLaunchKernelGGL(multi_partials_kernel, dim3(M.n_red), dim3(kBlock), 0, s, M.jobs, M.map_red,
