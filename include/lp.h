@@ -193,26 +193,30 @@ int32_t lp_update_options(lp_handle *h, const lp_options *opt);
  *    evaluations, restart and termination decisions).
  *  - Larger LPs advance together as one block-diagonal problem: every launch covers the row
  *    tiles of all of them, each LP with its own step sizes, restarts and termination;
- *    evaluation periods are replayed as one hipGraph for the whole group until every LP
- *    has stopped. Each such LP follows exactly the trajectory of its own lp_solve with the
- *    row-tile layout.
+ *    evaluation periods are replayed as one hipGraph for the group; when a quarter of the
+ *    group has stopped the launches are rebuilt over the running LPs. Each such LP follows
+ *    exactly the trajectory of its own lp_solve with the row-tile layout. The persistent
+ *    launch runs on a stream of its own beside these launches.
  * Each LP's result depends only on that LP (not on the other LPs or on where it ran), so it
  * is the same alone and in any batch. The handles' precisions may differ.
  * Solve-time options: batch_opt's eps_rel, max_iters, eval_every and restarts for every LP
  * when batch_opt is given, each handle's own otherwise (the LPs of the block-diagonal group
  * must then share eval_every); batch_opt->batch_wg_per_cu and batch_split_nnz set the
  * launches. Afterwards every handle is solved and lp_get_solution returns its result
- * (info.solve_seconds is the batch time). Runs on the first handle's stream and waits. */
+ * (info.solve_seconds is the batch time). Runs on the first handle's stream (and a
+ * temporary second stream for the persistent launch) and waits. */
 int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
 
 /* ---- serving form -------------------------------------------------------------------
  * A server solves LPs as they arrive, with continuous batching: a worker thread keeps a
  * running set of LPs on the device and advances all of them together, one evaluation
  * period (eval_every iterations, evaluation, restart decision) per round of shared
- * block-diagonal launches. Between rounds it retires the LPs that stopped (their result is
- * copied to the host and their device memory released) and admits queued requests in
- * arrival order while a slot is free and the request's device footprint fits the HBM
- * budget. Every LP starts at its own iteration 0 and keeps its own step sizes, restarts and
+ * block-diagonal launches (replayed as a hipGraph while the set is unchanged). Between
+ * rounds it retires the LPs that stopped (their result is copied to the host and their
+ * device memory released) and takes in the requests that are ready. A second (set-up)
+ * thread admits queued requests in arrival order while a slot is free and the request's
+ * device footprint fits the HBM budget, and sets each up on the device (upload, scaling,
+ * norm estimate) on its own stream while the rounds run. Every LP starts at its own iteration 0 and keeps its own step sizes, restarts and
  * counters, so its result is the same as when it is solved alone.
  * A submitted handle is a template: it must be created with opt->deferred = 1, it is not
  * modified, and it may be submitted any number of times, also while earlier submissions of

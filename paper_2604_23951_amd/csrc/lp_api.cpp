@@ -1055,6 +1055,7 @@ struct Ticket {
     lp_handle* h;
     double t_submit, t_admit, t_done;
     int64_t counted;  // iterations already added to the server's work counters
+    int32_t setup_rc; // result of the device set-up (materialize)
 };
 
 }  // namespace
@@ -1067,9 +1068,15 @@ struct lp_server {
     lp_options opt{};
     std::chrono::steady_clock::time_point t0;
     std::thread worker;
+    // Set-up thread: admits queued requests (arrival order, slot and budget permitting) and
+    // sets them up on the device on its own stream while the worker runs rounds.
+    std::thread setup_worker;
+    hipStream_t setup_stream = nullptr;
     std::mutex mu;
-    std::condition_variable cv_work, cv_idle;
+    std::condition_variable cv_work, cv_idle, cv_setup;
     std::deque<Ticket> queue;
+    std::deque<Ticket> ready;  // set up, waiting to join the running set
+    int64_t live = 0;          // admitted and not yet completed (slots in use)
     std::vector<Ticket> running;
     std::vector<uint64_t> done;
     std::unordered_map<uint64_t, Ticket> finished;       // completed, result not fetched yet
@@ -1086,30 +1093,20 @@ namespace {
 
 void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirty) {
     hipStream_t s = S->stream;
-    // admission: arrival order, while a slot is free and the footprint fits the budget
+    // requests the set-up thread has placed on the device join the running set
     std::vector<Ticket> newly;
     {
         std::unique_lock<std::mutex> lk(S->mu);
-        while (!S->queue.empty() && static_cast<int>(S->running.size() + newly.size()) < S->max_slots) {
-            Ticket& t = S->queue.front();
-            const int64_t fp = static_cast<int64_t>(t.h->arena_bytes);
-            if (S->st.bytes_in_use + fp > S->budget) break;
-            S->st.bytes_in_use += fp;
-            if (S->st.bytes_in_use > S->st.peak_bytes) S->st.peak_bytes = S->st.bytes_in_use;
-            t.t_admit = S->now();
-            newly.push_back(t);
-            S->queue.pop_front();
-            S->st.admitted++;
-            S->st.queued--;
+        while (!S->ready.empty()) {
+            newly.push_back(S->ready.front());
+            S->ready.pop_front();
         }
     }
     std::vector<Ticket> failed;
     std::vector<Ticket> ok;
     for (Ticket& t : newly) {
         t.h->stream = S->stream;
-        t.h->own_stream = false;
-        if (materialize(t.h) == LP_OK) ok.push_back(t);
-        else failed.push_back(t);
+        (t.setup_rc == LP_OK ? ok : failed).push_back(t);
     }
     if (!ok.empty()) {
         std::vector<lp_handle*> hs;
@@ -1190,12 +1187,45 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
             t.t_done = S->now();
             std::unique_lock<std::mutex> lk(S->mu);
             S->st.bytes_in_use -= fp;
+            S->live--;
             S->st.completed++;
             S->done.push_back(t.id);
             S->finished[t.id] = t;
             S->times[t.id] = {t.t_submit, t.t_admit, t.t_done};
         }
         S->cv_idle.notify_all();
+        S->cv_setup.notify_one();  // memory and a slot are free again
+    }
+}
+
+void setup_loop(lp_server* S) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        Ticket t;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (;;) {
+                if (S->stop) return;
+                if (!S->queue.empty() && S->live < S->max_slots &&
+                    S->st.bytes_in_use + static_cast<int64_t>(S->queue.front().h->arena_bytes) <= S->budget)
+                    break;
+                S->cv_setup.wait(lk);
+            }
+            t = S->queue.front();
+            S->queue.pop_front();
+            S->st.bytes_in_use += static_cast<int64_t>(t.h->arena_bytes);
+            if (S->st.bytes_in_use > S->st.peak_bytes) S->st.peak_bytes = S->st.bytes_in_use;
+            S->live++;
+            S->st.admitted++;
+            S->st.queued--;
+            t.t_admit = S->now();
+        }
+        t.h->stream = S->setup_stream;
+        t.h->own_stream = false;
+        t.setup_rc = materialize(t.h);
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->ready.push_back(t);
+        S->cv_work.notify_one();
     }
 }
 
@@ -1207,7 +1237,7 @@ void server_loop(lp_server* S) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (S->stop) break;
-            if (S->queue.empty() && S->running.empty()) {
+            if (S->ready.empty() && S->running.empty()) {
                 S->cv_idle.notify_all();
                 S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
                 continue;
@@ -1243,11 +1273,14 @@ int32_t lp_server_create(lp_server** out, int32_t device, int64_t hbm_budget_byt
         S->st.hbm_budget = hbm_budget_bytes;
         hipError_t e = hipSetDevice(device);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->setup_stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
+            if (S->stream) (void)hipStreamDestroy(S->stream);
             delete S;
             return fail(nullptr, LP_ERR_DEVICE, std::string("server stream: ") + hipGetErrorString(e));
         }
         S->worker = std::thread(server_loop, S);
+        S->setup_worker = std::thread(setup_loop, S);
         *out = S;
         return LP_OK;
     } catch (...) {
@@ -1268,12 +1301,12 @@ int32_t lp_server_submit(lp_server* S, lp_handle* h, uint64_t* ticket) {
         return fail(h, LP_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
     std::unique_lock<std::mutex> lk(S->mu);
-    Ticket t{S->next_ticket++, r, S->now(), 0.0, 0.0, 0};
+    Ticket t{S->next_ticket++, r, S->now(), 0.0, 0.0, 0, LP_OK};
     S->queue.push_back(t);
     S->st.submitted++;
     S->st.queued++;
     *ticket = t.id;
-    S->cv_work.notify_one();
+    S->cv_setup.notify_one();
     return LP_OK;
 }
 
@@ -1342,13 +1375,18 @@ void lp_server_destroy(lp_server* S) {
         S->stop = true;
     }
     S->cv_work.notify_all();
+    S->cv_setup.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    if (S->setup_worker.joinable()) S->setup_worker.join();
     (void)hipSetDevice(S->device);
     (void)hipStreamSynchronize(S->stream);
+    (void)hipStreamSynchronize(S->setup_stream);
     for (Ticket& t : S->running) lp_destroy(t.h);
+    for (Ticket& t : S->ready) lp_destroy(t.h);
     for (Ticket& t : S->queue) lp_destroy(t.h);
     for (auto& kv : S->finished) lp_destroy(kv.second.h);
     (void)hipStreamDestroy(S->stream);
+    (void)hipStreamDestroy(S->setup_stream);
     delete S;
 }
 
