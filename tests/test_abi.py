@@ -149,3 +149,16 @@ def test_tuned_layout_builds_both_on_the_host():
     assert L["units_a"] > 0 and L["units_at"] > 0 and L["tiles_a"] == T["tiles_a"]
     assert T["units_a"] == 0 and L["device_bytes"] > T["device_bytes"]
     assert L["layout"] == -1 and L["trial_ns_panels"] == 0 and L["trial_ns_tiles"] == 0
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    """Every function of the library's own namespace that one source file calls and another
+    defines is resolved inside the shared object (a lazily bound miss would only fail at
+    its first call, on the device path)."""
+    import shutil
+    import subprocess
+    if shutil.which("nm") is None:
+        pytest.skip("nm not available")
+    path = lpg.lib()._name
+    out = subprocess.run(["nm", "-D", "--undefined-only", "-C", path], capture_output=True, text=True, check=True)
+    assert "lpgpu::" not in out.stdout, out.stdout
