@@ -60,3 +60,23 @@ def test_full_size_solve_properties(oracle_lib, big):
     # This LP needs about 2e5 iterations to reach E_rel 1e-3; after 6400 it sits near 0.18.
     assert chk["erel"] < 0.25 * start["erel"]
     assert abs(sol.info.primal_obj - lp.p_star) <= 1e-2 * (1 + abs(lp.p_star))
+
+
+def test_full_size_fp32_halpern_to_tolerance(oracle_lib, big):
+    """The FP32 storage form (FP64 evaluation and refinement) with the reflected Halpern
+    iteration solves the full-size LP to E_rel 1e-4 (about 1.26e5 iterations, ~30 s). Error
+    against the FP64 oracle: its KKT check of the returned point on the original data gives
+    the same E_rel (to 1e-8) below the tolerance, and the objective is within 1e-5 of the
+    known optimum (the construction's p*)."""
+    lp = big
+    with lpg.Solver(lp, precision=lpg.LP_PREC_FP32_REFINED, method=lpg.LP_METHOD_HALPERN, eps_rel=1e-4,
+                    max_iters=300000, time_limit_s=150.0) as s:
+        sol = s.solve()
+    chk = oracle.kkt(lp, sol.x, sol.y)
+    rel_obj = abs(sol.info.primal_obj - lp.p_star) / (1 + abs(lp.p_star))
+    print(f"full-size FP32 Halpern: {sol.status}, {sol.info.iterations} iterations, {sol.info.solve_seconds:.1f}s, "
+          f"E_rel {sol.info.rel_kkt:.3e} (oracle {chk['erel']:.3e}), objective error {rel_obj:.2e}")
+    assert sol.status == "optimal"
+    assert chk["erel"] <= 1e-4 * (1 + 1e-9)
+    assert abs(chk["erel"] - sol.info.rel_kkt) <= 1e-8 * chk["erel"]
+    assert rel_obj <= 1e-5
