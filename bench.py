@@ -77,6 +77,25 @@ def run_cpu_baseline(lp, iters: int) -> dict:
                       f"{r.iter_s:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
 
 
+def run_cpu_baseline_batch(lps, method: int, budget_s: float = 20.0) -> dict:
+    """The oracle as it stands, single-threaded, solving LPs of the batch one after another
+    to E_rel 1e-4 (same method) in index order (sizes are random in that order) until
+    about `budget_s` seconds of solve time have been spent."""
+    import oracle
+
+    spent = 0.0
+    done = 0
+    for lp in lps:
+        r = oracle.solve(lp, eps_rel=1e-4, max_iters=400000, method=method)
+        spent += r.setup_s + r.iter_s
+        done += 1
+        if spent >= budget_s:
+            break
+    return {"value": done / spent, "unit": "LPs/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {done} LPs of the batch in index order, each to E_rel 1e-4 with the same "
+                      f"method, setup included, {spent:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
+
+
 def run_batch(args) -> int:
     """Batched workload: LPs j of the 4096-LP batch (m log-uniform in [50, 5000], n = 2m,
     random-sparse with density U[0.5%, 5%] for even j, transportation for odd j), solved
@@ -141,6 +160,11 @@ def run_batch(args) -> int:
         "speedup_vs_per_lp_loop": (len(sols) / dt) / loop_rate,
         "create_s": create_s,
     }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline: oracle on the first LPs of the batch", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = run_cpu_baseline_batch(lps, meth)
+    else:
+        result["cpu_baseline"] = None
     print(json.dumps(result), flush=True)
     return 0
 
