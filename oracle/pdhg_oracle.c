@@ -76,6 +76,8 @@ typedef struct {
     int32_t method;      /* 0: averaged PDHG; 1: reflected Halpern PDHG */
     int32_t pad3;
     double reflection;   /* rho of the Halpern form, in [0, 1] */
+    int32_t omega_steps; /* square-root steps of the primal-weight update (O11); 0: the form's */
+    int32_t pad4;
 } ora_opts;
 
 typedef struct {
@@ -540,6 +542,7 @@ void ora_default_opts(ora_opts *o) {
     o->eps_infeas = 1e-8;
     o->method = 0;
     o->reflection = 1.0;
+    o->omega_steps = 0;
 }
 
 /* Export the scaled problem: A~ values (in the caller's CSR order), R, C, and A~^T. */
@@ -620,8 +623,11 @@ static double dual_step(double y, double axn, double ax, double sigma, double bl
  * O10 candidate = average if its KKT_omega is strictly smaller; restart if
  *     (i) KKT_c <= 0.2 KKT_anchor, (ii) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev, or
  *     (iii) t >= 0.36 k.
- * O11 on restart omega <- sqrt(omega * dy / dx) when dx, dy > 1e-10 (the theta = 1/2 smoothing
- *     of log omega toward log(dy/dx)), the candidate becomes iterate, anchor and average.
+ * O11 on restart, when dx, dy > 1e-10, omega <- sqrt(omega * dy / dx) applied `omega_steps`
+ *     times: the smoothing of log omega toward log(dy/dx) with weight theta =
+ *     1 - 2^-omega_steps, built from correctly rounded operations only (0 selects the form's
+ *     default: one step, theta = 1/2, for the averaged form; two, theta = 3/4, for the
+ *     Halpern form); the candidate becomes iterate, anchor and average.
  * O12 x = C x~, y = R y~, z = projected reduced cost.
  *
  * Halpern form (method 1, a reading of the newer cuPDLPx-family iteration the paper names):
@@ -837,7 +843,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             /* O11 */
             const double *xc = use_avg ? xa : x, *yc = use_avg ? ya : y;
             double dx = diff_norm(n, xc, xan), dy = diff_norm(m, yc, yan);
-            if (dx > 1e-10 && dy > 1e-10) omega = sqrt((omega * dy) / dx);
+            const int32_t steps = o->omega_steps > 0 ? o->omega_steps : (halpern ? 2 : 1);
+            if (dx > 1e-10 && dy > 1e-10)
+                for (int32_t q = 0; q < steps; q++) omega = sqrt((omega * dy) / dx);
             tau = eta / omega;
             sigma = eta * omega;
             if (use_avg) {
