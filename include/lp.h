@@ -142,6 +142,11 @@ typedef struct lp_options {
     int32_t method;        /* lp_method (default LP_METHOD_AVERAGED) */
     int32_t pad2;
     double reflection;     /* rho of LP_METHOD_HALPERN, in [0, 1] (default 1) */
+    int32_t omega_steps;   /* primal-weight update at a restart: omega <- sqrt(omega * dy / dx)
+                            * applied this many times, i.e. log omega moves toward log(dy/dx)
+                            * by the fraction 1 - 2^-omega_steps; 1 to 8, or 0 (default) for
+                            * the form's own: 1 for LP_METHOD_AVERAGED, 2 for LP_METHOD_HALPERN */
+    int32_t pad3;
 } lp_options;
 
 typedef struct lp_info {
@@ -182,7 +187,7 @@ int32_t lp_create(lp_handle **out, int32_t m, int32_t n, int64_t nnz, const int3
 int32_t lp_solve(lp_handle *h);
 
 /* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every,
- * restarts, eps_infeas, method and reflection are taken from *opt; every other field of *opt
+ * restarts, eps_infeas, method, reflection and omega_steps are taken from *opt; every other field of *opt
  * is ignored (the problem setup, the step size and the trace capacity are fixed at lp_create). */
 int32_t lp_update_options(lp_handle *h, const lp_options *opt);
 

@@ -59,6 +59,7 @@ class lp_options(C.Structure):
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
         ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
         ("method", C.c_int32), ("pad2", C.c_int32), ("reflection", C.c_double),
+        ("omega_steps", C.c_int32), ("pad3", C.c_int32),
     ]
 
 
@@ -355,7 +356,7 @@ class Solver:
 
     def update(self, **options):
         """Change solve-time options (eps_rel, max_iters, time_limit_s, eval_every, restarts,
-        eps_infeas, method, reflection); the ones not given take their defaults."""
+        eps_infeas, method, reflection, omega_steps); the ones not given take their defaults."""
         lp_update_options(self.h, make_options(**options))
 
     def solve(self, with_trace: bool = False) -> Solution:

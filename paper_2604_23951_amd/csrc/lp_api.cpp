@@ -238,7 +238,8 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 2 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
-        o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0)) {
+        o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0) || o.omega_steps < 0 ||
+        o.omega_steps > 8) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
     }
@@ -330,6 +331,7 @@ BatchJob make_job(lp_handle* h, const lp_options* bo) {
     J.eps_infeas = o.eps_infeas;
     J.P.method = o.method;
     J.P.rho = o.reflection;
+    J.P.omega_steps = o.omega_steps > 0 ? o.omega_steps : (o.method == LP_METHOD_HALPERN ? 2 : 1);
     J.max_iters = o.max_iters;
     J.trace_cap = h->opt.trace_cap;
     J.eval_every = o.eval_every;
@@ -1426,6 +1428,7 @@ void lp_default_options(lp_options* o) {
     o->eps_infeas = 1e-8;
     o->method = LP_METHOD_AVERAGED;
     o->reflection = 1.0;
+    o->omega_steps = 0;
 }
 
 const char* lp_error_string(int32_t code) {
@@ -1524,6 +1527,8 @@ int32_t lp_solve(lp_handle* h) {
         if (int32_t rc = materialize(h)) return rc;
         h->P.method = h->opt.method;
         h->P.rho = h->opt.reflection;
+        h->P.omega_steps = h->opt.omega_steps > 0 ? h->opt.omega_steps
+                                                  : (h->opt.method == LP_METHOD_HALPERN ? 2 : 1);
         hipStream_t s = h->stream;
         const DevLP& P = h->P;
         const auto t0 = std::chrono::steady_clock::now();
@@ -1631,10 +1636,13 @@ int32_t lp_update_options(lp_handle* h, const lp_options* opt) {
     o.eps_infeas = opt->eps_infeas;
     o.method = opt->method;
     o.reflection = opt->reflection;
+    o.omega_steps = opt->omega_steps;
     std::string msg;
     if (int32_t rc = validate_options(o, &msg)) return fail(h, rc, msg);
-    // the captured iteration bundle bakes in the period, the form and its reflection
-    if (o.eval_every != h->opt.eval_every || o.method != h->opt.method || o.reflection != h->opt.reflection) {
+    // the captured iteration bundle bakes in the period, the form, its reflection and the
+    // primal-weight steps (the kernels take the solver state by value)
+    if (o.eval_every != h->opt.eval_every || o.method != h->opt.method || o.reflection != h->opt.reflection ||
+        o.omega_steps != h->opt.omega_steps) {
         if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
         if (h->graph) (void)hipGraphDestroy(h->graph);
         h->gexec = nullptr;

@@ -102,6 +102,7 @@ struct DevLP {
     // the PDHG output T(z), the only candidate of the evaluations.
     int method;
     double rho;
+    int omega_steps;                  // square-root steps of the primal-weight update (>= 1)
     double *partials;                 // nred * kNT
     Scalars* sc;
     double* trace;

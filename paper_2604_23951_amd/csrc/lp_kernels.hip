@@ -1239,7 +1239,8 @@ __device__ inline void set_output(Scalars* sc, const Kkt& K, int avg) {
 //  termination when E_rel(current) <= eps (then the average), or at max_iters the better one;
 //  restart candidate = average if its KKT_w is strictly smaller; restart on
 //  (1) KKT_c <= 0.2 KKT_anchor, (2) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev,
-//  (3) t >= 0.36 k; on restart omega <- sqrt(omega dy / dx) when dx, dy > 1e-10.
+//  (3) t >= 0.36 k; on restart omega <- sqrt(omega dy / dx), omega_steps times, when
+//  dx, dy > 1e-10.
 // Thread-0 part of the evaluation: tot holds the summed KKT quantities of the current
 // iterate (0..7) and, in mode 0, of the average (8..15).
 __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int mode) {
@@ -1338,7 +1339,8 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         if (why) {
             const Kkt& cd = use_avg ? avg : cur;
             const double dx = sqrt(cd.dx2), dy = sqrt(cd.dy2);
-            if (dx > 1e-10 && dy > 1e-10) om = sqrt((om * dy) / dx);
+            if (dx > 1e-10 && dy > 1e-10)
+                for (int q = 0; q < P.omega_steps; ++q) om = sqrt((om * dy) / dx);
             sc->omega = om;
             sc->tau = sc->eta / om;
             sc->sigma = sc->eta * om;

@@ -61,7 +61,7 @@ def _create_code(**a):
     ("lo_gt_hi_row", 3), ("lo_gt_hi_col", 3), ("lo_plus_inf", 3), ("hi_minus_inf", 3),
     ("unsorted_row", 2), ("duplicate_col", 2), ("col_out_of_range", 2), ("row_ptr_decreasing", 2),
     ("row_ptr_bad_end", 2), ("negative_m", 1), ("zero_n", 1), ("null_cost", 1), ("bad_eval_every", 1),
-    ("nan_c0", 4), ("bad_layout", 1),
+    ("nan_c0", 4), ("bad_layout", 1), ("omega_steps_negative", 1), ("omega_steps_nine", 1),
 ])
 def test_invalid_input_codes(case, code):
     lp = synth.cfg0(0)
@@ -109,6 +109,10 @@ def test_invalid_input_codes(case, code):
         a["c0"] = math.nan
     elif case == "bad_layout":
         a["opt"] = lpg.make_options(spmv_layout=3)
+    elif case == "omega_steps_negative":
+        a["opt"] = lpg.make_options(omega_steps=-1)
+    elif case == "omega_steps_nine":
+        a["opt"] = lpg.make_options(omega_steps=9)
     assert _create_code(**a) == code
     assert lpg.lp_last_error()  # a message is recorded
 

@@ -269,3 +269,22 @@ def test_layout_variants_match_oracle(oracle_lib, variant, name):
             s.solve()
             for a, b in zip(s.iterates(), oracle.split_snap(ref.snaps[i], lp.n, lp.m)):
                 assert _close(a, b) <= ITER_TOL, (variant, name, k)
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("name", ["cfg0", "large_recipe_small", "transport"])
+def test_primal_weight_steps(oracle_lib, name, method, steps):
+    """Primal-weight smoothings other than each form's default (one square-root step: theta
+    = 1/2; three: theta = 7/8): the device follows the oracle's trajectory (same iteration
+    and restart counts, same objective and final primal weight to 1e-6; the reductions
+    behind the restart distances differ in order, so late iterates agree to rounding drift,
+    not bit for bit) in both iteration forms."""
+    lp = _case(name)
+    ref = oracle.solve(lp, eps_rel=1e-4, max_iters=200000, method=method, omega_steps=steps)
+    with lpg.Solver(lp, eps_rel=1e-4, max_iters=200000, method=method, omega_steps=steps) as s:
+        sol = s.solve()
+    assert sol.status == ref.status
+    assert sol.info.iterations == ref.iters and sol.info.restarts == ref.restarts
+    assert abs(sol.info.primal_obj - ref.pobj) <= 1e-6 * max(1.0, abs(ref.pobj))
+    assert abs(sol.info.omega - ref.omega) <= 1e-6 * ref.omega
