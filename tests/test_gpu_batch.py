@@ -141,3 +141,27 @@ def test_block_diagonal_alone_equals_in_mix_and_split(oracle_lib):
         assert alone.info.iterations == in_mix[j].info.iterations, lp.name
         assert np.array_equal(alone.x, in_mix[j].x) and np.array_equal(alone.y, in_mix[j].y), lp.name
         assert oracle.kkt(lp, alone.x, alone.y)["erel"] <= 1e-5
+
+
+def test_full_4096_batch_sample_equals_solo():
+    """The whole 4096-LP batch of the batched workload in one lp_solve_batch (FP32 storage,
+    Halpern form, persistent and block-diagonal paths side by side): every LP reaches 1e-4,
+    and 16 LPs drawn across the batch (both paths) give bit-identical results solved alone."""
+    lps = [synth.cfg3_lp(j) for j in range(4096)]
+    kw = dict(spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED, method=lpg.LP_METHOD_HALPERN)
+    solvers = [lpg.Solver(lp, **kw) for lp in lps]
+    try:
+        sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=400000, method=lpg.LP_METHOD_HALPERN)
+    finally:
+        for s in solvers:
+            s.close()
+    assert all(s.status == "optimal" for s in sols)
+    rng = np.random.default_rng(4096)
+    pick = sorted(rng.choice(4096, 16, replace=False).tolist())
+    nnz = np.array([lps[j].nnz for j in pick])
+    assert (nnz > 20000).any() and (nnz <= 20000).any()  # both paths represented
+    for j in pick:
+        with lpg.Solver(lps[j], **kw) as s:
+            (alone,) = lpg.solve_batch([s], eps_rel=1e-4, max_iters=400000, method=lpg.LP_METHOD_HALPERN)
+        assert alone.info.iterations == sols[j].info.iterations, j
+        assert np.array_equal(alone.x, sols[j].x) and np.array_equal(alone.y, sols[j].y), j
