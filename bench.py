@@ -306,7 +306,9 @@ def run_presolve(args) -> int:
     lp = synth.presolve_lp(0, m=m, n=2 * m, density=args.presolve_density)
     print(f"[bench] presolve workload m={lp.m} n={lp.n} nnz={lp.nnz} generated in {time.time() - t0:.1f}s",
           file=sys.stderr, flush=True)
-    opts = dict(eps_rel=1e-4, max_iters=args.batch_max_iters, method=method_of(args, "halpern"))
+    # both legs with the layout tuner (row tiles beat panels at this size)
+    opts = dict(eps_rel=1e-4, max_iters=args.batch_max_iters, method=method_of(args, "halpern"),
+                spmv_layout=lpg.LP_LAYOUT_TUNED)
     lpg.solve_presolved(synth.presolve_lp(1, m=200, n=400, density=0.02), **opts)  # warm-up
     t1 = time.perf_counter()
     with lpg.Solver(lp, **opts) as s:
@@ -327,7 +329,7 @@ def run_presolve(args) -> int:
         "config": {"workload": f"presolve + solve to E_rel 1e-4 vs solve alone: KKT-constructed LP m={lp.m} "
                                f"n={lp.n} nnz={lp.nnz} with planted reducible structure (10% of rows / columns "
                                f"per type)", "m": lp.m, "n": lp.n, "nnz": lp.nnz,
-                   "method": {v: k for k, v in METHODS.items()}[opts["method"]]},
+                   "method": {v: k for k, v in METHODS.items()}[opts["method"]], "layout": "tuned"},
         "presolve": r.presolve, "times": r.times,
         "reduced": {"status": r.reduced.status, "iterations": int(r.reduced.info.iterations),
                     "rel_kkt": r.reduced.info.rel_kkt},
