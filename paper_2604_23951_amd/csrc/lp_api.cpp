@@ -1132,13 +1132,23 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
         }
     }
     std::vector<Ticket> finished = failed;
-    if (!S->running.empty()) {
-        if (dirty) {
-            std::vector<lp_handle*> hs;
-            for (Ticket& t : S->running) hs.push_back(t.h);
-            if (run_maps.build(hs, &S->opt, s, &S->err_sink) != LP_OK) return;
+    if (!S->running.empty() && dirty) {
+        std::vector<lp_handle*> hs;
+        for (Ticket& t : S->running) hs.push_back(t.h);
+        if (run_maps.build(hs, &S->opt, s, &S->err_sink) == LP_OK) {
             dirty = false;
+        } else {  // no launch maps for this set: its requests end as failed, not forgotten
+            std::unique_lock<std::mutex> lk(S->mu);
+            for (Ticket& t : S->running) {
+                t.h->err = S->err_sink.err;
+                finished.push_back(t);
+                failed.push_back(t);
+            }
+            S->running.clear();
+            S->st.running = 0;
         }
+    }
+    if (!S->running.empty()) {
         const MultiMaps& M = run_maps.M;
         run_round(run_maps, s, 1);
         (void)hipMemcpyAsync(run_maps.hstatus, M.active, sizeof(int) * M.count, hipMemcpyDeviceToHost, s);
