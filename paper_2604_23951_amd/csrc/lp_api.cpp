@@ -351,6 +351,24 @@ int32_t finish_batch(const std::vector<lp_handle*>& hs, hipStream_t s) {
     return LP_OK;
 }
 
+// Workgroups of a launch go to the 8 XCDs of the device round-robin by index. The tiles of
+// one form (LP after LP) are cut into kXcds contiguous runs of equal length and run k is
+// placed at entries k, k + kXcds, k + 2 kXcds, ...: each run executes on one XCD, so an LP's
+// gathered vector is cached in the L2 of one or two XCDs rather than all of them. Runs are
+// padded with entries of the stand-in job `pad_job`. Short lists keep their order.
+constexpr int kXcds = 8;
+
+void append_xcd_order(const std::vector<int2>& tiles, int pad_job, std::vector<int2>& out) {
+    const size_t len = tiles.size();
+    if (len < static_cast<size_t>(4 * kXcds)) {
+        out.insert(out.end(), tiles.begin(), tiles.end());
+        return;
+    }
+    const size_t per = (len + kXcds - 1) / kXcds, base = out.size();
+    out.resize(base + per * kXcds, make_int2(pad_job, 0));
+    for (size_t t = 0; t < len; ++t) out[base + (t % per) * kXcds + t / per] = tiles[t];
+}
+
 // Device jobs table and block maps of a set of LPs (grown as needed, reused across rounds;
 // every round ends with a stream synchronisation before the next rebuild).
 struct DevMaps {
@@ -360,6 +378,7 @@ struct DevMaps {
     int hcap = 0;
     MultiMaps M{};
     int E = 64;
+    Scalars stopped{};  // host copy of the stand-in job's scalar block (kept for the async copy)
     // The round's launches as a graph, captured once the same set has run one round
     // uncaptured (a set that changes every round is not worth an instantiation).
     hipGraph_t graph = nullptr;
@@ -379,19 +398,24 @@ struct DevMaps {
     int32_t build(const std::vector<lp_handle*>& hs, const lp_options* o, hipStream_t s, lp_handle* err_to) {
         drop_graph();
         const int count = static_cast<int>(hs.size());
-        std::vector<BatchJob> jobs(static_cast<size_t>(count));
+        // jobs[count] is a stand-in whose scalar block says "stopped": map entries that pad
+        // the XCD runs below point at it and their workgroups return at once
+        std::vector<BatchJob> jobs(static_cast<size_t>(count) + 1);
         std::vector<int2> ma, mat, mred, melem;
         int off_a[4], cnt_a[4], off_at[4], cnt_at[4];
         for (int i = 0; i < count; ++i) jobs[i] = make_job(hs[i], o);
-        for (int v = 0; v < 4; ++v) {  // tile maps grouped by form
-            off_a[v] = static_cast<int>(ma.size());
-            off_at[v] = static_cast<int>(mat.size());
+        for (int v = 0; v < 4; ++v) {  // tile maps grouped by form, each in XCD order
+            std::vector<int2> ta, tat;
             for (int i = 0; i < count; ++i) {
                 const lp_handle* h = hs[i];
                 if ((jobs[i].P.fp32 ? 2 : 0) + (jobs[i].P.method ? 1 : 0) != v) continue;
-                for (int t = 0; t < h->P.A.csr.ntiles; ++t) ma.push_back(make_int2(i, t));
-                for (int t = 0; t < h->P.AT.csr.ntiles; ++t) mat.push_back(make_int2(i, t));
+                for (int t = 0; t < h->P.A.csr.ntiles; ++t) ta.push_back(make_int2(i, t));
+                for (int t = 0; t < h->P.AT.csr.ntiles; ++t) tat.push_back(make_int2(i, t));
             }
+            off_a[v] = static_cast<int>(ma.size());
+            off_at[v] = static_cast<int>(mat.size());
+            append_xcd_order(ta, count, ma);
+            append_xcd_order(tat, count, mat);
             cnt_a[v] = static_cast<int>(ma.size()) - off_a[v];
             cnt_at[v] = static_cast<int>(mat.size()) - off_at[v];
         }
@@ -402,12 +426,13 @@ struct DevMaps {
             for (int b = 0; b < (mx + kBlock - 1) / kBlock; ++b) melem.push_back(make_int2(i, b));
         }
         E = count > 0 ? jobs[0].eval_every : 64;
-        for (const BatchJob& J : jobs)
-            if (J.eval_every != E) return fail(err_to, LP_ERR_INVALID_ARG, "block-diagonal LPs must share eval_every");
+        for (int i = 0; i < count; ++i)
+            if (jobs[i].eval_every != E) return fail(err_to, LP_ERR_INVALID_ARG, "block-diagonal LPs must share eval_every");
         Arena L;
         const size_t oj = L.add(sizeof(BatchJob) * jobs.size()), oa = L.add(sizeof(int2) * ma.size()),
                      oat = L.add(sizeof(int2) * mat.size()), ored = L.add(sizeof(int2) * mred.size()),
-                     oel = L.add(sizeof(int2) * melem.size()), ost = L.add(sizeof(int) * (count + 1));
+                     oel = L.add(sizeof(int2) * melem.size()), ost = L.add(sizeof(int) * (count + 1)),
+                     osc = L.add(sizeof(Scalars));
         if (L.off > cap) {
             if (buf) (void)hipFree(buf);
             buf = nullptr;
@@ -445,6 +470,13 @@ struct DevMaps {
         auto H2D = [&](size_t off, const void* src, size_t bytes) {
             return bytes ? hipMemcpyAsync(buf + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
         };
+        if (count > 0) {  // the stand-in: any LP's arrays, a stopped scalar block of its own
+            jobs[count] = jobs[0];
+            jobs[count].P.sc = reinterpret_cast<Scalars*>(buf + osc);
+            stopped = Scalars{};
+            stopped.status = 0;
+            HIP_TRY(err_to, H2D(osc, &stopped, sizeof(Scalars)));
+        }
         HIP_TRY(err_to, H2D(oj, jobs.data(), sizeof(BatchJob) * jobs.size()));
         HIP_TRY(err_to, H2D(oa, ma.data(), sizeof(int2) * ma.size()));
         HIP_TRY(err_to, H2D(oat, mat.data(), sizeof(int2) * mat.size()));
