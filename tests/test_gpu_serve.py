@@ -32,9 +32,9 @@ def _solo(lp, **kw):
         return s.solve()
 
 
-def _serve(lps, budget, slots, stagger=0.0, **kw):
+def _serve(lps, budget, slots, stagger=0.0, srv_kw=None, **kw):
     solvers = [lpg.Solver(lp, spmv_layout=1, deferred=1, **kw) for lp in lps]
-    with lpg.Server(budget, slots, **OPTS) as srv:
+    with lpg.Server(budget, slots, **OPTS, **(srv_kw or {})) as srv:
         tickets = []
         for s in solvers:
             tickets.append(srv.submit(s))
@@ -54,11 +54,12 @@ def _serve(lps, budget, slots, stagger=0.0, **kw):
     return solvers, sols, times, st
 
 
-def test_served_results_equal_solo():
+@pytest.mark.parametrize("method", [lpg.LP_METHOD_AVERAGED, lpg.LP_METHOD_HALPERN])
+def test_served_results_equal_solo(method):
     lps = _pool()
-    solvers, sols, times, st = _serve(lps, budget=1 << 34, slots=64, stagger=0.002)
+    solvers, sols, times, st = _serve(lps, budget=1 << 34, slots=64, stagger=0.002, srv_kw=dict(method=method))
     for lp, sol in zip(lps, sols):
-        ref = _solo(lp)
+        ref = _solo(lp, method=method)
         assert sol.status == ref.status and sol.info.iterations == ref.info.iterations, lp.name
         assert np.array_equal(sol.x, ref.x) and np.array_equal(sol.y, ref.y) and np.array_equal(sol.z, ref.z)
     assert st["completed"] == len(lps) and st["bytes_in_use"] == 0
