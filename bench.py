@@ -145,7 +145,8 @@ def run_batch(args) -> int:
     print(f"[bench] per-LP FP64 loop: {len(sub)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
           file=sys.stderr, flush=True)
     result = {
-        "metric": METRIC, "value": len(sols) / dt, "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        # LPs that reached E_rel 1e-4 per second of the batched solve
+        "metric": METRIC, "value": ok / dt, "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": ("batched LPs to E_rel 1e-4: the 4096-LP batch " if len(lps) == total else
@@ -157,7 +158,7 @@ def run_batch(args) -> int:
                    "iterations_median": int(np.median(iters)), "iterations_max": int(iters.max())},
         "per_lp_fp64_loop": {"lps": len(sub), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok,
                              "method": "same as the batch", "layout": "tuned per LP"},
-        "speedup_vs_per_lp_loop": (len(sols) / dt) / loop_rate,
+        "speedup_vs_per_lp_loop": (ok / dt) / loop_rate,
         "create_s": create_s,
     }
     if not args.no_cpu_baseline:
@@ -221,19 +222,28 @@ def run_serve(args) -> int:
         st = srv.stats()
         lat = []
         wait = []
+        status = []
         for t in done:
             ts, ta, td = srv.times(t)
             lat.append(td - ts)
             wait.append(ta - ts)
-            srv.result(t)
+            try:
+                status.append(srv.result(t).status)
+            except lpg.LpError:  # the request could not be set up on the device
+                status.append("failed")
         srv.close()
+        opt_in_window = sum(st_ == "optimal" for st_ in status[:in_window])
         lat = np.array(lat) if lat else np.array([np.nan])
         wait = np.array(wait) if wait else np.array([np.nan])
         # work: PDHG iterations x nnz(A) run by the server; with FP32 storage both products
         # stream 8 bytes (value + index) per nonzero, a lower bound on the traffic
         wsec = st_window["nnz_iterations"] / seconds
+        # LPs/s counts the requests that reached E_rel 1e-4 inside the window; the others that
+        # completed stopped at the iteration cap
         return {"offered_lps_per_s": rate, "seconds": seconds, "submitted": len(tickets),
-                "completed_in_window": in_window, "lps_per_s": in_window / seconds,
+                "completed_in_window": in_window, "optimal_in_window": opt_in_window,
+                "lps_per_s": opt_in_window / seconds,
+                "optimal": sum(st_ == "optimal" for st_ in status),
                 "completed": len(done), "drained": bool(drain and len(done) == len(tickets)),
                 "span_s": span,
                 "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
@@ -244,7 +254,8 @@ def run_serve(args) -> int:
                 "lp_iterations_per_s": st_window["lp_iterations"] / seconds}
 
     full = phase(args.rate, args.serve_seconds, 1, False)
-    print(f"[bench] offered {args.rate}/s: {full['lps_per_s']:.1f} LPs/s, p50 {full['latency_p50_s']:.3f}s, "
+    print(f"[bench] offered {args.rate}/s: {full['lps_per_s']:.1f} LPs/s to 1e-4 ({full['completed_in_window']} "
+          f"completed), p50 {full['latency_p50_s']:.3f}s, "
           f"p99 {full['latency_p99_s']:.3f}s, backlog {full['backlog_at_window_end']}, "
           f"{full['nnz_iterations_per_s']:.3g} nnz-it/s ({full['matrix_stream_GBps']:.0f} GB/s of A)",
           file=sys.stderr, flush=True)
