@@ -141,7 +141,7 @@ def run_batch(args) -> int:
             r = s1.solve()
             loop_t += time.perf_counter() - t3
             loop_ok += r.status == "optimal"
-    loop_rate = len(sub) / loop_t if loop_t > 0 else float("nan")
+    loop_rate = loop_ok / loop_t if loop_t > 0 else float("nan")  # LPs that reached 1e-4
     print(f"[bench] per-LP FP64 loop: {len(sub)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
           file=sys.stderr, flush=True)
     result = {
@@ -278,7 +278,7 @@ def run_serve(args) -> int:
             r = s1.solve()
             loop_t += time.perf_counter() - t3
             loop_ok += r.status == "optimal"
-    loop_rate = len(sub_lps) / loop_t if loop_t > 0 else float("nan")
+    loop_rate = loop_ok / loop_t if loop_t > 0 else float("nan")  # LPs that reached 1e-4
     print(f"[bench] per-LP FP64 loop: {len(sub_lps)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
           file=sys.stderr, flush=True)
     result = {
