@@ -266,7 +266,12 @@ void destroy_device(lp_handle* h) {
 // Keep the result on the host and give the device memory back (the handle stays usable:
 // a later solve places it on the device again).
 int32_t release_device(lp_handle* h) {
-    if (!h->on_device) return LP_OK;
+    if (!h->on_device) {  // a set-up that failed part way may still hold its allocation
+        if (h->arena) (void)hipFree(h->arena);
+        h->arena = nullptr;
+        if (!h->own_stream) h->stream = nullptr;
+        return LP_OK;
+    }
     if (h->solved) {
         h->res_x.resize(static_cast<size_t>(h->n));
         h->res_y.resize(static_cast<size_t>(h->m));
