@@ -288,3 +288,31 @@ def test_primal_weight_steps(oracle_lib, name, method, steps):
     assert sol.info.iterations == ref.iters and sol.info.restarts == ref.restarts
     assert abs(sol.info.primal_obj - ref.pobj) <= 1e-6 * max(1.0, abs(ref.pobj))
     assert abs(sol.info.omega - ref.omega) <= 1e-6 * ref.omega
+
+
+@pytest.mark.parametrize("name", ["no_rows", "one_column", "long_row_and_column"])
+@pytest.mark.parametrize("precision", [lpg.LP_PREC_FP64, lpg.LP_PREC_FP32_REFINED])
+def test_edge_cases_every_path(oracle_lib, name, precision):
+    """The degenerate LPs through the other paths: the tuned layout, the persistent batch
+    launch (one workgroup per LP) and the block-diagonal launches. Each reaches the
+    tolerance on the original data (oracle KKT check); the block-diagonal launches and the
+    row-tile solve agree bit for bit (an LP without nonzeros always takes the persistent
+    launch)."""
+    lp = _edge_lps()[name]
+    kw = dict(precision=precision, eps_rel=1e-6, max_iters=200000)
+    with lpg.Solver(lp, spmv_layout=lpg.LP_LAYOUT_TUNED, **kw) as s:
+        tuned = s.solve()
+    with lpg.Solver(lp, spmv_layout=1, **kw) as s:
+        tiles = s.solve()
+    outs = []
+    for split in (0, 1 << 40):  # all block-diagonal, all persistent
+        with lpg.Solver(lp, spmv_layout=1, precision=precision) as s:
+            (b,) = lpg.solve_batch([s], eps_rel=1e-6, max_iters=200000, batch_split_nnz=split)
+        outs.append(b)
+    for sol in (tuned, tiles, *outs):
+        assert sol.status == "optimal", (name, sol.status)
+        assert oracle.kkt(lp, sol.x, sol.y)["erel"] <= 1e-6 * (1 + 1e-9)
+    if lp.nnz > 0:
+        b = outs[0]
+        assert b.info.iterations == tiles.info.iterations
+        assert np.array_equal(b.x, tiles.x) and np.array_equal(b.y, tiles.y) and np.array_equal(b.z, tiles.z)
