@@ -23,6 +23,9 @@
  *    function. The restart constants (0.2 / 0.8 / 0.36), the evaluation period, the primal
  *    weight smoothing and the power-of-two scaling are heuristics the paper does not fix:
  *    parity unpinned for them beyond the invariants the tests check.
+ *  - Method 1 is the reflected Halpern form of the same family (see ora_solve); the
+ *    infeasibility certificates follow the remark after eq. (2) that an LP with no solution
+ *    of eq. (2) is infeasible or unbounded (see eval_rays).
  */
 #include <math.h>
 #include <stdint.h>
