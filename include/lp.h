@@ -122,8 +122,9 @@ typedef struct lp_options {
                             * choice depends on the measurement, so two handles of one LP may
                             * differ in rounding (deferred clones share their template's choice) */
     int32_t long_row_len;  /* rows longer than this get a workgroup of their own (default 256) */
-    int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for (default 4; one
-                              workgroup holds 4 units, so multiples of 4 fill every CU evenly) */
+    int32_t units_per_cu;  /* wave units per compute unit the panel layout aims for, never exceeds
+                              (default 4; a workgroup holds 2 units, each with a producer and a
+                              consumer wave, so even values fill every CU evenly) */
     int32_t batch_wg_per_cu; /* lp_solve_batch: workgroups per compute unit (default 3) */
     int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
     int64_t batch_split_nnz;   /* lp_solve_batch: LPs with more nonzeros go to the block-diagonal

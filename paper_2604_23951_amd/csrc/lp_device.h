@@ -70,7 +70,6 @@ struct Panels {
 };
 
 constexpr int kUnitRowCap = 2048;  // rows per wave unit at most
-constexpr int kUnitsPerBlock = 4;  // wave units per workgroup
 constexpr int kChunks = 4;         // 64-entry chunks a wave loads together (one group)
 constexpr int kStreamDepth = 4;    // groups of matrix entries a wave keeps loaded or in flight
 

@@ -223,28 +223,44 @@ __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __re
     tile_body(M, static_cast<int>(blockIdx.x), xin, epi, prod, red);
 }
 
-// Panel-packed SpMV, one wave64 per unit of rows. The wave walks its entries in packed order,
-// panel by panel (all resident waves do, so the slice of the gathered vector for the current
+// Panel-packed SpMV over wave units of rows. The entries of a unit are walked in packed order,
+// panel by panel (all resident units do, so the slice of the gathered vector for the current
 // panel stays in the L2 of each XCD), in chunks of 64 consecutive entries. Inside a panel
 // segment the entries are sorted by row, so between two places where the row id drops (the
 // start of a later segment) the rows of a chunk ascend and each row forms one run. The run's
-// first lane adds the run's products, in order, to the row's accumulator in wave-private LDS;
-// a chunk with drops is handled piece by piece, in order. Later runs of a row (later chunks,
-// later panels) follow in column order, so every row sum is formed in CSR order. The loop is
-// software-pipelined (see PanelGroups). After the last chunk each lane finishes rows lane,
-// lane + 64, ... with the epilogue. Rows listed as long have no packed entries; workgroups
-// past the panel ones reduce them, one long row each (fixed-shape tree), in the same launch.
+// first lane adds the run's products, in order, to the row's accumulator in LDS; a chunk with
+// drops is handled piece by piece, in order. Later runs of a row (later chunks, later panels)
+// follow in column order, so every row sum is formed in CSR order. Rows listed as long have no
+// packed entries; workgroups past the panel ones reduce them, one long row each (fixed-shape
+// tree), in the same launch.
 //
-// Pipeline: the entries of kStreamDepth groups of kChunks chunks are loaded or in flight and
-// the gathers of two groups are in flight: while group g is summed, the gathers of groups
-// g + 1 and g + 2 and the entry loads of groups g + 3 and g + 4 are outstanding. Slots are
-// indexed at compile time (the loop is unrolled by 12 = lcm(4, 3) steps) so that every group
-// stays in registers.
+// Each unit has two waves: a producer that streams the entries, gathers the vector and writes
+// each group's products and row ids to an LDS buffer, and a consumer that forms the run sums
+// of the previous group from the other buffer. A workgroup holds kPanelUnits units; its waves
+// meet at a barrier after every group step, so the two halves of the work overlap instead of
+// taking turns in one wave. After the last group both waves of a unit finish its rows with
+// the epilogue.
+//
+// Producer pipeline: the entries of kStreamDepth groups of kChunks chunks are loaded or in
+// flight and the gathers of two groups are in flight: while group g is multiplied, the gathers
+// of groups g + 1 and g + 2 and the entry loads of groups g + 3 and g + 4 are outstanding.
+// Slots are indexed at compile time (the loop is unrolled by 12 = lcm(4, 3) steps) so that
+// every group stays in registers.
+constexpr int kPanelUnits = 2;  // wave units per workgroup (a producer and a consumer wave each)
+static_assert(2 * kPanelUnits * 64 == kBlock, "a panel workgroup is one producer and one consumer wave per unit");
+
 template <class T>
 struct PanelGroups {
     unsigned pk[kStreamDepth][kChunks];
     T val[kStreamDepth][kChunks];
     T xv[3][kChunks];
+};
+
+// One group's products and row ids, handed from the producer to the consumer of a unit.
+template <class T>
+struct PanelBuf {
+    T prod[2][kChunks * 64];
+    int row[2][kChunks * 64];
 };
 
 struct PanelUnit {
@@ -297,12 +313,12 @@ __device__ inline void add_run(T* acc, const T* prodc, int row, T own, int lane,
     acc[row] = a;
 }
 
-// Step K of the unrolled loop on group g (K = g mod 12): issue the gathers of group g + 2 and
-// the entry loads of group g + 4, then sum group g. Steps past the end of the unit see empty
-// chunks and do only masked work.
+// Producer step K of the unrolled loop on group g (K = g mod 12): issue the gathers of group
+// g + 2 and the entry loads of group g + 4, then write the products and row ids of group g.
+// Steps past the end of the unit see empty chunks and do only masked work.
 template <class T, int K>
-__device__ inline void panel_step(PanelGroups<T>& G, int g, const PanelUnit& U, const unsigned* __restrict__ pkp,
-                                  const T* __restrict__ pvp, const T* __restrict__ xin, T* acc, T* prod) {
+__device__ inline void panel_produce(PanelGroups<T>& G, int g, const PanelUnit& U, const unsigned* __restrict__ pkp,
+                                     const T* __restrict__ pvp, const T* __restrict__ xin, T* prod, int* rowb) {
     constexpr int S = K % kStreamDepth, X = K % 3;
     constexpr int S2 = (K + 2) % kStreamDepth, X2 = (K + 2) % 3;
     panel_gather(G, S2, X2, g + 2, U, xin);
@@ -314,31 +330,36 @@ __device__ inline void panel_step(PanelGroups<T>& G, int g, const PanelUnit& U, 
         v[c] = G.val[S][c];
     }
     panel_load(G, S, g + kStreamDepth, U, pkp, pvp);
-    T p[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-        p[c] = v[c] * G.xv[X][c];
-        prod[c * 64 + U.lane] = p[c];
+        prod[c * 64 + U.lane] = v[c] * G.xv[X][c];
+        rowb[c * 64 + U.lane] = row[c];
     }
-    __builtin_amdgcn_wave_barrier();
+}
+
+// Consumer: the run sums of group g, chunk by chunk, from the producer's buffer.
+template <class T>
+__device__ inline void panel_consume(int g, const PanelUnit& U, const T* prod, const int* rowb, T* acc) {
     const int lane = U.lane;
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
         const int nvalid = min(64, U.e - U.chunk_start(g, c));
         if (nvalid <= 0) break;
-        const int prev = prev_lane_row(row[c]);
+        const int row = rowb[c * 64 + lane];
+        const T own = prod[c * 64 + lane];
+        const int prev = prev_lane_row(row);
         const bool valid = lane < nvalid;
-        const bool head = valid && prev != row[c];
+        const bool head = valid && prev != row;
         const unsigned long long heads = __ballot(head);
-        const unsigned long long drops = __ballot(valid && prev > row[c]);
+        const unsigned long long drops = __ballot(valid && prev > row);
         if (drops == 0) {
-            if (head) add_run(acc, prod + c * 64, row[c], p[c], lane, heads, nvalid);
+            if (head) add_run(acc, prod + c * 64, row, own, lane, heads, nvalid);
         } else {
             const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
             const int piece = __popcll(drops & upto);
             const int npieces = __popcll(drops) + 1;
             for (int j = 0; j < npieces; ++j) {
-                if (head && piece == j) add_run(acc, prod + c * 64, row[c], p[c], lane, heads, nvalid);
+                if (head && piece == j) add_run(acc, prod + c * 64, row, own, lane, heads, nvalid);
                 __builtin_amdgcn_wave_barrier();
             }
         }
@@ -349,8 +370,8 @@ __device__ inline void panel_step(PanelGroups<T>& G, int g, const PanelUnit& U, 
 template <class T, class Epi>
 __global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, Csr L, int panel_blocks,
                                                             const T* __restrict__ xin, Epi epi) {
-    extern __shared__ __align__(16) unsigned char panel_acc_lds[];  // kUnitsPerBlock x M.max_rows of T
-    __shared__ T prod_s[kUnitsPerBlock][kChunks * 64];
+    extern __shared__ __align__(16) unsigned char panel_acc_lds[];  // kPanelUnits x M.max_rows of T
+    __shared__ PanelBuf<T> bufs[kPanelUnits];
     __shared__ double red[kBlock / 64];
     if (!epi.begin()) return;
     if (static_cast<int>(blockIdx.x) >= panel_blocks) {
@@ -362,47 +383,71 @@ __global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, Csr L, int
     // scalar registers and its branches scalar.
     const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int u = blockIdx.x * kUnitsPerBlock + w;
-    if (u >= M.units) return;  // the whole wave leaves; no workgroup barrier follows
-    const int r0 = M.unit_row[u], nr = M.unit_row[u + 1] - r0;
-    T* acc = reinterpret_cast<T*>(panel_acc_lds) + w * M.max_rows;
-    T* prod = prod_s[w];
-    for (int r = lane; r < nr; r += 64) acc[r] = 0;
+    const int slot = w % kPanelUnits;
+    const bool producer = w < kPanelUnits;
+    const int u = blockIdx.x * kPanelUnits + slot;
+    const bool active = u < M.units;
+    // Group steps of the workgroup: those of its longest unit (the same value on every wave).
+    int groups = 0;
+#pragma unroll
+    for (int k = 0; k < kPanelUnits; ++k) {
+        const int uk = blockIdx.x * kPanelUnits + k;
+        if (uk < M.units) {
+            const int len = M.unit_seg[uk * (M.panels + 1) + M.panels] - M.unit_seg[uk * (M.panels + 1)];
+            groups = max(groups, (len + kChunks * 64 - 1) / (kChunks * 64));
+        }
+    }
+    const int r0 = active ? M.unit_row[u] : 0, nr = active ? M.unit_row[u + 1] - r0 : 0;
+    T* acc = reinterpret_cast<T*>(panel_acc_lds) + slot * M.max_rows;
     PanelUnit U;
-    U.s = M.unit_seg[u * (M.panels + 1)];
-    U.e = M.unit_seg[u * (M.panels + 1) + M.panels];
+    U.s = active ? M.unit_seg[u * (M.panels + 1)] : 0;
+    U.e = active ? M.unit_seg[u * (M.panels + 1) + M.panels] : 0;
     U.last = M.nnz > 0 ? M.nnz - 1 : 0;
     U.lane = lane;
     U.cb = M.col_bits;
     U.cmask = (1u << M.col_bits) - 1u;
     const unsigned* __restrict__ pkp = M.pk;
     const T* __restrict__ pvp = vals_of<T>(M);
-    const int ngroups = (U.e - U.s + kChunks * 64 - 1) / (kChunks * 64);
-    PanelGroups<T> G;
-#pragma unroll
-    for (int S = 0; S < kStreamDepth; ++S) panel_load(G, S, S, U, pkp, pvp);
-    panel_gather(G, 0, 0, 0, U, xin);
-    panel_gather(G, 1, 1, 1, U, xin);
-    __builtin_amdgcn_wave_barrier();
+    // Both roles run the same group steps with one barrier after each (the loops below have the
+    // same shape): at step t the producers write group t and the consumers sum group t - 1.
+    // The producer's steps are unconditional (steps past the end of its unit are masked), which
+    // keeps its loads in flight across steps.
     static_assert(kStreamDepth == 4, "the loop below is unrolled for four entry slots and three gather slots");
-    for (int g = 0; g < ngroups; g += 12) {
-        panel_step<T, 0>(G, g, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 1>(G, g + 1, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 2>(G, g + 2, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 3>(G, g + 3, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 4>(G, g + 4, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 5>(G, g + 5, U, pkp, pvp, xin, acc, prod);
-        if (g + 6 >= ngroups) break;
-        panel_step<T, 6>(G, g + 6, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 7>(G, g + 7, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 8>(G, g + 8, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 9>(G, g + 9, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 10>(G, g + 10, U, pkp, pvp, xin, acc, prod);
-        panel_step<T, 11>(G, g + 11, U, pkp, pvp, xin, acc, prod);
+    PanelBuf<T>& B = bufs[slot];
+    if (active && producer) {
+        PanelGroups<T> G;
+#pragma unroll
+        for (int S = 0; S < kStreamDepth; ++S) panel_load(G, S, S, U, pkp, pvp);
+        panel_gather(G, 0, 0, 0, U, xin);
+        panel_gather(G, 1, 1, 1, U, xin);
+#define LP_PRODUCE(K)                                                                                \
+    panel_produce<T, K>(G, t + K, U, pkp, pvp, xin, B.prod[(t + K) & 1], B.row[(t + K) & 1]); \
+    __syncthreads();
+        for (int t = 0; t <= groups; t += 12) {
+            LP_PRODUCE(0) LP_PRODUCE(1) LP_PRODUCE(2) LP_PRODUCE(3) LP_PRODUCE(4) LP_PRODUCE(5)
+            if (t + 6 > groups) break;
+            LP_PRODUCE(6) LP_PRODUCE(7) LP_PRODUCE(8) LP_PRODUCE(9) LP_PRODUCE(10) LP_PRODUCE(11)
+        }
+#undef LP_PRODUCE
+    } else {
+        if (active)
+            for (int r = lane; r < nr; r += 64) acc[r] = 0;
+#define LP_CONSUME(K)                                                                    \
+    if (active && t + K >= 1 && t + K <= groups)                                        \
+        panel_consume<T>(t + K - 1, U, B.prod[(t + K - 1) & 1], B.row[(t + K - 1) & 1], acc); \
+    __syncthreads();
+        for (int t = 0; t <= groups; t += 12) {
+            LP_CONSUME(0) LP_CONSUME(1) LP_CONSUME(2) LP_CONSUME(3) LP_CONSUME(4) LP_CONSUME(5)
+            if (t + 6 > groups) break;
+            LP_CONSUME(6) LP_CONSUME(7) LP_CONSUME(8) LP_CONSUME(9) LP_CONSUME(10) LP_CONSUME(11)
+        }
+#undef LP_CONSUME
     }
-    __builtin_amdgcn_wave_barrier();
+    // The last consumer step was followed by a barrier: every accumulator is complete.
+    if (!active) return;
     constexpr int kEpiRows = 8;  // rows per lane whose epilogue operands are loaded together
-    for (int r = lane; r < nr; r += kEpiRows * 64) {
+    const int half = producer ? 0 : 1;
+    for (int r = lane + half * kEpiRows * 64; r < nr; r += 2 * kEpiRows * 64) {
         typename Epi::Pre pre[kEpiRows];
         int rows[kEpiRows];
 #pragma unroll
@@ -811,14 +856,14 @@ void launch_spmv(const Mat& M, const T* xin, const Epi& epi, hipStream_t s) {
     Csr L = M.csr;
     L.rowlist = M.longrows;
     L.ntiles = M.nlong;
-    const int pb = (M.pan.units + kUnitsPerBlock - 1) / kUnitsPerBlock;
+    const int pb = (M.pan.units + kPanelUnits - 1) / kPanelUnits;
     const int g = pb + M.nlong;
-    const size_t lds = static_cast<size_t>(kUnitsPerBlock) * (M.pan.max_rows > 0 ? M.pan.max_rows : 1) * sizeof(T);
+    const size_t lds = static_cast<size_t>(kPanelUnits) * (M.pan.max_rows > 0 ? M.pan.max_rows : 1) * sizeof(T);
     // Allow the largest accumulator block once per kernel instance (thread-safe static init).
     static const bool lds_attr = [] {
         return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_panel_kernel<T, Epi>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   static_cast<int>(kUnitsPerBlock * kUnitRowCap * sizeof(T))) == hipSuccess;
+                                   static_cast<int>(kPanelUnits * kUnitRowCap * sizeof(T))) == hipSuccess;
     }();
     (void)lds_attr;
     if (g > 0)

@@ -45,11 +45,14 @@ PanelLayoutHost build_panel_layout(int rows, int cols, const int32_t* rp, const 
         for (int r : L.long_rows) L.is_long[r] = 1;
     }
 
-    // units: contiguous rows, balanced by short nonzeros, at most `cap` rows each
+    // units: contiguous rows, balanced by short nonzeros, at most `cap` rows each. The greedy
+    // split can leave a few more units than the target (rows do not divide evenly); the share
+    // per unit is raised in small steps until it does not, so that the units fit the resident
+    // wave slots the target was sized for (one launch round).
     if (target_units < 1) target_units = 1;
-    const int64_t per_unit = std::max<int64_t>(64, (nnz_short + target_units - 1) / target_units);
-    L.unit_row.push_back(0);
-    {
+    int64_t per_unit = std::max<int64_t>(64, (nnz_short + target_units - 1) / target_units);
+    for (int attempt = 0;; ++attempt) {
+        L.unit_row.assign(1, 0);
         int r = 0;
         while (r < rows) {
             const int start = r;
@@ -62,6 +65,8 @@ PanelLayoutHost build_panel_layout(int rows, int cols, const int32_t* rp, const 
             }
             L.unit_row.push_back(r);
         }
+        if (static_cast<int64_t>(L.unit_row.size()) - 1 <= target_units || attempt == 32) break;
+        per_unit += std::max<int64_t>(1, per_unit / 128);
     }
     L.units = static_cast<int>(L.unit_row.size()) - 1;
     for (int u = 0; u < L.units; ++u) L.max_unit_rows = std::max(L.max_unit_rows, L.unit_row[u + 1] - L.unit_row[u]);
