@@ -1,9 +1,10 @@
 // Host-side construction of the panel-packed SpMV layout (integer work done once per LP).
 //
 // A CSR matrix with R rows and N columns is cut into P column panels of equal width and
-// into "units" of contiguous rows, one wave64 per unit. The nonzeros of a unit are stored
-// panel by panel (inside a panel: by row, then column), so a wave sweeps the panels in
-// order and, while all resident waves do the same, the slice of the gathered vector that
+// into "units" of contiguous rows, each swept by one wave64 (with a second wave that sums
+// its products). The nonzeros of a unit are stored panel by panel (inside a panel: by row,
+// then column), so a wave sweeps the panels in order and, while all resident waves do the
+// same, the slice of the gathered vector that
 // belongs to the current panel stays in the L2 of each XCD. Each entry keeps its column in
 // the low `col_bits` of a 32-bit word and its row inside the unit in the high bits; the
 // unit's row count is capped so that both fit. Because columns inside a row ascend, the
