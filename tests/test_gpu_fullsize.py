@@ -25,6 +25,11 @@ def test_full_size_structure_and_iterates(oracle_lib, big):
     with lpg.Solver(lp, eps_rel=0.0, max_iters=1, pow_iters=20) as s:
         lay = s.layout()
         assert lay["long_rows_at"] >= 1  # power-law columns longer than one LDS tile
+        # the panel units never exceed their target (4 per CU), so every workgroup of two
+        # units is resident in one round
+        import torch
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        assert 0.9 * 4 * cus <= lay["units_a"] <= 4 * cus and 0.9 * 4 * cus <= lay["units_at"] <= 4 * cus
         gv, gR, gC, grp, gci, gvt = s.scaled()
         av, R, Cc, rpT, ciT, avT = oracle.scaled_problem(lp)
         assert np.array_equal(grp, rpT) and np.array_equal(gci, ciT)

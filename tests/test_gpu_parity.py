@@ -247,6 +247,11 @@ LAYOUT_VARIANTS = {
     "row_tiles": dict(spmv_layout=1),
     "tiny_panels_many_long_rows": dict(panel_slice_bytes=512, long_row_len=8, units_per_cu=1),
     "one_unit_per_cu": dict(units_per_cu=1, panel_slice_bytes=4096),
+    # another target (unit counts are often odd: the last workgroup then holds one unit and
+    # an idle slot)
+    "odd_units_per_cu": dict(units_per_cu=3, panel_slice_bytes=4096),
+    # many small units: at most a group or two of entries each
+    "many_small_units": dict(units_per_cu=32),
 }
 
 
@@ -264,6 +269,11 @@ def test_layout_variants_match_oracle(oracle_lib, variant, name):
             assert lay["panels_a"] > 8
             if name == "large_recipe_small":
                 assert lay["long_rows_at"] > 0
+        upc = LAYOUT_VARIANTS[variant].get("units_per_cu", 4)
+        if LAYOUT_VARIANTS[variant].get("spmv_layout", 0) == 0:
+            import torch
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            assert 0 < lay["units_a"] <= upc * cus and 0 < lay["units_at"] <= upc * cus
         for i, k in enumerate(ks):
             s.update(eps_rel=0.0, max_iters=k)
             s.solve()
