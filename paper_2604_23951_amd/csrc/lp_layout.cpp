@@ -46,12 +46,13 @@ PanelLayoutHost build_panel_layout(int rows, int cols, const int32_t* rp, const 
     }
 
     // units: contiguous rows, balanced by short nonzeros, at most `cap` rows each. The greedy
-    // split can leave a few more units than the target (rows do not divide evenly); the share
-    // per unit is raised in small steps until it does not, so that the units fit the resident
-    // wave slots the target was sized for (one launch round).
+    // split can leave more units than the target (rows do not divide evenly); the share per
+    // unit is then raised, in small steps first and by bisection after that, until it does
+    // not, so that the units fit the resident wave slots the target was sized for (one launch
+    // round). A larger share never gives more units, and the share of all short nonzeros
+    // gives the fewest the row cap allows.
     if (target_units < 1) target_units = 1;
-    int64_t per_unit = std::max<int64_t>(64, (nnz_short + target_units - 1) / target_units);
-    for (int attempt = 0;; ++attempt) {
+    auto split = [&](int64_t share) -> int64_t {
         L.unit_row.assign(1, 0);
         int r = 0;
         while (r < rows) {
@@ -59,14 +60,30 @@ PanelLayoutHost build_panel_layout(int rows, int cols, const int32_t* rp, const 
             int64_t nz = 0;
             while (r < rows && r - start < cap) {
                 const int64_t len = L.is_long.empty() || !L.is_long[r] ? rp[r + 1] - rp[r] : 0;
-                if (nz > 0 && nz + len > per_unit) break;
+                if (nz > 0 && nz + len > share) break;
                 nz += len;
                 ++r;
             }
             L.unit_row.push_back(r);
         }
-        if (static_cast<int64_t>(L.unit_row.size()) - 1 <= target_units || attempt == 32) break;
+        return static_cast<int64_t>(L.unit_row.size()) - 1;
+    };
+    int64_t per_unit = std::max<int64_t>(64, (nnz_short + target_units - 1) / target_units);
+    int64_t nunits = split(per_unit);
+    for (int attempt = 0; nunits > target_units && attempt < 32; ++attempt) {
         per_unit += std::max<int64_t>(1, per_unit / 128);
+        nunits = split(per_unit);
+    }
+    if (nunits > target_units) {
+        int64_t lo = per_unit, hi = std::max(per_unit, nnz_short);
+        if (split(hi) <= target_units) {
+            while (hi - lo > 1) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (split(mid) <= target_units) hi = mid;
+                else lo = mid;
+            }
+        }
+        split(hi);
     }
     L.units = static_cast<int>(L.unit_row.size()) - 1;
     for (int u = 0; u < L.units; ++u) L.max_unit_rows = std::max(L.max_unit_rows, L.unit_row[u + 1] - L.unit_row[u]);
