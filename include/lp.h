@@ -126,7 +126,7 @@ typedef struct lp_options {
                               (default 4; a workgroup holds 2 units, each with a producer and a
                               consumer wave, so even values fill every CU evenly) */
     int32_t batch_wg_per_cu; /* lp_solve_batch: workgroups per compute unit (default 3) */
-    int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 1 MiB) */
+    int64_t panel_slice_bytes; /* bytes of the gathered vector per column panel (default 512 KiB) */
     int64_t batch_split_nnz;   /* lp_solve_batch: LPs with more nonzeros go to the block-diagonal
                                   multi-LP launches, the rest to the persistent kernel (default 20000) */
     int32_t deferred;      /* 1: lp_create validates and prepares on the host only; device memory is

@@ -704,7 +704,7 @@ int32_t host_prep(lp_handle* h, const int32_t* rp, const int32_t* ci) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
     const int target_units = cus * (o.units_per_cu > 0 ? o.units_per_cu : 4);
-    const int64_t slice = o.panel_slice_bytes > 0 ? o.panel_slice_bytes : (int64_t(1) << 20);
+    const int64_t slice = o.panel_slice_bytes > 0 ? o.panel_slice_bytes : (int64_t(1) << 19);
     const int long_len = o.long_row_len > 0 ? o.long_row_len : 256;
     Q.panels = o.spmv_layout == 0 || o.spmv_layout == 2;
     if (Q.panels) {
@@ -1469,7 +1469,7 @@ void lp_default_options(lp_options* o) {
     o->units_per_cu = 4;
     o->batch_wg_per_cu = 3;
     o->batch_split_nnz = 20000;
-    o->panel_slice_bytes = int64_t(1) << 20;
+    o->panel_slice_bytes = int64_t(1) << 19;
     o->x0 = nullptr;
     o->y0 = nullptr;
     o->eps_infeas = 1e-8;

@@ -6,7 +6,7 @@
 namespace lpgpu {
 
 int choose_panels(int cols, int64_t slice_bytes) {
-    if (slice_bytes <= 0) slice_bytes = 1 << 20;
+    if (slice_bytes <= 0) slice_bytes = 1 << 19;
     const int64_t bytes = static_cast<int64_t>(cols) * 8;
     int64_t p = (bytes + slice_bytes - 1) / slice_bytes;
     if (p < 1) p = 1;
