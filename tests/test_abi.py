@@ -166,3 +166,16 @@ def test_library_has_no_unresolved_internal_symbols():
     path = lpg.lib()._name
     out = subprocess.run(["nm", "-D", "--undefined-only", "-C", path], capture_output=True, text=True, check=True)
     assert "lpgpu::" not in out.stdout, out.stdout
+
+
+def test_default_options_match_the_header():
+    """lp_default_options fills in the defaults that include/lp.h documents for each field."""
+    o = lpg.lp_default_options()
+    expected = dict(eps_rel=1e-4, max_iters=100000, time_limit_s=0.0, eval_every=64,
+                    precision=lpg.LP_PREC_FP64, scaling=1, ruiz_passes=10, pow_iters=200, restarts=1,
+                    step_size=0.0, omega0=0.0, device=0, trace_cap=4096, spmv_layout=0, long_row_len=256,
+                    units_per_cu=4, batch_wg_per_cu=3, panel_slice_bytes=512 * 1024, batch_split_nnz=20000,
+                    deferred=0, eps_infeas=1e-8, method=lpg.LP_METHOD_AVERAGED, reflection=1.0,
+                    omega_steps=0)
+    for k, v in expected.items():
+        assert getattr(o, k) == v, (k, getattr(o, k), v)
