@@ -274,10 +274,12 @@ void lp_server_destroy(lp_server *srv);
 
 /* ---- presolve and postsolve (Section 3) -----------------------------------------------
  * A lightweight host presolver built from the atomic reductions of Section 2.1 (fix a
- * variable, remove a constraint, change bounds, substitute a variable that appears in a
- * single equality row), driven by the fast explorers of Section 3.1 (Table 1): empty and singleton rows,
+ * variable, remove a constraint, change bounds, substitute a variable out through an
+ * equality row), driven by the fast explorers of Section 3.1 (Table 1): empty and singleton rows,
  * redundant rows and row sides by minimum / maximum activity, empty and fixed columns,
- * column singletons of equality rows and variable locks (Section 2.3). It runs sequentially
+ * column singletons of equality rows, doubleton equality rows whose substitution adds no
+ * nonzero (it changes values of existing entries of the partner column) and variable locks
+ * (Section 2.3). It runs sequentially
  * on the CPU and touches no device. lp_presolve takes an LP of eq. 1 (same arguments and
  * validation as lp_create) and keeps a reduced LP of the same form; lp_postsolve maps an
  * (approximate) solution of the reduced LP to (x, y, z) of the original (eq. 2): y of a
@@ -299,6 +301,8 @@ typedef struct lp_presolve_options {
     int32_t max_rounds;      /* rounds of all explorers at most (default 32) */
     int32_t dual_reductions; /* 1: fixing by variable locks (default); 0: primal reductions only */
     int32_t substitute;      /* 1: eliminate column singletons of equality rows (default) */
+    int32_t doubletons;      /* 1: eliminate doubleton equality rows whose substitution adds no
+                                nonzero (default) */
     double feas_tol;         /* tolerance of the infeasibility tests (default 1e-9) */
     double pivot_tol;        /* smallest |a_ik| / max_j |a_ij| accepted for a substitution (default 1e-3) */
 } lp_presolve_options;
@@ -311,6 +315,7 @@ typedef struct lp_presolve_info {
     int64_t empty_rows, singleton_rows, redundant_rows, dropped_sides;
     int64_t empty_cols, fixed_cols, lock_fixed_cols, substituted_cols;
     double seconds;          /* wall time of lp_presolve */
+    int64_t doubleton_cols;  /* columns eliminated through doubleton equality rows */
 } lp_presolve_info;
 
 void lp_presolve_default_options(lp_presolve_options *opt);

@@ -65,7 +65,7 @@ class lp_options(C.Structure):
 
 class lp_presolve_options(C.Structure):
     _fields_ = [("max_rounds", C.c_int32), ("dual_reductions", C.c_int32), ("substitute", C.c_int32),
-                ("pad", C.c_int32), ("feas_tol", C.c_double), ("pivot_tol", C.c_double)]
+                ("doubletons", C.c_int32), ("feas_tol", C.c_double), ("pivot_tol", C.c_double)]
 
 
 class lp_presolve_info(C.Structure):
@@ -73,7 +73,7 @@ class lp_presolve_info(C.Structure):
                 ("rounds", C.c_int32), ("pad2", C.c_int32)] + \
                [(k, C.c_int64) for k in ("empty_rows", "singleton_rows", "redundant_rows", "dropped_sides",
                                          "empty_cols", "fixed_cols", "lock_fixed_cols", "substituted_cols")] + \
-               [("seconds", C.c_double)]
+               [("seconds", C.c_double), ("doubleton_cols", C.c_int64)]
 
 
 class lp_server_stats(C.Structure):

@@ -3,17 +3,19 @@
 //   - fix a variable (and substitute its value into the rows and the objective),
 //   - remove a constraint,
 //   - change bounds (of a variable, or drop the redundant side of a row),
-//   - substitute a variable that appears in a single equality row,
+//   - substitute a variable out through an equality row,
 // driven by the fast explorers of Section 3.1 (Table 1): empty and singleton rows, redundant
 // rows and row sides by minimum / maximum activity (the redundant-constraint explorer of
-// Section 2.2), empty and fixed columns, column singletons of equality rows, and variable
+// Section 2.2), empty and fixed columns, column singletons of equality rows, doubleton
+// equality rows (Table 1; here only those whose substitution adds no nonzero), and variable
 // locks (Section 2.3); the activities, counts and locks are the internal statistics of
 // Section 3.2. Every reduction pushes a postsolve record;
 // lp_postsolve replays the records in reverse and maps a solution of the reduced LP to
 // (x, y, z) of the original one (eq. 2). Sequential CPU code: no device is touched.
 //
-// Data: the original CSR and its CSC copy stay fixed; rows and columns are switched off as
-// they leave the problem (no reduction here adds nonzeros), and the active row and column
+// Data: the original CSR and its CSC copy keep their structure; rows and columns are switched
+// off as they leave the problem (no reduction here adds nonzeros; a doubleton substitution
+// changes values of existing entries in both copies), and the active row and column
 // counts are kept up to date. Explorers run in rounds over all active rows and columns until
 // a round changes nothing.
 #include <algorithm>
@@ -31,7 +33,7 @@ namespace {
 
 constexpr double kInf = HUGE_VAL;
 
-enum RecKind : int { kDelRow = 0, kSingletonRow = 1, kFixCol = 2, kSubstCol = 3 };
+enum RecKind : int { kDelRow = 0, kSingletonRow = 1, kFixCol = 2, kSubstCol = 3, kDoubleton = 4 };
 
 // One postsolve record. Entry lists (rows of a fixed column, columns of a substituted row)
 // live in the presolver's shared idx / val arrays at [off, off + len).
@@ -39,10 +41,13 @@ struct Rec {
     int kind;
     int i;          // row
     int k;          // column
-    double a;       // a_ik (singleton row, substitution)
+    int j;          // doubleton: the column that stays
+    double a;       // a_ik (singleton row, substitution, doubleton)
+    double aj;      // doubleton: a_ij
     double v;       // fixed value (fix), equality right-hand side (substitution)
     double ck;      // cost of column k when the reduction was applied
-    int from_row;   // singleton row: bit 0 = new lower bound of x_k came from the row, bit 1 = upper
+    int from_row;   // singleton row: bit 0 = new lower bound of x_k came from the row, bit 1 = upper;
+                    // doubleton: the same for x_j's bounds taken from x_k's
     int64_t off;
     int64_t len;
 };
@@ -99,6 +104,8 @@ public:
             cols_pass();
             if (P.status != LP_PRESOLVE_REDUCED) break;
             if (P.opt.substitute) substitution_pass();
+            if (P.status != LP_PRESOLVE_REDUCED) break;
+            if (P.opt.doubletons) doubleton_pass();
             if (P.status != LP_PRESOLVE_REDUCED) break;
             activity_pass();
             if (P.status != LP_PRESOLVE_REDUCED) break;
@@ -290,6 +297,112 @@ private:
         }
     }
 
+    // Adds d to the entry (q, j), which exists, in the CSR and the CSC copy.
+    void add_to_entry(int q, int j, double d) {
+        for (int e = P.rp[q]; e < P.rp[q + 1]; ++e)
+            if (P.ci[e] == j) {
+                P.av[e] += d;
+                break;
+            }
+        for (int e = P.cp[j]; e < P.cp[j + 1]; ++e)
+            if (P.ri[e] == q) {
+                P.cv[e] += d;
+                break;
+            }
+    }
+
+    // True when every active row other than i that holds a nonzero of column k also holds
+    // column j, so that substituting x_k through row i adds no nonzero.
+    bool no_fill(int i, int k, int j) const {
+        for (int e = P.cp[k]; e < P.cp[k + 1]; ++e) {
+            const int q = P.ri[e];
+            if (q == i || !P.row_on[q] || P.cv[e] == 0.0) continue;
+            bool has = false;
+            for (int f = P.rp[q]; f < P.rp[q + 1] && !has; ++f) has = P.ci[f] == j;
+            if (!has) return false;
+        }
+        return true;
+    }
+
+    // Doubleton equality row i: a_ij x_j + a_ik x_k = b, so x_k = beta - alpha x_j with
+    // alpha = a_ij / a_ik, beta = b / a_ik. Every other row q with x_k gets a_qj -= a_qk alpha
+    // and its sides shifted by a_qk beta; c_j -= c_k alpha and the offset gains c_k beta; the
+    // bounds of x_k become bounds of x_j; row i and column k leave.
+    void eliminate_doubleton(int i, int k, int j, double ak, double aj) {
+        const double b = P.lo[i];
+        const double alpha = aj / ak, beta = b / ak;
+        Rec r{};
+        r.kind = kDoubleton;
+        r.i = i;
+        r.k = k;
+        r.j = j;
+        r.a = ak;
+        r.aj = aj;
+        r.v = b;
+        r.ck = P.c[k];
+        r.off = static_cast<int64_t>(P.rec_idx.size());
+        for (int e = P.cp[k]; e < P.cp[k + 1]; ++e) {
+            const int q = P.ri[e];
+            if (q == i || !P.row_on[q]) continue;
+            const double aqk = P.cv[e];
+            P.rec_idx.push_back(q);
+            P.rec_val.push_back(aqk);
+            if (aqk == 0.0) continue;
+            add_to_entry(q, j, -aqk * alpha);
+            const double s = aqk * beta;
+            if (finite(P.lo[q])) P.lo[q] -= s;
+            if (finite(P.hi[q])) P.hi[q] -= s;
+        }
+        r.len = static_cast<int64_t>(P.rec_idx.size()) - r.off;
+        P.c[j] -= P.c[k] * alpha;
+        P.c0 += P.c[k] * beta;
+        // x_k = beta - alpha x_j in [lb_k, ub_k]
+        const double l = alpha > 0 ? (beta - P.ub[k]) / alpha : (beta - P.lb[k]) / alpha;
+        const double u = alpha > 0 ? (beta - P.lb[k]) / alpha : (beta - P.ub[k]) / alpha;
+        if (l > P.lb[j]) {
+            P.lb[j] = l;
+            r.from_row |= 1;
+        }
+        if (u < P.ub[j]) {
+            P.ub[j] = u;
+            r.from_row |= 2;
+        }
+        if (P.lb[j] > P.ub[j]) {
+            if (P.lb[j] - P.ub[j] > tol() * (1.0 + std::fabs(P.ub[j]))) return infeasible();
+            const double mid = 0.5 * (P.lb[j] + P.ub[j]);
+            P.lb[j] = P.ub[j] = mid;
+        }
+        ++P.info.doubleton_cols;
+        P.recs.push_back(r);
+        remove_row(i);
+        remove_col(k);
+    }
+
+    // Doubleton equality rows (Table 1) whose substitution adds no nonzero: the column with
+    // fewer entries is eliminated if its pivot passes the pivot tolerance and no fill-in
+    // arises, else the other one under the same conditions.
+    void doubleton_pass() {
+        const double ptol = P.opt.pivot_tol > 0 ? P.opt.pivot_tol : 1e-3;
+        for (int i = 0; i < P.m0 && P.status == LP_PRESOLVE_REDUCED; ++i) {
+            if (!P.row_on[i] || P.row_cnt[i] != 2 || !(P.lo[i] == P.hi[i]) || !finite(P.lo[i])) continue;
+            int e1 = -1, e2 = -1;
+            for (int e = P.rp[i]; e < P.rp[i + 1]; ++e)
+                if (P.col_on[P.ci[e]]) (e1 < 0 ? e1 : e2) = e;
+            if (e2 < 0 || P.av[e1] == 0.0 || P.av[e2] == 0.0) continue;
+            int cand[2] = {e1, e2};
+            if (P.col_cnt[P.ci[e2]] < P.col_cnt[P.ci[e1]]) std::swap(cand[0], cand[1]);
+            for (int t = 0; t < 2; ++t) {
+                const int ek = cand[t], ej = cand[1 - t];
+                const int k = P.ci[ek], j = P.ci[ej];
+                const double ak = P.av[ek], aj = P.av[ej];
+                if (std::fabs(ak) < ptol * std::max(std::fabs(ak), std::fabs(aj))) continue;
+                if (!no_fill(i, k, j)) continue;
+                eliminate_doubleton(i, k, j, ak, aj);
+                break;
+            }
+        }
+    }
+
     Activity activity(int i) const {
         Activity A;
         for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
@@ -427,6 +540,7 @@ void lp_presolve_default_options(lp_presolve_options* opt) {
     opt->max_rounds = 32;
     opt->dual_reductions = 1;
     opt->substitute = 1;
+    opt->doubletons = 1;
     opt->feas_tol = 1e-9;
     opt->pivot_tol = 1e-3;
 }
@@ -576,6 +690,25 @@ int32_t lp_postsolve(const lp_presolver* p, const double* x, const double* y, co
                     double s = R.ck;
                     for (int64_t q = R.off; q < R.off + R.len; ++q) s -= P.rec_val[q] * Y[P.rec_idx[q]];
                     Z[R.k] = s;
+                    break;
+                }
+                case kDoubleton: {
+                    // x_k from row i; then the multipliers: S_k = c_k - sum_q a_qk y_q over the
+                    // other rows. If x_j rests on a bound it took from x_k, that multiplier is
+                    // x_k's: z_j = 0, z_k = -(a_ik / a_ij) z_j', y_i = z_j' / a_ij + S_k / a_ik;
+                    // otherwise z_k = 0 and y_i = S_k / a_ik (z_j is unchanged).
+                    X[R.k] = (R.v - R.aj * X[R.j]) / R.a;
+                    double sk = R.ck;
+                    for (int64_t q = R.off; q < R.off + R.len; ++q) sk -= P.rec_val[q] * Y[P.rec_idx[q]];
+                    const double zj = Z[R.j];
+                    if ((zj > 0 && (R.from_row & 1)) || (zj < 0 && (R.from_row & 2))) {
+                        Y[R.i] = zj / R.aj + sk / R.a;
+                        Z[R.k] = -(R.a / R.aj) * zj;
+                        Z[R.j] = 0.0;
+                    } else {
+                        Y[R.i] = sk / R.a;
+                        Z[R.k] = 0.0;
+                    }
                     break;
                 }
                 case kSubstCol: {

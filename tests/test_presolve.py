@@ -110,7 +110,7 @@ def test_workload_lps(case):
 
 
 @pytest.mark.parametrize("opts", [dict(dual_reductions=0), dict(substitute=0), dict(dual_reductions=0, substitute=0),
-                                  dict(max_rounds=1)])
+                                  dict(max_rounds=1), dict(doubletons=0)])
 def test_option_subsets(opts):
     lp = synth.presolve_lp(3, m=400, n=800, density=0.01)
     with lpg.Presolve(lp, **opts) as P:
@@ -121,13 +121,17 @@ def test_option_subsets(opts):
             assert st["substituted_cols"] == 0
         if opts.get("max_rounds") == 1:
             assert st["rounds"] == 1
+        if opts.get("doubletons") == 0:
+            assert st["doubleton_cols"] == 0
         _, _, _, k, red_obj = exact_roundtrip(lp, P, tol=1e-8)
         assert red_obj == pytest.approx(lp.p_star, rel=1e-9, abs=1e-9)
 
 
 def test_reduced_structure_and_maps():
     lp = synth.presolve_lp(4, m=400, n=800, density=0.01)
-    with lpg.Presolve(lp) as P:
+    # doubleton substitutions change values of existing entries; without them every reduced
+    # entry is an original one
+    with lpg.Presolve(lp, doubletons=0) as P:
         r = P.reduced
         rm, cm = P.maps()
         assert np.all(np.diff(rm) > 0) and np.all(np.diff(cm) > 0)
@@ -191,3 +195,86 @@ def test_validation_errors():
     assert lpg.ERRORS[e.value.code] == "LP_ERR_NAN_INPUT"
     with pytest.raises(TypeError):
         lpg.Presolve(lp, no_such_option=1)
+
+
+def test_doubleton_bound_transfer_hand_lp():
+    """Doubleton equality x1 + 2 x2 = 4 (Table 1): x2 has fewer entries and every other row
+    with x2 also holds x1, so x2 = (4 - x1) / 2 is substituted without fill-in and its bounds
+    [0, 1.5] become x1 in [1, 4]. At the optimum (x1 = 1, x2 = 1.5, x3 = 0.5, objective 3.5,
+    checked by HiGHS on the original) x1 rests on the bound it took from x2, so postsolve must
+    move that multiplier to x2 for the point to pass the KKT check."""
+    lp = _lp([[1, 2, 0], [1, 1, 1], [1, 0, -1]], [3, 0, 1], [4, 3, "-inf"], [4, "inf", 8],
+             [0, 0, 0], [10, 1.5, 5])
+    ref = highs(lp)
+    assert ref["obj"] == pytest.approx(3.5, abs=1e-12)
+    with lpg.Presolve(lp, dual_reductions=0) as P:
+        assert P.stats()["doubleton_cols"] == 1
+        x, y, z, k, red_obj = exact_roundtrip(lp, P)
+        assert red_obj == pytest.approx(3.5, abs=1e-12)
+        np.testing.assert_allclose(x, [1.0, 1.5, 0.5], atol=1e-12)
+        assert z[1] < 0 and z[0] == 0.0  # x2 at its upper bound carries the multiplier
+
+
+def _with_doubletons(seed, m=60, n=80, pairs=25):
+    """A random boxed LP with a known feasible point, plus `pairs` planted doubleton pairs:
+    a new column k whose rows are a subset of an existing column j's rows, tied to x_j by a new
+    equality row a_j x_j + a_k x_k = b that the feasible point satisfies."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((m, n))
+    mask = rng.random((m, n)) < 0.08
+    A[mask] = rng.choice([-1, 1], mask.sum()) * rng.uniform(0.5, 2.0, mask.sum())
+    xl = rng.choice([0.0, -5.0], n)
+    xh = xl + rng.uniform(2.0, 10.0, n)
+    x0 = rng.uniform(xl, xh)
+    rows, cols = [A], []
+    for _ in range(pairs):
+        j = int(rng.integers(n))
+        sup = np.nonzero(rows[0][:, j])[0]
+        colk = np.zeros(rows[0].shape[0])
+        take = sup[rng.random(sup.size) < 0.6]
+        colk[take] = rng.uniform(-2, 2, take.size)
+        cols.append((j, colk))
+    mk = A.shape[0]
+    nk = n + pairs
+    B = np.zeros((mk + pairs, nk))
+    B[:mk, :n] = A
+    lo = np.concatenate([xl, np.zeros(pairs)])
+    hi = np.concatenate([xh, np.zeros(pairs)])
+    xx = np.concatenate([x0, np.zeros(pairs)])
+    for t, (j, colk) in enumerate(cols):
+        k = n + t
+        B[:mk, k] = colk
+        lo[k] = -rng.uniform(1, 6)
+        hi[k] = rng.uniform(1, 6)
+        xx[k] = rng.uniform(lo[k], hi[k])
+        aj, ak = rng.choice([-1, 1]) * rng.uniform(0.5, 2), rng.choice([-1, 1]) * rng.uniform(0.5, 2)
+        B[mk + t, j] = aj
+        B[mk + t, k] = ak
+    act = B @ xx
+    bl = act - rng.uniform(0.0, 3.0, act.size)
+    bh = act + rng.uniform(0.0, 3.0, act.size)
+    eq = rng.random(mk) < 0.3
+    bh[:mk][eq] = bl[:mk][eq] = act[:mk][eq]
+    bl[mk:] = bh[mk:] = act[mk:]
+    bl[:mk][~eq & (rng.random(mk) < 0.3)] = -np.inf
+    c = rng.normal(size=nk)
+    return _lp(B.tolist(), c.tolist(), bl.tolist(), bh.tolist(), lo.tolist(), hi.tolist())
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_planted_doubletons(seed):
+    """Random boxed LPs with planted doubleton pairs: the doubletons are eliminated, the
+    reduced LP's optimum plus its offset equals the original's (HiGHS), and postsolve of the
+    reduced optimum passes the oracle's KKT check on the original."""
+    lp = _with_doubletons(seed)
+    ref = highs(lp)
+    assert ref["status"] == "optimal"
+    for opts in (dict(), dict(dual_reductions=0, substitute=0)):
+        with lpg.Presolve(lp, **opts) as P:
+            assert P.status in ("reduced", "solved")
+            assert P.stats()["doubleton_cols"] > 0
+            assert P.info.nnz <= lp.nnz
+            _, _, _, k, red_obj = exact_roundtrip(lp, P, tol=1e-8)
+            assert red_obj == pytest.approx(ref["obj"], rel=1e-9, abs=1e-9)
+            assert k["pobj"] == pytest.approx(ref["obj"], rel=1e-8, abs=1e-8)
+
