@@ -7,8 +7,9 @@ it shares no code with the solver.
 Parity notes: the problem form, the dual sign rules and the reduced-cost identity follow
 the paper's Section 2 (eq. 1, eq. 2) and Section 2.1. The PDHG iteration, restart rules,
 step size, primal weight and scaling are the published PDLP-family method the paper
-names without detail; for the restart constants and the primal-weight smoothing the
-parity is unpinned beyond the invariants the tests check.
+names without detail; the restart constants (0.2, 0.8, 0.36) and the evaluation period are
+readings with parity unpinned, while the restart cycle itself is pinned by
+tests/test_oracle_restarts.py.
 """
 from __future__ import annotations
 

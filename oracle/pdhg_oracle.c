@@ -20,9 +20,11 @@
  *  - The paper names PDHG (Zhu-Chan, Chambolle-Pock) and the PDLP family but does not spell
  *    the iteration out. The iteration, restarts, step size and primal weight below are the
  *    published averaged, restarted PDHG of that family, in the reading stated beside each
- *    function. The restart constants (0.2 / 0.8 / 0.36), the evaluation period, the primal
- *    weight smoothing and the power-of-two scaling are heuristics the paper does not fix:
- *    parity unpinned for them beyond the invariants the tests check.
+ *    function. The restart constants (0.2 / 0.8 / 0.36) and the evaluation period are
+ *    heuristics the paper does not fix: parity unpinned for them. The implementation of the
+ *    restart cycle is pinned by the tests (a restart equals a fresh start at the candidate,
+ *    every decision recomputed from the iterates, the primal-weight update balancing the
+ *    weighted distances), and the power-of-two scaling by its exactness.
  *  - Method 1 is the reflected Halpern form of the same family (see ora_solve); the
  *    infeasibility certificates follow the remark after eq. (2) that an LP with no solution
  *    of eq. (2) is infeasible or unbounded (see eval_rays).

@@ -1,8 +1,9 @@
 """The oracle's pins must catch plausible mistakes. Each mutant below plants one mistake in
 a temporary copy of the oracle source (CPU only), and the quick pin subset must fail on it.
 
-Mutants of the restart heuristics (constants, primal-weight smoothing) are deliberately
-absent: the paper does not fix them, so no external pin exists (parity unpinned)."""
+The restart cycle is covered by mutants of its implementation (candidate choice, primal-weight
+update direction, the no-progress test, the anchor reset). Its constants (0.2, 0.8, 0.36) are
+readings the paper does not fix, so no mutant changes them (parity unpinned for them)."""
 import os
 import subprocess
 import sys
@@ -36,6 +37,10 @@ MUTANTS = {
                               "double wk = (double)(t + 1) / (double)(t + 3);"),
     "halpern_reflection_sign": ("x[j] = wk * (r1 * xa[j] - rho * x[j]) + wa * xan[j];",
                                 "x[j] = wk * (r1 * xa[j] + rho * x[j]) + wa * xan[j];"),
+    "restart_candidate_inverted": ("int use_avg = halpern ? 1 : ka < kc;", "int use_avg = halpern ? 1 : ka > kc;"),
+    "primal_weight_inverted": ("omega = sqrt((omega * dy) / dx);", "omega = sqrt((omega * dx) / dy);"),
+    "restart_no_progress_flipped": ("kcand > kkt_prev) why = 2;", "kcand < kkt_prev) why = 2;"),
+    "restart_anchor_not_reset": ("memcpy(xan, x, nb);", "(void)0;"),
 }
 
 QUICK = [
@@ -46,6 +51,7 @@ QUICK = [
     "tests/test_oracle_structure.py",
     "tests/test_oracle_infeasible.py",
     "tests/test_oracle_halpern.py",
+    "tests/test_oracle_restarts.py",
 ]
 
 

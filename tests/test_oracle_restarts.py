@@ -1,0 +1,189 @@
+"""Pins of the oracle's restart cycle: the candidate choice, the three restart tests, the
+primal-weight update and the reset of iterate, anchor, averages and A~x at a restart.
+
+The paper names the restarted PDHG family of its GPU solver (Sections 1 and 4) without its
+restart rules, so the constants (0.2, 0.8, 0.36) and the evaluation period are readings and
+stay unpinned. What is pinned here is that the oracle does what the rules say:
+
+* A restart is a fresh start. Right after a restart the solve must continue exactly as a new
+  solve started at the restart candidate with the new primal weight would: iterate, anchor,
+  running averages and the stored A~x are all reset. Compared bit for bit over the 64
+  iterations that follow, in both iteration forms, with and without scaling.
+* Every decision, recomputed in dense numpy from the iterates at each evaluation: the
+  KKT error in the omega-weighted norm of the current point and of the average, the
+  candidate (the average only if strictly smaller), the anchor's and the previous
+  candidate's error, the restart reason (first of: deep decay, no progress after some decay,
+  long cycle), and the invariant that the candidate is never worse than the current point.
+* The primal-weight update balances the weighted distances moved in the cycle: with s
+  square-root steps the log of the imbalance omega * dx / dy shrinks by exactly 2^-s.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.usefixtures("oracle_lib")
+
+EVAL = 64
+
+
+def _lp(j):
+    rng = np.random.default_rng([11, j])
+    m = 40 + 10 * j
+    return synth.kkt_constructed(m, 2 * m, synth.random_sparse_pattern(m, 2 * m, 0.06, rng), rng)
+
+
+def _kkt_w(lp, a, x, y, omega):
+    """KKT error of (x, y) in the omega-weighted norm, from the definitions of eq. 2 on the
+    unscaled data: row-bound violation of Ax, the reduced cost minus its projection on the
+    sign cone of the bounds (plus sign violations of y), and the gap of the primal and dual
+    objectives (0 * inf taken as 0)."""
+    ax = a @ x
+    rp = ax - np.clip(ax, lp.b_lo, lp.b_hi)
+    lam = lp.c - a.T @ y
+    flo, fhi = np.isfinite(lp.x_lo), np.isfinite(lp.x_hi)
+    z = np.where(flo & fhi, lam, np.where(flo, np.maximum(lam, 0.0), np.where(fhi, np.minimum(lam, 0.0), 0.0)))
+    rd2 = float(np.sum((lam - z) ** 2))
+    viol = np.where(np.isneginf(lp.b_lo) & (y > 0), y, 0.0) + np.where(np.isposinf(lp.b_hi) & (y < 0), -y, 0.0)
+    rd2 += float(np.sum(viol**2))
+    yp, ym = np.maximum(y, 0.0), np.minimum(y, 0.0)
+    zp, zm = np.maximum(z, 0.0), np.minimum(z, 0.0)
+    dual = (np.sum(np.where(yp > 0, lp.b_lo, 0.0) * yp) + np.sum(np.where(ym < 0, lp.b_hi, 0.0) * ym)
+            + np.sum(np.where(zp > 0, lp.x_lo, 0.0) * zp) + np.sum(np.where(zm < 0, lp.x_hi, 0.0) * zm))
+    gap = float(lp.c @ x) - float(dual)
+    return math.sqrt(omega**2 * float(rp @ rp) + rd2 / omega**2 + gap**2)
+
+
+def _close(a, b, rel=1e-9, noise=1e-11):
+    """Agreement of two evaluations of a KKT error: the gap term cancels the objectives
+    (O(10) here), so the recomputation carries an absolute rounding noise besides the
+    relative one."""
+    if math.isinf(a) or math.isinf(b):
+        return a == b
+    return abs(a - b) <= rel * max(abs(a), abs(b)) + noise
+
+
+def _tie(a, b):
+    return _close(a, b, 1e-8, 1e-10)
+
+
+def _solve(oracle_lib, lp, eta, method, scaling, **kw):
+    return oracle_lib.solve(lp, eps_rel=1e-9, max_iters=6000, scaling=scaling, eta=eta, method=method,
+                            omega0=1.0, trace_cap=4096, **kw)
+
+
+@pytest.mark.parametrize("scaling", [False, True])
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("j", [0, 2])
+def test_restart_equals_fresh_start(oracle_lib, j, method, scaling):
+    lp = _lp(j)
+    eta = 0.95 / np.linalg.norm(lp.dense(), 2)
+    base = _solve(oracle_lib, lp, eta, method, scaling)
+    tr = base.trace
+    # one restart of each reason that has 64 iterations after it (the last record is the stop)
+    picks = {}
+    for rec in tr[:-1]:
+        why, k = int(rec[7]), int(rec[0])
+        if why and why not in picks and k + EVAL <= base.iters:
+            picks[why] = rec
+    assert picks, "no restart to check"
+    R = C = None
+    if scaling:
+        _, R, C, _, _, _ = oracle_lib.scaled_problem(lp)
+    for why, rec in picks.items():
+        k, use_avg, omega = int(rec[0]), bool(rec[6]) or method == 1, float(rec[8])
+        ks = [k] + list(range(k + 1, k + EVAL + 1))
+        run = _solve(oracle_lib, lp, eta, method, scaling, snap_k=ks)
+        x, y, xa, ya = oracle_lib.split_snap(run.snaps[0], lp.n, lp.m)
+        xc, yc = (xa, ya) if use_avg else (x, y)
+        x0, y0 = (xc * C, yc * R) if scaling else (xc.copy(), yc.copy())
+        fresh = oracle_lib.solve(lp, eps_rel=0.0, max_iters=EVAL, scaling=scaling, eta=eta, omega0=omega,
+                                 method=method, x0=x0, y0=y0, snap_k=list(range(1, EVAL + 1)))
+        for i in range(EVAL):
+            after = oracle_lib.split_snap(run.snaps[i + 1], lp.n, lp.m)
+            new = oracle_lib.split_snap(fresh.snaps[i], lp.n, lp.m)
+            for name, u, v in zip(("x", "y", "x_avg", "y_avg"), after, new):
+                assert np.array_equal(u, v), f"reason {why} at k={k}: {name} differs {i + 1} iterations later"
+
+
+def _check_decisions(oracle_lib, lp, method, omega_steps=0, seen=None):
+    a = lp.dense()
+    eta = 0.95 / np.linalg.norm(a, 2)
+    base = _solve(oracle_lib, lp, eta, method, False, omega_steps=omega_steps)
+    tr = base.trace
+    ks = [int(r[0]) for r in tr]
+    run = _solve(oracle_lib, lp, eta, method, False, omega_steps=omega_steps, snap_k=ks)
+    assert np.array_equal(run.trace, tr)
+    steps = omega_steps if omega_steps else (2 if method == 1 else 1)
+    x_an = np.clip(np.zeros(lp.n), lp.x_lo, lp.x_hi)
+    y_an = np.zeros(lp.m)
+    omega = 1.0
+    prev = math.inf
+    k_last = 0
+    anc = _kkt_w(lp, a, x_an, y_an, omega)
+    for idx, rec in enumerate(tr[:-1]):
+        k = int(rec[0])
+        x, y, xa, ya = oracle_lib.split_snap(run.snaps[idx], lp.n, lp.m)
+        cur = (xa, ya) if method == 1 else (x, y)
+        kc = _kkt_w(lp, a, *cur, omega)
+        ka = _kkt_w(lp, a, xa, ya, omega)
+        assert _close(rec[2], kc) and _close(rec[3], ka), (k, rec[2], kc, rec[3], ka)
+        assert _close(rec[9], anc), (k, rec[9], anc)
+        assert _close(rec[10], prev), (k, rec[10], prev)
+        t = k - k_last
+        assert int(rec[1]) == t
+        # candidate: the average only when its error is strictly smaller (the Halpern form has one)
+        if method == 0 and not _tie(ka, kc):
+            assert bool(rec[6]) == (ka < kc), (k, ka, kc)
+        use_avg = method == 1 or bool(rec[6])
+        kcand = ka if use_avg else kc
+        assert kcand <= kc * (1 + 1e-12)
+        # restart reason: the first test that holds
+        ties = [_tie(kcand, 0.2 * anc), _tie(kcand, 0.8 * anc), t == 0.36 * k, _tie(kcand, prev)]
+        if not any(ties):
+            if kcand <= 0.2 * anc:
+                why = 1
+            elif kcand <= 0.8 * anc and kcand > prev:
+                why = 2
+            elif t >= 0.36 * k:
+                why = 3
+            else:
+                why = 0
+            assert int(rec[7]) == why, (k, int(rec[7]), why, kcand / anc, kcand, prev, t / k)
+        why = int(rec[7])
+        if seen is not None:
+            seen.add(why)
+        if why:
+            xc, yc = (xa, ya) if use_avg else (x, y)
+            dx, dy = np.linalg.norm(xc - x_an), np.linalg.norm(yc - y_an)
+            new = float(rec[8])
+            if dx > 1e-10 and dy > 1e-10:
+                before = math.log(omega * dx / dy)
+                after = math.log(new * dx / dy)
+                assert abs(after - before * 2.0**-steps) <= 1e-12 * (1 + abs(before)), (k, before, after, steps)
+            else:
+                assert new == omega
+            omega = new
+            x_an, y_an = xc.copy(), yc.copy()
+            anc = _kkt_w(lp, a, x_an, y_an, omega)
+            prev = math.inf
+            k_last = k
+        else:
+            assert float(rec[8]) == omega
+            prev = kcand
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_restart_decisions_recomputed(oracle_lib, method):
+    seen = set()
+    for j in range(4):
+        _check_decisions(oracle_lib, _lp(j), method, seen=seen)
+    # the cases exercise every restart reason (the Halpern form rarely meets "no progress")
+    assert {1, 3} <= seen and (method == 1 or 2 in seen), seen
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3])
+def test_primal_weight_balances_distances(oracle_lib, steps):
+    _check_decisions(oracle_lib, _lp(1), 0, omega_steps=steps)
