@@ -213,6 +213,27 @@ int32_t lp_update_options(lp_handle *h, const lp_options *opt);
  * temporary second stream for the persistent launch) and waits. */
 int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
 
+/* Allocation-free form of lp_solve_batch, for callers that cannot allocate device memory
+ * (work issued inside a stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc). On success it calls no hipMalloc, hipFree, stream or event creation and no
+ * other allocating routine; it still waits for the GPU before returning.
+ *  - Every LP runs in the persistent one-workgroup-per-LP launch of lp_solve_batch, whatever
+ *    its size (lp_solve_batch sends LPs above batch_split_nnz to block-diagonal launches,
+ *    whose per-call maps would need allocations). An LP's result is bit-identical to the one
+ *    lp_solve_batch gives it in the persistent launch.
+ *  - The launch's job table, LP order and work counter live in a library-owned static device
+ *    array of fixed size (LP_STATIC_BATCH_MAX jobs, 3.2 MB), one copy per device, held
+ *    until the process ends; the counter is cleared by a kernel at every call. count above
+ *    LP_STATIC_BATCH_MAX returns LP_ERR_INVALID_ARG.
+ *  - Every handle must already hold its device memory (created with deferred = 0, or solved
+ *    once): LP_ERR_INVALID_ARG otherwise, as for handles on different devices.
+ *  - Calls on one device share that array: two calls that overlap in time on one device race
+ *    and must be serialised by the caller. Runs on the first handle's stream.
+ * Options as for lp_solve_batch (batch_opt's eps_rel, max_iters, eval_every, restarts,
+ * eps_infeas, method, reflection, omega_steps and batch_wg_per_cu, or each handle's own). */
+#define LP_STATIC_BATCH_MAX 4096
+int32_t lp_solve_batch_static(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
+
 /* ---- serving form -------------------------------------------------------------------
  * A server solves LPs as they arrive, with continuous batching: a worker thread keeps a
  * running set of LPs on the device and advances all of them together, one evaluation

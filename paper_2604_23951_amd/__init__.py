@@ -30,10 +30,11 @@ LP_LAYOUT_TUNED = 2
 LP_PREC_FP64 = 0
 LP_PREC_FP32_REFINED = 1
 TRACE_WIDTH = 12
+LP_STATIC_BATCH_MAX = 4096  # include/lp.h
 
 # names of every function include/lp.h declares
 EXPORTS = (
-    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_solve_batch", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
     "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
@@ -129,6 +130,8 @@ def lib():
         L.lp_solve.restype = I32
         L.lp_solve_batch.argtypes = [P, I32, P]
         L.lp_solve_batch.restype = I32
+        L.lp_solve_batch_static.argtypes = [P, I32, P]
+        L.lp_solve_batch_static.restype = I32
         L.lp_get_solution.argtypes = [P, P, P, P, P]
         L.lp_get_solution.restype = I32
         L.lp_destroy.argtypes = [P]
@@ -221,6 +224,12 @@ def lp_solve(h):
 def lp_solve_batch(handles, opt: Optional[lp_options] = None):
     arr = (C.c_void_p * max(len(handles), 1))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
     rc = lib().lp_solve_batch(arr, len(handles), None if opt is None else C.byref(opt))
+    _check(rc)
+
+
+def lp_solve_batch_static(handles, opt: Optional[lp_options] = None):
+    arr = (C.c_void_p * max(len(handles), 1))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    rc = lib().lp_solve_batch_static(arr, len(handles), None if opt is None else C.byref(opt))
     _check(rc)
 
 

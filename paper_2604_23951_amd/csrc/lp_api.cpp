@@ -1672,6 +1672,72 @@ int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo
     }
 }
 
+int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_options* bo) {
+    static_assert(LP_STATIC_BATCH_MAX == kStaticBatchMax, "the header's maximum is the scratch array's");
+    if (count < 0 || (count > 0 && !hs)) return fail(nullptr, LP_ERR_INVALID_ARG, "bad batch arguments");
+    if (count > LP_STATIC_BATCH_MAX)
+        return fail(nullptr, LP_ERR_INVALID_ARG, "lp_solve_batch_static: more LPs than LP_STATIC_BATCH_MAX");
+    if (count == 0) return LP_OK;
+    try {
+        for (int32_t i = 0; i < count; ++i) {
+            if (!hs[i]) return fail(nullptr, LP_ERR_INVALID_ARG, "NULL handle in batch");
+            if (!hs[i]->on_device)
+                return fail(hs[i], LP_ERR_INVALID_ARG,
+                            "lp_solve_batch_static: the handle holds no device memory (a deferred handle is placed "
+                            "on the device by lp_solve or lp_solve_batch)");
+            if (hs[i]->device != hs[0]->device)
+                return fail(nullptr, LP_ERR_INVALID_ARG, "batch handles on different devices");
+        }
+        if (bo && (!(bo->eps_rel >= 0.0) || bo->max_iters < 0 || bo->eval_every < 1 || bo->batch_wg_per_cu < 0 ||
+                   !(bo->eps_infeas >= 0.0) || bo->method < LP_METHOD_AVERAGED || bo->method > LP_METHOD_HALPERN ||
+                   !(bo->reflection >= 0.0 && bo->reflection <= 1.0) || bo->omega_steps < 0 || bo->omega_steps > 8))
+            return fail(nullptr, LP_ERR_INVALID_ARG, "invalid option value");
+        lp_handle* h0 = hs[0];
+        const int dev = h0->device;
+        HIP_TRY(h0, hipSetDevice(dev));
+        StaticBatchScratch S{};
+        HIP_TRY(h0, static_batch_scratch(dev, &S));
+        const auto t0 = std::chrono::steady_clock::now();
+        hipStream_t s = h0->stream;
+        // largest LP first (ties by position: a strict order, so the sort needs no buffer)
+        int32_t order[LP_STATIC_BATCH_MAX];
+        for (int32_t i = 0; i < count; ++i) order[i] = i;
+        std::sort(order, order + count, [&](int32_t a, int32_t b) {
+            return hs[a]->nnz != hs[b]->nnz ? hs[a]->nnz > hs[b]->nnz : a < b;
+        });
+        // job table through a small stack buffer, copied chunk by chunk on the stream
+        constexpr int32_t kChunk = 16;
+        BatchJob buf[kChunk];
+        for (int32_t i = 0; i < count; i += kChunk) {
+            const int32_t nb = std::min(kChunk, count - i);
+            for (int32_t j = 0; j < nb; ++j) buf[j] = make_job(hs[i + j], bo);
+            HIP_TRY(h0, hipMemcpyAsync(S.jobs + i, buf, sizeof(BatchJob) * nb, hipMemcpyHostToDevice, s));
+            HIP_TRY(h0, hipStreamSynchronize(s));
+        }
+        HIP_TRY(h0, hipMemcpyAsync(S.order, order, sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+        launch_zero_int(S.counter, s);
+        int cus = 256;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+        const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
+        const int grid = std::min(cus * wpc, static_cast<int>(count));
+        launch_batch(S.jobs, S.order, count, S.counter, grid, s);
+        if (int32_t rc = check_launch(h0, "allocation-free batched solve")) return rc;
+        HIP_TRY(h0, hipStreamSynchronize(s));
+        for (int32_t i = 0; i < count; ++i)
+            HIP_TRY(hs[i], hipMemcpyAsync(hs[i]->h_sc, hs[i]->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h0, hipStreamSynchronize(s));
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int32_t i = 0; i < count; ++i) {
+            fill_info(hs[i]);
+            hs[i]->info.solve_seconds = secs;
+            hs[i]->solved = true;
+        }
+        return LP_OK;
+    } catch (...) {
+        return fail(nullptr, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
 int32_t lp_update_options(lp_handle* h, const lp_options* opt) {
     if (!h || !opt) return fail(h, LP_ERR_INVALID_ARG, "handle or options NULL");
     lp_options o = h->opt;

@@ -186,6 +186,21 @@ void launch_materialize(const DevLP& P, hipStream_t s);
 // Batched form: `grid` workgroups take LPs jobs[order[0]], jobs[order[1]], ... from the
 // device counter (which must start at 0) and each solves one LP at a time, entirely on chip.
 void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s);
+
+// Allocation-free batched form: the job table, LP order and work counter of at most
+// kStaticBatchMax LPs live in a file-scope device array of the kernel source (one copy per
+// device, kept until the process ends). static_batch_scratch returns its device address on
+// `device`, which must be the current device; the address is looked up once per device.
+constexpr int kStaticBatchMax = 4096;
+struct StaticBatchScratch {
+    BatchJob* jobs;  // kStaticBatchMax entries
+    int* order;      // kStaticBatchMax entries
+    int* counter;    // one work counter
+};
+hipError_t static_batch_scratch(int device, StaticBatchScratch* out);
+size_t static_batch_scratch_bytes();
+// Sets *p = 0 with a one-thread kernel (no memset node if the caller captures the stream).
+void launch_zero_int(int* p, hipStream_t s);
 // One launch of a block-diagonal batch; it_or_mode is the iteration inside the bundle for
 // MULTI_PRIMAL / MULTI_DUAL and the evaluation mode for MULTI_PARTIALS / MULTI_DECIDE.
 void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s);

@@ -17,6 +17,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace lpgpu {
 
 namespace {
@@ -2119,6 +2121,46 @@ void launch_batch(const BatchJob* jobs, const int* order, int count, int* counte
     if (count <= 0 || grid <= 0) return;
     hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlock), 0, s, jobs, order, count, counter);
 }
+
+// ------------------------------------------------------ allocation-free batched form
+// Scratch of lp_solve_batch_static: job table, LP order, work counter. Host code never takes
+// the array's name as an address (in host code it is only a stand-in for the symbol); the
+// device address comes from hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kStaticJobsBytes = (sizeof(BatchJob) * kStaticBatchMax + 255) / 256 * 256;
+constexpr size_t kStaticOrderBytes = (sizeof(int) * kStaticBatchMax + 255) / 256 * 256;
+constexpr size_t kStaticScratchBytes = kStaticJobsBytes + kStaticOrderBytes + 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[kMaxDevices] = {};
+
+__global__ void zero_int_kernel(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+}  // namespace
+
+hipError_t static_batch_scratch(int device, StaticBatchScratch* out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = static_cast<char*>(ptr);
+    }
+    char* b = g_scratch_addr[device];
+    out->jobs = reinterpret_cast<BatchJob*>(b);
+    out->order = reinterpret_cast<int*>(b + kStaticJobsBytes);
+    out->counter = reinterpret_cast<int*>(b + kStaticJobsBytes + kStaticOrderBytes);
+    return hipSuccess;
+}
+
+size_t static_batch_scratch_bytes() { return kStaticScratchBytes; }
+
+void launch_zero_int(int* p, hipStream_t s) { hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, p); }
 
 void launch_to_float(const double* src, float* dst, long long n, hipStream_t s) {
     if (n <= 0) return;
