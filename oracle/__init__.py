@@ -66,7 +66,8 @@ class _OptsStruct(C.Structure):
         ("n_snap", C.c_int32), ("pad1", C.c_int32), ("snap_k", C.c_void_p), ("snap_out", C.c_void_p),
         ("trace_cap", C.c_int32), ("pad2", C.c_int32), ("trace", C.c_void_p), ("eps_infeas", C.c_double),
         ("method", C.c_int32), ("pad3", C.c_int32), ("reflection", C.c_double),
-        ("omega_steps", C.c_int32), ("pad4", C.c_int32),
+        ("omega_steps", C.c_int32), ("pad4", C.c_int32), ("pw_rule", C.c_int32), ("pad5", C.c_int32),
+        ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
     ]
 
 
@@ -226,7 +227,8 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
           ruiz_passes: int = 10, pow_iters: int = 200, restarts: bool = True, eta: float = 0.0,
           omega0: float = 0.0, seed: int = 0x5EED0C0FFEE, x0=None, y0=None,
           snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8, method: int = 0,
-          reflection: float = 1.0, omega_steps: int = 0) -> Result:
+          reflection: float = 1.0, omega_steps: int = 0, pw_rule: int = 0, pid_kp: Optional[float] = None,
+          pid_ki: Optional[float] = None, pid_kd: Optional[float] = None) -> Result:
     """Run the oracle. `snap_k` lists iterations whose scaled-space state
     (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration."""
     b = _Bound(lp)
@@ -246,6 +248,13 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     o.method = method
     o.reflection = reflection
     o.omega_steps = omega_steps
+    o.pw_rule = pw_rule
+    if pid_kp is not None:
+        o.pid_kp = pid_kp
+    if pid_ki is not None:
+        o.pid_ki = pid_ki
+    if pid_kd is not None:
+        o.pid_kd = pid_kd
     keep = []
     if x0 is not None:
         x0 = np.ascontiguousarray(x0, dtype=np.float64)

@@ -83,6 +83,10 @@ typedef struct {
     double reflection;   /* rho of the Halpern form, in [0, 1] */
     int32_t omega_steps; /* square-root steps of the primal-weight update (O11); 0: the form's */
     int32_t pad4;
+    int32_t pw_rule;     /* primal-weight update at a restart: 1 smoothing (omega_steps), 2 PID
+                            controller; 0: the default (smoothing) */
+    int32_t pad5;
+    double pid_kp, pid_ki, pid_kd; /* gains of the PID rule */
 } ora_opts;
 
 typedef struct {
@@ -548,6 +552,10 @@ void ora_default_opts(ora_opts *o) {
     o->method = 0;
     o->reflection = 1.0;
     o->omega_steps = 0;
+    o->pw_rule = 0;
+    o->pid_kp = 0.99;
+    o->pid_ki = 0.01;
+    o->pid_kd = 0.0;
 }
 
 /* Export the scaled problem: A~ values (in the caller's CSR order), R, C, and A~^T. */
@@ -628,11 +636,17 @@ static double dual_step(double y, double axn, double ax, double sigma, double bl
  * O10 candidate = average if its KKT_omega is strictly smaller; restart if
  *     (i) KKT_c <= 0.2 KKT_anchor, (ii) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev, or
  *     (iii) t >= 0.36 k.
- * O11 on restart, when dx, dy > 1e-10, omega <- sqrt(omega * dy / dx) applied `omega_steps`
- *     times: the smoothing of log omega toward log(dy/dx) with weight theta =
- *     1 - 2^-omega_steps, built from correctly rounded operations only (0 selects the form's
- *     default: one step, theta = 1/2, for the averaged form; two, theta = 3/4, for the
- *     Halpern form); the candidate becomes iterate, anchor and average.
+ * O11 on restart, when dx, dy > 1e-10 (the distances the candidate moved from the anchor),
+ *     the primal weight is updated so that the weighted distances omega * dx and dy / omega
+ *     move toward balance, i.e. log omega toward log(dy/dx):
+ *     - smoothing (pw_rule 1): omega <- sqrt(omega * dy / dx) applied `omega_steps` times,
+ *       log omega moving by the fraction theta = 1 - 2^-omega_steps, from correctly rounded
+ *       operations only (0 selects one step, theta = 1/2, for the averaged form and two,
+ *       theta = 3/4, for the Halpern form);
+ *     - PID controller (pw_rule 2) on the error e = log(omega * dx / dy) of this restart:
+ *       I += e, log omega -= kp e + ki I + kd (e - e_prev), e_prev = e (I and e_prev start
+ *       at 0). With ki = kd = 0 it is the smoothing with theta = kp.
+ *     The candidate becomes iterate, anchor and average.
  * O12 x = C x~, y = R y~, z = projected reduced cost.
  *
  * Halpern form (method 1, a reading of the newer cuPDLPx-family iteration the paper names):
@@ -708,6 +722,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     Kanc = Kc;
     double kkt_anchor = kkt_omega(&Kanc, omega);
     double kkt_prev = INFINITY;
+    /* primal-weight rule and the PID controller's state (integral, previous error) */
+    const int pid = o->pw_rule == 2;
+    double pid_int = 0.0, pid_prev = 0.0;
     int64_t k = 0, t = 0, restarts = 0, ntr = 0;
     int status = -1, out_avg = 0;
     int64_t snap_i = 0;
@@ -849,8 +866,17 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             const double *xc = use_avg ? xa : x, *yc = use_avg ? ya : y;
             double dx = diff_norm(n, xc, xan), dy = diff_norm(m, yc, yan);
             const int32_t steps = o->omega_steps > 0 ? o->omega_steps : (halpern ? 2 : 1);
-            if (dx > 1e-10 && dy > 1e-10)
-                for (int32_t q = 0; q < steps; q++) omega = sqrt((omega * dy) / dx);
+            if (dx > 1e-10 && dy > 1e-10) {
+                if (pid) {
+                    const double e = log((omega * dx) / dy);
+                    pid_int += e;
+                    const double u = o->pid_kp * e + o->pid_ki * pid_int + o->pid_kd * (e - pid_prev);
+                    pid_prev = e;
+                    omega = omega * exp(-u);
+                } else {
+                    for (int32_t q = 0; q < steps; q++) omega = sqrt((omega * dy) / dx);
+                }
+            }
             tau = eta / omega;
             sigma = eta * omega;
             if (use_avg) {

@@ -41,6 +41,8 @@ MUTANTS = {
     "primal_weight_inverted": ("omega = sqrt((omega * dy) / dx);", "omega = sqrt((omega * dx) / dy);"),
     "restart_no_progress_flipped": ("kcand > kkt_prev) why = 2;", "kcand < kkt_prev) why = 2;"),
     "restart_anchor_not_reset": ("memcpy(xan, x, nb);", "(void)0;"),
+    "pid_integral_not_accumulated": ("pid_int += e;", "pid_int = e;"),
+    "pid_derivative_sign": ("o->pid_kd * (e - pid_prev);", "o->pid_kd * (pid_prev - e);"),
 }
 
 QUICK = [

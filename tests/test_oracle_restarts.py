@@ -108,15 +108,23 @@ def test_restart_equals_fresh_start(oracle_lib, j, method, scaling):
                 assert np.array_equal(u, v), f"reason {why} at k={k}: {name} differs {i + 1} iterations later"
 
 
-def _check_decisions(oracle_lib, lp, method, omega_steps=0, seen=None):
+def _check_decisions(oracle_lib, lp, method, omega_steps=0, seen=None, pid=None):
+    """pid = (kp, ki, kd) selects the PID rule of the primal weight, checked against the
+    closed form of its cumulative change: with the errors e_i = log(omega_i dx_i / dy_i) of
+    the restarts so far and I_i = e_1 + ... + e_i, the derivative terms telescope and
+    log omega_n - log omega_0 = -(kp sum e_i + ki sum I_i + kd e_n)."""
     a = lp.dense()
     eta = 0.95 / np.linalg.norm(a, 2)
-    base = _solve(oracle_lib, lp, eta, method, False, omega_steps=omega_steps)
+    kw = dict(omega_steps=omega_steps)
+    if pid is not None:
+        kw.update(pw_rule=2, pid_kp=pid[0], pid_ki=pid[1], pid_kd=pid[2])
+    base = _solve(oracle_lib, lp, eta, method, False, **kw)
     tr = base.trace
     ks = [int(r[0]) for r in tr]
-    run = _solve(oracle_lib, lp, eta, method, False, omega_steps=omega_steps, snap_k=ks)
+    run = _solve(oracle_lib, lp, eta, method, False, snap_k=ks, **kw)
     assert np.array_equal(run.trace, tr)
     steps = omega_steps if omega_steps else (2 if method == 1 else 1)
+    errors = []
     x_an = np.clip(np.zeros(lp.n), lp.x_lo, lp.x_hi)
     y_an = np.zeros(lp.m)
     omega = 1.0
@@ -162,7 +170,13 @@ def _check_decisions(oracle_lib, lp, method, omega_steps=0, seen=None):
             if dx > 1e-10 and dy > 1e-10:
                 before = math.log(omega * dx / dy)
                 after = math.log(new * dx / dy)
-                assert abs(after - before * 2.0**-steps) <= 1e-12 * (1 + abs(before)), (k, before, after, steps)
+                if pid is None:
+                    assert abs(after - before * 2.0**-steps) <= 1e-12 * (1 + abs(before)), (k, before, after, steps)
+                else:
+                    errors.append(before)
+                    e = np.array(errors)
+                    total = -(pid[0] * e.sum() + pid[1] * np.cumsum(e).sum() + pid[2] * e[-1])
+                    assert abs(math.log(new) - total) <= 1e-11 * (1 + abs(total)), (k, math.log(new), total)
             else:
                 assert new == omega
             omega = new
@@ -187,3 +201,30 @@ def test_restart_decisions_recomputed(oracle_lib, method):
 @pytest.mark.parametrize("steps", [1, 2, 3])
 def test_primal_weight_balances_distances(oracle_lib, steps):
     _check_decisions(oracle_lib, _lp(1), 0, omega_steps=steps)
+
+
+@pytest.mark.parametrize("gains", [(0.99, 0.01, 0.0), (0.6, 0.15, 0.3)])
+@pytest.mark.parametrize("method", [0, 1])
+def test_pid_primal_weight_closed_form(oracle_lib, method, gains):
+    """PID rule of the primal weight (omega starts at 1, so log omega_0 = 0): every decision
+    recomputed as above and the weight after each restart equal to the closed form of the
+    controller's cumulative output."""
+    seen = set()
+    for j in range(2):
+        _check_decisions(oracle_lib, _lp(j), method, seen=seen, pid=gains)
+    assert 1 in seen and 3 in seen
+
+
+def test_pid_proportional_is_smoothing(oracle_lib):
+    """With ki = kd = 0 the PID rule moves log omega by the fraction kp toward log(dy/dx): at
+    kp = 1/2 it is the one-step smoothing, so the weights and decisions of both runs agree
+    (to the rounding of exp/log against the square root, which the iteration then carries:
+    the first weights agree to 1e-14, later ones drift by up to ~1e-7)."""
+    lp = _lp(1)
+    eta = 0.95 / np.linalg.norm(lp.dense(), 2)
+    a = _solve(oracle_lib, lp, eta, 0, False, pw_rule=1, omega_steps=1)
+    b = _solve(oracle_lib, lp, eta, 0, False, pw_rule=2, pid_kp=0.5, pid_ki=0.0, pid_kd=0.0)
+    assert a.iters == b.iters and a.restarts == b.restarts
+    assert np.array_equal(a.trace[:, [0, 1, 6, 7]], b.trace[:, [0, 1, 6, 7]])
+    np.testing.assert_allclose(b.trace[:6, 8], a.trace[:6, 8], rtol=1e-14)
+    np.testing.assert_allclose(b.trace[:, 8], a.trace[:, 8], rtol=1e-6)
