@@ -121,17 +121,19 @@ private:
 
     double tol() const { return P.opt.feas_tol > 0 ? P.opt.feas_tol : 1e-9; }
 
+    // The counts are of active nonzero entries: an explicit zero, or an entry that a
+    // substitution cancels to zero, counts nowhere.
     void remove_row(int i) {
         P.row_on[i] = 0;
         for (int e = P.rp[i]; e < P.rp[i + 1]; ++e)
-            if (P.col_on[P.ci[e]]) --P.col_cnt[P.ci[e]];
+            if (P.col_on[P.ci[e]] && P.av[e] != 0.0) --P.col_cnt[P.ci[e]];
         changed = true;
     }
 
     void remove_col(int k) {
         P.col_on[k] = 0;
         for (int e = P.cp[k]; e < P.cp[k + 1]; ++e)
-            if (P.row_on[P.ri[e]]) --P.row_cnt[P.ri[e]];
+            if (P.row_on[P.ri[e]] && P.cv[e] != 0.0) --P.row_cnt[P.ri[e]];
         changed = true;
     }
 
@@ -180,15 +182,9 @@ private:
                 del_row(i);
             } else if (P.row_cnt[i] == 1) {
                 int e = P.rp[i];
-                while (!P.col_on[P.ci[e]]) ++e;
+                while (!P.col_on[P.ci[e]] || P.av[e] == 0.0) ++e;
                 const int k = P.ci[e];
                 const double a = P.av[e];
-                if (a == 0.0) {  // an explicit zero: the row is empty in effect
-                    if (P.lo[i] > tol() || P.hi[i] < -tol()) return infeasible();
-                    ++P.info.empty_rows;
-                    del_row(i);
-                    continue;
-                }
                 double ilb = a > 0 ? P.lo[i] / a : P.hi[i] / a;
                 double iub = a > 0 ? P.hi[i] / a : P.lo[i] / a;
                 if (std::isnan(ilb)) ilb = -kInf;
@@ -257,10 +253,10 @@ private:
         for (int k = 0; k < P.n0; ++k) {
             if (!P.col_on[k] || P.col_cnt[k] != 1) continue;
             int e = P.cp[k];
-            while (!P.row_on[P.ri[e]]) ++e;
+            while (!P.row_on[P.ri[e]] || P.cv[e] == 0.0) ++e;
             const int i = P.ri[e];
             const double a = P.cv[e];
-            if (!(P.lo[i] == P.hi[i]) || P.row_cnt[i] < 2 || a == 0.0) continue;
+            if (!(P.lo[i] == P.hi[i]) || P.row_cnt[i] < 2) continue;
             double amax = 0.0;
             for (int f = P.rp[i]; f < P.rp[i + 1]; ++f)
                 if (P.col_on[P.ci[f]]) amax = std::max(amax, std::fabs(P.av[f]));
@@ -297,18 +293,29 @@ private:
         }
     }
 
-    // Adds d to the entry (q, j), which exists, in the CSR and the CSC copy.
+    // Adds d to the entry (q, j), which exists, in the CSR and the CSC copy (both hold the
+    // same value). An entry that becomes exactly zero leaves the counts of its row and
+    // column (and the reduced LP); one that becomes nonzero joins them.
     void add_to_entry(int q, int j, double d) {
+        double before = 0.0, after = 0.0;
         for (int e = P.rp[q]; e < P.rp[q + 1]; ++e)
             if (P.ci[e] == j) {
+                before = P.av[e];
                 P.av[e] += d;
+                after = P.av[e];
                 break;
             }
         for (int e = P.cp[j]; e < P.cp[j + 1]; ++e)
             if (P.ri[e] == q) {
-                P.cv[e] += d;
+                P.cv[e] = after;
                 break;
             }
+        if ((before != 0.0) != (after != 0.0)) {
+            const int step = after != 0.0 ? 1 : -1;
+            P.row_cnt[q] += step;
+            P.col_cnt[j] += step;
+            ++P.info.cancelled_entries;
+        }
     }
 
     // True when every active row other than i that holds a nonzero of column k also holds
@@ -387,8 +394,8 @@ private:
             if (!P.row_on[i] || P.row_cnt[i] != 2 || !(P.lo[i] == P.hi[i]) || !finite(P.lo[i])) continue;
             int e1 = -1, e2 = -1;
             for (int e = P.rp[i]; e < P.rp[i + 1]; ++e)
-                if (P.col_on[P.ci[e]]) (e1 < 0 ? e1 : e2) = e;
-            if (e2 < 0 || P.av[e1] == 0.0 || P.av[e2] == 0.0) continue;
+                if (P.col_on[P.ci[e]] && P.av[e] != 0.0) (e1 < 0 ? e1 : e2) = e;
+            if (e2 < 0) continue;
             int cand[2] = {e1, e2};
             if (P.col_cnt[P.ci[e2]] < P.col_cnt[P.ci[e1]]) std::swap(cand[0], cand[1]);
             for (int t = 0; t < 2; ++t) {
@@ -517,7 +524,7 @@ void build_reduced(lp_presolver& P) {
         }
     int64_t nnz = 0;
     for (int i : P.row_map)
-        for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) nnz += P.col_on[P.ci[e]] ? 1 : 0;
+        for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) nnz += P.col_on[P.ci[e]] && P.av[e] != 0.0 ? 1 : 0;
     P.red_nnz = nnz;
     P.info.m = static_cast<int32_t>(P.row_map.size());
     P.info.n = static_cast<int32_t>(P.col_map.size());
@@ -592,8 +599,14 @@ int32_t lp_presolve(lp_presolver** out, int32_t m, int32_t n, int64_t nnz, const
         P->col_on.assign(n, 1);
         P->row_cnt.resize(m);
         P->col_cnt.resize(n);
-        for (int i = 0; i < m; ++i) P->row_cnt[i] = row_ptr[i + 1] - row_ptr[i];
-        for (int k = 0; k < n; ++k) P->col_cnt[k] = P->cp[k + 1] - P->cp[k];
+        for (int i = 0; i < m; ++i) {
+            P->row_cnt[i] = 0;
+            for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) P->row_cnt[i] += vals[e] != 0.0;
+        }
+        for (int k = 0; k < n; ++k) {
+            P->col_cnt[k] = 0;
+            for (int e = P->cp[k]; e < P->cp[k + 1]; ++e) P->col_cnt[k] += P->cv[e] != 0.0;
+        }
         Presolve(*P).run();
         build_reduced(*P);
         P->info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -627,7 +640,7 @@ int32_t lp_presolve_get_reduced(const lp_presolver* p, int32_t* row_ptr, int32_t
         const int i = P.row_map[r];
         for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
             const int k = P.ci[e];
-            if (!P.col_on[k]) continue;
+            if (!P.col_on[k] || P.av[e] == 0.0) continue;
             col_idx[e_out] = P.col_new[k];
             vals[e_out] = P.av[e];
             ++e_out;

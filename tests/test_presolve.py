@@ -278,3 +278,45 @@ def test_planted_doubletons(seed):
             assert red_obj == pytest.approx(ref["obj"], rel=1e-9, abs=1e-9)
             assert k["pobj"] == pytest.approx(ref["obj"], rel=1e-8, abs=1e-8)
 
+
+
+def test_doubleton_cancellation_drops_the_entry():
+    """A +-1 doubleton that cancels an entry: row 0 is x1 + x2 = 1, row 1 is x1 + x2 + x3 >= 0.5.
+    Substituting x1 = 1 - x2 (or x2 = 1 - x1) through row 0 turns row 1's other entry into
+    1 - 1 = 0, so row 1 is x3 >= -0.5: the cancelled entry leaves the counts and the reduced
+    LP, and row 1 is then found as a singleton row (a bound on x3). The postsolved point
+    solves the original (HiGHS's optimum, the oracle's KKT check)."""
+    lp = _lp([[1, 1, 0], [1, 1, 1], [0, 1, -1]], [1, 2, 1], [1, 0.5, -3], [1, "inf", 3],
+             [0, 0, -1], [4, 4, 4])
+    ref = highs(lp)
+    assert ref["status"] == "optimal"
+    with lpg.Presolve(lp, dual_reductions=0) as P:
+        st = P.stats()
+        assert st["doubleton_cols"] == 1 and st["cancelled_entries"] == 1
+        assert st["singleton_rows"] >= 1
+        red = P.reduced
+        assert np.all(red.vals != 0.0)
+        assert red.row_ptr[-1] <= 2  # row 0 gone, row 1 gone as a singleton, row 2 keeps 2 entries at most
+        x, y, z, k, red_obj = exact_roundtrip(lp, P)
+        assert red_obj == pytest.approx(ref["obj"], abs=1e-12)
+        chk = oracle.kkt(lp, x, y)
+        assert chk["erel"] <= 1e-12
+
+
+def test_explicit_zeros_are_not_exported():
+    """Explicit zeros of the input count nowhere: a row whose only other entry is an explicit
+    zero is a singleton row, and the reduced LP holds no zero value."""
+    lp = _lp([[1, 0, 1], [2, 1, 0], [0, 1, 1]], [1, 1, 1], [1, 1, 1], ["inf", "inf", "inf"],
+             [0, 0, 0], [5, 5, 5])
+    # store the zero of row 1, column 2 explicitly
+    rows = [[0, 2], [0, 1, 2], [1, 2]]
+    vals = [[1.0, 1.0], [2.0, 1.0, 0.0], [1.0, 1.0]]
+    lp.row_ptr = np.array([0, 2, 5, 7], np.int32)
+    lp.col_idx = np.array([c for r in rows for c in r], np.int32)
+    lp.vals = np.array([v for r in vals for v in r])
+    ref = highs(lp)
+    with lpg.Presolve(lp, dual_reductions=0, substitute=0, doubletons=0) as P:
+        if P.reduced is not None and P.reduced.row_ptr[-1] > 0:
+            assert np.all(P.reduced.vals != 0.0)
+        x, y, z, k, red_obj = exact_roundtrip(lp, P)
+        assert red_obj == pytest.approx(ref["obj"], abs=1e-12)
