@@ -148,7 +148,23 @@ typedef struct lp_options {
                             * by the fraction 1 - 2^-omega_steps; 1 to 8, or 0 (default) for
                             * the form's own: 1 for LP_METHOD_AVERAGED, 2 for LP_METHOD_HALPERN */
     int32_t pad3;
+    int32_t pw_rule;       /* lp_primal_weight_rule of the update at a restart (default 0) */
+    int32_t pad4;
+    double pid_kp, pid_ki, pid_kd; /* gains of LP_PW_PID (defaults 0.99, 0.01, 0), each in [0, 2] */
 } lp_options;
+
+/* Primal-weight update at a restart, from the distances dx, dy the restart point moved
+ * (scaled space) since the previous restart, when both exceed 1e-10:
+ *  LP_PW_SMOOTH: omega <- sqrt(omega * dy / dx), omega_steps times (the default);
+ *  LP_PW_PID:    a PID controller on the error e = log(omega * dx / dy) of the imbalance of
+ *                the weighted distances: I += e, log omega -= kp e + ki I + kd (e - e_prev),
+ *                e_prev = e (I and e_prev are 0 at the start of a solve). With ki = kd = 0
+ *                it is the smoothing with fraction kp. */
+typedef enum {
+    LP_PW_DEFAULT = 0, /* LP_PW_SMOOTH */
+    LP_PW_SMOOTH = 1,
+    LP_PW_PID = 2
+} lp_primal_weight_rule;
 
 typedef struct lp_info {
     int32_t status;        /* lp_termination */
@@ -168,7 +184,8 @@ typedef struct lp_info {
 void lp_default_options(lp_options *opt);
 
 /* Create a solver handle for the LP of eq. (1) and prepare it on the GPU.
- *   m >= 0 rows, n >= 1 columns, nnz = row_ptr[m] entries.
+ *   m >= 0 rows, n >= 1 columns, nnz = row_ptr[m] entries with nnz <= 2^31 - 2^16 - 1 (the
+ *   kernels form entry offsets in 32 bits; LP_ERR_INVALID_ARG above that).
  *   row_ptr[m+1] (int32, row_ptr[0] = 0, non-decreasing), col_idx[nnz] (int32 in [0, n),
  *   strictly increasing inside each row), vals[nnz] (finite float64; explicit zeros kept).
  *   c[n] finite; c0 finite constant; b_lo[m], b_hi[m], x_lo[n], x_hi[n] with lower <= upper,
@@ -188,8 +205,8 @@ int32_t lp_create(lp_handle **out, int32_t m, int32_t n, int64_t nnz, const int3
 int32_t lp_solve(lp_handle *h);
 
 /* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every,
- * restarts, eps_infeas, method, reflection and omega_steps are taken from *opt; every other field of *opt
- * is ignored (the problem setup, the step size and the trace capacity are fixed at lp_create). */
+ * restarts, eps_infeas, method, reflection, omega_steps, pw_rule and the three pid gains are
+ * taken from *opt; every other field of *opt is ignored (the problem setup, the step size and the trace capacity are fixed at lp_create). */
 int32_t lp_update_options(lp_handle *h, const lp_options *opt);
 
 /* Batched form: solve the LPs of `count` handles (created on the same device) together.
@@ -337,6 +354,9 @@ typedef struct lp_presolve_info {
     int64_t empty_cols, fixed_cols, lock_fixed_cols, substituted_cols;
     double seconds;          /* wall time of lp_presolve */
     int64_t doubleton_cols;  /* columns eliminated through doubleton equality rows */
+    int64_t cancelled_entries; /* entries a doubleton substitution turned to exactly zero (they
+                                  leave the counts and the reduced LP; explicit zeros of the
+                                  input are never counted or exported either) */
 } lp_presolve_info;
 
 void lp_presolve_default_options(lp_presolve_options *opt);

@@ -14,7 +14,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "liblpgpu.so")
+LIB_PATH = os.environ.get("LPGPU_LIB_OVERRIDE", os.path.join(_HERE, "_lib", "liblpgpu.so"))
 
 LP_OK = 0
 ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONSISTENT_BOUNDS",
@@ -24,6 +24,9 @@ STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_err
           5: "dual_infeasible"}
 LP_METHOD_AVERAGED = 0
 LP_METHOD_HALPERN = 1
+LP_PW_DEFAULT = 0
+LP_PW_SMOOTH = 1
+LP_PW_PID = 2
 LP_LAYOUT_PANELS = 0
 LP_LAYOUT_TILES = 1
 LP_LAYOUT_TUNED = 2
@@ -60,7 +63,8 @@ class lp_options(C.Structure):
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
         ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
         ("method", C.c_int32), ("pad2", C.c_int32), ("reflection", C.c_double),
-        ("omega_steps", C.c_int32), ("pad3", C.c_int32),
+        ("omega_steps", C.c_int32), ("pad3", C.c_int32), ("pw_rule", C.c_int32), ("pad4", C.c_int32),
+        ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
     ]
 
 
@@ -74,7 +78,7 @@ class lp_presolve_info(C.Structure):
                 ("rounds", C.c_int32), ("pad2", C.c_int32)] + \
                [(k, C.c_int64) for k in ("empty_rows", "singleton_rows", "redundant_rows", "dropped_sides",
                                          "empty_cols", "fixed_cols", "lock_fixed_cols", "substituted_cols")] + \
-               [("seconds", C.c_double), ("doubleton_cols", C.c_int64)]
+               [("seconds", C.c_double), ("doubleton_cols", C.c_int64), ("cancelled_entries", C.c_int64)]
 
 
 class lp_server_stats(C.Structure):
@@ -365,7 +369,8 @@ class Solver:
 
     def update(self, **options):
         """Change solve-time options (eps_rel, max_iters, time_limit_s, eval_every, restarts,
-        eps_infeas, method, reflection, omega_steps); the ones not given take their defaults."""
+        eps_infeas, method, reflection, omega_steps, pw_rule, pid_kp, pid_ki, pid_kd); the ones
+        not given take their defaults."""
         lp_update_options(self.h, make_options(**options))
 
     def solve(self, with_trace: bool = False) -> Solution:

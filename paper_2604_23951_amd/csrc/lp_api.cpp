@@ -108,8 +108,8 @@ namespace lpgpu {
 int32_t validate_lp(int32_t m, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* ci, const double* v,
                  const double* c, double c0, const double* bl, const double* bu, const double* xl, const double* xu,
                  std::string* msg) {
-    if (m < 0 || n < 1 || nnz < 0 || nnz > 0x7fffffffLL) {
-        *msg = "sizes must satisfy m >= 0, n >= 1, 0 <= nnz < 2^31";
+    if (m < 0 || n < 1 || nnz < 0 || nnz > kMaxEntries) {
+        *msg = "sizes must satisfy m >= 0, n >= 1, 0 <= nnz <= 2^31 - 2^16 - 1";
         return LP_ERR_INVALID_ARG;
     }
     if (!rp || !c || !xl || !xu || (m > 0 && (!bl || !bu)) || (nnz > 0 && (!ci || !v))) {
@@ -239,7 +239,8 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
         o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0) || o.omega_steps < 0 ||
-        o.omega_steps > 8) {
+        o.omega_steps > 8 || o.pw_rule < LP_PW_DEFAULT || o.pw_rule > LP_PW_PID || !(o.pid_kp >= 0.0 && o.pid_kp <= 2.0) ||
+        !(o.pid_ki >= 0.0 && o.pid_ki <= 2.0) || !(o.pid_kd >= 0.0 && o.pid_kd <= 2.0)) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
     }
@@ -328,15 +329,24 @@ void fill_info(lp_handle* h) {
 }
 
 
+// The iteration form and primal-weight rule of a solve, from its options.
+void set_form(DevLP& P, const lp_options& o) {
+    P.method = o.method;
+    P.rho = o.reflection;
+    P.omega_steps = o.omega_steps > 0 ? o.omega_steps : (o.method == LP_METHOD_HALPERN ? 2 : 1);
+    P.pw_rule = o.pw_rule == LP_PW_PID ? 2 : 1;
+    P.kp = o.pid_kp;
+    P.ki = o.pid_ki;
+    P.kd = o.pid_kd;
+}
+
 BatchJob make_job(lp_handle* h, const lp_options* bo) {
     const lp_options& o = bo ? *bo : h->opt;
     BatchJob J{};
     J.P = h->P;
     J.eps_rel = o.eps_rel;
     J.eps_infeas = o.eps_infeas;
-    J.P.method = o.method;
-    J.P.rho = o.reflection;
-    J.P.omega_steps = o.omega_steps > 0 ? o.omega_steps : (o.method == LP_METHOD_HALPERN ? 2 : 1);
+    set_form(J.P, o);
     J.max_iters = o.max_iters;
     J.trace_cap = h->opt.trace_cap;
     J.eval_every = o.eval_every;
@@ -1476,6 +1486,10 @@ void lp_default_options(lp_options* o) {
     o->method = LP_METHOD_AVERAGED;
     o->reflection = 1.0;
     o->omega_steps = 0;
+    o->pw_rule = LP_PW_DEFAULT;
+    o->pid_kp = 0.99;
+    o->pid_ki = 0.01;
+    o->pid_kd = 0.0;
 }
 
 const char* lp_error_string(int32_t code) {
@@ -1572,10 +1586,7 @@ int32_t lp_solve(lp_handle* h) {
     try {
         HIP_TRY(h, hipSetDevice(h->device));
         if (int32_t rc = materialize(h)) return rc;
-        h->P.method = h->opt.method;
-        h->P.rho = h->opt.reflection;
-        h->P.omega_steps = h->opt.omega_steps > 0 ? h->opt.omega_steps
-                                                  : (h->opt.method == LP_METHOD_HALPERN ? 2 : 1);
+        set_form(h->P, h->opt);
         hipStream_t s = h->stream;
         const DevLP& P = h->P;
         const auto t0 = std::chrono::steady_clock::now();
@@ -1690,7 +1701,9 @@ int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_opti
         }
         if (bo && (!(bo->eps_rel >= 0.0) || bo->max_iters < 0 || bo->eval_every < 1 || bo->batch_wg_per_cu < 0 ||
                    !(bo->eps_infeas >= 0.0) || bo->method < LP_METHOD_AVERAGED || bo->method > LP_METHOD_HALPERN ||
-                   !(bo->reflection >= 0.0 && bo->reflection <= 1.0) || bo->omega_steps < 0 || bo->omega_steps > 8))
+                   !(bo->reflection >= 0.0 && bo->reflection <= 1.0) || bo->omega_steps < 0 || bo->omega_steps > 8 ||
+                   bo->pw_rule < LP_PW_DEFAULT || bo->pw_rule > LP_PW_PID || !(bo->pid_kp >= 0.0 && bo->pid_kp <= 2.0) ||
+                   !(bo->pid_ki >= 0.0 && bo->pid_ki <= 2.0) || !(bo->pid_kd >= 0.0 && bo->pid_kd <= 2.0)))
             return fail(nullptr, LP_ERR_INVALID_ARG, "invalid option value");
         lp_handle* h0 = hs[0];
         const int dev = h0->device;
@@ -1750,12 +1763,17 @@ int32_t lp_update_options(lp_handle* h, const lp_options* opt) {
     o.method = opt->method;
     o.reflection = opt->reflection;
     o.omega_steps = opt->omega_steps;
+    o.pw_rule = opt->pw_rule;
+    o.pid_kp = opt->pid_kp;
+    o.pid_ki = opt->pid_ki;
+    o.pid_kd = opt->pid_kd;
     std::string msg;
     if (int32_t rc = validate_options(o, &msg)) return fail(h, rc, msg);
     // the captured iteration bundle bakes in the period, the form, its reflection and the
     // primal-weight steps (the kernels take the solver state by value)
     if (o.eval_every != h->opt.eval_every || o.method != h->opt.method || o.reflection != h->opt.reflection ||
-        o.omega_steps != h->opt.omega_steps) {
+        o.omega_steps != h->opt.omega_steps || o.pw_rule != h->opt.pw_rule || o.pid_kp != h->opt.pid_kp ||
+        o.pid_ki != h->opt.pid_ki || o.pid_kd != h->opt.pid_kd) {
         if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
         if (h->graph) (void)hipGraphDestroy(h->graph);
         h->gexec = nullptr;

@@ -19,6 +19,12 @@ constexpr int kTraceW = 12;
 
 constexpr int kRunning = -1;
 
+// Largest nonzero count accepted. The kernels form entry offsets in 32-bit ints and clamp
+// indices that run past the end of a row, tile or unit (by at most a few thousand entries:
+// the panel producer's prefetch reaches 16 groups of 256 entries ahead); the margin keeps
+// every such offset below 2^31.
+constexpr long long kMaxEntries = 0x7fffffffLL - (1LL << 16);
+
 // Device-resident scalar state of one solve. The iteration kernels read it; only the
 // single-workgroup decision kernels write it.
 struct Scalars {
@@ -27,6 +33,7 @@ struct Scalars {
     double kkt_anchor, kkt_prev;
     double eps_infeas, ray_scale;  // certificate tolerance (0: off); 1/D or 1/G of a certificate
     double anc_rps2, anc_rds2, anc_gap;
+    double pid_int, pid_prev;  // PID rule of the primal weight: integral and previous error
     // statistics of the returned point
     double out_pobj, out_dobj, out_rel_p, out_rel_d, out_rel_gap, out_erel;
     long long k, t, max_iters, restarts, n_trace, trace_cap;
@@ -102,6 +109,8 @@ struct DevLP {
     int method;
     double rho;
     int omega_steps;                  // square-root steps of the primal-weight update (>= 1)
+    int pw_rule;                      // 1 smoothing (omega_steps), 2 PID controller
+    double kp, ki, kd;                // gains of the PID rule
     double *partials;                 // nred * kNT
     Scalars* sc;
     double* trace;

@@ -1073,6 +1073,8 @@ __global__ void reset_kernel(Scalars* sc, double eps_rel, double eps_infeas, lon
     sc->out_avg = 0;
     sc->last_restart = 0;
     sc->kkt_prev = __builtin_inf();
+    sc->pid_int = 0.0;
+    sc->pid_prev = 0.0;
 }
 
 __device__ inline void init_state_at(const DevLP& P, int g, const double* x0, const double* y0) {
@@ -1286,8 +1288,9 @@ __device__ inline void set_output(Scalars* sc, const Kkt& K, int avg) {
 //  termination when E_rel(current) <= eps (then the average), or at max_iters the better one;
 //  restart candidate = average if its KKT_w is strictly smaller; restart on
 //  (1) KKT_c <= 0.2 KKT_anchor, (2) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev,
-//  (3) t >= 0.36 k; on restart omega <- sqrt(omega dy / dx), omega_steps times, when
-//  dx, dy > 1e-10.
+//  (3) t >= 0.36 k; on restart, when dx, dy > 1e-10, omega <- sqrt(omega dy / dx),
+//  omega_steps times, or the PID rule (log omega -= kp e + ki I + kd (e - e_prev) with
+//  e = log(omega dx / dy), I the sum of the errors so far).
 // Thread-0 part of the evaluation: tot holds the summed KKT quantities of the current
 // iterate (0..7) and, in mode 0, of the average (8..15).
 __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int mode) {
@@ -1386,8 +1389,18 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         if (why) {
             const Kkt& cd = use_avg ? avg : cur;
             const double dx = sqrt(cd.dx2), dy = sqrt(cd.dy2);
-            if (dx > 1e-10 && dy > 1e-10)
-                for (int q = 0; q < P.omega_steps; ++q) om = sqrt((om * dy) / dx);
+            if (dx > 1e-10 && dy > 1e-10) {
+                if (P.pw_rule == 2) {
+                    // PID controller on the log imbalance of the weighted distances
+                    const double e = log((om * dx) / dy);
+                    sc->pid_int += e;
+                    const double u = P.kp * e + P.ki * sc->pid_int + P.kd * (e - sc->pid_prev);
+                    sc->pid_prev = e;
+                    om = om * exp(-u);
+                } else {
+                    for (int q = 0; q < P.omega_steps; ++q) om = sqrt((om * dy) / dx);
+                }
+            }
             sc->omega = om;
             sc->tau = sc->eta / om;
             sc->sigma = sc->eta * om;
@@ -1672,6 +1685,8 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
         ssc->out_avg = 0;
         ssc->last_restart = 0;
         ssc->kkt_prev = __builtin_inf();
+        ssc->pid_int = 0.0;
+        ssc->pid_prev = 0.0;
     }
     __syncthreads();
     const int mx = P.m > P.n ? P.m : P.n;
@@ -1872,6 +1887,8 @@ __global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
     sc->out_avg = 0;
     sc->last_restart = 0;
     sc->kkt_prev = __builtin_inf();
+    sc->pid_int = 0.0;
+    sc->pid_prev = 0.0;
 }
 
 __global__ void multi_status_kernel(const BatchJob* jobs, int count, int* status) {

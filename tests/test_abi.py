@@ -62,6 +62,7 @@ def _create_code(**a):
     ("unsorted_row", 2), ("duplicate_col", 2), ("col_out_of_range", 2), ("row_ptr_decreasing", 2),
     ("row_ptr_bad_end", 2), ("negative_m", 1), ("zero_n", 1), ("null_cost", 1), ("bad_eval_every", 1),
     ("nan_c0", 4), ("bad_layout", 1), ("omega_steps_negative", 1), ("omega_steps_nine", 1),
+    ("pw_rule_three", 1), ("pid_gain_negative", 1), ("pid_gain_nan", 1),
 ])
 def test_invalid_input_codes(case, code):
     lp = synth.cfg0(0)
@@ -113,6 +114,12 @@ def test_invalid_input_codes(case, code):
         a["opt"] = lpg.make_options(omega_steps=-1)
     elif case == "omega_steps_nine":
         a["opt"] = lpg.make_options(omega_steps=9)
+    elif case == "pw_rule_three":
+        a["opt"] = lpg.make_options(pw_rule=3)
+    elif case == "pid_gain_negative":
+        a["opt"] = lpg.make_options(pw_rule=lpg.LP_PW_PID, pid_ki=-0.1)
+    elif case == "pid_gain_nan":
+        a["opt"] = lpg.make_options(pw_rule=lpg.LP_PW_PID, pid_kd=math.nan)
     assert _create_code(**a) == code
     assert lpg.lp_last_error()  # a message is recorded
 
@@ -176,6 +183,64 @@ def test_default_options_match_the_header():
                     step_size=0.0, omega0=0.0, device=0, trace_cap=4096, spmv_layout=0, long_row_len=256,
                     units_per_cu=4, batch_wg_per_cu=3, panel_slice_bytes=512 * 1024, batch_split_nnz=20000,
                     deferred=0, eps_infeas=1e-8, method=lpg.LP_METHOD_AVERAGED, reflection=1.0,
-                    omega_steps=0)
+                    omega_steps=0, pw_rule=lpg.LP_PW_DEFAULT, pid_kp=0.99, pid_ki=0.01, pid_kd=0.0)
     for k, v in expected.items():
         assert getattr(o, k) == v, (k, getattr(o, k), v)
+
+
+def test_presolve_default_options_match_the_header():
+    o = lpg.lp_presolve_options()
+    lpg.lib().lp_presolve_default_options(__import__("ctypes").byref(o))
+    expected = dict(max_rounds=32, dual_reductions=1, substitute=1, doubletons=1, feas_tol=1e-9, pivot_tol=1e-3)
+    for k, v in expected.items():
+        assert getattr(o, k) == v, (k, getattr(o, k), v)
+
+
+@pytest.mark.parametrize("struct", ["lp_options", "lp_info", "lp_server_stats", "lp_presolve_options",
+                                    "lp_presolve_info"])
+def test_binding_structs_match_the_header(tmp_path, struct):
+    """The binding's ctypes structures have the size and field offsets of the C structs of
+    include/lp.h (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    cls = getattr(lpg, struct)
+    fields = [f[0] for f in cls._fields_ if not f[0].startswith("pad")]
+    lines = [f'printf("%zu\\n", sizeof({struct}));']
+    lines += [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = tmp_path / "probe.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "lp.h"\nint main(void) {\n'
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    import ctypes
+    assert out[0] == ctypes.sizeof(cls), (struct, out[0], ctypes.sizeof(cls))
+    for f, off in zip(fields, out[1:]):
+        assert getattr(cls, f).offset == off, (struct, f, getattr(cls, f).offset, off)
+
+
+def test_entry_count_bound():
+    """nnz above 2^31 - 2^16 - 1 is rejected before any array is read (the kernels form entry
+    offsets in 32 bits and prefetch a few thousand entries past a unit's end); at the bound
+    the size check passes and validation goes on to the arrays."""
+    import ctypes
+    L = lpg.lib()
+    bound = 2**31 - 2**16 - 1
+    rp = np.array([0, 1], np.int32)
+    ci = np.zeros(1, np.int32)
+    v = np.ones(1)
+    c = np.zeros(2)
+    bl, bu = np.zeros(1), np.ones(1)
+    xl, xu = np.zeros(2), np.ones(2)
+    h = ctypes.c_void_p()
+    args = lambda nnz: (ctypes.byref(h), 1, 2, nnz, rp.ctypes.data, ci.ctypes.data, v.ctypes.data, c.ctypes.data,
+                        0.0, bl.ctypes.data, bu.ctypes.data, xl.ctypes.data, xu.ctypes.data, None)
+    assert L.lp_create(*args(bound + 1)) == 1
+    assert "2^31" in lpg.lp_last_error()
+    assert L.lp_create(*args(bound)) == 2  # size accepted; row_ptr[m] != nnz
+    p = ctypes.c_void_p()
+    assert L.lp_presolve(ctypes.byref(p), 1, 2, bound + 1, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                         c.ctypes.data, 0.0, bl.ctypes.data, bu.ctypes.data, xl.ctypes.data, xu.ctypes.data,
+                         None, None) == 1

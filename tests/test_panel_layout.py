@@ -19,7 +19,9 @@ CSRC = os.path.join(os.path.dirname(HERE), "paper_2604_23951_amd", "csrc")
 @pytest.mark.skipif(shutil.which("g++") is None, reason="needs a host C++ compiler")
 def test_panel_layout_and_run_sum_order(tmp_path):
     exe = str(tmp_path / "panel_layout_check")
-    cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-I", CSRC, "-o", exe,
+    # the host sanitizer run (test_host_sanitizers.py) substitutes an instrumented compiler line
+    cxx = os.environ.get("HOST_CXX", "g++").split()
+    cmd = [*cxx, "-O2", "-std=c++17", "-Wall", "-I", CSRC, "-o", exe,
            os.path.join(HERE, "panel_layout_check.cpp"), os.path.join(CSRC, "lp_layout.cpp")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
