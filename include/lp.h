@@ -150,7 +150,7 @@ typedef struct lp_options {
     int32_t pad3;
     int32_t pw_rule;       /* lp_primal_weight_rule of the update at a restart (default 0) */
     int32_t pad4;
-    double pid_kp, pid_ki, pid_kd; /* gains of LP_PW_PID (defaults 0.99, 0.01, 0), each in [0, 2] */
+    double pid_kp, pid_ki, pid_kd; /* gains of LP_PW_PID (defaults 0.7, 0.05, 0.2), each in [0, 2] */
 } lp_options;
 
 /* Primal-weight update at a restart, from the distances dx, dy the restart point moved

@@ -553,9 +553,9 @@ void ora_default_opts(ora_opts *o) {
     o->reflection = 1.0;
     o->omega_steps = 0;
     o->pw_rule = 0;
-    o->pid_kp = 0.99;
-    o->pid_ki = 0.01;
-    o->pid_kd = 0.0;
+    o->pid_kp = 0.7;
+    o->pid_ki = 0.05;
+    o->pid_kd = 0.2;
 }
 
 /* Export the scaled problem: A~ values (in the caller's CSR order), R, C, and A~^T. */

@@ -1487,9 +1487,9 @@ void lp_default_options(lp_options* o) {
     o->reflection = 1.0;
     o->omega_steps = 0;
     o->pw_rule = LP_PW_DEFAULT;
-    o->pid_kp = 0.99;
-    o->pid_ki = 0.01;
-    o->pid_kd = 0.0;
+    o->pid_kp = 0.7;
+    o->pid_ki = 0.05;
+    o->pid_kd = 0.2;
 }
 
 const char* lp_error_string(int32_t code) {
