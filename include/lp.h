@@ -132,7 +132,11 @@ typedef struct lp_options {
     int32_t deferred;      /* 1: lp_create validates and prepares on the host only; device memory is
                               allocated (and the setup run) when the LP is first solved or admitted
                               by a server, and released by the server when it completes (default 0) */
-    int32_t pad1;
+    int32_t small_lp_lds;  /* lp_solve_batch: bytes of LDS per workgroup (0 to 131072, default 131072)
+                              for LPs held on chip: an LP of the persistent launch whose matrices and
+                              iteration vectors (in its precision) fit is solved from LDS by a
+                              launch of its own (one workgroup per CU), bit-identical to the solve
+                              from global memory; 0 turns this off */
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
     double eps_infeas;     /* relative tolerance of the infeasibility certificates (default 1e-8;

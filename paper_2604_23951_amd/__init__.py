@@ -61,7 +61,7 @@ class lp_options(C.Structure):
         ("spmv_layout", C.c_int32), ("long_row_len", C.c_int32), ("units_per_cu", C.c_int32),
         ("batch_wg_per_cu", C.c_int32),
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
-        ("pad1", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
+        ("small_lp_lds", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
         ("method", C.c_int32), ("pad2", C.c_int32), ("reflection", C.c_double),
         ("omega_steps", C.c_int32), ("pad3", C.c_int32), ("pw_rule", C.c_int32), ("pad4", C.c_int32),
         ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),

@@ -237,6 +237,7 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
     if (!(o.eps_rel >= 0.0) || o.max_iters < 0 || o.eval_every < 1 || o.ruiz_passes < 0 || o.pow_iters < 0 ||
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 2 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
+        o.small_lp_lds < 0 || o.small_lp_lds > kSmallLpLdsMax ||
         std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
         o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0) || o.omega_steps < 0 ||
         o.omega_steps > 8 || o.pw_rule < LP_PW_DEFAULT || o.pw_rule > LP_PW_PID || !(o.pid_kp >= 0.0 && o.pid_kp <= 2.0) ||
@@ -558,56 +559,87 @@ struct PersistentRun {
     std::vector<BatchJob> jobs;
     std::vector<int32_t> order;
     char* buf = nullptr;
-    hipStream_t s = nullptr;
+    hipStream_t s[2] = {nullptr, nullptr};
 };
 
+// Two persistent launches at most, each on a stream of its own: the LPs whose iteration
+// arrays fit in the small-LP LDS budget (one workgroup per CU, each LP solved from LDS) and
+// the others (batch_wg_per_cu workgroups per CU, from global memory). Each launch takes its
+// LPs largest first.
 int32_t start_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo, PersistentRun& R) {
     const int count = static_cast<int>(hs.size());
     lp_handle* h0 = hs[0];
     for (lp_handle* h : hs)
         if (int32_t rc = materialize(h)) return rc;
+    const int budget = bo ? bo->small_lp_lds : h0->opt.small_lp_lds;
     R.jobs.resize(static_cast<size_t>(count));
     R.order.resize(static_cast<size_t>(count));
+    std::vector<size_t> need(static_cast<size_t>(count));
+    size_t cap = 0;
+    int n_lds = 0;
     for (int i = 0; i < count; ++i) {
         R.jobs[i] = make_job(hs[i], bo);
         R.order[i] = i;
+        need[i] = small_lp_lds_bytes(R.jobs[i].P);
+        if (budget > 0 && need[i] <= static_cast<size_t>(budget)) {
+            cap = std::max(cap, need[i]);
+            ++n_lds;
+        }
     }
-    std::stable_sort(R.order.begin(), R.order.end(), [&](int32_t a, int32_t b) { return hs[a]->nnz > hs[b]->nnz; });
+    auto in_lds = [&](int32_t i) { return budget > 0 && need[i] <= static_cast<size_t>(budget); };
+    // LDS LPs first, then the others; each part largest first
+    std::stable_sort(R.order.begin(), R.order.end(), [&](int32_t a, int32_t b) {
+        if (in_lds(a) != in_lds(b)) return in_lds(a);
+        return hs[a]->nnz > hs[b]->nnz;
+    });
+    const int lds_cap = n_lds ? static_cast<int>((cap + 16383) / 16384 * 16384) : 0;
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h0->device) != hipSuccess || cus < 1)
         cus = 256;
     const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;
-    int grid = cus * wpc;
-    if (grid > count) grid = count;
     const size_t bj = sizeof(BatchJob) * static_cast<size_t>(count), bo_ = sizeof(int32_t) * static_cast<size_t>(count);
     const size_t oc = (bj + bo_ + 255) / 256 * 256;
-    HIP_TRY(h0, hipStreamCreateWithFlags(&R.s, hipStreamNonBlocking));
-    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&R.buf), oc + 256));
+    HIP_TRY(h0, hipMalloc(reinterpret_cast<void**>(&R.buf), oc + 512));
     BatchJob* djobs = reinterpret_cast<BatchJob*>(R.buf);
     int32_t* dorder = reinterpret_cast<int32_t*>(R.buf + bj);
-    int32_t* dcounter = reinterpret_cast<int32_t*>(R.buf + oc);
-    hipError_t e = hipMemcpyAsync(djobs, R.jobs.data(), bj, hipMemcpyHostToDevice, R.s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dorder, R.order.data(), bo_, hipMemcpyHostToDevice, R.s);
-    if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, sizeof(int32_t), R.s);
-    if (e == hipSuccess) {
-        launch_batch(djobs, dorder, count, dcounter, grid, R.s);
+    int32_t* dcounter = reinterpret_cast<int32_t*>(R.buf + oc);  // one counter per launch, 256 bytes apart
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < 2 && e == hipSuccess; ++l)
+        e = hipStreamCreateWithFlags(&R.s[l], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemcpyAsync(djobs, R.jobs.data(), bj, hipMemcpyHostToDevice, R.s[0]);
+    if (e == hipSuccess) e = hipMemcpyAsync(dorder, R.order.data(), bo_, hipMemcpyHostToDevice, R.s[0]);
+    if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, 512, R.s[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(R.s[0]);
+    if (e == hipSuccess && n_lds > 0) {
+        launch_batch(djobs, dorder, n_lds, dcounter, std::min(cus, n_lds), R.s[1], lds_cap);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && count > n_lds) {
+        launch_batch(djobs, dorder + n_lds, count - n_lds, dcounter + 64, std::min(cus * wpc, count - n_lds), R.s[0]);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return fail(h0, LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
     return LP_OK;
 }
 
-// Waits for the persistent launch (also after an error elsewhere: its kernels must have
+// Waits for the persistent launches (also after an error elsewhere: their kernels must have
 // ended before their memory goes) and collects the results when `collect`.
 int32_t finish_persistent(const std::vector<lp_handle*>& hs, PersistentRun& R, bool collect) {
-    hipError_t e = R.s ? hipStreamSynchronize(R.s) : hipSuccess;
+    hipError_t e = hipSuccess;
+    for (hipStream_t st : R.s)
+        if (st) {
+            const hipError_t e1 = hipStreamSynchronize(st);
+            if (e == hipSuccess) e = e1;
+        }
     if (R.buf) (void)hipFree(R.buf);
     R.buf = nullptr;
     int32_t rc = LP_OK;
     if (e != hipSuccess) rc = fail(hs[0], LP_ERR_DEVICE, std::string("batched solve: ") + hipGetErrorString(e));
-    else if (collect) rc = finish_batch(hs, R.s);
-    if (R.s) (void)hipStreamDestroy(R.s);
-    R.s = nullptr;
+    else if (collect) rc = finish_batch(hs, R.s[0]);
+    for (hipStream_t& st : R.s) {
+        if (st) (void)hipStreamDestroy(st);
+        st = nullptr;
+    }
     return rc;
 }
 
@@ -1479,6 +1511,7 @@ void lp_default_options(lp_options* o) {
     o->units_per_cu = 4;
     o->batch_wg_per_cu = 3;
     o->batch_split_nnz = 20000;
+    o->small_lp_lds = kSmallLpLdsMax;
     o->panel_slice_bytes = int64_t(1) << 19;
     o->x0 = nullptr;
     o->y0 = nullptr;

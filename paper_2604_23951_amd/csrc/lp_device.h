@@ -194,7 +194,12 @@ void launch_to_float(const double* src, float* dst, long long n, hipStream_t s);
 void launch_materialize(const DevLP& P, hipStream_t s);
 // Batched form: `grid` workgroups take LPs jobs[order[0]], jobs[order[1]], ... from the
 // device counter (which must start at 0) and each solves one LP at a time, entirely on chip.
-void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s);
+// lds_cap > 0: each workgroup holds lds_cap bytes of LDS (at most kSmallLpLdsMax) and solves an LP
+// from LDS when small_lp_lds_bytes(LP) <= lds_cap (bit-identical result, lower latency).
+constexpr int kSmallLpLdsMax = 128 * 1024;
+void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s,
+                  int lds_cap = 0);
+size_t small_lp_lds_bytes(const DevLP& P);
 
 // Allocation-free batched form: the job table, LP order and work counter of at most
 // kStaticBatchMax LPs live in a file-scope device array of the kernel source (one copy per

@@ -1663,8 +1663,8 @@ __device__ void wg_kkt(const DevLP& P, int mode, double* tot, double* red16) {
 // One LP solved by one workgroup: the same restarted, averaged PDHG as the multi-kernel
 // path (same kernels' epilogues, evaluation and decision logic), with the scalar state in
 // LDS and a workgroup barrier between the phases.
-__device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* red, double* red16, double* tot) {
-    const DevLP& P = J.P;
+__device__ void wg_solve(const DevLP& P, const BatchJob& J, Scalars* ssc, double* lds, double* red, double* red16,
+                         double* tot) {
     const int tid = threadIdx.x;
     if (tid == 0) {
         *ssc = *P.sc;
@@ -1757,15 +1757,137 @@ __device__ void wg_solve(const BatchJob& J, Scalars* ssc, double* lds, double* r
     if (tid == 0) *P.sc = *ssc;
 }
 
+// ------------------------------------------------------------- small LPs held in LDS
+// For an LP that fits, the arrays its iterations touch are copied into the workgroup's LDS
+// for the whole solve and a copy of its DevLP points at them (generic pointers, so the same
+// code reads LDS or global memory): both matrices (row pointers, column indices, row tiles and
+// the values of the iteration's precision) and the iteration vectors (FP64 form: c~, x
+// bounds, x, x_avg, x anchor, b~ bounds, y, y_avg, A~x, y anchor, A~x of the anchor,
+// A~x_avg; FP32 form: the correction data and iterates). Everything else (the FP64 values in
+// the FP32 form, the scale factors, the evaluation products, the saved previous point, the
+// outputs, the trace) stays in global memory. The copy is exact and the operations are the
+// same, so the result is bit-identical to the solve from global memory; only the latency of
+// the hot accesses changes. At the end the iterates the host can inspect are copied back.
+struct LdsCarve {
+    char* base;
+    size_t off;
+    template <class T>
+    __host__ __device__ T* take(long long count) {
+        T* p = reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(base) + off);
+        off += (static_cast<size_t>(count > 0 ? count : 1) * sizeof(T) + 15) & ~size_t(15);
+        return p;
+    }
+};
+
+// Lays the staged arrays of G out from `base` and writes their pointers into *L (a copy of
+// G); with base == nullptr only the size is computed. Returns the bytes needed.
+__host__ __device__ inline size_t carve_small_lp(const DevLP& G, DevLP* L, char* base) {
+    LdsCarve c{base, 0};
+    const long long m = G.m, n = G.n, nnz = G.nnz;
+    DevLP D = G;
+    auto mat = [&](Csr& M, long long rows) {
+        M.rp = c.take<int>(rows + 1);
+        M.ci = c.take<int>(nnz);
+        M.tiles = c.take<int>(M.ntiles + 1);
+        if (G.fp32) M.v32 = c.take<float>(nnz);
+        else M.v = c.take<double>(nnz);
+    };
+    mat(D.A.csr, m);
+    mat(D.AT.csr, n);
+    if (G.fp32) {
+        D.d32 = c.take<float>(n);
+        D.lo32 = c.take<float>(n);
+        D.hi32 = c.take<float>(n);
+        D.dx = c.take<float>(n);
+        D.dxa = c.take<float>(n);
+        D.rl32 = c.take<float>(m);
+        D.ru32 = c.take<float>(m);
+        D.yh32 = c.take<float>(m);
+        D.dy = c.take<float>(m);
+        D.dya = c.take<float>(m);
+        D.adx = c.take<float>(m);
+    } else {
+        D.c = c.take<double>(n);
+        D.xl = c.take<double>(n);
+        D.xu = c.take<double>(n);
+        D.x = c.take<double>(n);
+        D.xa = c.take<double>(n);
+        D.xan = c.take<double>(n);
+        D.bl = c.take<double>(m);
+        D.bu = c.take<double>(m);
+        D.y = c.take<double>(m);
+        D.ya = c.take<double>(m);
+        D.ax = c.take<double>(m);
+        D.yan = c.take<double>(m);
+        D.axan = c.take<double>(m);
+        D.axa = c.take<double>(m);
+    }
+    if (L) *L = D;
+    return c.off;
+}
+
+template <class T>
+__device__ inline void lds_copy(T* dst, const T* src, long long count) {
+    for (long long i = threadIdx.x; i < count; i += kBlock) dst[i] = src[i];
+}
+
+// Called by every thread; ends with a barrier. The read-only arrays are copied in; the
+// iteration vectors are written by the solve's own start (initial point, first products,
+// the FP32 form's first refinement) before they are read.
+__device__ void stage_small_lp(const DevLP& G, DevLP* L, char* buf) {
+    if (threadIdx.x == 0) carve_small_lp(G, L, buf);
+    __syncthreads();
+    const long long m = G.m, n = G.n, nnz = G.nnz;
+    lds_copy(const_cast<int*>(L->A.csr.rp), G.A.csr.rp, m + 1);
+    lds_copy(const_cast<int*>(L->A.csr.ci), G.A.csr.ci, nnz);
+    lds_copy(const_cast<int*>(L->A.csr.tiles), G.A.csr.tiles, G.A.csr.ntiles + 1);
+    lds_copy(const_cast<int*>(L->AT.csr.rp), G.AT.csr.rp, n + 1);
+    lds_copy(const_cast<int*>(L->AT.csr.ci), G.AT.csr.ci, nnz);
+    lds_copy(const_cast<int*>(L->AT.csr.tiles), G.AT.csr.tiles, G.AT.csr.ntiles + 1);
+    if (G.fp32) {
+        lds_copy(const_cast<float*>(L->A.csr.v32), G.A.csr.v32, nnz);
+        lds_copy(const_cast<float*>(L->AT.csr.v32), G.AT.csr.v32, nnz);
+    } else {
+        lds_copy(const_cast<double*>(L->A.csr.v), G.A.csr.v, nnz);
+        lds_copy(const_cast<double*>(L->AT.csr.v), G.AT.csr.v, nnz);
+        lds_copy(const_cast<double*>(L->c), G.c, n);
+        lds_copy(const_cast<double*>(L->xl), G.xl, n);
+        lds_copy(const_cast<double*>(L->xu), G.xu, n);
+        lds_copy(const_cast<double*>(L->bl), G.bl, m);
+        lds_copy(const_cast<double*>(L->bu), G.bu, m);
+    }
+    __syncthreads();
+}
+
+// The iterates lp_get_iterates reads, back to global memory. Ends with a barrier.
+__device__ void unstage_small_lp(const DevLP& L, const DevLP& G) {
+    if (G.fp32) {
+        lds_copy(G.dx, L.dx, G.n);
+        lds_copy(G.dxa, L.dxa, G.n);
+        lds_copy(G.dy, L.dy, G.m);
+        lds_copy(G.dya, L.dya, G.m);
+    } else {
+        lds_copy(G.x, L.x, G.n);
+        lds_copy(G.xa, L.xa, G.n);
+        lds_copy(G.y, L.y, G.m);
+        lds_copy(G.ya, L.ya, G.m);
+    }
+    __syncthreads();
+}
+
 // Persistent batched solve. Every workgroup loops: take the next LP from the counter,
-// solve it, until the counter passes `count`; then all of its waves return together.
+// solve it, until the counter passes `count`; then all of its waves return together. With
+// `lds_cap` > 0 the launch holds that many bytes of dynamic LDS per workgroup and an LP
+// whose staged arrays fit is solved from LDS.
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, const int* order, int count,
-                                                        int* counter) {
+                                                        int* counter, int lds_cap) {
+    extern __shared__ __align__(16) char small_lp_lds[];
     __shared__ double lds[kTileNnz];
     __shared__ double red[kBlock / 64];
     __shared__ double red16[(kBlock / 64) * kNT];
     __shared__ double tot[kNT];
     __shared__ Scalars ssc;
+    __shared__ DevLP staged;
     __shared__ int job;
     for (;;) {
         __syncthreads();
@@ -1773,7 +1895,14 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, con
         __syncthreads();
         const int j = job;
         if (j >= count) return;
-        wg_solve(jobs[order[j]], &ssc, lds, red, red16, tot);
+        const BatchJob& J = jobs[order[j]];
+        if (lds_cap > 0 && carve_small_lp(J.P, nullptr, nullptr) <= static_cast<size_t>(lds_cap)) {
+            stage_small_lp(J.P, &staged, small_lp_lds);
+            wg_solve(staged, J, &ssc, lds, red, red16, tot);
+            unstage_small_lp(staged, J.P);
+        } else {
+            wg_solve(J.P, J, &ssc, lds, red, red16, tot);
+        }
     }
 }
 
@@ -2134,10 +2263,21 @@ void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s) {
     }
 }
 
-void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s) {
+void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s,
+                  int lds_cap) {
     if (count <= 0 || grid <= 0) return;
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlock), 0, s, jobs, order, count, counter);
+    if (lds_cap > 0) {
+        static const bool attr = [] {
+            return hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kSmallLpLdsMax) == hipSuccess;
+        }();
+        if (!attr) lds_cap = 0;
+    }
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlock), static_cast<size_t>(lds_cap), s, jobs, order, count,
+                       counter, lds_cap);
 }
+
+size_t small_lp_lds_bytes(const DevLP& P) { return carve_small_lp(P, nullptr, nullptr); }
 
 // ------------------------------------------------------ allocation-free batched form
 // Scratch of lp_solve_batch_static: job table, LP order, work counter. Host code never takes

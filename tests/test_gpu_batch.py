@@ -165,3 +165,31 @@ def test_full_4096_batch_sample_equals_solo():
             (alone,) = lpg.solve_batch([s], eps_rel=1e-4, max_iters=400000, method=lpg.LP_METHOD_HALPERN)
         assert alone.info.iterations == sols[j].info.iterations, j
         assert np.array_equal(alone.x, sols[j].x) and np.array_equal(alone.y, sols[j].y), j
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("method", [0, 1])
+def test_small_lps_from_lds_equal_global(precision, method):
+    """LPs of the persistent launch whose arrays fit the small-LP LDS budget are solved from
+    LDS (a launch of their own): their iterates after a fixed count and their solves equal,
+    bit for bit, the same LPs solved from global memory (small_lp_lds = 0)."""
+    lps = [synth.cfg0(0), synth.cfg3_lp(576), synth.cfg3_lp(3568), synth.transportation(60, np.random.default_rng(4)),
+           synth.cfg3_lp(1, m_max=900)]
+    opts = dict(spmv_layout=1, precision=precision, method=method)
+    out = {}
+    for budget in (0, 128 * 1024):
+        solvers = [lpg.Solver(lp, **opts) for lp in lps]
+        try:
+            lpg.solve_batch(solvers, eps_rel=0.0, max_iters=130, small_lp_lds=budget, **opts)
+            its = [s.iterates() for s in solvers]
+            sols = lpg.solve_batch(solvers, eps_rel=1e-5, max_iters=100000, small_lp_lds=budget, **opts)
+        finally:
+            for s in solvers:
+                s.close()
+        out[budget] = (its, sols)
+    (ia, sa), (ib, sb) = out[0], out[128 * 1024]
+    for j, lp in enumerate(lps):
+        for u, v in zip(ia[j], ib[j]):
+            assert np.array_equal(u, v), (lp.name, "iterates")
+        assert sa[j].status == sb[j].status and sa[j].info.iterations == sb[j].info.iterations, lp.name
+        assert np.array_equal(sa[j].x, sb[j].x) and np.array_equal(sa[j].y, sb[j].y) and np.array_equal(sa[j].z, sb[j].z)
