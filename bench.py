@@ -13,6 +13,12 @@ decision. `value` is PDHG iterations per second with the problem resident in HBM
 
 The per-kernel durations of the primal and the dual kernel are measured with HIP events
 on the solver stream during the timed region (one sampled iteration per step).
+
+The default run adds the rest of the metric as extra keys of the same JSON line, each leg
+bounded in time: `small_lp` (the latency-bound 200 x 400 LP, microseconds per iteration),
+`batch` (a 256-LP sample of the 4096-LP batch to E_rel 1e-4: LPs/s against the per-LP FP64
+loop on the same GPU) and `serving` (Poisson arrivals at 2000/s for 20 s: LPs/s, and p50/p99
+latency at half that throughput), each with its own CPU baseline.
 """
 from __future__ import annotations
 
@@ -96,19 +102,21 @@ def run_cpu_baseline_batch(lps, method: int, budget_s: float = 20.0) -> dict:
                       f"method, setup included, {spent:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
 
 
-def run_batch(args) -> int:
-    """Batched workload: LPs j of the 4096-LP batch (m log-uniform in [50, 5000], n = 2m,
-    random-sparse with density U[0.5%, 5%] for even j, transportation for odd j), solved
-    to E_rel 1e-4 in one persistent launch in the FP32 storage form, against the plain
-    per-LP FP64 lp_solve loop on the same GPU (on a sub-sample)."""
+def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budget_s: float = 0.0) -> dict:
+    """Batched workload: `count` LPs of the 4096-LP batch (every (4096 / count)-th; m
+    log-uniform in [50, 5000], n = 2m, random-sparse with density U[0.5%, 5%] for even j,
+    transportation for odd j), solved to E_rel 1e-4 together (one persistent launch for the
+    small LPs beside block-diagonal launches for the large ones) in the FP32 storage form,
+    against the plain per-LP FP64 lp_solve loop on the same GPU (a sub-sample) and, with a
+    budget, the oracle on the host."""
     import numpy as np
 
     import paper_2604_23951_amd as lpg
     import synth
 
     total = 4096
-    stride = max(1, total // args.batch_count)
-    ids = list(range(0, total, stride))[: args.batch_count]
+    stride = max(1, total // count)
+    ids = list(range(0, total, stride))[:count]
     t0 = time.time()
     lps = [synth.cfg3_lp(j) for j in ids]
     gen_s = time.time() - t0
@@ -116,27 +124,32 @@ def run_batch(args) -> int:
     print(f"[bench] generated {len(lps)} LPs (nnz total {nnz.sum():.3e}, max {nnz.max()}) in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
     t1 = time.time()
-    meth = method_of(args, "halpern")
-    solvers = [lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED, method=meth) for lp in lps]
+    solvers = [lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED, method=method) for lp in lps]
     create_s = time.time() - t1
     print(f"[bench] created {len(solvers)} handles in {create_s:.1f}s", file=sys.stderr, flush=True)
-    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64, method=meth)  # warm-up launch
+    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64, method=method)  # warm-up launch
     t2 = time.perf_counter()
-    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth)
+    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=max_iters, method=method)
     dt = time.perf_counter() - t2
     ok = sum(s.status == "optimal" for s in sols)
     iters = np.array([s.info.iterations for s in sols])
+    # per-LP completion instants on the device clock, relative to the first LP to finish
+    done = np.array([s.info.done_clock for s in sols], dtype=np.float64)
+    hz = sols[0].info.clock_hz or 1e8
+    rel = (done - done.min()) / hz
+    hist, _ = np.histogram(rel / max(rel.max(), 1e-12), bins=10, range=(0.0, 1.0))
     print(f"[bench] batch: {len(sols)} LPs in {dt:.2f}s ({len(sols) / dt:.1f} LPs/s), {ok} optimal, "
-          f"iterations median {int(np.median(iters))} max {iters.max()}", file=sys.stderr, flush=True)
+          f"iterations median {int(np.median(iters))} max {iters.max()}; completions (s after the first) "
+          f"p50 {np.percentile(rel, 50):.3f} p90 {np.percentile(rel, 90):.3f} p99 {np.percentile(rel, 99):.3f} "
+          f"max {rel.max():.3f}", file=sys.stderr, flush=True)
     for s in solvers:
         s.close()
     # plain per-LP FP64 loop on a sub-sample
-    sub = lps[:: max(1, len(lps) // args.loop_count)][: args.loop_count]
+    sub = lps[:: max(1, len(lps) // loop_count)][:loop_count]
     loop_t = 0.0
     loop_ok = 0
     for lp in sub:
-        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth,
-                        spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=max_iters, method=method, spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
             t3 = time.perf_counter()
             r = s1.solve()
             loop_t += time.perf_counter() - t3
@@ -144,28 +157,48 @@ def run_batch(args) -> int:
     loop_rate = loop_ok / loop_t if loop_t > 0 else float("nan")  # LPs that reached 1e-4
     print(f"[bench] per-LP FP64 loop: {len(sub)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
           file=sys.stderr, flush=True)
-    result = {
+    out = {
         # LPs that reached E_rel 1e-4 per second of the batched solve
-        "metric": METRIC, "value": ok / dt, "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": ("batched LPs to E_rel 1e-4: the 4096-LP batch " if len(lps) == total else
-                                f"batched LPs to E_rel 1e-4: every {stride}th LP of the 4096-LP batch ") +
-                               "(m log-uniform [50,5000], n=2m, random-sparse density U[0.5%,5%] / transportation "
-                               "50/50), FP32 storage form with FP64 evaluation and refinement, one persistent launch",
-                   "method": {v: k for k, v in METHODS.items()}[meth],
-                   "lps": len(sols), "nnz_total": int(nnz.sum()), "optimal": ok,
-                   "iterations_median": int(np.median(iters)), "iterations_max": int(iters.max())},
+        "lps_per_s": ok / dt, "seconds": dt,
+        "workload": ("batched LPs to E_rel 1e-4: the 4096-LP batch " if len(lps) == total else
+                     f"batched LPs to E_rel 1e-4: every {stride}th LP of the 4096-LP batch ") +
+                    "(m log-uniform [50,5000], n=2m, random-sparse density U[0.5%,5%] / transportation "
+                    "50/50), FP32 storage form with FP64 evaluation and refinement",
+        "method": {v: k for k, v in METHODS.items()}[method],
+        "lps": len(sols), "nnz_total": int(nnz.sum()), "optimal": ok,
+        "iterations_median": int(np.median(iters)), "iterations_p99": float(np.percentile(iters, 99)),
+        "iterations_max": int(iters.max()),
+        "completion_s_after_first": {"p50": float(np.percentile(rel, 50)), "p90": float(np.percentile(rel, 90)),
+                                     "p99": float(np.percentile(rel, 99)), "max": float(rel.max()),
+                                     "histogram_tenths_of_span": hist.tolist()},
         "per_lp_fp64_loop": {"lps": len(sub), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok,
                              "method": "same as the batch", "layout": "tuned per LP"},
         "speedup_vs_per_lp_loop": (ok / dt) / loop_rate,
         "create_s": create_s,
+        "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
+    if cpu_budget_s > 0:
         print("[bench] cpu baseline: oracle on the first LPs of the batch", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = run_cpu_baseline_batch(lps, meth)
-    else:
-        result["cpu_baseline"] = None
+        out["cpu_baseline"] = run_cpu_baseline_batch(lps, method, cpu_budget_s)
+    return out
+
+
+def run_batch(args) -> int:
+    """The batched workload alone (--workload batch): one JSON line with LPs/s as `value`."""
+    meth = method_of(args, "halpern")
+    leg = leg_batch(args.batch_count, args.loop_count, args.batch_max_iters, meth,
+                    0.0 if args.no_cpu_baseline else 20.0)
+    result = {
+        "metric": METRIC, "value": leg["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": leg["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": leg["workload"], "method": leg["method"], "lps": leg["lps"],
+                   "nnz_total": leg["nnz_total"], "optimal": leg["optimal"],
+                   "iterations_median": leg["iterations_median"], "iterations_max": leg["iterations_max"]},
+        "completion_s_after_first": leg["completion_s_after_first"],
+        "per_lp_fp64_loop": leg["per_lp_fp64_loop"], "speedup_vs_per_lp_loop": leg["speedup_vs_per_lp_loop"],
+        "create_s": leg["create_s"], "cpu_baseline": leg["cpu_baseline"],
+    }
     print(json.dumps(result), flush=True)
     return 0
 
@@ -213,11 +246,76 @@ def run_blockdiag(args) -> int:
     return 0
 
 
-def run_serve(args) -> int:
+def simulate_mgc(service, rate: float, seconds: float, servers: int, seed: int) -> dict:
+    """First-come first-served queue with `servers` servers: Poisson arrivals at `rate` for
+    `seconds`, service times drawn at random from `service`. Returns the completions inside
+    the window per second and the latency percentiles of every arrival of the window (run to
+    completion)."""
+    import heapq
+    import random
+
+    import numpy as np
+
+    rng = random.Random(seed)
+    free = [0.0] * servers
+    t, lat, in_window = 0.0, [], 0
+    while t < seconds:
+        s = service[rng.randrange(len(service))]
+        start = max(t, heapq.heappop(free))
+        heapq.heappush(free, start + s)
+        lat.append(start + s - t)
+        in_window += start + s <= seconds
+        t += rng.expovariate(rate)
+    lat = np.array(lat) if lat else np.array([np.nan])
+    return {"lps_per_s": in_window / seconds, "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)), "arrivals": len(lat)}
+
+
+def cpu_serving_baseline(pool, requests, rate: float, seconds: float, method: int, budget_s: float) -> dict:
+    """The oracle as the host's server, simulated: its rate in nonzero-iterations per second is
+    measured on 8 LPs spread over the pool's size range (same method, single-threaded, each
+    for about budget_s / 8 seconds of iterations); each completed GPU request of the drained
+    phase (its LP's nnz and the iterations it needed) then gets the service time
+    iterations * nnz / that rate, and an M/G/c queue with c = the host's cores serves Poisson
+    arrivals at `rate` (saturated) and at half the simulated capacity (latency)."""
+    import numpy as np
+
+    import oracle
+
+    order = sorted(range(len(pool)), key=lambda j: pool[j].nnz)
+    picks = [order[round(q * (len(order) - 1) / 7)] for q in range(8)]
+    work = spent = 0.0
+    for j in picks:
+        # about budget_s / 8 seconds each at ~2.5e8 nonzero-iterations per second
+        its = int(max(64, min(20000, budget_s / 8 * 2.5e8 / max(pool[j].nnz, 1))))
+        r = oracle.solve(pool[j], eps_rel=0.0, max_iters=its, method=method)
+        work += float(r.iters) * pool[j].nnz
+        spent += r.iter_s
+    solved = len(picks)
+    per_s = work / spent
+    service = [it * pool[j].nnz / per_s for j, it in requests]
+    cores = os.cpu_count() or 1
+    sat = simulate_mgc(service, rate, seconds, cores, 11)
+    cap = cores / float(np.mean(service))
+    sub = simulate_mgc(service, 0.5 * cap, seconds, cores, 12)
+    return {"value": sat["lps_per_s"], "unit": "LPs/s", "cores": cores, "kind": "oracle",
+            "simulated": True, "latency_p50_s": sub["latency_p50_s"], "latency_p99_s": sub["latency_p99_s"],
+            "latency_offered_lps_per_s": 0.5 * cap,
+            "sample": f"simulated: the oracle ran {solved} pool LPs spread over its size range for {spent:.1f} s "
+                      f"({per_s:.3g} nnz-iterations/s on one core of '{cpu_model()}'); service time of each of "
+                      f"the {len(service)} requests of the GPU's drained phase = its iterations x nnz / that rate; "
+                      f"M/G/{cores} first-come first-served queue, Poisson arrivals at {rate}/s for {seconds}s "
+                      f"(LPs/s) and at half the simulated capacity (p50/p99)"}
+
+
+def leg_serve(pool_size: int, rate: float, seconds: float, sub_seconds: float, drain_seconds: float,
+              hbm_budget_gb: int, slots: int, max_iters: int, method: int, loop_count: int,
+              cpu_budget_s: float = 0.0) -> dict:
     """Serving workload: Poisson arrivals drawn from a pre-generated pool of LPs
     (m log-uniform on [100, 2e5], n = 1.5m, 3-20 nonzeros per row, KKT-constructed),
     FP32 storage form with FP64 evaluation and refinement, to E_rel 1e-4; continuous
-    batching with admission by device footprint."""
+    batching with admission by device footprint. A saturated phase at `rate` gives LPs/s;
+    a second phase at half that throughput, drained, gives the latency percentiles."""
     import random
 
     import numpy as np
@@ -226,21 +324,20 @@ def run_serve(args) -> int:
     import synth
 
     t0 = time.time()
-    pool = [synth.cfg4_lp(j) for j in range(args.pool)]
+    pool = [synth.cfg4_lp(j) for j in range(pool_size)]
     nnz = np.array([lp.nnz for lp in pool])
-    meth = method_of(args, "halpern")
-    tmpl = [lpg.Solver(lp, spmv_layout=1, deferred=1, precision=lpg.LP_PREC_FP32_REFINED, method=meth) for lp in pool]
+    tmpl = [lpg.Solver(lp, spmv_layout=1, deferred=1, precision=lpg.LP_PREC_FP32_REFINED, method=method)
+            for lp in pool]
     print(f"[bench] pool of {len(pool)} LPs (mean nnz {nnz.mean():.3g}, max {nnz.max()}) ready in "
           f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     def phase(rate, seconds, seed, drain):
         """Poisson arrivals at `rate` for `seconds`; with `drain`, keep serving (no new
         arrivals) until every request submitted in the window has completed, at most
-        args.drain_seconds more, so that latency covers the whole window."""
+        drain_seconds more, so that latency covers the whole window."""
         rng = random.Random(seed)
-        srv = lpg.Server(args.hbm_budget_gb * 2**30, args.slots, eps_rel=1e-4, max_iters=args.batch_max_iters,
-                         method=meth)
-        tickets = []
+        srv = lpg.Server(hbm_budget_gb * 2**30, slots, eps_rel=1e-4, max_iters=max_iters, method=method)
+        tickets = {}
         start = time.perf_counter()
         t_next = 0.0
         done = []
@@ -249,7 +346,8 @@ def run_serve(args) -> int:
             if now >= seconds:
                 break
             if now >= t_next:
-                tickets.append(srv.submit(tmpl[rng.randrange(len(tmpl))]))
+                j = rng.randrange(len(tmpl))
+                tickets[srv.submit(tmpl[j])] = j
                 t_next += rng.expovariate(rate)
                 continue
             done += srv.poll()
@@ -258,20 +356,20 @@ def run_serve(args) -> int:
         in_window = len(done)
         st_window = srv.stats()
         if drain:
-            while len(done) < len(tickets) and time.perf_counter() - start < seconds + args.drain_seconds:
+            while len(done) < len(tickets) and time.perf_counter() - start < seconds + drain_seconds:
                 time.sleep(0.002)
                 done += srv.poll()
         span = time.perf_counter() - start
         st = srv.stats()
-        lat = []
-        wait = []
-        status = []
+        lat, wait, status, reqs = [], [], [], []
         for t in done:
             ts, ta, td = srv.times(t)
             lat.append(td - ts)
             wait.append(ta - ts)
             try:
-                status.append(srv.result(t).status)
+                r = srv.result(t)
+                status.append(r.status)
+                reqs.append((tickets[t], int(r.info.iterations)))
             except lpg.LpError:  # the request could not be set up on the device
                 status.append("failed")
         srv.close()
@@ -294,16 +392,16 @@ def run_serve(args) -> int:
                 "backlog_at_window_end": st_window["queued"] + st_window["running"], "rounds": st["rounds"],
                 "peak_device_bytes": st["peak_bytes"],
                 "nnz_iterations_per_s": wsec, "matrix_stream_GBps": 16 * wsec / 1e9,
-                "lp_iterations_per_s": st_window["lp_iterations"] / seconds}
+                "lp_iterations_per_s": st_window["lp_iterations"] / seconds}, reqs
 
-    full = phase(args.rate, args.serve_seconds, 1, False)
-    print(f"[bench] offered {args.rate}/s: {full['lps_per_s']:.1f} LPs/s to 1e-4 ({full['completed_in_window']} "
+    full, _ = phase(rate, seconds, 1, False)
+    print(f"[bench] offered {rate}/s: {full['lps_per_s']:.1f} LPs/s to 1e-4 ({full['completed_in_window']} "
           f"completed), p50 {full['latency_p50_s']:.3f}s, "
           f"p99 {full['latency_p99_s']:.3f}s, backlog {full['backlog_at_window_end']}, "
           f"{full['nnz_iterations_per_s']:.3g} nnz-it/s ({full['matrix_stream_GBps']:.0f} GB/s of A)",
           file=sys.stderr, flush=True)
     sub_rate = max(0.5, 0.5 * full["lps_per_s"])
-    sub = phase(sub_rate, args.sub_seconds, 2, True)
+    sub, sub_reqs = phase(sub_rate, sub_seconds, 2, True)
     print(f"[bench] offered {sub_rate:.2f}/s: {sub['completed']}/{sub['submitted']} completed (drained "
           f"{sub['drained']}), p50 {sub['latency_p50_s']:.3f}s, p99 {sub['latency_p99_s']:.3f}s, "
           f"{sub['nnz_iterations_per_s']:.3g} nnz-it/s", file=sys.stderr, flush=True)
@@ -311,12 +409,11 @@ def run_serve(args) -> int:
         t.close()
     # plain per-LP FP64 loop: every 12th LP of the pool (the pool is drawn at random), same
     # method and tolerance, lp_solve one after another on the same GPU
-    sub_lps = pool[::12][: args.loop_count]
+    sub_lps = pool[::12][:loop_count]
     loop_t = 0.0
     loop_ok = 0
     for lp in sub_lps:
-        with lpg.Solver(lp, eps_rel=1e-4, max_iters=args.batch_max_iters, method=meth,
-                        spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=max_iters, method=method, spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
             t3 = time.perf_counter()
             r = s1.solve()
             loop_t += time.perf_counter() - t3
@@ -324,27 +421,88 @@ def run_serve(args) -> int:
     loop_rate = loop_ok / loop_t if loop_t > 0 else float("nan")  # LPs that reached 1e-4
     print(f"[bench] per-LP FP64 loop: {len(sub_lps)} LPs in {loop_t:.2f}s ({loop_rate:.2f} LPs/s)",
           file=sys.stderr, flush=True)
-    result = {
-        "metric": METRIC, "value": full["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": args.serve_seconds * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": f"serving: Poisson arrivals at {args.rate}/s for {args.serve_seconds}s from a pool of "
-                               f"{len(pool)} LPs (m log-uniform [100, 2e5], n=1.5m, 3-20 nnz/row), FP32 storage "
-                               f"form + FP64 refinement to E_rel 1e-4, continuous batching, HBM budget "
-                               f"{args.hbm_budget_gb} GiB, {args.slots} slots",
-                   "pool_mean_nnz": float(nnz.mean()), "method": {v: k for k, v in METHODS.items()}[meth]},
+    out = {
+        "lps_per_s": full["lps_per_s"],
+        "workload": f"serving: Poisson arrivals at {rate}/s for {seconds}s from a pool of {len(pool)} LPs "
+                    f"(m log-uniform [100, 2e5], n=1.5m, 3-20 nnz/row), FP32 storage form + FP64 refinement to "
+                    f"E_rel 1e-4, continuous batching, HBM budget {hbm_budget_gb} GiB, {slots} slots",
+        "pool_mean_nnz": float(nnz.mean()), "method": {v: k for k, v in METHODS.items()}[method],
         # latency of every request of the half-load window (drained); under saturation the
         # queue grows without bound and only early, small requests complete in the window
         "latency_p50_s": sub["latency_p50_s"], "latency_p99_s": sub["latency_p99_s"],
         "latency_phase": f"offered {sub_rate:.2f}/s (half the saturated rate), all requests of a "
-                         f"{args.sub_seconds}s window",
+                         f"{sub_seconds}s window",
         "saturated": full, "sub_saturation": sub,
         "per_lp_fp64_loop": {"lps": len(sub_lps), "seconds": loop_t, "lps_per_s": loop_rate, "optimal": loop_ok,
                              "method": "same as the server", "layout": "tuned per LP"},
         "speedup_vs_per_lp_loop": full["lps_per_s"] / loop_rate,
+        "cpu_baseline": None,
     }
+    if cpu_budget_s > 0 and sub_reqs:
+        print("[bench] cpu baseline: oracle service rate on the pool, M/G/c simulation", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_serving_baseline(pool, sub_reqs, rate, seconds, method, cpu_budget_s)
+    return out
+
+
+def run_serve(args) -> int:
+    """The serving workload alone (--workload serve): one JSON line with LPs/s as `value`."""
+    leg = leg_serve(args.pool, args.rate, args.serve_seconds, args.sub_seconds, args.drain_seconds,
+                    args.hbm_budget_gb, args.slots, args.batch_max_iters, method_of(args, "halpern"),
+                    args.loop_count, 0.0 if args.no_cpu_baseline else 20.0)
+    result = {
+        "metric": METRIC, "value": leg["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": args.serve_seconds * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": leg["workload"], "pool_mean_nnz": leg["pool_mean_nnz"], "method": leg["method"]},
+    }
+    result.update({k: v for k, v in leg.items() if k not in ("workload", "pool_mean_nnz", "method", "lps_per_s")})
     print(json.dumps(result), flush=True)
     return 0
+
+
+def leg_small_lp(cpu: bool) -> dict:
+    """The small LP (m = 200, n = 400, 2% density, KKT-constructed), 5000 FP64 iterations with
+    eps 0 and restarts active: its working set (~80 KB) sits in the caches, so it is bound by
+    latency, not HBM; reported as microseconds per iteration for lp_solve (hipGraph bundles of
+    64 iterations) and for the one-workgroup persistent launch (a batch of one), and the
+    oracle's iterations per second on one host core."""
+    import numpy as np
+
+    import paper_2604_23951_amd as lpg
+    import synth
+
+    lp = synth.cfg0(0)
+    iters = 5000
+    out = {"workload": "small LP m=200 n=400 (2% density, KKT-constructed), FP64, 5000 iterations, eps 0",
+           "iterations": iters, "bound": "latency (working set in cache)"}
+    for name, layout in (("lp_solve_us_per_iter", 0), ("lp_solve_tiles_us_per_iter", 1)):
+        with lpg.Solver(lp, eps_rel=0.0, max_iters=iters, spmv_layout=layout) as s:
+            s.solve()
+            ts = []
+            for _ in range(3):
+                t = time.perf_counter()
+                s.solve()
+                ts.append(time.perf_counter() - t)
+        out[name] = float(np.median(ts)) / iters * 1e6
+    with lpg.Solver(lp, spmv_layout=1) as s:
+        lpg.solve_batch([s], eps_rel=0.0, max_iters=iters)
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            lpg.solve_batch([s], eps_rel=0.0, max_iters=iters)
+            ts.append(time.perf_counter() - t)
+    out["one_workgroup_us_per_iter"] = float(np.median(ts)) / iters * 1e6
+    print(f"[bench] small LP: lp_solve {out['lp_solve_us_per_iter']:.1f} us/it, one workgroup "
+          f"{out['one_workgroup_us_per_iter']:.1f} us/it", file=sys.stderr, flush=True)
+    out["cpu_baseline"] = None
+    if cpu:
+        import oracle
+
+        r = oracle.solve(lp, eps_rel=0.0, max_iters=iters, scaling=True)
+        out["cpu_baseline"] = {"value": iters / r.iter_s, "unit": "iters/s", "cores": 1, "kind": "oracle",
+                               "us_per_iter": r.iter_s / iters * 1e6,
+                               "sample": f"the same 5000 iterations on one core of '{cpu_model()}'"}
+    return out
 
 
 def run_presolve(args) -> int:
@@ -471,6 +629,11 @@ def main(argv=None):
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--loop-count", type=int, default=8)
     ap.add_argument("--batch-max-iters", type=int, default=400000)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="large LP only (skip the small-LP, batch-sample and serving legs of the default run)")
+    ap.add_argument("--leg-batch-count", type=int, default=256)
+    ap.add_argument("--leg-serve-seconds", type=float, default=20.0)
+    ap.add_argument("--leg-sub-seconds", type=float, default=15.0)
     ap.add_argument("--slice-bytes", type=int, default=0)
     ap.add_argument("--units-per-cu", type=int, default=0)
     ap.add_argument("--long-row-len", type=int, default=0)
@@ -646,6 +809,17 @@ def main(argv=None):
         result["cpu_baseline"] = run_cpu_baseline(lp, args.cpu_iters)
     else:
         result["cpu_baseline"] = None
+    del lp
+    if not args.no_legs:
+        # the rest of the metric, each bounded so that the whole run stays within minutes:
+        # the latency-bound small LP, a sample of the batch and a shorter serving window
+        cpu = not args.no_cpu_baseline
+        meth = method_of(args, "halpern")
+        result["small_lp"] = leg_small_lp(cpu)
+        result["batch"] = leg_batch(args.leg_batch_count, 8, args.batch_max_iters, meth, 10.0 if cpu else 0.0)
+        result["serving"] = leg_serve(args.pool, args.rate, args.leg_serve_seconds, args.leg_sub_seconds, 30.0,
+                                      args.hbm_budget_gb, args.slots, args.batch_max_iters, meth, 4,
+                                      10.0 if cpu else 0.0)
     print(json.dumps(result), flush=True)
     return 0
 

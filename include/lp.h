@@ -132,7 +132,7 @@ typedef struct lp_options {
     int32_t deferred;      /* 1: lp_create validates and prepares on the host only; device memory is
                               allocated (and the setup run) when the LP is first solved or admitted
                               by a server, and released by the server when it completes (default 0) */
-    int32_t small_lp_lds;  /* lp_solve_batch: bytes of LDS per workgroup (0 to 131072, default 131072)
+    int32_t small_lp_lds;  /* lp_solve_batch: bytes of LDS per workgroup (0 to 114688, default 114688)
                               for LPs held on chip: an LP of the persistent launch whose matrices and
                               iteration vectors (in its precision) fit is solved from LDS by a
                               launch of its own (one workgroup per CU), bit-identical to the solve
@@ -155,6 +155,14 @@ typedef struct lp_options {
     int32_t pw_rule;       /* lp_primal_weight_rule of the update at a restart (default 0) */
     int32_t pad4;
     double pid_kp, pid_ki, pid_kd; /* gains of LP_PW_PID (defaults 0.7, 0.05, 0.2), each in [0, 2] */
+    int32_t tile_nnz;      /* row-tile shape of the row-tile products (lp_solve with spmv_layout 1 or
+                              2, lp_solve_batch, servers): 1024, 2048 or 4096 nonzeros per tile (and
+                              a quarter as many rows), or 0 (default) for the shape the tuned table
+                              gives this LP's precision, mean row length and size (the table is
+                              written by paper_2604_23951_amd/tune_tiles.py on the device). A row
+                              longer than the tile is reduced by a workgroup of its own, so the
+                              shape decides which rows are summed by a tree */
+    int32_t pad5;
 } lp_options;
 
 /* Primal-weight update at a restart, from the distances dx, dy the restart point moved
@@ -182,6 +190,10 @@ typedef struct lp_info {
     double omega;          /* final primal weight */
     double setup_seconds;  /* lp_create: upload, transpose, scaling, norm estimate */
     double solve_seconds;  /* last lp_solve */
+    int64_t done_clock;    /* the device's wall clock when this LP's solve stopped (in a batch:
+                              each LP's own instant); ticks of clock_hz, comparable across the
+                              LPs of one device */
+    double clock_hz;       /* rate of that clock */
 } lp_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -438,7 +450,8 @@ int32_t lp_get_kernel_times(lp_handle *h, double *primal_ms, double *dual_ms, in
  * [6] = wave units of A^T, [7] = column panels of A, [8] = column panels of A^T,
  * [9] = layout of the products (0 panels, 1 row tiles; -1 before the handle is on the
  * device), [10] / [11] = the layout tuner's time in nanoseconds of one A x + A^T y pair in
- * panels / row tiles (0 unless spmv_layout is 2). */
+ * panels / row tiles (0 unless spmv_layout is 2), [12] = nonzeros per row tile (the shape
+ * chosen from tile_nnz or the tuned table). */
 int32_t lp_get_layout(lp_handle *h, int64_t *sizes, int32_t cap);
 
 #ifdef __cplusplus

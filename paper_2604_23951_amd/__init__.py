@@ -65,6 +65,7 @@ class lp_options(C.Structure):
         ("method", C.c_int32), ("pad2", C.c_int32), ("reflection", C.c_double),
         ("omega_steps", C.c_int32), ("pad3", C.c_int32), ("pw_rule", C.c_int32), ("pad4", C.c_int32),
         ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
+        ("tile_nnz", C.c_int32), ("pad5", C.c_int32),
     ]
 
 
@@ -93,7 +94,7 @@ class lp_info(C.Structure):
         ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_primal_res", C.c_double),
         ("rel_dual_res", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double), ("sigma_max", C.c_double),
         ("step_size", C.c_double), ("omega", C.c_double), ("setup_seconds", C.c_double),
-        ("solve_seconds", C.c_double),
+        ("solve_seconds", C.c_double), ("done_clock", C.c_int64), ("clock_hz", C.c_double),
     ]
 
 
@@ -282,10 +283,10 @@ def lp_get_kernel_times(h):
 
 
 def lp_get_layout(h):
-    out = np.zeros(12, np.int64)
-    _check(lib().lp_get_layout(h, _p(out), 12), h)
+    out = np.zeros(13, np.int64)
+    _check(lib().lp_get_layout(h, _p(out), 13), h)
     keys = ("tiles_a", "tiles_at", "long_rows_a", "long_rows_at", "device_bytes", "units_a", "units_at",
-            "panels_a", "panels_at", "layout", "trial_ns_panels", "trial_ns_tiles")
+            "panels_a", "panels_at", "layout", "trial_ns_panels", "trial_ns_tiles", "tile_nnz")
     return {k: int(v) for k, v in zip(keys, out)}
 
 

@@ -25,6 +25,7 @@
 #include "lp_device.h"
 #include "lp_layout.h"
 #include "lp_check.h"
+#include "lp_tile_table.h"
 
 using namespace lpgpu;
 
@@ -42,9 +43,10 @@ struct Arena {
     }
 };
 
-// Row tiles for the LDS-staged SpMV: consecutive rows while the tile holds at most kTileNnz
-// nonzeros and kTileRows rows; a row longer than kTileNnz is a tile of its own.
-std::vector<int32_t> build_tiles(int32_t rows, const int32_t* rp, int64_t* n_long) {
+// Row tiles for the LDS-staged SpMV: consecutive rows while the tile holds at most tn
+// nonzeros and tn / 4 rows; a row longer than tn is a tile of its own.
+std::vector<int32_t> build_tiles(int32_t rows, const int32_t* rp, int32_t tn, int64_t* n_long) {
+    const int32_t tile_rows = tn / 4;
     std::vector<int32_t> t;
     t.reserve(static_cast<size_t>(rows) / 64 + 2);
     t.push_back(0);
@@ -53,14 +55,14 @@ std::vector<int32_t> build_tiles(int32_t rows, const int32_t* rp, int64_t* n_lon
     while (r < rows) {
         const int32_t start = r;
         const int64_t len = rp[r + 1] - rp[r];
-        if (len > kTileNnz) {
+        if (len > tn) {
             ++r;
             ++nl;
         } else {
             int64_t nz = 0;
-            while (r < rows && r - start < kTileRows) {
+            while (r < rows && r - start < tile_rows) {
                 const int64_t l = rp[r + 1] - rp[r];
-                if (l > kTileNnz || nz + l > kTileNnz) break;
+                if (l > tn || nz + l > tn) break;
                 nz += l;
                 ++r;
             }
@@ -75,6 +77,7 @@ std::vector<int32_t> build_tiles(int32_t rows, const int32_t* rp, int64_t* n_lon
 struct Prep {
     std::vector<int32_t> rpT, ciT, perm, tA, tAT;
     PanelLayoutHost LA, LAT;
+    int shape = 1;  // row-tile shape
     bool panels = false;
     int nred = 1;
     bool ready = false;
@@ -182,6 +185,7 @@ struct lp_handle {
     double c0 = 0.0;
     int64_t long_a = 0, long_at = 0;
     int64_t units_a = 0, units_at = 0, panels_a = 0, panels_at = 0;
+    int tile_shape = 1;  // row-tile shape chosen at lp_create
     double trial_us[2] = {0.0, 0.0};  // layout tuner's times (panels, row tiles)
     char* arena = nullptr;
     size_t arena_bytes = 0;
@@ -238,6 +242,7 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
         o.trace_cap < 0 || o.precision < LP_PREC_FP64 || o.precision > LP_PREC_FP32_REFINED || o.spmv_layout < 0 || o.spmv_layout > 2 ||
         o.long_row_len < 0 || o.units_per_cu < 0 || o.batch_wg_per_cu < 0 || o.batch_split_nnz < 0 || o.panel_slice_bytes < 0 || std::isnan(o.step_size) || std::isnan(o.omega0) ||
         o.small_lp_lds < 0 || o.small_lp_lds > kSmallLpLdsMax ||
+        !(o.tile_nnz == 0 || o.tile_nnz == 1024 || o.tile_nnz == 2048 || o.tile_nnz == 4096) ||
         std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
         o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0) || o.omega_steps < 0 ||
         o.omega_steps > 8 || o.pw_rule < LP_PW_DEFAULT || o.pw_rule > LP_PW_PID || !(o.pid_kp >= 0.0 && o.pid_kp <= 2.0) ||
@@ -327,6 +332,9 @@ void fill_info(lp_handle* h) {
     inf.sigma_max = sc.sigma_max;
     inf.step_size = sc.eta;
     inf.omega = sc.omega;
+    inf.done_clock = sc.done_clock;
+    int khz = 0;
+    inf.clock_hz = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess ? 1e3 * khz : 0.0;
 }
 
 
@@ -418,13 +426,14 @@ struct DevMaps {
         // the XCD runs below point at it and their workgroups return at once
         std::vector<BatchJob> jobs(static_cast<size_t>(count) + 1);
         std::vector<int2> ma, mat, mred, melem;
-        int off_a[4], cnt_a[4], off_at[4], cnt_at[4];
+        int off_a[kMapGroups], cnt_a[kMapGroups], off_at[kMapGroups], cnt_at[kMapGroups];
         for (int i = 0; i < count; ++i) jobs[i] = make_job(hs[i], o);
-        for (int v = 0; v < 4; ++v) {  // tile maps grouped by form, each in XCD order
+        for (int v = 0; v < kMapGroups; ++v) {  // tile maps grouped by form and shape, each in XCD order
             std::vector<int2> ta, tat;
             for (int i = 0; i < count; ++i) {
                 const lp_handle* h = hs[i];
-                if ((jobs[i].P.fp32 ? 2 : 0) + (jobs[i].P.method ? 1 : 0) != v) continue;
+                const int form = (jobs[i].P.fp32 ? 2 : 0) + (jobs[i].P.method ? 1 : 0);
+                if (form * kTileShapes + jobs[i].P.A.csr.shape != v) continue;
                 for (int t = 0; t < h->P.A.csr.ntiles; ++t) ta.push_back(make_int2(i, t));
                 for (int t = 0; t < h->P.AT.csr.ntiles; ++t) tat.push_back(make_int2(i, t));
             }
@@ -472,7 +481,7 @@ struct DevMaps {
         M.n_a = static_cast<int>(ma.size());
         M.map_at = reinterpret_cast<const int2*>(buf + oat);
         M.n_at = static_cast<int>(mat.size());
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < kMapGroups; ++v) {
             M.off_a[v] = off_a[v];
             M.cnt_a[v] = cnt_a[v];
             M.off_at[v] = off_at[v];
@@ -740,8 +749,11 @@ int32_t host_prep(lp_handle* h, const int32_t* rp, const int32_t* ci) {
             }
     }
     int64_t dummy_long = 0;
-    Q.tA = build_tiles(m, rp, &dummy_long);
-    Q.tAT = build_tiles(n, Q.rpT.data(), &dummy_long);
+    Q.shape = o.tile_nnz > 0 ? (o.tile_nnz == 1024 ? 0 : o.tile_nnz == 2048 ? 1 : 2)
+                             : tuned_tile_shape(o.precision == LP_PREC_FP32_REFINED, m, n, nnz);
+    h->tile_shape = Q.shape;
+    Q.tA = build_tiles(m, rp, tile_nnz_of(Q.shape), &dummy_long);
+    Q.tAT = build_tiles(n, Q.rpT.data(), tile_nnz_of(Q.shape), &dummy_long);
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus < 1)
         cus = 256;
@@ -927,8 +939,8 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.n = n;
     P.nnz = nnz;
     P.nred = Q.nred;
-    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), I(O.arp), I(O.aci), D(O.av), I(O.at), nullptr, nullptr};
-    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), I(O.trp), I(O.tci), D(O.tv), I(O.tt), nullptr, nullptr};
+    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), Q.shape, I(O.arp), I(O.aci), D(O.av), I(O.at), nullptr, nullptr};
+    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), Q.shape, I(O.trp), I(O.tci), D(O.tv), I(O.tt), nullptr, nullptr};
     P.A.layout = P.AT.layout = panels ? 0 : 1;
     auto bind_layout = [&](const PanelLayoutHost& L, const size_t* off, Mat& M) {
         M.pan = Panels{L.units, L.panels, L.col_bits, static_cast<int>(L.nnz_packed), L.max_unit_rows, I(off[0]), I(off[1]),
@@ -1512,6 +1524,7 @@ void lp_default_options(lp_options* o) {
     o->batch_wg_per_cu = 3;
     o->batch_split_nnz = 20000;
     o->small_lp_lds = kSmallLpLdsMax;
+    o->tile_nnz = 0;
     o->panel_slice_bytes = int64_t(1) << 19;
     o->x0 = nullptr;
     o->y0 = nullptr;
@@ -1922,11 +1935,12 @@ int32_t lp_get_kernel_times(lp_handle* h, double* primal_ms, double* dual_ms, in
 
 int32_t lp_get_layout(lp_handle* h, int64_t* sizes, int32_t cap) {
     if (!h || !sizes || cap < 0) return fail(h, LP_ERR_INVALID_ARG, "bad layout arguments");
-    const int64_t v[12] = {h->P.A.csr.ntiles, h->P.AT.csr.ntiles, h->long_a, h->long_at,
+    const int64_t v[13] = {h->P.A.csr.ntiles, h->P.AT.csr.ntiles, h->long_a, h->long_at,
                            static_cast<int64_t>(h->arena_bytes), h->units_a, h->units_at, h->panels_a, h->panels_at,
                            h->on_device ? h->P.A.layout : -1,
-                           static_cast<int64_t>(h->trial_us[0] * 1e3), static_cast<int64_t>(h->trial_us[1] * 1e3)};
-    for (int32_t i = 0; i < cap && i < 12; ++i) sizes[i] = v[i];
+                           static_cast<int64_t>(h->trial_us[0] * 1e3), static_cast<int64_t>(h->trial_us[1] * 1e3),
+                           tile_nnz_of(h->tile_shape)};
+    for (int32_t i = 0; i < cap && i < 13; ++i) sizes[i] = v[i];
     return LP_OK;
 }
 

@@ -9,8 +9,12 @@
 namespace lpgpu {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
-constexpr int kTileNnz = 2048;    // nonzeros staged in LDS per SpMV tile
-constexpr int kTileRows = 512;    // rows per SpMV tile at most
+// Row-tile shapes of the LDS-staged SpMV: shape h holds at most tile_nnz_of(h) nonzeros
+// (1024, 2048, 4096) and a quarter as many rows; the shape of an LP comes from its options or
+// the tuned table (lp_tile_table.h).
+constexpr int kTileShapes = 3;
+__host__ __device__ constexpr int tile_nnz_of(int shape) { return 1024 << shape; }
+constexpr int kTileNnzMax = 4096;
 constexpr int kMaxRedBlocks = 512;
 constexpr int kNQ = 8;            // reduced quantities per candidate
 constexpr int kNR = 4;            // reduced quantities of the candidate rays (infeasibility)
@@ -37,6 +41,7 @@ struct Scalars {
     // statistics of the returned point
     double out_pobj, out_dobj, out_rel_p, out_rel_d, out_rel_gap, out_erel;
     long long k, t, max_iters, restarts, n_trace, trace_cap;
+    long long done_clock;  // device wall clock (wall_clock64) when the solve stopped
     int status;        // kRunning or an lp_termination value
     int out_avg;       // returned point: 1 = running average
     int last_restart;  // what the apply kernel must do: 0 nothing, 1 keep current, 2 take average
@@ -51,6 +56,7 @@ struct Csr {
     int rows;
     int ntiles;
     int nnz;
+    int shape;  // row-tile shape (tile_nnz_of(shape) nonzeros per tile at most)
     const int* rp;
     const int* ci;
     const double* v;
@@ -151,10 +157,13 @@ struct MultiMaps {
     int n_elem;
     int* active;          // number of LPs still running (MULTI_ACTIVE) or each LP's status (MULTI_STATUS)
     // The tile maps are grouped by form v = 2 * fp32 + method (FP64 / FP32 storage, averaged /
-    // Halpern): the tiles of form v are entries [off_a[v], off_a[v] + cnt_a[v]) of map_a (and
-    // likewise of map_at), so the iteration launches one kernel specialised per form present.
-    int off_a[4], cnt_a[4], off_at[4], cnt_at[4];
+    // Halpern) and row-tile shape h: the tiles of group g = 3 v + h are entries
+    // [off_a[g], off_a[g] + cnt_a[g]) of map_a (and likewise of map_at), so every launch runs
+    // one kernel specialised per form and shape present.
+    int off_a[12], cnt_a[12], off_at[12], cnt_at[12];
 };
+
+constexpr int kMapGroups = 4 * kTileShapes;
 
 enum MultiLaunch {
     MULTI_PRIMAL = 0, MULTI_DUAL, MULTI_AX_ALL, MULTI_AX_FP32, MULTI_ATY, MULTI_AXA, MULTI_ATYA, MULTI_PARTIALS,
@@ -196,7 +205,7 @@ void launch_materialize(const DevLP& P, hipStream_t s);
 // device counter (which must start at 0) and each solves one LP at a time, entirely on chip.
 // lds_cap > 0: each workgroup holds lds_cap bytes of LDS (at most kSmallLpLdsMax) and solves an LP
 // from LDS when small_lp_lds_bytes(LP) <= lds_cap (bit-identical result, lower latency).
-constexpr int kSmallLpLdsMax = 128 * 1024;
+constexpr int kSmallLpLdsMax = 112 * 1024;
 void launch_batch(const BatchJob* jobs, const int* order, int count, int* counter, int grid, hipStream_t s,
                   int lds_cap = 0);
 size_t small_lp_lds_bytes(const DevLP& P);

@@ -91,15 +91,13 @@ inline unsigned grid_for(long long n, int per_block = kBlock) {
 
 // ------------------------------------------------------------------ SpMV with epilogues
 
-// One workgroup per tile. Short tiles (at most kTileNnz nonzeros): every thread owns
-// kPerThread nonzeros of the tile; it first issues all their index and value loads, then all
+// One workgroup per tile. Short tiles (at most TN nonzeros, TN one of the row-tile shapes):
+// every thread owns TN / kBlock nonzeros of the tile; it first issues all their index and value loads, then all
 // the gathers of the vector entries, and stores the products to LDS, so each thread keeps
 // kPerThread independent memory requests in flight. The epilogue operands of the rows a
 // thread finishes are loaded before the barrier. After the barrier each thread forms the sum
 // of one row from LDS in CSR order and runs the epilogue. A tile that is a single row longer
-// than kTileNnz is reduced by the whole workgroup (fixed-shape tree).
-constexpr int kPerThread = kTileNnz / kBlock;
-constexpr int kRowsPerThread = kTileRows / kBlock;
+// than TN is reduced by the whole workgroup (fixed-shape tree).
 
 // Matrix values in the arithmetic type of a kernel instance.
 template <class T>
@@ -121,10 +119,11 @@ __device__ inline T block_sum_t(T v, double* red) {
 }
 
 // Row r reduced by the whole workgroup: thread t adds the products of entries t, t + kBlock,
-// ... in order (kPerThread loads in flight per round), then a fixed-shape tree over the
-// workgroup. Called by every thread of the workgroup.
-template <class T, class Epi>
+// ... in order (TN / kBlock loads in flight per round; the order of the additions does not
+// depend on TN), then a fixed-shape tree over the workgroup. Called by every thread.
+template <int TN, class T, class Epi>
 __device__ void row_tree_body(const Csr& M, int r, const T* __restrict__ xin, const Epi& epi, double* red) {
+    constexpr int kPerThread = TN / kBlock;
     const int p0 = M.rp[r], p1 = M.rp[r + 1];
     const int tid = threadIdx.x;
     const int* __restrict__ ci = M.ci;
@@ -132,7 +131,7 @@ __device__ void row_tree_body(const Csr& M, int r, const T* __restrict__ xin, co
     const int elast = M.nnz > 0 ? M.nnz - 1 : 0;
     const typename Epi::Pre pre = epi.load(r);
     T s = 0;
-    for (int base = p0; base < p1; base += kTileNnz) {
+    for (int base = p0; base < p1; base += TN) {
         int col[kPerThread];
         T val[kPerThread];
 #pragma unroll
@@ -157,8 +156,10 @@ __device__ void row_tree_body(const Csr& M, int r, const T* __restrict__ xin, co
     if (tid == 0) epi.finish(r, s, pre);
 }
 
-template <class T, class Epi>
+template <int TN, class T, class Epi>
 __device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const Epi& epi, T* prod, double* red) {
+    constexpr int kPerThread = TN / kBlock;
+    constexpr int kRowsPerThread = TN / 4 / kBlock;
     const int r0 = M.tiles[b], r1 = M.tiles[b + 1];
     const int p0 = M.rp[r0], p1 = M.rp[r1];
     const int tid = threadIdx.x;
@@ -167,7 +168,7 @@ __device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const 
     // Loads below are unconditional on clamped, in-bounds indices (every array holds at least
     // one element) so that they issue back to back; out-of-range lanes are masked afterwards.
     const int elast = M.nnz > 0 ? M.nnz - 1 : 0;
-    if (p1 - p0 <= kTileNnz) {
+    if (p1 - p0 <= TN) {
         int col[kPerThread];
         T val[kPerThread];
 #pragma unroll
@@ -213,16 +214,25 @@ __device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const 
             }
         }
     } else {
-        row_tree_body<T>(M, r0, xin, epi, red);
+        row_tree_body<TN, T>(M, r0, xin, epi, red);
     }
 }
 
+// The tile body of the LP's row-tile shape (Csr::shape; prod holds kTileNnzMax values).
 template <class T, class Epi>
+__device__ inline void tile_body_any(const Csr& M, int b, const T* __restrict__ xin, const Epi& epi, T* prod,
+                                     double* red) {
+    if (M.shape == 0) tile_body<tile_nnz_of(0)>(M, b, xin, epi, prod, red);
+    else if (M.shape == 1) tile_body<tile_nnz_of(1)>(M, b, xin, epi, prod, red);
+    else tile_body<tile_nnz_of(2)>(M, b, xin, epi, prod, red);
+}
+
+template <class T, class Epi, int TN>
 __global__ __launch_bounds__(kBlock) void spmv_tiles_kernel(Csr M, const T* __restrict__ xin, Epi epi) {
-    __shared__ T prod[kTileNnz];
+    __shared__ T prod[TN];
     __shared__ double red[kBlock / 64];
     if (!epi.begin()) return;
-    tile_body(M, static_cast<int>(blockIdx.x), xin, epi, prod, red);
+    tile_body<TN>(M, static_cast<int>(blockIdx.x), xin, epi, prod, red);
 }
 
 // Panel-packed SpMV over wave units of rows. The entries of a unit are walked in packed order,
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, Csr L, int
     if (!epi.begin()) return;
     if (static_cast<int>(blockIdx.x) >= panel_blocks) {
         const int r = L.rowlist[blockIdx.x - panel_blocks];
-        row_tree_body<T>(L, r, xin, epi, red);
+        row_tree_body<tile_nnz_of(1), T>(L, r, xin, epi, red);
         return;
     }
     // The wave index is the same on every lane; saying so keeps the unit's bookkeeping in
@@ -844,7 +854,12 @@ __host__ __device__ inline EpiDual32H epi_dual32_h(const DevLP& P, const Scalars
 template <class T, class Epi>
 void launch_tiles(const Csr& M, const T* xin, const Epi& epi, hipStream_t s) {
     if (M.ntiles <= 0) return;
-    hipLaunchKernelGGL((spmv_tiles_kernel<T, Epi>), dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
+    if (M.shape == 0)
+        hipLaunchKernelGGL((spmv_tiles_kernel<T, Epi, tile_nnz_of(0)>), dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
+    else if (M.shape == 1)
+        hipLaunchKernelGGL((spmv_tiles_kernel<T, Epi, tile_nnz_of(1)>), dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
+    else
+        hipLaunchKernelGGL((spmv_tiles_kernel<T, Epi, tile_nnz_of(2)>), dim3(M.ntiles), dim3(kBlock), 0, s, M, xin, epi);
 }
 
 // One sparse product with its fused epilogue: one launch holding the panel-packed units and,
@@ -1308,7 +1323,10 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         if (isnan(cur.erel)) sc->status = 3;
         else if (cur.erel <= sc->eps_rel) sc->status = 0;
         else if (sc->max_iters <= 0) sc->status = 1;
-        if (sc->status != kRunning) set_output(sc, cur, 0);
+        if (sc->status != kRunning) {
+            set_output(sc, cur, 0);
+            sc->done_clock = static_cast<long long>(wall_clock64());
+        }
         return;
     }
     // Halpern form: the PDHG output is the only candidate (slots 0..7), returned as "average"
@@ -1361,6 +1379,7 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
     if (status != kRunning) {
         sc->t = t;
         sc->status = status;
+        sc->done_clock = static_cast<long long>(wall_clock64());
         sc->last_restart = 0;
         set_output(sc, out_avg ? avg : cur, out_avg);
         rec[6] = out_avg;
@@ -1513,6 +1532,7 @@ __global__ void apply_restart_kernel(DevLP P) {
 __global__ void stop_kernel(Scalars* sc, int status) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && sc->status == kRunning) {
         sc->status = status;
+        sc->done_clock = static_cast<long long>(wall_clock64());
         sc->out_avg = 0;
         sc->last_restart = 0;
     }
@@ -1625,7 +1645,7 @@ template <class T, class Epi>
 __device__ void wg_spmv(const Csr& M, const T* xin, const Epi& epi, double* lds, double* red) {
     T* prod = reinterpret_cast<T*>(lds);
     for (int b = 0; b < M.ntiles; ++b) {
-        tile_body(M, b, xin, epi, prod, red);
+        tile_body_any(M, b, xin, epi, prod, red);
         __syncthreads();
     }
 }
@@ -1882,7 +1902,7 @@ __device__ void unstage_small_lp(const DevLP& L, const DevLP& G) {
 __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, const int* order, int count,
                                                         int* counter, int lds_cap) {
     extern __shared__ __align__(16) char small_lp_lds[];
-    __shared__ double lds[kTileNnz];
+    __shared__ double lds[kTileNnzMax];
     __shared__ double red[kBlock / 64];
     __shared__ double red16[(kBlock / 64) * kNT];
     __shared__ double tot[kNT];
@@ -1915,32 +1935,32 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(const BatchJob* jobs, con
 enum MultiKind { MK_PRIMAL = 0, MK_DUAL, MK_AX_ALL, MK_AX_FP32, MK_ATY, MK_AXA, MK_ATYA };
 
 // One row tile with an epilogue whose begin() may decline the work (LP stopped).
-template <class T, class Epi>
+template <int TN, class T, class Epi>
 __device__ inline void run_tile(const Csr& M, int b, const T* xin, Epi e, T* prod, double* red) {
     if (!e.begin()) return;
-    tile_body(M, b, xin, e, prod, red);
+    tile_body<TN>(M, b, xin, e, prod, red);
 }
 
 // FORM = 2 * fp32 + method for the iteration kinds (one instance per form: the four fused
 // epilogues in one kernel would hold the registers of the largest and halve occupancy), -1
-// for the evaluation products.
-template <int KIND, int FORM>
+// for the evaluation products; TN the row-tile shape of the LPs of the launch.
+template <int KIND, int FORM, int TN>
 __global__ __launch_bounds__(kBlock) void multi_tiles_kernel(const BatchJob* jobs, const int2* map, int it) {
-    __shared__ double lds[kTileNnz];
+    __shared__ double lds[TN];
     __shared__ double red[kBlock / 64];
     const int2 mt = map[blockIdx.x];
     const DevLP& P = jobs[mt.x].P;
     float* lds32 = reinterpret_cast<float*>(lds);
     if constexpr (KIND == MK_PRIMAL) {
-        if constexpr (FORM == 3) run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32_h(P, P.sc, it), lds32, red);
-        else if constexpr (FORM == 2) run_tile(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32(P, P.sc, it), lds32, red);
-        else if constexpr (FORM == 1) run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal_h(P, P.sc, it), lds, red);
-        else run_tile(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal(P, P.sc, it), lds, red);
+        if constexpr (FORM == 3) run_tile<TN>(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32_h(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 2) run_tile<TN>(P.AT.csr, mt.y, static_cast<const float*>(P.dy), epi_primal32(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 1) run_tile<TN>(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal_h(P, P.sc, it), lds, red);
+        else run_tile<TN>(P.AT.csr, mt.y, static_cast<const double*>(P.y), epi_primal(P, P.sc, it), lds, red);
     } else if constexpr (KIND == MK_DUAL) {
-        if constexpr (FORM == 3) run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dxa), epi_dual32_h(P, P.sc, it), lds32, red);
-        else if constexpr (FORM == 2) run_tile(P.A.csr, mt.y, static_cast<const float*>(P.dx), epi_dual32(P, P.sc, it), lds32, red);
-        else if constexpr (FORM == 1) run_tile(P.A.csr, mt.y, static_cast<const double*>(P.xa), epi_dual_h(P, P.sc, it), lds, red);
-        else run_tile(P.A.csr, mt.y, static_cast<const double*>(P.x), epi_dual(P, P.sc, it), lds, red);
+        if constexpr (FORM == 3) run_tile<TN>(P.A.csr, mt.y, static_cast<const float*>(P.dxa), epi_dual32_h(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 2) run_tile<TN>(P.A.csr, mt.y, static_cast<const float*>(P.dx), epi_dual32(P, P.sc, it), lds32, red);
+        else if constexpr (FORM == 1) run_tile<TN>(P.A.csr, mt.y, static_cast<const double*>(P.xa), epi_dual_h(P, P.sc, it), lds, red);
+        else run_tile<TN>(P.A.csr, mt.y, static_cast<const double*>(P.x), epi_dual(P, P.sc, it), lds, red);
     } else {
         if (P.sc->status != kRunning) return;
         if (KIND == MK_AX_FP32 && (!P.fp32 || P.method)) return;
@@ -1951,7 +1971,7 @@ __global__ __launch_bounds__(kBlock) void multi_tiles_kernel(const BatchJob* job
         const bool onA = KIND == MK_AX_ALL || KIND == MK_AX_FP32 || KIND == MK_AXA;
         const double* xin = KIND == MK_ATY ? P.y : KIND == MK_ATYA ? P.ya : KIND == MK_AXA ? P.xa : P.x;
         double* out = KIND == MK_ATY ? P.aty : KIND == MK_ATYA ? P.atya : KIND == MK_AXA ? P.axa : P.ax;
-        tile_body(onA ? P.A.csr : P.AT.csr, mt.y, xin, EpiStore{out, nullptr}, lds, red);
+        tile_body<TN>(onA ? P.A.csr : P.AT.csr, mt.y, xin, EpiStore{out, nullptr}, lds, red);
     }
 }
 
@@ -2214,28 +2234,44 @@ void launch_apply_restart(const DevLP& P, hipStream_t s) {
 }
 
 
+// Tile launches of one kind: one per group of the maps (form v = 2 * fp32 + method and
+// row-tile shape h, group g = 3 v + h), each with the kernel instance of its form and shape.
+template <int KIND, int FORM>
+void multi_tiles_group(const MultiMaps& M, int g, bool on_a, int it_or_mode, hipStream_t s) {
+    const int n = on_a ? M.cnt_a[g] : M.cnt_at[g];
+    if (n <= 0) return;
+    const int2* map = on_a ? M.map_a + M.off_a[g] : M.map_at + M.off_at[g];
+    switch (g % kTileShapes) {
+        case 0: hipLaunchKernelGGL((multi_tiles_kernel<KIND, FORM, tile_nnz_of(0)>), dim3(n), dim3(kBlock), 0, s, M.jobs, map, it_or_mode); break;
+        case 1: hipLaunchKernelGGL((multi_tiles_kernel<KIND, FORM, tile_nnz_of(1)>), dim3(n), dim3(kBlock), 0, s, M.jobs, map, it_or_mode); break;
+        default: hipLaunchKernelGGL((multi_tiles_kernel<KIND, FORM, tile_nnz_of(2)>), dim3(n), dim3(kBlock), 0, s, M.jobs, map, it_or_mode); break;
+    }
+}
+
+template <int KIND>
+void multi_tiles_iter(const MultiMaps& M, bool on_a, int it, hipStream_t s) {
+    for (int h = 0; h < kTileShapes; ++h) {
+        multi_tiles_group<KIND, 0>(M, 0 * kTileShapes + h, on_a, it, s);
+        multi_tiles_group<KIND, 1>(M, 1 * kTileShapes + h, on_a, it, s);
+        multi_tiles_group<KIND, 2>(M, 2 * kTileShapes + h, on_a, it, s);
+        multi_tiles_group<KIND, 3>(M, 3 * kTileShapes + h, on_a, it, s);
+    }
+}
+
+template <int KIND>
+void multi_tiles_eval(const MultiMaps& M, bool on_a, int mode, hipStream_t s) {
+    for (int g = 0; g < kMapGroups; ++g) multi_tiles_group<KIND, -1>(M, g, on_a, mode, s);
+}
+
 void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s) {
-    auto tiles = [&](auto kern, int n, const int2* map) {
-        if (n > 0) hipLaunchKernelGGL(kern, dim3(n), dim3(kBlock), 0, s, M.jobs, map, it_or_mode);
-    };
     switch (kind) {
-        case MULTI_PRIMAL:
-            tiles(multi_tiles_kernel<MK_PRIMAL, 0>, M.cnt_at[0], M.map_at + M.off_at[0]);
-            tiles(multi_tiles_kernel<MK_PRIMAL, 1>, M.cnt_at[1], M.map_at + M.off_at[1]);
-            tiles(multi_tiles_kernel<MK_PRIMAL, 2>, M.cnt_at[2], M.map_at + M.off_at[2]);
-            tiles(multi_tiles_kernel<MK_PRIMAL, 3>, M.cnt_at[3], M.map_at + M.off_at[3]);
-            break;
-        case MULTI_DUAL:
-            tiles(multi_tiles_kernel<MK_DUAL, 0>, M.cnt_a[0], M.map_a + M.off_a[0]);
-            tiles(multi_tiles_kernel<MK_DUAL, 1>, M.cnt_a[1], M.map_a + M.off_a[1]);
-            tiles(multi_tiles_kernel<MK_DUAL, 2>, M.cnt_a[2], M.map_a + M.off_a[2]);
-            tiles(multi_tiles_kernel<MK_DUAL, 3>, M.cnt_a[3], M.map_a + M.off_a[3]);
-            break;
-        case MULTI_AX_ALL: tiles(multi_tiles_kernel<MK_AX_ALL, -1>, M.n_a, M.map_a); break;
-        case MULTI_AX_FP32: tiles(multi_tiles_kernel<MK_AX_FP32, -1>, M.n_a, M.map_a); break;
-        case MULTI_ATY: tiles(multi_tiles_kernel<MK_ATY, -1>, M.n_at, M.map_at); break;
-        case MULTI_AXA: tiles(multi_tiles_kernel<MK_AXA, -1>, M.n_a, M.map_a); break;
-        case MULTI_ATYA: tiles(multi_tiles_kernel<MK_ATYA, -1>, M.n_at, M.map_at); break;
+        case MULTI_PRIMAL: multi_tiles_iter<MK_PRIMAL>(M, false, it_or_mode, s); break;
+        case MULTI_DUAL: multi_tiles_iter<MK_DUAL>(M, true, it_or_mode, s); break;
+        case MULTI_AX_ALL: multi_tiles_eval<MK_AX_ALL>(M, true, it_or_mode, s); break;
+        case MULTI_AX_FP32: multi_tiles_eval<MK_AX_FP32>(M, true, it_or_mode, s); break;
+        case MULTI_ATY: multi_tiles_eval<MK_ATY>(M, false, it_or_mode, s); break;
+        case MULTI_AXA: multi_tiles_eval<MK_AXA>(M, true, it_or_mode, s); break;
+        case MULTI_ATYA: multi_tiles_eval<MK_ATYA>(M, false, it_or_mode, s); break;
         case MULTI_PARTIALS:
             if (M.n_red > 0)
                 hipLaunchKernelGGL(multi_partials_kernel, dim3(M.n_red), dim3(kBlock), 0, s, M.jobs, M.map_red,

@@ -182,8 +182,9 @@ def test_default_options_match_the_header():
                     precision=lpg.LP_PREC_FP64, scaling=1, ruiz_passes=10, pow_iters=200, restarts=1,
                     step_size=0.0, omega0=0.0, device=0, trace_cap=4096, spmv_layout=0, long_row_len=256,
                     units_per_cu=4, batch_wg_per_cu=3, panel_slice_bytes=512 * 1024, batch_split_nnz=20000,
-                    deferred=0, small_lp_lds=128 * 1024, eps_infeas=1e-8, method=lpg.LP_METHOD_AVERAGED, reflection=1.0,
-                    omega_steps=0, pw_rule=lpg.LP_PW_DEFAULT, pid_kp=0.7, pid_ki=0.05, pid_kd=0.2)
+                    deferred=0, eps_infeas=1e-8, method=lpg.LP_METHOD_AVERAGED, reflection=1.0,
+                    omega_steps=0, pw_rule=lpg.LP_PW_DEFAULT, pid_kp=0.7, pid_ki=0.05, pid_kd=0.2, tile_nnz=0,
+                    small_lp_lds=112 * 1024)
     for k, v in expected.items():
         assert getattr(o, k) == v, (k, getattr(o, k), v)
 
