@@ -177,7 +177,7 @@ def test_small_lps_from_lds_equal_global(precision, method):
            synth.cfg3_lp(1, m_max=900)]
     opts = dict(spmv_layout=1, precision=precision, method=method)
     out = {}
-    for budget in (0, 128 * 1024):
+    for budget in (0, 112 * 1024):
         solvers = [lpg.Solver(lp, **opts) for lp in lps]
         try:
             lpg.solve_batch(solvers, eps_rel=0.0, max_iters=130, small_lp_lds=budget, **opts)
@@ -187,7 +187,7 @@ def test_small_lps_from_lds_equal_global(precision, method):
             for s in solvers:
                 s.close()
         out[budget] = (its, sols)
-    (ia, sa), (ib, sb) = out[0], out[128 * 1024]
+    (ia, sa), (ib, sb) = out[0], out[112 * 1024]
     for j, lp in enumerate(lps):
         for u, v in zip(ia[j], ib[j]):
             assert np.array_equal(u, v), (lp.name, "iterates")
