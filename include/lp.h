@@ -194,6 +194,8 @@ typedef struct lp_info {
                               each LP's own instant); ticks of clock_hz, comparable across the
                               LPs of one device */
     double clock_hz;       /* rate of that clock */
+    int64_t polish_primal_iterations, polish_dual_iterations; /* of the last lp_polish (0 after lp_solve) */
+    double polish_seconds; /* last lp_polish */
 } lp_info;
 
 /* Fill *opt with the defaults listed above. */
@@ -219,6 +221,23 @@ int32_t lp_create(lp_handle **out, int32_t m, int32_t n, int64_t nnz, const int3
  * a certificate or a limit. Every call starts again from x0, y0 (the handle keeps the
  * problem, not the iterates). */
 int32_t lp_solve(lp_handle *h);
+
+/* Feasibility polishing of the point the last lp_solve returned (the PDLP family's polishing;
+ * the paper runs a solver of that family, Section 4), two more solves of the same form on the
+ * device, warm-started at that point and stopped on one residual alone:
+ *  - primal: the LP's constraints with the objective removed (c = 0), from (x, 0), until the
+ *    relative primal residual ||r_p|| / (1 + ||q||) is at most eps: a point that satisfies the
+ *    constraints to eps, near x;
+ *  - dual: the LP's matrix and costs with every finite row and variable bound set to 0 (the
+ *    problem whose dual constraints are those of the LP), from (0, y), until the relative dual
+ *    residual ||r_d|| / (1 + ||c||) is at most eps: a dual point feasible to eps, near y.
+ * Both start at primal weight 1 (one of ||c||, ||q|| vanishes in each) with the LP's step size
+ * and stop at max_iters iterations at most. lp_get_solution then returns x of the first, y of
+ * the second and z = the projected reduced cost of that y, and info holds their E_rel terms
+ * (the gap is not polished), the status of the lp_solve and the polishing iterations. The
+ * handle's data are restored. LP_ERR_NOT_SOLVED before lp_solve; LP_ERR_INVALID_ARG after a
+ * solve that returned a certificate, or for eps <= 0. */
+int32_t lp_polish(lp_handle *h, double eps, int64_t max_iters);
 
 /* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every,
  * restarts, eps_infeas, method, reflection, omega_steps, pw_rule and the three pid gains are

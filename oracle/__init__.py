@@ -68,6 +68,7 @@ class _OptsStruct(C.Structure):
         ("method", C.c_int32), ("pad3", C.c_int32), ("reflection", C.c_double),
         ("omega_steps", C.c_int32), ("pad4", C.c_int32), ("pw_rule", C.c_int32), ("pad5", C.c_int32),
         ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
+        ("term_mode", C.c_int32), ("pad6", C.c_int32),
     ]
 
 
@@ -228,7 +229,7 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
           omega0: float = 0.0, seed: int = 0x5EED0C0FFEE, x0=None, y0=None,
           snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8, method: int = 0,
           reflection: float = 1.0, omega_steps: int = 0, pw_rule: int = 0, pid_kp: Optional[float] = None,
-          pid_ki: Optional[float] = None, pid_kd: Optional[float] = None) -> Result:
+          pid_ki: Optional[float] = None, pid_kd: Optional[float] = None, term_mode: int = 0) -> Result:
     """Run the oracle. `snap_k` lists iterations whose scaled-space state
     (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration."""
     b = _Bound(lp)
@@ -249,6 +250,7 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     o.reflection = reflection
     o.omega_steps = omega_steps
     o.pw_rule = pw_rule
+    o.term_mode = term_mode
     if pid_kp is not None:
         o.pid_kp = pid_kp
     if pid_ki is not None:
@@ -289,3 +291,51 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
 def split_snap(snap: np.ndarray, n: int, m: int):
     """(x~, y~, x~avg, y~avg) views of one snapshot row."""
     return snap[:n], snap[n : n + m], snap[n + m : 2 * n + m], snap[2 * n + m :]
+
+
+@dataclass
+class Polished:
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    primal_iters: int
+    dual_iters: int
+    primal_status: str
+    dual_status: str
+    kkt: dict
+
+
+def polish(lp, x, y, *, eps: float = 1e-8, max_iters: int = 100000, method: int = 0, **kw) -> Polished:
+    """Feasibility polishing of an approximate solution (x, y) (original scale): two more
+    restarted-PDHG solves warm-started at it, each stopped on one residual alone.
+
+    Primal: the same constraints with the objective removed (c = 0), started at (x, 0) and run
+    until the relative primal residual is at most eps: its iterate is a point that satisfies
+    the constraints to eps near x. Dual: the same matrix and costs with every finite row and
+    variable bound set to 0 (the recession cone of the feasible set, whose dual constraints
+    are those of the LP), started at (0, y) and run until the relative dual residual is at
+    most eps: its y is dual feasible to eps near y. Reading (the paper names the PDLP family;
+    this is that family's polishing): the polished point is (x_primal, y_dual), z its projected
+    reduced cost, and its KKT record on the original data is returned. Both solves take the
+    modified LP's own primal weight (1: one of ||c|| and ||q|| vanishes) and the same step."""
+    import dataclasses
+
+    zero_c = dataclasses.replace(lp, c=np.zeros(lp.n)) if dataclasses.is_dataclass(lp) else _with(lp, c=np.zeros(lp.n))
+    cone = dict(b_lo=np.where(np.isfinite(lp.b_lo), 0.0, lp.b_lo), b_hi=np.where(np.isfinite(lp.b_hi), 0.0, lp.b_hi),
+                x_lo=np.where(np.isfinite(lp.x_lo), 0.0, lp.x_lo), x_hi=np.where(np.isfinite(lp.x_hi), 0.0, lp.x_hi))
+    homog = dataclasses.replace(lp, **cone) if dataclasses.is_dataclass(lp) else _with(lp, **cone)
+    rp = solve(zero_c, eps_rel=eps, max_iters=max_iters, x0=x, y0=np.zeros(lp.m), eps_infeas=0.0, method=method,
+               term_mode=1, **kw)
+    rd = solve(homog, eps_rel=eps, max_iters=max_iters, x0=np.zeros(lp.n), y0=y, eps_infeas=0.0, method=method,
+               term_mode=2, **kw)
+    k = kkt(lp, rp.x, rd.y)
+    return Polished(rp.x, rd.y, k["z"], rp.iters, rd.iters, rp.status, rd.status, k)
+
+
+def _with(lp, **fields):
+    import copy
+
+    out = copy.copy(lp)
+    for key, v in fields.items():
+        setattr(out, key, v)
+    return out

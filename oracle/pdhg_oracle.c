@@ -87,6 +87,10 @@ typedef struct {
                             controller; 0: the default (smoothing) */
     int32_t pad5;
     double pid_kp, pid_ki, pid_kd; /* gains of the PID rule */
+    int32_t term_mode;   /* what must fall to eps_rel to stop: 0 E_rel, 1 the relative primal
+                            residual alone, 2 the relative dual residual alone (the two
+                            feasibility polishing solves) */
+    int32_t pad6;
 } ora_opts;
 
 typedef struct {
@@ -365,6 +369,13 @@ static void eval_kkt(const prob *P, const double *x, const double *y, const doub
     K->erel = e;
 }
 
+/* The quantity termination compares with eps_rel (term_mode of ora_opts). */
+static double term_value(const kkt_t *K, int32_t mode) {
+    if (mode == 1) return isnan(K->erel) ? NAN : K->rel_p;
+    if (mode == 2) return isnan(K->erel) ? NAN : K->rel_d;
+    return K->erel;
+}
+
 /* KKT error in the primal-weighted norm on the scaled problem (restart metric). */
 static double kkt_omega(const kkt_t *K, double omega) {
     double w2 = omega * omega;
@@ -633,6 +644,8 @@ static double dual_step(double y, double axn, double ax, double sigma, double bl
  * O8  every `eval_every` iterations (and at max_iters) both the current and the average
  *     iterate are evaluated as in eval_kkt.
  * O9  stop when E_rel(current) <= eps (then the average); at max_iters return the better.
+ *     (term_mode 1 / 2 compare the relative primal / dual residual instead of E_rel: the
+ *     feasibility polishing solves, see ora_polish in the Python module.)
  * O10 candidate = average if its KKT_omega is strictly smaller; restart if
  *     (i) KKT_c <= 0.2 KKT_anchor, (ii) KKT_c <= 0.8 KKT_anchor and KKT_c > KKT_prev, or
  *     (iii) t >= 0.36 k.
@@ -732,7 +745,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     double t1 = now_s();
 
     if (isnan(Kc.erel)) status = ORA_NUMERICAL_ERROR;
-    else if (Kc.erel <= o->eps_rel) status = ORA_OPTIMAL;
+    else if (term_value(&Kc, o->term_mode) <= o->eps_rel) status = ORA_OPTIMAL;
     else if (o->max_iters <= 0) status = ORA_ITERATION_LIMIT;
 
     while (status < 0) {
@@ -817,10 +830,10 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         /* O9 */
         if (isnan(Kc.erel) || isnan(Ka.erel)) {
             status = ORA_NUMERICAL_ERROR;
-        } else if (Kc.erel <= o->eps_rel) {
+        } else if (term_value(&Kc, o->term_mode) <= o->eps_rel) {
             status = ORA_OPTIMAL;
             out_avg = halpern;
-        } else if (Ka.erel <= o->eps_rel) {
+        } else if (term_value(&Ka, o->term_mode) <= o->eps_rel) {
             status = ORA_OPTIMAL;
             out_avg = 1;
         } else {
@@ -831,7 +844,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             }
             if (status < 0 && k >= o->max_iters) {
                 status = ORA_ITERATION_LIMIT;
-                out_avg = halpern ? 1 : Ka.erel < Kc.erel;
+                out_avg = halpern ? 1 : term_value(&Ka, o->term_mode) < term_value(&Kc, o->term_mode);
             }
         }
         if (status >= 0) {

@@ -37,7 +37,7 @@ LP_STATIC_BATCH_MAX = 4096  # include/lp.h
 
 # names of every function include/lp.h declares
 EXPORTS = (
-    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_polish", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
     "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
@@ -95,6 +95,8 @@ class lp_info(C.Structure):
         ("rel_dual_res", C.c_double), ("rel_gap", C.c_double), ("rel_kkt", C.c_double), ("sigma_max", C.c_double),
         ("step_size", C.c_double), ("omega", C.c_double), ("setup_seconds", C.c_double),
         ("solve_seconds", C.c_double), ("done_clock", C.c_int64), ("clock_hz", C.c_double),
+        ("polish_primal_iterations", C.c_int64), ("polish_dual_iterations", C.c_int64),
+        ("polish_seconds", C.c_double),
     ]
 
 
@@ -135,6 +137,8 @@ def lib():
         L.lp_solve.restype = I32
         L.lp_solve_batch.argtypes = [P, I32, P]
         L.lp_solve_batch.restype = I32
+        L.lp_polish.argtypes = [P, D, I64]
+        L.lp_polish.restype = I32
         L.lp_solve_batch_static.argtypes = [P, I32, P]
         L.lp_solve_batch_static.restype = I32
         L.lp_get_solution.argtypes = [P, P, P, P, P]
@@ -382,6 +386,15 @@ class Solver:
         info = lp_get_solution(self.h, x, y, z)
         tr = lp_get_trace(self.h, self.trace_cap) if with_trace else np.zeros((0, TRACE_WIDTH))
         return Solution(STATUS.get(info.status, str(info.status)), x, y[: self.m], z, info, tr)
+
+    def polish(self, eps: float = 1e-8, max_iters: int = 100000) -> Solution:
+        """Feasibility polishing of the last solve's point (lp_polish); returns the polished point."""
+        _check(lib().lp_polish(self.h, float(eps), int(max_iters)), self.h)
+        x = np.empty(self.n)
+        y = np.empty(max(self.m, 1))
+        z = np.empty(self.n)
+        info = lp_get_solution(self.h, x, y, z)
+        return Solution(STATUS.get(info.status, str(info.status)), x, y[: self.m], z, info)
 
     def iterates(self):
         x, xa = np.empty(self.n), np.empty(self.n)

@@ -1627,59 +1627,163 @@ int32_t lp_create(lp_handle** out, int32_t m, int32_t n, int64_t nnz, const int3
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+// The solve loop of lp_solve from a scaled start point (x0s, y0s: device arrays or NULL for
+// 0), stopping on E_rel (term_mode 0) or on one residual alone (1 primal, 2 dual: the
+// polishing solves), with the set-up primal weight or omega0 > 0.
+int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_mode, double omega0) {
+    set_form(h->P, h->opt);
+    hipStream_t s = h->stream;
+    const DevLP& P = h->P;
+    const auto t0 = std::chrono::steady_clock::now();
+    launch_reset(P, h->opt.eps_rel, h->opt.eps_infeas, h->opt.max_iters, h->opt.eval_every, h->opt.restarts,
+                 h->opt.trace_cap, s, term_mode, omega0);
+    launch_init_state(P, x0s, y0s, s);
+    launch_evaluate(P, 1, s);
+    if (int32_t rc = check_launch(h, "initial evaluation")) return rc;
+    HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    const bool use_graph = !h->timing;
+    if (use_graph) capture_graph(h);
+    const int timed_it = h->opt.eval_every / 2;
+    while (h->h_sc->status == kRunning) {
+        const long long k_before = h->h_sc->k;
+        if (use_graph && h->gexec) {
+            HIP_TRY(h, hipGraphLaunch(h->gexec, s));
+        } else {
+            record_bundle(h, h->timing ? timed_it : -1);
+            if (int32_t rc = check_launch(h, "iteration kernels")) return rc;
+        }
+        HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        if (h->timing && k_before + timed_it < h->opt.max_iters) {
+            float a = 0.f, b = 0.f;
+            if (hipEventElapsedTime(&a, h->ev[0], h->ev[1]) == hipSuccess &&
+                hipEventElapsedTime(&b, h->ev[1], h->ev[2]) == hipSuccess) {
+                h->sum_p_ms += a;
+                h->sum_d_ms += b;
+                h->samples += 1;
+            }
+        }
+        if (h->h_sc->status != kRunning) break;
+        if (h->opt.time_limit_s > 0.0 &&
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > h->opt.time_limit_s) {
+            launch_stop(P, LP_TIME_LIMIT, s);
+            launch_evaluate(P, 2, s);
+            break;
+        }
+    }
+    launch_extract(P, s);
+    if (int32_t rc = check_launch(h, "extract")) return rc;
+    HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    fill_info(h);
+    h->info.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    h->solved = true;
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int32_t lp_solve(lp_handle* h) {
     if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
     try {
         HIP_TRY(h, hipSetDevice(h->device));
         if (int32_t rc = materialize(h)) return rc;
-        set_form(h->P, h->opt);
+        const int32_t rc = solve_from(h, h->d_x0, h->d_y0, 0, 0.0);
+        h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
+        return rc;
+    } catch (...) {
+        return fail(h, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t lp_polish(lp_handle* h, double eps, int64_t max_iters) {
+    if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
+    if (!(eps > 0.0) || max_iters < 0) return fail(h, LP_ERR_INVALID_ARG, "polish needs eps > 0 and max_iters >= 0");
+    if (!h->solved || !h->on_device) return fail(h, LP_ERR_NOT_SOLVED, "lp_polish before lp_solve");
+    const int st = h->info.status;
+    if (st != LP_OPTIMAL && st != LP_ITERATION_LIMIT && st != LP_TIME_LIMIT)
+        return fail(h, LP_ERR_INVALID_ARG, "lp_polish needs a solve that ended at a point, not a certificate");
+    try {
+        HIP_TRY(h, hipSetDevice(h->device));
+        DevLP& P = h->P;
         hipStream_t s = h->stream;
-        const DevLP& P = h->P;
+        const size_t n = static_cast<size_t>(h->n), m = static_cast<size_t>(h->m);
+        double* tmp = nullptr;
+        HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&tmp), sizeof(double) * (4 * n + 3 * m + 1)));
+        struct Free {
+            double* p;
+            ~Free() { (void)hipFree(p); }
+        } release{tmp};
+        // px, the objective's and the variable bounds' copies (n each); py, the row bounds' copies (m each)
+        double *px = tmp, *cb = px + n, *xlb = cb + n, *xub = xlb + n, *py = xub + n, *blb = py + m, *bub = blb + m;
+        double *c = const_cast<double*>(P.c), *xl = const_cast<double*>(P.xl), *xu = const_cast<double*>(P.xu);
+        double *bl = const_cast<double*>(P.bl), *bu = const_cast<double*>(P.bu);
+        auto D2D = [&](double* dst, const double* src, size_t count) {
+            return count ? hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToDevice, s) : hipSuccess;
+        };
+        const lp_options saved = h->opt;
         const auto t0 = std::chrono::steady_clock::now();
-        launch_reset(P, h->opt.eps_rel, h->opt.eps_infeas, h->opt.max_iters, h->opt.eval_every, h->opt.restarts,
-                     h->opt.trace_cap, s);
-        launch_init_state(P, h->d_x0, h->d_y0, s);
-        launch_evaluate(P, 1, s);
-        if (int32_t rc = check_launch(h, "initial evaluation")) return rc;
-        HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-        HIP_TRY(h, hipStreamSynchronize(s));
-        const bool use_graph = !h->timing;
-        if (use_graph) capture_graph(h);
-        const int timed_it = h->opt.eval_every / 2;
-        while (h->h_sc->status == kRunning) {
-            const long long k_before = h->h_sc->k;
-            if (use_graph && h->gexec) {
-                HIP_TRY(h, hipGraphLaunch(h->gexec, s));
-            } else {
-                record_bundle(h, h->timing ? timed_it : -1);
-                if (int32_t rc = check_launch(h, "iteration kernels")) return rc;
-            }
-            HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-            HIP_TRY(h, hipStreamSynchronize(s));
-            if (h->timing && k_before + timed_it < h->opt.max_iters) {
-                float a = 0.f, b = 0.f;
-                if (hipEventElapsedTime(&a, h->ev[0], h->ev[1]) == hipSuccess &&
-                    hipEventElapsedTime(&b, h->ev[1], h->ev[2]) == hipSuccess) {
-                    h->sum_p_ms += a;
-                    h->sum_d_ms += b;
-                    h->samples += 1;
-                }
-            }
-            if (h->h_sc->status != kRunning) break;
-            if (h->opt.time_limit_s > 0.0 &&
-                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > h->opt.time_limit_s) {
-                launch_stop(P, LP_TIME_LIMIT, s);
-                launch_evaluate(P, 2, s);
-                break;
-            }
+        // the returned point, in the scaled space
+        const int avg = h->h_sc->out_avg;
+        HIP_TRY(h, D2D(px, avg ? P.xa : P.x, n));
+        HIP_TRY(h, D2D(py, avg ? P.ya : P.y, m));
+        h->opt.eps_rel = eps;
+        h->opt.max_iters = max_iters;
+        h->opt.eps_infeas = 0.0;
+        // primal: objective removed, start (x, 0), stop on the primal residual
+        HIP_TRY(h, D2D(cb, c, n));
+        launch_fill(c, static_cast<long long>(n), 0.0, s);
+        int32_t rc = solve_from(h, px, nullptr, 1, 1.0);
+        HIP_TRY(h, D2D(c, cb, n));
+        const int64_t pit = h->h_sc->k;
+        if (!rc) HIP_TRY(h, D2D(px, h->h_sc->out_avg ? P.xa : P.x, n));
+        // dual: every finite bound set to 0, start (0, y), stop on the dual residual
+        if (!rc) {
+            HIP_TRY(h, D2D(xlb, xl, n));
+            HIP_TRY(h, D2D(xub, xu, n));
+            HIP_TRY(h, D2D(blb, bl, m));
+            HIP_TRY(h, D2D(bub, bu, m));
+            launch_zero_finite(xl, static_cast<long long>(n), s);
+            launch_zero_finite(xu, static_cast<long long>(n), s);
+            launch_zero_finite(bl, static_cast<long long>(m), s);
+            launch_zero_finite(bu, static_cast<long long>(m), s);
+            rc = solve_from(h, nullptr, py, 2, 1.0);
+            HIP_TRY(h, D2D(xl, xlb, n));
+            HIP_TRY(h, D2D(xu, xub, n));
+            HIP_TRY(h, D2D(bl, blb, m));
+            HIP_TRY(h, D2D(bu, bub, m));
         }
+        const int64_t dit = h->h_sc->k;
+        h->opt = saved;
+        if (rc) {
+            (void)hipStreamSynchronize(s);
+            return rc;
+        }
+        HIP_TRY(h, D2D(py, h->h_sc->out_avg ? P.ya : P.y, m));
+        // the polished point (x of the primal solve, y of the dual one) and its statistics
+        HIP_TRY(h, D2D(P.x, px, n));
+        HIP_TRY(h, D2D(P.xa, px, n));
+        HIP_TRY(h, D2D(P.y, py, m));
+        HIP_TRY(h, D2D(P.ya, py, m));
+        launch_evaluate_point(P, s);
         launch_extract(P, s);
-        if (int32_t rc = check_launch(h, "extract")) return rc;
+        if (int32_t rc2 = check_launch(h, "polished point")) return rc2;
         HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
         HIP_TRY(h, hipStreamSynchronize(s));
+        const double before = h->info.solve_seconds;
         fill_info(h);
-        h->info.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        h->solved = true;
+        h->info.status = st;
+        h->info.polish_primal_iterations = pit;
+        h->info.polish_dual_iterations = dit;
+        h->info.solve_seconds = before;
+        h->info.polish_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return LP_OK;
     } catch (...) {
         return fail(h, LP_ERR_INTERNAL, "unexpected exception");

@@ -47,7 +47,7 @@ struct Scalars {
     int last_restart;  // what the apply kernel must do: 0 nothing, 1 keep current, 2 take average
     int eval_every;
     int restarts_on;
-    int pad;
+    int term_mode;     // what must fall to eps_rel to stop: 0 E_rel, 1 rel. primal residual, 2 rel. dual residual
 };
 
 // CSR matrix with its LDS tiling: tile b covers rows [tiles[b], tiles[b+1]), or, when
@@ -186,8 +186,13 @@ void launch_power_steps(const DevLP& P, int iters, double* v, double* u, double*
 void launch_finalize_setup(const DevLP& P, double eta_override, double omega_override, double c0, hipStream_t s);
 
 // ---- solve ------------------------------------------------------------------------
+// omega_override > 0 starts the solve at that primal weight instead of the set-up one.
 void launch_reset(const DevLP& P, double eps_rel, double eps_infeas, long long max_iters, int eval_every, int restarts_on,
-                  long long trace_cap, hipStream_t s);
+                  long long trace_cap, hipStream_t s, int term_mode = 0, double omega_override = 0.0);
+// Statistics (products, reductions, decision in mode 2) of the point held in x = xa, y = ya.
+void launch_evaluate_point(const DevLP& P, hipStream_t s);
+// p[i] <- 0 where p[i] is finite (the recession cone of a bound vector).
+void launch_zero_finite(double* p, long long n, hipStream_t s);
 void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s);
 void launch_spmv_store(const Mat& M, const double* xin, double* out, const Scalars* gate, hipStream_t s);
 // reps pairs of products (A~ x, then A~^T y) in the given layout (0 panels, 1 row tiles) in the

@@ -1068,9 +1068,10 @@ __global__ __launch_bounds__(kBlock) void finalize_setup_kernel(DevLP P, int npa
 // ------------------------------------------------------------------- solve kernels
 
 __global__ void reset_kernel(Scalars* sc, double eps_rel, double eps_infeas, long long max_iters, int eval_every,
-                             int restarts_on, long long trace_cap) {
+                             int restarts_on, long long trace_cap, int term_mode, double omega_override) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    sc->omega = sc->omega0;
+    sc->omega = omega_override > 0.0 ? omega_override : sc->omega0;
+    sc->term_mode = term_mode;
     sc->tau = sc->eta / sc->omega;
     sc->sigma = sc->eta * sc->omega;
     sc->eps_rel = eps_rel;
@@ -1282,6 +1283,12 @@ __device__ inline Kkt make_kkt(const double* q, const Scalars* sc) {
     return K;
 }
 
+// The quantity termination compares with eps_rel: E_rel, or (polishing) one residual alone.
+__device__ inline double term_value(const Kkt& K, int mode) {
+    if (isnan(K.erel)) return K.erel;
+    return mode == 1 ? K.rel_p : mode == 2 ? K.rel_d : K.erel;
+}
+
 // KKT error in the primal-weighted norm on the scaled problem (the restart metric).
 __device__ inline double kkt_w(double rps2, double rds2, double gap, double omega) {
     const double w2 = omega * omega;
@@ -1321,7 +1328,7 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         sc->kkt_anchor = kkt_w(cur.rps2, cur.rds2, cur.pobj - cur.dobj, sc->omega);
         sc->kkt_prev = __builtin_inf();
         if (isnan(cur.erel)) sc->status = 3;
-        else if (cur.erel <= sc->eps_rel) sc->status = 0;
+        else if (term_value(cur, sc->term_mode) <= sc->eps_rel) sc->status = 0;
         else if (sc->max_iters <= 0) sc->status = 1;
         if (sc->status != kRunning) {
             set_output(sc, cur, 0);
@@ -1352,10 +1359,10 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
     int status = kRunning, out_avg = 0;
     if (isnan(cur.erel) || isnan(avg.erel)) {
         status = 3;
-    } else if (cur.erel <= sc->eps_rel) {
+    } else if (term_value(cur, sc->term_mode) <= sc->eps_rel) {
         status = 0;
         out_avg = halpern;
-    } else if (avg.erel <= sc->eps_rel) {
+    } else if (term_value(avg, sc->term_mode) <= sc->eps_rel) {
         status = 0;
         out_avg = 1;
     } else {
@@ -1372,7 +1379,7 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         if (status != kRunning) out_avg = halpern;
         if (status == kRunning && k >= sc->max_iters) {
             status = 1;
-            out_avg = halpern ? 1 : avg.erel < cur.erel;
+            out_avg = halpern ? 1 : term_value(avg, sc->term_mode) < term_value(cur, sc->term_mode);
         }
     }
     sc->k = k;
@@ -1707,6 +1714,7 @@ __device__ void wg_solve(const DevLP& P, const BatchJob& J, Scalars* ssc, double
         ssc->kkt_prev = __builtin_inf();
         ssc->pid_int = 0.0;
         ssc->pid_prev = 0.0;
+        ssc->term_mode = 0;
     }
     __syncthreads();
     const int mx = P.m > P.n ? P.m : P.n;
@@ -2038,6 +2046,7 @@ __global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
     sc->kkt_prev = __builtin_inf();
     sc->pid_int = 0.0;
     sc->pid_prev = 0.0;
+    sc->term_mode = 0;
 }
 
 __global__ void multi_status_kernel(const BatchJob* jobs, int count, int* status) {
@@ -2125,9 +2134,32 @@ void launch_finalize_setup(const DevLP& P, double eta_override, double omega_ove
 }
 
 void launch_reset(const DevLP& P, double eps_rel, double eps_infeas, long long max_iters, int eval_every,
-                  int restarts_on, long long trace_cap, hipStream_t s) {
+                  int restarts_on, long long trace_cap, hipStream_t s, int term_mode, double omega_override) {
     hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, s, P.sc, eps_rel, eps_infeas, max_iters, eval_every,
-                       restarts_on, trace_cap);
+                       restarts_on, trace_cap, term_mode, omega_override);
+}
+
+__global__ void zero_finite_kernel(double* p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        if (finite_d(p[i])) p[i] = 0.0;
+}
+
+void launch_zero_finite(double* p, long long n, hipStream_t s) {
+    if (n <= 0) return;
+    unsigned g = grid_for(n);
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(zero_finite_kernel, dim3(g), dim3(kBlock), 0, s, p, n);
+}
+
+void launch_evaluate_point(const DevLP& P, hipStream_t s) {
+    if (P.m > 0) {
+        launch_spmv_store(P.A, P.x, P.ax, nullptr, s);
+        launch_spmv_store(P.A, P.xa, P.axa, nullptr, s);
+    }
+    launch_spmv_store(P.AT, P.y, P.aty, nullptr, s);
+    launch_spmv_store(P.AT, P.ya, P.atya, nullptr, s);
+    hipLaunchKernelGGL(kkt_partials_kernel, dim3(P.nred), dim3(kBlock), 0, s, P, 2);
+    hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(kBlock), 0, s, P, 2);
 }
 
 void launch_init_state(const DevLP& P, const double* x0, const double* y0, hipStream_t s) {

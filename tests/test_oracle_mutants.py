@@ -43,6 +43,8 @@ MUTANTS = {
     "restart_anchor_not_reset": ("memcpy(xan, x, nb);", "(void)0;"),
     "pid_integral_not_accumulated": ("pid_int += e;", "pid_int = e;"),
     "pid_derivative_sign": ("o->pid_kd * (e - pid_prev);", "o->pid_kd * (pid_prev - e);"),
+    "polish_stops_on_wrong_residual": ("if (mode == 1) return isnan(K->erel) ? NAN : K->rel_p;",
+                                       "if (mode == 1) return isnan(K->erel) ? NAN : K->rel_d;"),
 }
 
 QUICK = [
@@ -54,6 +56,7 @@ QUICK = [
     "tests/test_oracle_infeasible.py",
     "tests/test_oracle_halpern.py",
     "tests/test_oracle_restarts.py",
+    "tests/test_oracle_polish.py",
 ]
 
 
