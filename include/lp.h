@@ -101,7 +101,11 @@ typedef enum lp_layout {
 typedef struct lp_options {
     double eps_rel;        /* relative tolerance on E_rel (default 1e-4) */
     int64_t max_iters;     /* iteration limit (default 100000) */
-    double time_limit_s;   /* wall-clock limit of lp_solve, checked every eval_every iterations (default: none, 0) */
+    double time_limit_s;   /* wall-clock limit of a solve (default: none, 0), checked at every evaluation
+                              (each eval_every iterations): by the host in lp_solve; on the device, against
+                              its wall clock, for each LP of lp_solve_batch and lp_solve_batch_static (from
+                              the start of the call) and for each request of a server (from its admission).
+                              A solve stopped by it returns LP_TIME_LIMIT and the point last evaluated. */
     int32_t eval_every;    /* iterations between KKT evaluations / restart checks (default 64) */
     int32_t precision;     /* lp_precision (default LP_PREC_FP64) */
     int32_t scaling;       /* 1: power-of-two Ruiz + Pock-Chambolle scaling (default), 0: none */
@@ -257,7 +261,7 @@ int32_t lp_update_options(lp_handle *h, const lp_options *opt);
  *    launch runs on a stream of its own beside these launches.
  * Each LP's result depends only on that LP (not on the other LPs or on where it ran), so it
  * is the same alone and in any batch. The handles' precisions may differ.
- * Solve-time options: batch_opt's eps_rel, max_iters, eval_every and restarts for every LP
+ * Solve-time options: batch_opt's eps_rel, max_iters, time_limit_s, eval_every and restarts for every LP
  * when batch_opt is given, each handle's own otherwise (the LPs of the block-diagonal group
  * must then share eval_every); batch_opt->batch_wg_per_cu and batch_split_nnz set the
  * launches. Afterwards every handle is solved and lp_get_solution returns its result
@@ -281,7 +285,7 @@ int32_t lp_solve_batch(lp_handle *const *hs, int32_t count, const lp_options *ba
  *    once): LP_ERR_INVALID_ARG otherwise, as for handles on different devices.
  *  - Calls on one device share that array: two calls that overlap in time on one device race
  *    and must be serialised by the caller. Runs on the first handle's stream.
- * Options as for lp_solve_batch (batch_opt's eps_rel, max_iters, eval_every, restarts,
+ * Options as for lp_solve_batch (batch_opt's eps_rel, max_iters, time_limit_s, eval_every, restarts,
  * eps_infeas, method, reflection, omega_steps and batch_wg_per_cu, or each handle's own). */
 #define LP_STATIC_BATCH_MAX 4096
 int32_t lp_solve_batch_static(lp_handle *const *hs, int32_t count, const lp_options *batch_opt);
@@ -316,7 +320,8 @@ typedef struct lp_server_stats {
 
 /* Start a server on `device` with a device-memory budget for admitted LPs and at most
  * max_slots LPs in the running set. The solve-time fields of *opt (eps_rel, max_iters,
- * eval_every, restarts) apply to every LP; opt may be NULL (defaults). */
+ * time_limit_s counted from each request's admission, eval_every, restarts) apply to every
+ * LP; opt may be NULL (defaults). */
 int32_t lp_server_create(lp_server **out, int32_t device, int64_t hbm_budget_bytes, int32_t max_slots,
                          const lp_options *opt);
 

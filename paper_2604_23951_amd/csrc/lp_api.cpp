@@ -362,6 +362,15 @@ BatchJob make_job(lp_handle* h, const lp_options* bo) {
     J.restarts_on = o.restarts;
     J.x0 = h->d_x0;
     J.y0 = h->d_y0;
+    // the time limit becomes a device-clock deadline, checked at every evaluation on the device
+    J.limit_ticks = 0;
+    J.t0 = nullptr;
+    int khz = 0;
+    if (o.time_limit_s > 0.0 && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess &&
+        khz > 0) {
+        const double ticks = o.time_limit_s * 1e3 * khz;
+        J.limit_ticks = ticks >= 9.0e18 ? static_cast<long long>(9.0e18) : std::max(1LL, static_cast<long long>(ticks));
+    }
     return J;
 }
 
@@ -612,12 +621,18 @@ int32_t start_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo
     BatchJob* djobs = reinterpret_cast<BatchJob*>(R.buf);
     int32_t* dorder = reinterpret_cast<int32_t*>(R.buf + bj);
     int32_t* dcounter = reinterpret_cast<int32_t*>(R.buf + oc);  // one counter per launch, 256 bytes apart
+    long long* dt0 = reinterpret_cast<long long*>(R.buf + oc + 128);  // device clock at the start of the call
+    for (BatchJob& J : R.jobs) J.t0 = dt0;
     hipError_t e = hipSuccess;
     for (int l = 0; l < 2 && e == hipSuccess; ++l)
         e = hipStreamCreateWithFlags(&R.s[l], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemcpyAsync(djobs, R.jobs.data(), bj, hipMemcpyHostToDevice, R.s[0]);
     if (e == hipSuccess) e = hipMemcpyAsync(dorder, R.order.data(), bo_, hipMemcpyHostToDevice, R.s[0]);
     if (e == hipSuccess) e = hipMemsetAsync(dcounter, 0, 512, R.s[0]);
+    if (e == hipSuccess) {
+        launch_batch_start(dcounter, dt0, R.s[0]);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(R.s[0]);
     if (e == hipSuccess && n_lds > 0) {
         launch_batch(djobs, dorder, n_lds, dcounter, std::min(cus, n_lds), R.s[1], lds_cap);
@@ -1853,7 +1868,8 @@ int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_opti
                    !(bo->eps_infeas >= 0.0) || bo->method < LP_METHOD_AVERAGED || bo->method > LP_METHOD_HALPERN ||
                    !(bo->reflection >= 0.0 && bo->reflection <= 1.0) || bo->omega_steps < 0 || bo->omega_steps > 8 ||
                    bo->pw_rule < LP_PW_DEFAULT || bo->pw_rule > LP_PW_PID || !(bo->pid_kp >= 0.0 && bo->pid_kp <= 2.0) ||
-                   !(bo->pid_ki >= 0.0 && bo->pid_ki <= 2.0) || !(bo->pid_kd >= 0.0 && bo->pid_kd <= 2.0)))
+                   !(bo->pid_ki >= 0.0 && bo->pid_ki <= 2.0) || !(bo->pid_kd >= 0.0 && bo->pid_kd <= 2.0) ||
+                   std::isnan(bo->time_limit_s)))
             return fail(nullptr, LP_ERR_INVALID_ARG, "invalid option value");
         lp_handle* h0 = hs[0];
         const int dev = h0->device;
@@ -1873,12 +1889,15 @@ int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_opti
         BatchJob buf[kChunk];
         for (int32_t i = 0; i < count; i += kChunk) {
             const int32_t nb = std::min(kChunk, count - i);
-            for (int32_t j = 0; j < nb; ++j) buf[j] = make_job(hs[i + j], bo);
+            for (int32_t j = 0; j < nb; ++j) {
+                buf[j] = make_job(hs[i + j], bo);
+                buf[j].t0 = S.t0;
+            }
             HIP_TRY(h0, hipMemcpyAsync(S.jobs + i, buf, sizeof(BatchJob) * nb, hipMemcpyHostToDevice, s));
             HIP_TRY(h0, hipStreamSynchronize(s));
         }
         HIP_TRY(h0, hipMemcpyAsync(S.order, order, sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
-        launch_zero_int(S.counter, s);
+        launch_batch_start(S.counter, S.t0, s);
         int cus = 256;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
         const int wpc = (bo && bo->batch_wg_per_cu > 0) ? bo->batch_wg_per_cu : 3;

@@ -42,6 +42,7 @@ struct Scalars {
     double out_pobj, out_dobj, out_rel_p, out_rel_d, out_rel_gap, out_erel;
     long long k, t, max_iters, restarts, n_trace, trace_cap;
     long long done_clock;  // device wall clock (wall_clock64) when the solve stopped
+    long long deadline;    // device wall clock at which an evaluation stops the solve with LP_TIME_LIMIT (0: none)
     int status;        // kRunning or an lp_termination value
     int out_avg;       // returned point: 1 = running average
     int last_restart;  // what the apply kernel must do: 0 nothing, 1 keep current, 2 take average
@@ -141,6 +142,8 @@ struct BatchJob {
     int restarts_on;
     const double* x0;
     const double* y0;
+    long long limit_ticks;  // time limit in device wall-clock ticks (0: none)
+    const long long* t0;    // device wall clock at the start of the call (null: the LP's reset)
 };
 
 // Block maps of a block-diagonal batch: entry b of a map is (LP index, tile or block of it).
@@ -224,11 +227,13 @@ struct StaticBatchScratch {
     BatchJob* jobs;  // kStaticBatchMax entries
     int* order;      // kStaticBatchMax entries
     int* counter;    // one work counter
+    long long* t0;   // device wall clock at the start of the call
 };
 hipError_t static_batch_scratch(int device, StaticBatchScratch* out);
 size_t static_batch_scratch_bytes();
-// Sets *p = 0 with a one-thread kernel (no memset node if the caller captures the stream).
-void launch_zero_int(int* p, hipStream_t s);
+// Sets *counter = 0 and *t0 = the device wall clock, with a one-thread kernel (no memset
+// node if the caller captures the stream).
+void launch_batch_start(int* counter, long long* t0, hipStream_t s);
 // One launch of a block-diagonal batch; it_or_mode is the iteration inside the bundle for
 // MULTI_PRIMAL / MULTI_DUAL and the evaluation mode for MULTI_PARTIALS / MULTI_DECIDE.
 void launch_multi(const MultiMaps& M, int kind, int it_or_mode, hipStream_t s);

@@ -1072,6 +1072,7 @@ __global__ void reset_kernel(Scalars* sc, double eps_rel, double eps_infeas, lon
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     sc->omega = omega_override > 0.0 ? omega_override : sc->omega0;
     sc->term_mode = term_mode;
+    sc->deadline = 0;  // lp_solve checks its time limit on the host between evaluation periods
     sc->tau = sc->eta / sc->omega;
     sc->sigma = sc->eta * sc->omega;
     sc->eps_rel = eps_rel;
@@ -1380,6 +1381,11 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         if (status == kRunning && k >= sc->max_iters) {
             status = 1;
             out_avg = halpern ? 1 : term_value(avg, sc->term_mode) < term_value(cur, sc->term_mode);
+        }
+        // time limit: the evaluated point is returned, as after a stop between evaluations
+        if (status == kRunning && sc->deadline > 0 && static_cast<long long>(wall_clock64()) >= sc->deadline) {
+            status = 2;
+            out_avg = halpern;
         }
     }
     sc->k = k;
@@ -1715,6 +1721,9 @@ __device__ void wg_solve(const DevLP& P, const BatchJob& J, Scalars* ssc, double
         ssc->pid_int = 0.0;
         ssc->pid_prev = 0.0;
         ssc->term_mode = 0;
+        ssc->deadline = J.limit_ticks > 0
+                            ? (J.t0 ? *J.t0 : static_cast<long long>(wall_clock64())) + J.limit_ticks
+                            : 0;
     }
     __syncthreads();
     const int mx = P.m > P.n ? P.m : P.n;
@@ -2047,6 +2056,7 @@ __global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
     sc->pid_int = 0.0;
     sc->pid_prev = 0.0;
     sc->term_mode = 0;
+    sc->deadline = J.limit_ticks > 0 ? (J.t0 ? *J.t0 : static_cast<long long>(wall_clock64())) + J.limit_ticks : 0;
 }
 
 __global__ void multi_status_kernel(const BatchJob* jobs, int count, int* status) {
@@ -2361,8 +2371,11 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 char* g_scratch_addr[kMaxDevices] = {};
 
-__global__ void zero_int_kernel(int* p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+__global__ void batch_start_kernel(int* counter, long long* t0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *counter = 0;
+        *t0 = static_cast<long long>(wall_clock64());
+    }
 }
 }  // namespace
 
@@ -2380,12 +2393,15 @@ hipError_t static_batch_scratch(int device, StaticBatchScratch* out) {
     out->jobs = reinterpret_cast<BatchJob*>(b);
     out->order = reinterpret_cast<int*>(b + kStaticJobsBytes);
     out->counter = reinterpret_cast<int*>(b + kStaticJobsBytes + kStaticOrderBytes);
+    out->t0 = reinterpret_cast<long long*>(b + kStaticJobsBytes + kStaticOrderBytes + 128);
     return hipSuccess;
 }
 
 size_t static_batch_scratch_bytes() { return kStaticScratchBytes; }
 
-void launch_zero_int(int* p, hipStream_t s) { hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, p); }
+void launch_batch_start(int* counter, long long* t0, hipStream_t s) {
+    hipLaunchKernelGGL(batch_start_kernel, dim3(1), dim3(64), 0, s, counter, t0);
+}
 
 void launch_to_float(const double* src, float* dst, long long n, hipStream_t s) {
     if (n <= 0) return;
