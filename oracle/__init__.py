@@ -68,7 +68,7 @@ class _OptsStruct(C.Structure):
         ("method", C.c_int32), ("pad3", C.c_int32), ("reflection", C.c_double),
         ("omega_steps", C.c_int32), ("pad4", C.c_int32), ("pw_rule", C.c_int32), ("pad5", C.c_int32),
         ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
-        ("term_mode", C.c_int32), ("pad6", C.c_int32),
+        ("term_mode", C.c_int32), ("ray_candidates", C.c_int32),
     ]
 
 
@@ -78,7 +78,7 @@ class _InfoStruct(C.Structure):
         ("restarts", C.c_int64), ("n_trace", C.c_int64), ("pobj", C.c_double), ("dobj", C.c_double),
         ("rel_p", C.c_double), ("rel_d", C.c_double), ("rel_gap", C.c_double), ("erel", C.c_double),
         ("sigma_max", C.c_double), ("eta", C.c_double), ("omega", C.c_double),
-        ("setup_s", C.c_double), ("iter_s", C.c_double),
+        ("setup_s", C.c_double), ("iter_s", C.c_double), ("ray_source", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -222,6 +222,7 @@ class Result:
     output_is_avg: bool
     trace: np.ndarray = field(default_factory=lambda: np.zeros((0, TRACE_W)))
     snaps: Optional[np.ndarray] = None
+    ray_source: int = 0  # candidate that gave a certificate: 1 displacement, 2 anchored average
 
 
 def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int = 64, scaling: bool = True,
@@ -229,9 +230,12 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
           omega0: float = 0.0, seed: int = 0x5EED0C0FFEE, x0=None, y0=None,
           snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8, method: int = 0,
           reflection: float = 1.0, omega_steps: int = 0, pw_rule: int = 0, pid_kp: Optional[float] = None,
-          pid_ki: Optional[float] = None, pid_kd: Optional[float] = None, term_mode: int = 0) -> Result:
+          pid_ki: Optional[float] = None, pid_kd: Optional[float] = None, term_mode: int = 0,
+          ray_candidates: int = 0) -> Result:
     """Run the oracle. `snap_k` lists iterations whose scaled-space state
-    (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration."""
+    (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration.
+    `ray_candidates`: 0 both candidate rays, 1 the displacement since the previous evaluation
+    only, 2 the averaged point's displacement from the restart anchor only."""
     b = _Bound(lp)
     o = _OptsStruct()
     lib().ora_default_opts(C.byref(o))
@@ -251,6 +255,7 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     o.omega_steps = omega_steps
     o.pw_rule = pw_rule
     o.term_mode = term_mode
+    o.ray_candidates = ray_candidates
     if pid_kp is not None:
         o.pid_kp = pid_kp
     if pid_ki is not None:
@@ -285,7 +290,8 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     ntr = min(int(info.n_trace), trace_cap)
     return Result(STATUS.get(info.status, str(info.status)), x, y[: lp.m], z, int(info.iters), int(info.restarts),
                   info.pobj, info.dobj, info.rel_p, info.rel_d, info.rel_gap, info.erel, info.sigma_max, info.eta,
-                  info.omega, info.setup_s, info.iter_s, bool(info.output_is_avg), trace[:ntr].copy(), snaps)
+                  info.omega, info.setup_s, info.iter_s, bool(info.output_is_avg), trace[:ntr].copy(), snaps,
+                  int(info.ray_source))
 
 
 def split_snap(snap: np.ndarray, n: int, m: int):

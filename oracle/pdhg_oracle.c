@@ -90,7 +90,9 @@ typedef struct {
     int32_t term_mode;   /* what must fall to eps_rel to stop: 0 E_rel, 1 the relative primal
                             residual alone, 2 the relative dual residual alone (the two
                             feasibility polishing solves) */
-    int32_t pad6;
+    int32_t ray_candidates; /* which candidate rays are tested: 0 both (default), 1 the
+                               displacement since the previous evaluation only, 2 the averaged
+                               point's displacement from the restart anchor only */
 } ora_opts;
 
 typedef struct {
@@ -100,6 +102,8 @@ typedef struct {
     double pobj, dobj, rel_p, rel_d, rel_gap, erel;
     double sigma_max, eta, omega;
     double setup_s, iter_s;
+    int32_t ray_source; /* candidate that gave the certificate: 1 displacement, 2 anchored average */
+    int32_t pad;
 } ora_info;
 
 /* ---------------------------------------------------------------- helpers */
@@ -384,9 +388,15 @@ static double kkt_omega(const kkt_t *K, double omega) {
 }
 
 /* Infeasibility certificates (the sign remarks after eq. (2): an LP with no solution of
- * eq. (2) is infeasible or unbounded). Reading: the candidate rays are the differences
- * between the iterate at this evaluation and the one at the previous evaluation (after its
- * restart decision), taken on the original scale:
+ * eq. (2) is infeasible or unbounded). Reading: a candidate ray is the difference of two
+ * points, taken on the original scale. Two candidates are tested at every evaluation, in
+ * this order: (1) the evaluated point minus the one of the previous evaluation (after its
+ * restart decision); (2) the averaged point (the running average; the PDHG output in the
+ * Halpern form) minus the anchor of the current restart cycle: for an LP without a
+ * solution the iterates drift along the infimal displacement, and the average's distance
+ * from the anchor grows along it about linearly in the iterations since the restart, with
+ * the oscillations of the iterates averaged out (the normalised average). For a pair
+ * (x~, y~) minus (x~p, y~p), with their products:
  *   dual ray   y^ = R (y~ - y~p), with lambda = -A^T y^ = -C^-1 (A~^T y~ - A~^T y~p) and
  *              z^ = lambda projected onto the sign cone of eq. (2);
  *              rd2 = ||lambda - z^||^2 + ||sign violations of y^||^2 (y^ > 0 where b_lo = -inf,
@@ -688,7 +698,8 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     /* point at the previous evaluation (after its restart decision), for the candidate rays */
     double *xp = (double *)malloc(nb), *atyp = (double *)malloc(nb);
     double *yp = (double *)malloc(mb), *axp = (double *)malloc(mb);
-    double *axan = (double *)malloc(mb); /* A~ x~ of the anchor (Halpern form) */
+    double *axan = (double *)malloc(mb); /* A~ x~ of the anchor */
+    double *atyan = (double *)malloc(nb); /* A~^T y~ of the anchor (anchored-average rays) */
     const int halpern = o->method == 1;
     const double rho = o->reflection;
 
@@ -722,6 +733,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     csr_mv(m, P.rp, P.ci, P.av, x, ax);
     csr_mv(n, P.rpT, P.ciT, P.avT, y, aty);
     memcpy(axan, ax, sizeof(double) * (size_t)m);
+    memcpy(atyan, aty, nb);
     memcpy(axa, ax, sizeof(double) * (size_t)m);
     memcpy(atya, aty, nb);
     kkt_t Kc, Ka, Kanc;
@@ -732,6 +744,8 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     memcpy(axp, ax, sizeof(double) * (size_t)m);
     ray_t Rray;
     memset(&Rray, 0, sizeof(Rray));
+    int ray_src = 0;
+    const int try_disp = o->ray_candidates != 2, try_anch = o->ray_candidates != 1;
     Kanc = Kc;
     double kkt_anchor = kkt_omega(&Kanc, omega);
     double kkt_prev = INFINITY;
@@ -837,10 +851,17 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             status = ORA_OPTIMAL;
             out_avg = 1;
         } else {
-            if (o->eps_infeas > 0.0) {
+            if (o->eps_infeas > 0.0 && try_disp) {
                 eval_rays(&P, ex, ey, eax, eaty, xp, yp, axp, atyp, &Rray, NULL, NULL, NULL);
                 if (Rray.D > 0.0 && sqrt(Rray.rd2) <= o->eps_infeas * Rray.D) status = ORA_PRIMAL_INFEASIBLE;
                 else if (Rray.G > 0.0 && sqrt(Rray.rp2) <= o->eps_infeas * Rray.G) status = ORA_DUAL_INFEASIBLE;
+                if (status >= 0) ray_src = 1;
+            }
+            if (status < 0 && o->eps_infeas > 0.0 && try_anch) {
+                eval_rays(&P, xa, ya, axa, atya, xan, yan, axan, atyan, &Rray, NULL, NULL, NULL);
+                if (Rray.D > 0.0 && sqrt(Rray.rd2) <= o->eps_infeas * Rray.D) status = ORA_PRIMAL_INFEASIBLE;
+                else if (Rray.G > 0.0 && sqrt(Rray.rp2) <= o->eps_infeas * Rray.G) status = ORA_DUAL_INFEASIBLE;
+                if (status >= 0) ray_src = 2;
             }
             if (status < 0 && k >= o->max_iters) {
                 status = ORA_ITERATION_LIMIT;
@@ -897,10 +918,13 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
                 memcpy(y, ya, sizeof(double) * (size_t)m);
                 memcpy(ax, axa, sizeof(double) * (size_t)m);
                 memcpy(axan, axa, sizeof(double) * (size_t)m);
+                memcpy(atyan, atya, nb);
                 Kanc = Ka;
             } else {
                 memcpy(xa, x, nb);
                 memcpy(ya, y, sizeof(double) * (size_t)m);
+                memcpy(axan, ax, sizeof(double) * (size_t)m);
+                memcpy(atyan, aty, nb);
                 Kanc = Kc;
             }
             memcpy(xan, x, nb);
@@ -948,7 +972,8 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     if (status == ORA_PRIMAL_INFEASIBLE || status == ORA_DUAL_INFEASIBLE) {
         /* the certificate, normalised so that D = 1 (dual ray in y, z) or G = 1 (primal ray in x) */
         double *xr = (double *)malloc(nb), *yr = (double *)malloc(mb), *zr = (double *)malloc(nb);
-        if (halpern) eval_rays(&P, xa, ya, axa, atya, xp, yp, axp, atyp, &Rray, xr, yr, zr);
+        if (ray_src == 2) eval_rays(&P, xa, ya, axa, atya, xan, yan, axan, atyan, &Rray, xr, yr, zr);
+        else if (halpern) eval_rays(&P, xa, ya, axa, atya, xp, yp, axp, atyp, &Rray, xr, yr, zr);
         else eval_rays(&P, x, y, ax, aty, xp, yp, axp, atyp, &Rray, xr, yr, zr);
         if (status == ORA_PRIMAL_INFEASIBLE) {
             double s = 1.0 / Rray.D;
@@ -966,6 +991,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         free(zr);
     }
     info->status = status;
+    info->ray_source = ray_src;
     info->output_is_avg = out_avg;
     info->iters = k;
     info->restarts = restarts;
@@ -979,7 +1005,7 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     info->sigma_max = sig;
     info->eta = eta;
     info->omega = omega;
-    free(xp); free(yp); free(axp); free(atyp); free(axan);
+    free(xp); free(yp); free(axp); free(atyp); free(axan); free(atyan);
     free(x); free(xa); free(xan); free(aty); free(atya);
     free(y); free(ya); free(yan); free(ax); free(axn); free(axa);
     prob_free(&P);

@@ -135,3 +135,95 @@ def test_no_false_certificate_on_feasible_lps(oracle_lib, j, method):
     lp = synth.cfg0(j) if j < 2 else synth.transportation(40 + 20 * j, np.random.default_rng(j))
     r = oracle_lib.solve(lp, eps_rel=1e-7, max_iters=200000, eps_infeas=EPS, method=method)
     assert r.status == "optimal"
+
+
+# ---- the second candidate ray: the averaged point's displacement from the restart anchor
+def _infeasible_cases():
+    cases = {name: lp for name, (lp, _) in infeasible_lps().items()}
+    for j in range(3):
+        rng = np.random.default_rng([synth.SEED_ROOT, 6, j])
+        base = synth.kkt_constructed(40, 80, synth.random_sparse_pattern(40, 80, 0.08, rng), rng, eq_frac=0.5)
+        cases[f"pinf{j}"] = _contradicting_rows(base, rng, 1 + j)
+    for j in range(3):
+        rng = np.random.default_rng([synth.SEED_ROOT, 7, j])
+        base = synth.kkt_constructed(40, 80, synth.random_sparse_pattern(40, 80, 0.08, rng), rng, eq_frac=0.3)
+        cases[f"unb{j}"] = _free_descent_column(base, rng)
+    return cases
+
+
+CASES = _infeasible_cases()
+
+
+def _check_certificate(lp, r):
+    if r.status == "primal_infeasible":
+        check_dual_ray(lp, r.y, r.z, 2 * EPS)
+    else:
+        assert r.status == "dual_infeasible", r.status
+        check_primal_ray(lp, r.x, 2 * EPS)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_anchored_average_ray_alone_certifies(oracle_lib, name, method):
+    """With only the anchored-average candidate tested, every LP without a solution still gets
+    a certificate that meets its definition."""
+    lp = CASES[name]
+    r = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=100000, eps_infeas=EPS, method=method, ray_candidates=2)
+    assert r.ray_source == 2
+    _check_certificate(lp, r)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_both_candidates_stop_at_the_first_of_either(oracle_lib, method):
+    """The candidates do not change the iterates, so with both tested the solve stops at the
+    first evaluation where either certifies, with that candidate's certificate (the
+    displacement first when both do), bit for bit."""
+    earlier = 0
+    for name, lp in CASES.items():
+        kw = dict(eps_rel=1e-8, max_iters=100000, eps_infeas=EPS, method=method)
+        r1 = oracle_lib.solve(lp, ray_candidates=1, **kw)
+        r2 = oracle_lib.solve(lp, ray_candidates=2, **kw)
+        rb = oracle_lib.solve(lp, **kw)
+        assert rb.iters == min(r1.iters, r2.iters), name
+        src = r1 if r1.iters <= r2.iters else r2
+        assert rb.ray_source == src.ray_source and rb.status == src.status, name
+        for a, b in ((rb.x, src.x), (rb.y, src.y), (rb.z, src.z)):
+            np.testing.assert_array_equal(a, b)
+        earlier += r2.iters < r1.iters
+    if method == 0:
+        assert earlier >= 1  # on these LPs the averaged candidate certifies first at least once
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("name", ["pinf1", "pinf2", "unb0", "unb1"])
+def test_anchored_ray_is_average_minus_anchor(oracle_lib, name, method):
+    """Recompute the anchored-average ray from snapshots: the anchor is the candidate chosen at
+    the last restart before the detecting evaluation (trace columns 6 and 7), or the start
+    point; the ray is C (x~avg - x~anchor) or R (y~avg - y~anchor), normalised."""
+    lp = CASES[name]
+    kw = dict(eps_rel=1e-8, max_iters=100000, eps_infeas=EPS, method=method, ray_candidates=2)
+    r = oracle_lib.solve(lp, **kw)
+    tr = r.trace
+    rst = [int(row[0]) for row in tr[:-1] if row[7] != 0]
+    k_r = rst[-1] if rst else 0
+    use_avg = {int(row[0]): int(row[6]) for row in tr}
+    snaps = [k_r, r.iters] if k_r else [r.iters]
+    rs = oracle_lib.solve(lp, snap_k=snaps, **kw)
+    assert rs.iters == r.iters and rs.status == r.status
+    n, m = lp.n, lp.m
+    _, R, Cc, _, _, _ = oracle_lib.scaled_problem(lp)
+    _, _, xa, ya = oracle_lib.split_snap(rs.snaps[-1], n, m)
+    if k_r:
+        x, y, xav, yav = oracle_lib.split_snap(rs.snaps[0], n, m)
+        xan, yan = (xav, yav) if use_avg[k_r] else (x, y)
+    else:  # the start point: x~ = clamp(0, x~lo, x~hi), y~ = 0
+        xan, yan = np.clip(0.0, lp.x_lo / Cc, lp.x_hi / Cc), np.zeros(m)
+    if r.status == "dual_infeasible":
+        d = Cc * (xa - xan)
+        expect = d / (-(lp.c @ d))
+        np.testing.assert_allclose(r.x, expect, rtol=1e-9, atol=1e-12 * np.max(np.abs(expect)))
+    else:
+        d = R * (ya - yan)
+        scale = r.y[np.argmax(np.abs(d))] / d[np.argmax(np.abs(d))]
+        assert scale > 0
+        np.testing.assert_allclose(r.y, scale * d, rtol=1e-9, atol=1e-12 * np.max(np.abs(r.y)))

@@ -45,6 +45,10 @@ MUTANTS = {
     "pid_derivative_sign": ("o->pid_kd * (e - pid_prev);", "o->pid_kd * (pid_prev - e);"),
     "polish_stops_on_wrong_residual": ("if (mode == 1) return isnan(K->erel) ? NAN : K->rel_p;",
                                        "if (mode == 1) return isnan(K->erel) ? NAN : K->rel_d;"),
+    "anchored_ray_from_previous_point": (
+        "eval_rays(&P, xa, ya, axa, atya, xan, yan, axan, atyan, &Rray, NULL, NULL, NULL);",
+        "eval_rays(&P, xa, ya, axa, atya, xp, yp, axp, atyp, &Rray, NULL, NULL, NULL);"),
+    "anchor_products_not_moved": ("memcpy(atyan, atya, nb);", "(void)0;"),
 }
 
 QUICK = [
