@@ -144,10 +144,13 @@ typedef struct lp_options {
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
     double eps_infeas;     /* relative tolerance of the infeasibility certificates (default 1e-8;
-                              0 turns the test off). At each evaluation after the first, the
-                              displacement of the iterate since the previous evaluation is
-                              tested as a dual ray (primal infeasibility) and as a primal ray
-                              (dual infeasibility); see LP_PRIMAL_INFEASIBLE / LP_DUAL_INFEASIBLE */
+                              0 turns the test off). At each evaluation after the first, two
+                              candidate rays are tested as a dual ray (primal infeasibility) and
+                              as a primal ray (dual infeasibility), in this order: the
+                              displacement of the evaluated point since the previous evaluation,
+                              then the averaged point (the PDHG output in the Halpern form)
+                              minus the anchor of the restart cycle; see LP_PRIMAL_INFEASIBLE /
+                              LP_DUAL_INFEASIBLE and lp_info.ray_source */
     int32_t method;        /* lp_method (default LP_METHOD_AVERAGED) */
     int32_t pad2;
     double reflection;     /* rho of LP_METHOD_HALPERN, in [0, 1] (default 1) */
@@ -200,6 +203,11 @@ typedef struct lp_info {
     double clock_hz;       /* rate of that clock */
     int64_t polish_primal_iterations, polish_dual_iterations; /* of the last lp_polish (0 after lp_solve) */
     double polish_seconds; /* last lp_polish */
+    int32_t ray_source;    /* with a certificate (status 4 or 5), the candidate ray it came from:
+                              1 the displacement of the evaluated point since the previous
+                              evaluation, 2 the averaged point (the PDHG output in the Halpern
+                              form) minus the restart anchor; 0 otherwise */
+    int32_t pad0;
 } lp_info;
 
 /* Fill *opt with the defaults listed above. */

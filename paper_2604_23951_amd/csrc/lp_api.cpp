@@ -92,7 +92,7 @@ struct Prep {
 struct Offsets {
     size_t arp, aci, av, at, trp, tci, tv, tt, perm, c, xl, xu, C, Ci, bl, bu, R, Ri;
     size_t x, xa, xan, aty, atya, ox, oz, y, ya, yan, ax, axa, oy, x0, y0;
-    size_t xp, atyp, yp, axp, axan;
+    size_t xp, atyp, yp, axp, axan, atyan;
     size_t f32[15] = {0};
     size_t pA[7] = {0}, pAT[7] = {0}, pA32 = 0, pAT32 = 0;
     size_t part, sc, tr;
@@ -333,6 +333,7 @@ void fill_info(lp_handle* h) {
     inf.step_size = sc.eta;
     inf.omega = sc.omega;
     inf.done_clock = sc.done_clock;
+    inf.ray_source = (sc.status == LP_PRIMAL_INFEASIBLE || sc.status == LP_DUAL_INFEASIBLE) ? sc.ray_src : 0;
     int khz = 0;
     inf.clock_hz = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess ? 1e3 * khz : 0.0;
 }
@@ -840,6 +841,7 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
     O->yp = L.add(sm);
     O->axp = L.add(sm);
     O->axan = L.add(sm);
+    O->atyan = L.add(sn);
     O->x0 = h->has_x0 ? L.add(sn) : 0;
     O->y0 = h->has_y0 ? L.add(sm) : 0;
     const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
@@ -1017,6 +1019,7 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.yp = D(O.yp);
     P.axp = D(O.axp);
     P.axan = D(O.axan);
+    P.atyan = D(O.atyan);
     P.partials = D(O.part);
     P.sc = reinterpret_cast<Scalars*>(b + O.sc);
     P.trace = o.trace_cap > 0 ? D(O.tr) : nullptr;

@@ -17,7 +17,7 @@ __host__ __device__ constexpr int tile_nnz_of(int shape) { return 1024 << shape;
 constexpr int kTileNnzMax = 4096;
 constexpr int kMaxRedBlocks = 512;
 constexpr int kNQ = 8;            // reduced quantities per candidate
-constexpr int kNR = 4;            // reduced quantities of the candidate rays (infeasibility)
+constexpr int kNR = 8;            // reduced quantities of the two candidate rays (infeasibility), 4 each
 constexpr int kNT = 2 * kNQ + kNR;  // all reduced quantities of one evaluation
 constexpr int kTraceW = 12;
 
@@ -49,6 +49,7 @@ struct Scalars {
     int eval_every;
     int restarts_on;
     int term_mode;     // what must fall to eps_rel to stop: 0 E_rel, 1 rel. primal residual, 2 rel. dual residual
+    int ray_src;       // candidate ray of a certificate: 1 displacement since the previous evaluation, 2 anchored average
 };
 
 // CSR matrix with its LDS tiling: tile b covers rows [tiles[b], tiles[b+1]), or, when
@@ -109,7 +110,7 @@ struct DevLP {
     double *ax, *axa, *aty, *atya;    // A~x, A~x_avg, A~^T y, A~^T y_avg
     double *xan, *yan;                // anchor (start of the current restart cycle)
     double *xp, *yp, *axp, *atyp;     // point of the previous evaluation (candidate rays)
-    double *axan;                     // A~x of the anchor (Halpern form)
+    double *axan, *atyan;             // A~x, A~^T y of the anchor
     // iteration form of the current solve: 0 averaged PDHG, 1 reflected Halpern PDHG with
     // reflection rho. In the Halpern form (x, y, ax) is the Halpern iterate and (xa, ya, axa)
     // the PDHG output T(z), the only candidate of the evaluations.

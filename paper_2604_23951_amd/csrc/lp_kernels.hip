@@ -1078,6 +1078,7 @@ __global__ void reset_kernel(Scalars* sc, double eps_rel, double eps_infeas, lon
     sc->eps_rel = eps_rel;
     sc->eps_infeas = eps_infeas;
     sc->ray_scale = 0.0;
+    sc->ray_src = 0;
     sc->max_iters = max_iters;
     sc->eval_every = eval_every;
     sc->restarts_on = restarts_on;
@@ -1159,16 +1160,19 @@ __device__ inline void col_terms(const DevLP& P, int j, const double* x, const d
     acc[6] += dx * dx;
 }
 
-// Candidate rays for the infeasibility certificates: the displacement of the iterate since
-// the previous evaluation, on the original scale. acc: 0 rd2, 1 D, 2 rp2, 3 G, where
-//   dual ray y^ = R (y~ - y~p), lambda = -C^-1 (A~^T y~ - A~^T y~p), z^ = lambda projected on
+// Candidate rays for the infeasibility certificates: the difference of two points (y~, A~x~)
+// minus (y~b, A~x~b) on the original scale: the displacement of the evaluated point since the
+// previous evaluation (base: the saved previous point), or the averaged point minus the
+// restart anchor. acc: 0 rd2, 1 D, 2 rp2, 3 G, where
+//   dual ray y^ = R (y~ - y~b), lambda = -C^-1 (A~^T y~ - A~^T y~b), z^ = lambda projected on
 //   the sign cone of eq. 2: rd2 = ||lambda - z^||^2 + ||sign violations of y^||^2,
 //   D = sum_i (b_lo y^+ - b_hi y^-) + sum_k (x_lo z^+ - x_hi z^-) over finite bounds;
-//   primal ray x^ = C (x~ - x~p), A x^ = R^-1 (A~x~ - A~x~p): rp2 = squared parts of A x^ and
+//   primal ray x^ = C (x~ - x~b), A x^ = R^-1 (A~x~ - A~x~b): rp2 = squared parts of A x^ and
 //   x^ outside the recession cones of the row and variable bounds, G = -c^T x^.
-__device__ inline void row_ray_terms(const DevLP& P, int i, const double* y, const double* ax, double* acc) {
-    const double dy = (y[i] - P.yp[i]) * P.R[i];
-    const double v = (ax[i] - P.axp[i]) * P.Ri[i];
+__device__ inline void row_ray_terms(const DevLP& P, int i, const double* y, const double* ax, const double* yb,
+                                     const double* axb, double* acc) {
+    const double dy = (y[i] - yb[i]) * P.R[i];
+    const double v = (ax[i] - axb[i]) * P.Ri[i];
     const double bl = P.bl[i], bu = P.bu[i], Ri = P.Ri[i];
     const bool flo = finite_d(bl), fhi = finite_d(bu);
     if (dy > 0.0 && flo) acc[1] += (bl * Ri) * dy;
@@ -1184,8 +1188,9 @@ __device__ inline void row_ray_terms(const DevLP& P, int i, const double* y, con
     acc[2] += w * w;
 }
 
-__device__ inline void col_ray_terms(const DevLP& P, int j, const double* x, const double* aty, double* acc) {
-    const double lam = -(aty[j] - P.atyp[j]) * P.Ci[j];
+__device__ inline void col_ray_terms(const DevLP& P, int j, const double* x, const double* aty, const double* xb,
+                                     const double* atyb, double* acc) {
+    const double lam = -(aty[j] - atyb[j]) * P.Ci[j];
     const double lo = P.xl[j], hi = P.xu[j], Cj = P.C[j];
     const bool flo = finite_d(lo), fhi = finite_d(hi);
     double zs = lam;
@@ -1196,7 +1201,7 @@ __device__ inline void col_ray_terms(const DevLP& P, int j, const double* x, con
     acc[0] += r * r;
     if (zs > 0.0) acc[1] += (lo * Cj) * zs;
     if (zs < 0.0) acc[1] += (hi * Cj) * zs;
-    const double xh = (x[j] - P.xp[j]) * Cj;
+    const double xh = (x[j] - xb[j]) * Cj;
     acc[3] -= (P.c[j] * P.Ci[j]) * xh;
     double w = 0.0;
     if (flo && fhi) w = xh;
@@ -1206,9 +1211,10 @@ __device__ inline void col_ray_terms(const DevLP& P, int j, const double* x, con
 }
 
 // Per-thread sums of one evaluation over rows and columns start, start + stride, ...
-// Averaged form, mode 0: the current iterate (slots 0..7), the running average (8..15) and the
-// candidate rays of the current iterate (16..19). Halpern form, mode 0: the PDHG output
-// (xa, ya) in slots 0..7 and its rays. Modes 1 and 2: the current iterate only.
+// Averaged form, mode 0: the current iterate (slots 0..7), the running average (8..15), the
+// displacement ray of the current iterate (16..19) and the anchored ray of the average
+// (20..23). Halpern form, mode 0: the PDHG output (xa, ya) in slots 0..7 and its two rays.
+// Modes 1 and 2: the current iterate only.
 __device__ inline void eval_terms(const DevLP& P, int mode, int start, int stride, double* acc) {
     const bool both = mode == 0 && !P.method;
     const bool cand = (mode == 0 || mode == 2) && P.method;
@@ -1220,12 +1226,18 @@ __device__ inline void eval_terms(const DevLP& P, int mode, int start, int strid
     for (int i = start; i < P.m; i += stride) {
         row_terms(P, i, eax, ey, acc);
         if (both) row_terms(P, i, P.axa, P.ya, acc + kNQ);
-        if (rays) row_ray_terms(P, i, ey, eax, acc + 2 * kNQ);
+        if (rays) {
+            row_ray_terms(P, i, ey, eax, P.yp, P.axp, acc + 2 * kNQ);
+            row_ray_terms(P, i, P.ya, P.axa, P.yan, P.axan, acc + 2 * kNQ + 4);
+        }
     }
     for (int j = start; j < P.n; j += stride) {
         col_terms(P, j, ex, eaty, acc);
         if (both) col_terms(P, j, P.xa, P.atya, acc + kNQ);
-        if (rays) col_ray_terms(P, j, ex, eaty, acc + 2 * kNQ);
+        if (rays) {
+            col_ray_terms(P, j, ex, eaty, P.xp, P.atyp, acc + 2 * kNQ);
+            col_ray_terms(P, j, P.xa, P.atya, P.xan, P.atyan, acc + 2 * kNQ + 4);
+        }
     }
 }
 
@@ -1368,13 +1380,17 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
         out_avg = 1;
     } else {
         if (sc->eps_infeas > 0.0 && P.xp != nullptr) {
-            const double* ray = tot + 2 * kNQ;  // rd2, D, rp2, G
-            if (ray[1] > 0.0 && sqrt(ray[0]) <= sc->eps_infeas * ray[1]) {
-                status = 4;
-                sc->ray_scale = 1.0 / ray[1];
-            } else if (ray[3] > 0.0 && sqrt(ray[2]) <= sc->eps_infeas * ray[3]) {
-                status = 5;
-                sc->ray_scale = 1.0 / ray[3];
+            // the displacement ray first, then the anchored ray of the average
+            for (int src = 1; src <= 2 && status == kRunning; ++src) {
+                const double* ray = tot + 2 * kNQ + 4 * (src - 1);  // rd2, D, rp2, G
+                if (ray[1] > 0.0 && sqrt(ray[0]) <= sc->eps_infeas * ray[1]) {
+                    status = 4;
+                    sc->ray_scale = 1.0 / ray[1];
+                } else if (ray[3] > 0.0 && sqrt(ray[2]) <= sc->eps_infeas * ray[3]) {
+                    status = 5;
+                    sc->ray_scale = 1.0 / ray[3];
+                }
+                if (status != kRunning) sc->ray_src = src;
             }
         }
         if (status != kRunning) out_avg = halpern;
@@ -1490,6 +1506,7 @@ __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
             P.xa[g] = v;
         }
         P.xan[g] = v;
+        P.atyan[g] = lr == 2 ? P.atya[g] : P.aty[g];
     }
     if (g < P.m) {
         double v;
@@ -1497,10 +1514,11 @@ __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
             v = P.ya[g];
             P.y[g] = v;
             P.ax[g] = P.axa[g];
-            if (P.method) P.axan[g] = P.axa[g];
+            P.axan[g] = P.axa[g];
         } else {
             v = P.y[g];
             P.ya[g] = v;
+            P.axan[g] = P.ax[g];
         }
         P.yan[g] = v;
     }
@@ -1512,11 +1530,14 @@ __device__ inline void apply_restart_at(const DevLP& P, int lr, int g) {
 // evaluation (init) it equals the start, whose products A~x, A~^T y also seed axa, atya and
 // the anchor's A~x.
 __device__ inline void save_prev_at(const DevLP& P, int lr, bool init, int g) {
-    if (init && P.method) {
-        if (g < P.n) P.atya[g] = P.aty[g];
+    if (init) {  // the start is the first anchor
+        if (g < P.n) {
+            P.atyan[g] = P.aty[g];
+            if (P.method) P.atya[g] = P.aty[g];
+        }
         if (g < P.m) {
-            P.axa[g] = P.ax[g];
             P.axan[g] = P.ax[g];
+            if (P.method) P.axa[g] = P.ax[g];
         }
     }
     if (P.xp == nullptr) return;
@@ -1554,21 +1575,26 @@ __global__ void stop_kernel(Scalars* sc, int status) {
 // Returned point on the original scale: x = C x~, y = R y~, z = projected reduced cost.
 // With a certificate (status 4: primal infeasible, 5: dual infeasible) the ray replaces the
 // dual pair (y, z) or the primal x, scaled by `scale` so that its ray objective is 1.
-__device__ inline void extract_at(const DevLP& P, int avg, int status, double scale, int g) {
+__device__ inline void extract_at(const DevLP& P, int avg, int status, double scale, int src, int g) {
     const double* xs = avg ? P.xa : P.x;
     const double* ys = avg ? P.ya : P.y;
     const double* at = avg ? P.atya : P.aty;
     const bool dual_ray = status == 4 && P.xp != nullptr;
     const bool primal_ray = status == 5 && P.xp != nullptr;
-    // the rays start at the evaluated point: (x, y) or, in the Halpern form, the PDHG output
-    const double* rx = P.method ? P.xa : P.x;
-    const double* ry = P.method ? P.ya : P.y;
-    const double* raty = P.method ? P.atya : P.aty;
+    // a ray is the evaluated point ((x, y), or in the Halpern form the PDHG output) minus the
+    // previous evaluation's point, or (src 2) the averaged point minus the anchor
+    const bool anch = src == 2;
+    const double* rx = (P.method || anch) ? P.xa : P.x;
+    const double* ry = (P.method || anch) ? P.ya : P.y;
+    const double* raty = (P.method || anch) ? P.atya : P.aty;
+    const double* bx = anch ? P.xan : P.xp;
+    const double* by = anch ? P.yan : P.yp;
+    const double* baty = anch ? P.atyan : P.atyp;
     if (g < P.n) {
-        P.out_x[g] = primal_ray ? ((rx[g] - P.xp[g]) * P.C[g]) * scale : xs[g] * P.C[g];
+        P.out_x[g] = primal_ray ? ((rx[g] - bx[g]) * P.C[g]) * scale : xs[g] * P.C[g];
         const bool flo = finite_d(P.xl[g]), fhi = finite_d(P.xu[g]);
         if (dual_ray) {
-            const double lam = -(raty[g] - P.atyp[g]) * P.Ci[g];
+            const double lam = -(raty[g] - baty[g]) * P.Ci[g];
             double zs = lam;
             if (!flo && !fhi) zs = 0.0;
             else if (flo && !fhi) zs = lam > 0.0 ? lam : 0.0;
@@ -1583,11 +1609,11 @@ __device__ inline void extract_at(const DevLP& P, int avg, int status, double sc
             P.out_z[g] = zs * P.Ci[g];
         }
     }
-    if (g < P.m) P.out_y[g] = dual_ray ? ((ry[g] - P.yp[g]) * P.R[g]) * scale : ys[g] * P.R[g];
+    if (g < P.m) P.out_y[g] = dual_ray ? ((ry[g] - by[g]) * P.R[g]) * scale : ys[g] * P.R[g];
 }
 
 __global__ void extract_kernel(DevLP P) {
-    extract_at(P, P.sc->out_avg, P.sc->status, P.sc->ray_scale, blockIdx.x * blockDim.x + threadIdx.x);
+    extract_at(P, P.sc->out_avg, P.sc->status, P.sc->ray_scale, P.sc->ray_src, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 
@@ -1618,6 +1644,7 @@ __device__ inline void rebase_at(const DevLP& P, int lr, int g) {
         const double at = avg ? P.atya[g] : P.aty[g];
         P.xh[g] = xc;
         P.xan[g] = xc;
+        P.atyan[g] = at;
         P.d32[g] = static_cast<float>(P.c[g] - at);
         P.lo32[g] = static_cast<float>(P.xl[g] - xc);
         P.hi32[g] = static_cast<float>(P.xu[g] - xc);
@@ -1629,6 +1656,7 @@ __device__ inline void rebase_at(const DevLP& P, int lr, int g) {
         const double ax = avg ? P.axa[g] : P.ax[g];
         P.yh[g] = yc;
         P.yan[g] = yc;
+        P.axan[g] = ax;
         P.yh32[g] = static_cast<float>(yc);
         P.rl32[g] = static_cast<float>(P.bl[g] - ax);
         P.ru32[g] = static_cast<float>(P.bu[g] - ax);
@@ -1721,6 +1749,7 @@ __device__ void wg_solve(const DevLP& P, const BatchJob& J, Scalars* ssc, double
         ssc->pid_int = 0.0;
         ssc->pid_prev = 0.0;
         ssc->term_mode = 0;
+        ssc->ray_src = 0;
         ssc->deadline = J.limit_ticks > 0
                             ? (J.t0 ? *J.t0 : static_cast<long long>(wall_clock64())) + J.limit_ticks
                             : 0;
@@ -1789,7 +1818,7 @@ __device__ void wg_solve(const DevLP& P, const BatchJob& J, Scalars* ssc, double
             __syncthreads();
         }
     }
-    for (int g = tid; g < mx; g += kBlock) extract_at(P, ssc->out_avg, ssc->status, ssc->ray_scale, g);
+    for (int g = tid; g < mx; g += kBlock) extract_at(P, ssc->out_avg, ssc->status, ssc->ray_scale, ssc->ray_src, g);
     __syncthreads();
     if (tid == 0) *P.sc = *ssc;
 }
@@ -2027,7 +2056,7 @@ __global__ __launch_bounds__(kBlock) void multi_elem_kernel(const BatchJob* jobs
         if (P.fp32) rebase_at(P, lr, g);
         else apply_restart_at(P, lr, g);
     } else {
-        extract_at(P, sc->out_avg, sc->status, sc->ray_scale, g);
+        extract_at(P, sc->out_avg, sc->status, sc->ray_scale, sc->ray_src, g);
     }
 }
 
@@ -2056,6 +2085,7 @@ __global__ void multi_reset_kernel(const BatchJob* jobs, int count) {
     sc->pid_int = 0.0;
     sc->pid_prev = 0.0;
     sc->term_mode = 0;
+    sc->ray_src = 0;
     sc->deadline = J.limit_ticks > 0 ? (J.t0 ? *J.t0 : static_cast<long long>(wall_clock64())) + J.limit_ticks : 0;
 }
 
