@@ -60,3 +60,13 @@ def test_polish_errors():
         s.solve()
         with pytest.raises(lpg.LpError):
             s.polish(eps=0.0)
+
+
+def test_polish_refused_after_a_certificate():
+    from test_oracle_infeasible import infeasible_lps
+
+    lp, _ = infeasible_lps()["I1"]
+    with lpg.Solver(lp, eps_rel=1e-8, max_iters=10000) as s:
+        assert s.solve().status == "primal_infeasible"
+        with pytest.raises(lpg.LpError):
+            s.polish()

@@ -21,7 +21,7 @@ SAN = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=unde
        "-shared-libsan"]
 TESTS = ["tests/test_abi.py", "tests/test_presolve.py", "tests/test_panel_layout.py", "tests/test_oracle_pins.py",
          "tests/test_oracle_exact.py", "tests/test_oracle_structure.py", "tests/test_oracle_infeasible.py",
-         "tests/test_oracle_halpern.py", "tests/test_oracle_restarts.py"]
+         "tests/test_oracle_halpern.py", "tests/test_oracle_restarts.py", "tests/test_oracle_polish.py"]
 
 
 def _runtime():
