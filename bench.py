@@ -35,6 +35,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# Random 8-byte gathers in the panel-sweep pattern of the product kernels (12-byte entries,
+# 8-32 column panels, 4 waves per CU) peaked at 1.66e11 gathers/s in a micro-benchmark on
+# MI355X: one L1-to-L2 request per gathered entry, bounded by the requests a CU keeps in
+# flight. A product of nnz entries therefore needs at least nnz / 1.66e11 s.
+GATHER_CEILING_PER_S = 1.66e11
 METRIC = "PDHG iters/s & HBM GB/s vs roofline; batched LPs/s to 1e-4 KKT, p50/p99"
 
 
@@ -772,7 +777,10 @@ def main(argv=None):
                    "layout": layout_info},
         "roofline": {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["kernel"],
-                     "alg_bytes_per_launch": dom["bytes"], "avg_launch_ms": dom["ms"]},
+                     "alg_bytes_per_launch": dom["bytes"], "avg_launch_ms": dom["ms"],
+                     "gather_ceiling": {"gathers_per_launch": nnz, "rate_per_s": GATHER_CEILING_PER_S,
+                                        "min_launch_ms": nnz / GATHER_CEILING_PER_S * 1e3,
+                                        "frac": (nnz / GATHER_CEILING_PER_S * 1e3) / dom["ms"]}},
         "kernels": {"primal_ms": p_ms, "primal_alg_bytes": bp, "primal_gbs": gbs_p,
                     "dual_ms": d_ms, "dual_alg_bytes": bd, "dual_gbs": gbs_d, "samples": samples},
         "iteration_alg_bytes": iter_bytes,
