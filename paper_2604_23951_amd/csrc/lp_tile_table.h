@@ -16,30 +16,46 @@ struct TileRule {
 
 // TUNED-TABLE-BEGIN (generated; a class the sweep did not measure takes shape 1)
 constexpr TileRule kTileRules[] = {
-    {0, 6.0, 20000, 2},  // 1024: 117.5 ms, 2048: 85.0 ms, 4096: 72.9 ms
-    {0, 6.0, 500000, 0},  // 1024: 17.4 ms, 2048: 17.7 ms, 4096: 17.8 ms
-    {0, 6.0, INT64_MAX, 0},  // 1024: 7.8 ms, 2048: 8.0 ms, 4096: 8.1 ms
-    {0, 12.0, 20000, 2},  // 1024: 67.2 ms, 2048: 53.1 ms, 4096: 45.7 ms
-    {0, 12.0, 500000, 0},  // 1024: 8.0 ms, 2048: 8.3 ms, 4096: 9.4 ms
-    {0, 12.0, INT64_MAX, 1},  // 1024: 4.7 ms, 2048: 4.6 ms, 4096: 5.2 ms
-    {0, 24.0, 20000, 2},  // 1024: 61.8 ms, 2048: 44.0 ms, 4096: 35.8 ms
-    {0, 24.0, 500000, 0},  // 1024: 7.0 ms, 2048: 7.2 ms, 4096: 8.1 ms
-    {0, 24.0, INT64_MAX, 0},  // 1024: 3.4 ms, 2048: 3.5 ms, 4096: 3.5 ms
-    {0, 1e300, 20000, 2},  // 1024: 66.2 ms, 2048: 44.3 ms, 4096: 32.7 ms
-    {0, 1e300, 500000, 1},  // 1024: 7.8 ms, 2048: 7.3 ms, 4096: 7.8 ms
-    {0, 1e300, INT64_MAX, 1},  // 1024: 4.2 ms, 2048: 3.9 ms, 4096: 4.2 ms
-    {1, 6.0, 20000, 2},  // 1024: 99.4 ms, 2048: 70.9 ms, 4096: 56.9 ms
-    {1, 6.0, 500000, 1},  // 1024: 9.3 ms, 2048: 8.7 ms, 4096: 9.6 ms
-    {1, 6.0, INT64_MAX, 1},  // 1024: 6.6 ms, 2048: 6.5 ms, 4096: 6.6 ms
-    {1, 12.0, 20000, 2},  // 1024: 57.1 ms, 2048: 41.3 ms, 4096: 34.5 ms
-    {1, 12.0, 500000, 1},  // 1024: 5.5 ms, 2048: 5.3 ms, 4096: 5.8 ms
-    {1, 12.0, INT64_MAX, 1},  // 1024: 3.6 ms, 2048: 3.6 ms, 4096: 4.0 ms
-    {1, 24.0, 20000, 2},  // 1024: 50.0 ms, 2048: 35.5 ms, 4096: 29.4 ms
-    {1, 24.0, 500000, 1},  // 1024: 6.2 ms, 2048: 5.7 ms, 4096: 6.3 ms
-    {1, 24.0, INT64_MAX, 1},  // 1024: 3.8 ms, 2048: 3.3 ms, 4096: 3.6 ms
-    {1, 1e300, 20000, 2},  // 1024: 63.8 ms, 2048: 40.8 ms, 4096: 29.7 ms
-    {1, 1e300, 500000, 1},  // 1024: 5.0 ms, 2048: 4.8 ms, 4096: 5.6 ms
-    {1, 1e300, INT64_MAX, 1},  // 1024: 3.7 ms, 2048: 3.2 ms, 4096: 3.4 ms
+    {0, 6.0, 1024, 1},  // 1024: 19.9 ms, 2048: 16.2 ms, 4096: 16.8 ms
+    {0, 6.0, 2048, 2},  // 1024: 30.1 ms, 2048: 27.2 ms, 4096: 26.9 ms
+    {0, 6.0, 20000, 2},  // 1024: 123.2 ms, 2048: 89.3 ms, 4096: 78.5 ms
+    {0, 6.0, 500000, 1},  // 1024: 12.4 ms, 2048: 11.7 ms, 4096: 12.8 ms
+    {0, 6.0, INT64_MAX, 0},  // 1024: 5.9 ms, 2048: 6.4 ms, 4096: 6.6 ms
+    {0, 12.0, 1024, 0},  // 1024: 11.7 ms, 2048: 11.8 ms, 4096: 15.4 ms
+    {0, 12.0, 2048, 1},  // 1024: 17.9 ms, 2048: 16.9 ms, 4096: 17.4 ms
+    {0, 12.0, 20000, 2},  // 1024: 59.4 ms, 2048: 43.1 ms, 4096: 38.5 ms
+    {0, 12.0, 500000, 2},  // 1024: 11.8 ms, 2048: 11.5 ms, 4096: 11.2 ms
+    {0, 12.0, INT64_MAX, 0},  // 1024: 4.7 ms, 2048: 5.2 ms, 4096: 5.1 ms
+    {0, 24.0, 1024, 0},  // 1024: 9.6 ms, 2048: 11.5 ms, 4096: 15.4 ms
+    {0, 24.0, 2048, 1},  // 1024: 16.4 ms, 2048: 12.4 ms, 4096: 16.1 ms
+    {0, 24.0, 20000, 2},  // 1024: 53.6 ms, 2048: 36.1 ms, 4096: 33.2 ms
+    {0, 24.0, 500000, 2},  // 1024: 9.9 ms, 2048: 10.0 ms, 4096: 9.6 ms
+    {0, 24.0, INT64_MAX, 1},  // 1024: 5.3 ms, 2048: 5.0 ms, 4096: 5.2 ms
+    {0, 1e300, 1024, 0},  // 1024: 9.6 ms, 2048: 11.8 ms, 4096: 15.7 ms
+    {0, 1e300, 2048, 1},  // 1024: 18.1 ms, 2048: 12.5 ms, 4096: 16.6 ms
+    {0, 1e300, 20000, 2},  // 1024: 63.7 ms, 2048: 43.9 ms, 4096: 34.0 ms
+    {0, 1e300, 500000, 2},  // 1024: 8.4 ms, 2048: 8.6 ms, 4096: 7.8 ms
+    {0, 1e300, INT64_MAX, 0},  // 1024: 3.7 ms, 2048: 3.9 ms, 4096: 4.1 ms
+    {1, 6.0, 1024, 2},  // 1024: 15.2 ms, 2048: 13.7 ms, 4096: 13.3 ms
+    {1, 6.0, 2048, 2},  // 1024: 25.2 ms, 2048: 21.1 ms, 4096: 20.2 ms
+    {1, 6.0, 20000, 2},  // 1024: 100.0 ms, 2048: 68.8 ms, 4096: 56.3 ms
+    {1, 6.0, 500000, 1},  // 1024: 6.7 ms, 2048: 6.6 ms, 4096: 6.9 ms
+    {1, 6.0, INT64_MAX, 0},  // 1024: 5.0 ms, 2048: 5.1 ms, 4096: 5.5 ms
+    {1, 12.0, 1024, 0},  // 1024: 8.6 ms, 2048: 9.8 ms, 4096: 12.6 ms
+    {1, 12.0, 2048, 1},  // 1024: 14.3 ms, 2048: 10.7 ms, 4096: 13.2 ms
+    {1, 12.0, 20000, 2},  // 1024: 55.6 ms, 2048: 40.5 ms, 4096: 33.7 ms
+    {1, 12.0, 500000, 1},  // 1024: 8.4 ms, 2048: 7.8 ms, 4096: 8.2 ms
+    {1, 12.0, INT64_MAX, 1},  // 1024: 4.7 ms, 2048: 4.3 ms, 4096: 4.5 ms
+    {1, 24.0, 1024, 0},  // 1024: 9.1 ms, 2048: 10.4 ms, 4096: 12.9 ms
+    {1, 24.0, 2048, 1},  // 1024: 15.2 ms, 2048: 10.7 ms, 4096: 13.3 ms
+    {1, 24.0, 20000, 2},  // 1024: 59.3 ms, 2048: 39.4 ms, 4096: 31.8 ms
+    {1, 24.0, 500000, 1},  // 1024: 5.6 ms, 2048: 4.7 ms, 4096: 5.3 ms
+    {1, 24.0, INT64_MAX, 1},  // 1024: 3.8 ms, 2048: 3.5 ms, 4096: 3.8 ms
+    {1, 1e300, 1024, 0},  // 1024: 9.6 ms, 2048: 10.6 ms, 4096: 12.8 ms
+    {1, 1e300, 2048, 1},  // 1024: 16.5 ms, 2048: 11.4 ms, 4096: 14.0 ms
+    {1, 1e300, 20000, 2},  // 1024: 61.3 ms, 2048: 39.0 ms, 4096: 30.0 ms
+    {1, 1e300, 500000, 1},  // 1024: 6.5 ms, 2048: 5.5 ms, 4096: 5.9 ms
+    {1, 1e300, INT64_MAX, 1},  // 1024: 3.4 ms, 2048: 3.4 ms, 4096: 3.5 ms
 };
 constexpr const char* kTileTableSource = "tune_tiles.py on AMD Radeon Graphics, 2026-12-03";
 // TUNED-TABLE-END

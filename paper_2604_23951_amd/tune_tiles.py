@@ -4,7 +4,9 @@ For each LP class (precision x mean row length of A x size), a set of synthetic 
 class (KKT-constructed, random sparse pattern with the class's row length, n = 2m) is solved
 with lp_solve_batch for a fixed number of iterations with every row-tile shape (1024, 2048
 and 4096 nonzeros per tile), LPs at or below 20000 nonzeros in the persistent launch and the
-larger ones in the block-diagonal launches, as in a production batch. The fastest shape of
+larger ones in the block-diagonal launches, as in a production batch. The two smallest size
+classes hold fewer LPs than the device has compute units, so their time is the iteration
+latency of one workgroup, which sets a batch's time when one small LP needs many iterations. The fastest shape of
 each class becomes a rule of csrc/lp_tile_table.h, which the library reads at lp_create
 when tile_nnz is 0:
 
@@ -27,7 +29,9 @@ TABLE = os.path.join(HERE, "csrc", "lp_tile_table.h")
 SHAPES = (1024, 2048, 4096)
 ROW_LEN_EDGES = (6.0, 12.0, 24.0, math.inf)   # mean nonzeros per row of A
 SIZE_CLASSES = (                              # (max nnz, LPs, nnz range, iterations)
-    (20000, 48, (2000, 20000), 640),
+    (1024, 24, (200, 1024), 2000),            # fewer LPs than CUs: the time is one LP's latency
+    (2048, 24, (1025, 2048), 2000),
+    (20000, 48, (2049, 20000), 640),
     (500000, 6, (50000, 500000), 256),
     (2**62, 1, (1000000, 1500000), 128),
 )
