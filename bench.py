@@ -88,7 +88,7 @@ def run_cpu_baseline(lp, iters: int) -> dict:
                       f"{r.iter_s:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
 
 
-def run_cpu_baseline_batch(lps, method: int, budget_s: float = 20.0) -> dict:
+def run_cpu_baseline_batch(lps, method: int, budget_s: float = 20.0, eval_every: int = 64) -> dict:
     """The oracle as it stands, single-threaded, solving LPs of the batch one after another
     to E_rel 1e-4 (same method) in index order (sizes are random in that order) until
     about `budget_s` seconds of solve time have been spent."""
@@ -97,7 +97,7 @@ def run_cpu_baseline_batch(lps, method: int, budget_s: float = 20.0) -> dict:
     spent = 0.0
     done = 0
     for lp in lps:
-        r = oracle.solve(lp, eps_rel=1e-4, max_iters=400000, method=method)
+        r = oracle.solve(lp, eps_rel=1e-4, max_iters=400000, method=method, eval_every=eval_every)
         spent += r.setup_s + r.iter_s
         done += 1
         if spent >= budget_s:
@@ -107,7 +107,8 @@ def run_cpu_baseline_batch(lps, method: int, budget_s: float = 20.0) -> dict:
                       f"method, setup included, {spent:.1f} s of CPU time on '{cpu_model()}' (nproc={os.cpu_count()})"}
 
 
-def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budget_s: float = 0.0) -> dict:
+def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budget_s: float = 0.0,
+              eval_every: int = 64) -> dict:
     """Batched workload: `count` LPs of the 4096-LP batch (every (4096 / count)-th; m
     log-uniform in [50, 5000], n = 2m, random-sparse with density U[0.5%, 5%] for even j,
     transportation for odd j), solved to E_rel 1e-4 together (one persistent launch for the
@@ -132,9 +133,9 @@ def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budg
     solvers = [lpg.Solver(lp, spmv_layout=1, precision=lpg.LP_PREC_FP32_REFINED, method=method) for lp in lps]
     create_s = time.time() - t1
     print(f"[bench] created {len(solvers)} handles in {create_s:.1f}s", file=sys.stderr, flush=True)
-    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64, method=method)  # warm-up launch
+    lpg.solve_batch(solvers[-8:], eps_rel=1e-4, max_iters=64, method=method, eval_every=eval_every)  # warm-up launch
     t2 = time.perf_counter()
-    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=max_iters, method=method)
+    sols = lpg.solve_batch(solvers, eps_rel=1e-4, max_iters=max_iters, method=method, eval_every=eval_every)
     dt = time.perf_counter() - t2
     ok = sum(s.status == "optimal" for s in sols)
     iters = np.array([s.info.iterations for s in sols])
@@ -154,7 +155,8 @@ def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budg
     loop_t = 0.0
     loop_ok = 0
     for lp in sub:
-        with lpg.Solver(lp, eps_rel=1e-4, max_iters=max_iters, method=method, spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=max_iters, method=method, spmv_layout=lpg.LP_LAYOUT_TUNED,
+                        eval_every=eval_every) as s1:
             t3 = time.perf_counter()
             r = s1.solve()
             loop_t += time.perf_counter() - t3
@@ -184,7 +186,8 @@ def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budg
     }
     if cpu_budget_s > 0:
         print("[bench] cpu baseline: oracle on the first LPs of the batch", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = run_cpu_baseline_batch(lps, method, cpu_budget_s)
+        out["cpu_baseline"] = run_cpu_baseline_batch(lps, method, cpu_budget_s, eval_every)
+    out["eval_every"] = eval_every
     return out
 
 
@@ -192,7 +195,7 @@ def run_batch(args) -> int:
     """The batched workload alone (--workload batch): one JSON line with LPs/s as `value`."""
     meth = method_of(args, "halpern")
     leg = leg_batch(args.batch_count, args.loop_count, args.batch_max_iters, meth,
-                    0.0 if args.no_cpu_baseline else 20.0)
+                    0.0 if args.no_cpu_baseline else 20.0, args.batch_eval_every)
     result = {
         "metric": METRIC, "value": leg["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": leg["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -276,7 +279,8 @@ def simulate_mgc(service, rate: float, seconds: float, servers: int, seed: int) 
             "latency_p99_s": float(np.percentile(lat, 99)), "arrivals": len(lat)}
 
 
-def cpu_serving_baseline(pool, requests, rate: float, seconds: float, method: int, budget_s: float) -> dict:
+def cpu_serving_baseline(pool, requests, rate: float, seconds: float, method: int, budget_s: float,
+                         eval_every: int = 64) -> dict:
     """The oracle as the host's server, simulated: its rate in nonzero-iterations per second is
     measured on 8 LPs spread over the pool's size range (same method, single-threaded, each
     for about budget_s / 8 seconds of iterations); each completed GPU request of the drained
@@ -293,7 +297,7 @@ def cpu_serving_baseline(pool, requests, rate: float, seconds: float, method: in
     for j in picks:
         # about budget_s / 8 seconds each at ~2.5e8 nonzero-iterations per second
         its = int(max(64, min(20000, budget_s / 8 * 2.5e8 / max(pool[j].nnz, 1))))
-        r = oracle.solve(pool[j], eps_rel=0.0, max_iters=its, method=method)
+        r = oracle.solve(pool[j], eps_rel=0.0, max_iters=its, method=method, eval_every=eval_every)
         work += float(r.iters) * pool[j].nnz
         spent += r.iter_s
     solved = len(picks)
@@ -315,7 +319,7 @@ def cpu_serving_baseline(pool, requests, rate: float, seconds: float, method: in
 
 def leg_serve(pool_size: int, rate: float, seconds: float, sub_seconds: float, drain_seconds: float,
               hbm_budget_gb: int, slots: int, max_iters: int, method: int, loop_count: int,
-              cpu_budget_s: float = 0.0) -> dict:
+              cpu_budget_s: float = 0.0, eval_every: int = 64) -> dict:
     """Serving workload: Poisson arrivals drawn from a pre-generated pool of LPs
     (m log-uniform on [100, 2e5], n = 1.5m, 3-20 nonzeros per row, KKT-constructed),
     FP32 storage form with FP64 evaluation and refinement, to E_rel 1e-4; continuous
@@ -341,7 +345,8 @@ def leg_serve(pool_size: int, rate: float, seconds: float, sub_seconds: float, d
         arrivals) until every request submitted in the window has completed, at most
         drain_seconds more, so that latency covers the whole window."""
         rng = random.Random(seed)
-        srv = lpg.Server(hbm_budget_gb * 2**30, slots, eps_rel=1e-4, max_iters=max_iters, method=method)
+        srv = lpg.Server(hbm_budget_gb * 2**30, slots, eps_rel=1e-4, max_iters=max_iters, method=method,
+                         eval_every=eval_every)
         tickets = {}
         start = time.perf_counter()
         t_next = 0.0
@@ -418,7 +423,8 @@ def leg_serve(pool_size: int, rate: float, seconds: float, sub_seconds: float, d
     loop_t = 0.0
     loop_ok = 0
     for lp in sub_lps:
-        with lpg.Solver(lp, eps_rel=1e-4, max_iters=max_iters, method=method, spmv_layout=lpg.LP_LAYOUT_TUNED) as s1:
+        with lpg.Solver(lp, eps_rel=1e-4, max_iters=max_iters, method=method, spmv_layout=lpg.LP_LAYOUT_TUNED,
+                        eval_every=eval_every) as s1:
             t3 = time.perf_counter()
             r = s1.solve()
             loop_t += time.perf_counter() - t3
@@ -445,7 +451,8 @@ def leg_serve(pool_size: int, rate: float, seconds: float, sub_seconds: float, d
     }
     if cpu_budget_s > 0 and sub_reqs:
         print("[bench] cpu baseline: oracle service rate on the pool, M/G/c simulation", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_serving_baseline(pool, sub_reqs, rate, seconds, method, cpu_budget_s)
+        out["cpu_baseline"] = cpu_serving_baseline(pool, sub_reqs, rate, seconds, method, cpu_budget_s, eval_every)
+    out["eval_every"] = eval_every
     return out
 
 
@@ -453,7 +460,7 @@ def run_serve(args) -> int:
     """The serving workload alone (--workload serve): one JSON line with LPs/s as `value`."""
     leg = leg_serve(args.pool, args.rate, args.serve_seconds, args.sub_seconds, args.drain_seconds,
                     args.hbm_budget_gb, args.slots, args.batch_max_iters, method_of(args, "halpern"),
-                    args.loop_count, 0.0 if args.no_cpu_baseline else 20.0)
+                    args.loop_count, 0.0 if args.no_cpu_baseline else 20.0, args.serve_eval_every)
     result = {
         "metric": METRIC, "value": leg["lps_per_s"], "unit": "LPs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": args.serve_seconds * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -610,6 +617,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--eval-every", type=int, default=64)
+    # evaluation periods of the batched and the served LPs (also of their per-LP loops and
+    # oracle baselines); the library's default of 64 unless asked otherwise
+    ap.add_argument("--batch-eval-every", type=int, default=64)
+    ap.add_argument("--serve-eval-every", type=int, default=64)
     ap.add_argument("--cpu-iters", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solve", action="store_true", help="also solve the LP to E_rel 1e-4 and toward 1e-8 (long)")
@@ -841,10 +852,11 @@ def main(argv=None):
         cpu = not args.no_cpu_baseline
         meth = method_of(args, "halpern")
         result["small_lp"] = leg_small_lp(cpu)
-        result["batch"] = leg_batch(args.leg_batch_count, 8, args.batch_max_iters, meth, 10.0 if cpu else 0.0)
+        result["batch"] = leg_batch(args.leg_batch_count, 8, args.batch_max_iters, meth, 10.0 if cpu else 0.0,
+                                    args.batch_eval_every)
         result["serving"] = leg_serve(args.pool, args.rate, args.leg_serve_seconds, args.leg_sub_seconds, 30.0,
                                       args.hbm_budget_gb, args.slots, args.batch_max_iters, meth, 4,
-                                      10.0 if cpu else 0.0)
+                                      10.0 if cpu else 0.0, args.serve_eval_every)
     print(json.dumps(result), flush=True)
     return 0
 
