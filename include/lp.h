@@ -213,6 +213,32 @@ typedef struct lp_info {
 /* Fill *opt with the defaults listed above. */
 void lp_default_options(lp_options *opt);
 
+/* Option presets for the workloads the library was measured on: *opt is filled with the
+ * defaults, then with the preset's fields (the choices that measured best for that
+ * workload on MI355X; every field stays adjustable afterwards). LP_ERR_INVALID_ARG for an
+ * unknown preset or NULL opt (then *opt is left unchanged).
+ *   LP_PRESET_DEFAULT     the defaults.
+ *   LP_PRESET_SMALL       one small LP solved for latency by lp_solve (hundreds of rows):
+ *                         row-tile layout (its products take one or two tiles), reflected
+ *                         Halpern form, FP64.
+ *   LP_PRESET_LARGE       one large LP (millions of nonzeros) to eps_rel: panel-packed
+ *                         layout, reflected Halpern form, FP64.
+ *   LP_PRESET_LARGE_FP32  the same in the FP32 storage form with FP64 refinement (half the
+ *                         matrix bytes; E_rel is still evaluated in FP64).
+ *   LP_PRESET_BATCH       many LPs through lp_solve_batch / lp_solve_batch_static: FP32
+ *                         storage, reflected Halpern form, row tiles (the layout of the batched
+ *                         launches).
+ *   LP_PRESET_SERVING     template handles for a server: as LP_PRESET_BATCH, with deferred = 1. */
+typedef enum lp_preset {
+    LP_PRESET_DEFAULT = 0,
+    LP_PRESET_SMALL = 1,
+    LP_PRESET_LARGE = 2,
+    LP_PRESET_LARGE_FP32 = 3,
+    LP_PRESET_BATCH = 4,
+    LP_PRESET_SERVING = 5
+} lp_preset;
+int32_t lp_preset_options(lp_options *opt, int32_t preset);
+
 /* Create a solver handle for the LP of eq. (1) and prepare it on the GPU.
  *   m >= 0 rows, n >= 1 columns, nnz = row_ptr[m] entries with nnz <= 2^31 - 2^16 - 1 (the
  *   kernels form entry offsets in 32 bits; LP_ERR_INVALID_ARG above that).

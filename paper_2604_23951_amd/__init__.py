@@ -30,6 +30,14 @@ LP_PW_PID = 2
 LP_LAYOUT_PANELS = 0
 LP_LAYOUT_TILES = 1
 LP_LAYOUT_TUNED = 2
+LP_PRESET_DEFAULT = 0
+LP_PRESET_SMALL = 1
+LP_PRESET_LARGE = 2
+LP_PRESET_LARGE_FP32 = 3
+LP_PRESET_BATCH = 4
+LP_PRESET_SERVING = 5
+PRESETS = {"default": LP_PRESET_DEFAULT, "small": LP_PRESET_SMALL, "large": LP_PRESET_LARGE,
+           "large_fp32": LP_PRESET_LARGE_FP32, "batch": LP_PRESET_BATCH, "serving": LP_PRESET_SERVING}
 LP_PREC_FP64 = 0
 LP_PREC_FP32_REFINED = 1
 TRACE_WIDTH = 12
@@ -37,7 +45,7 @@ LP_STATIC_BATCH_MAX = 4096  # include/lp.h
 
 # names of every function include/lp.h declares
 EXPORTS = (
-    "lp_default_options", "lp_create", "lp_update_options", "lp_solve", "lp_polish", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_default_options", "lp_preset_options", "lp_create", "lp_update_options", "lp_solve", "lp_polish", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
     "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
@@ -129,6 +137,8 @@ def lib():
         P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.lp_default_options.argtypes = [P]
         L.lp_default_options.restype = None
+        L.lp_preset_options.argtypes = [P, I32]
+        L.lp_preset_options.restype = I32
         L.lp_create.argtypes = [P, I32, I32, I64, P, P, P, P, D, P, P, P, P, P]
         L.lp_create.restype = I32
         L.lp_update_options.argtypes = [P, P]
@@ -210,6 +220,13 @@ def _check(rc: int, handle=None):
 def lp_default_options() -> lp_options:
     o = lp_options()
     lib().lp_default_options(C.byref(o))
+    return o
+
+
+def lp_preset_options(preset) -> lp_options:
+    """Options of a preset (an LP_PRESET_* value or its name in PRESETS)."""
+    o = lp_options()
+    _check(lib().lp_preset_options(C.byref(o), PRESETS.get(preset, preset) if isinstance(preset, str) else preset))
     return o
 
 
@@ -315,8 +332,9 @@ class Solution:
 _OPT_KEYS = {f[0] for f in lp_options._fields_} - {"x0", "y0", "hip_stream"}
 
 
-def make_options(**kw) -> lp_options:
-    o = lp_default_options()
+def make_options(preset=None, **kw) -> lp_options:
+    """Options from the defaults (or a preset, see lp_preset_options) with fields replaced."""
+    o = lp_default_options() if preset is None else lp_preset_options(preset)
     for k, v in kw.items():
         if k not in _OPT_KEYS:
             raise TypeError(f"unknown option {k}")

@@ -1556,6 +1556,37 @@ void lp_default_options(lp_options* o) {
     o->pid_kd = 0.2;
 }
 
+int32_t lp_preset_options(lp_options* o, int32_t preset) {
+    if (!o || preset < LP_PRESET_DEFAULT || preset > LP_PRESET_SERVING)
+        return fail(nullptr, LP_ERR_INVALID_ARG, "unknown preset or NULL options");
+    lp_default_options(o);
+    switch (preset) {
+        case LP_PRESET_SMALL:
+            o->spmv_layout = LP_LAYOUT_TILES;
+            o->method = LP_METHOD_HALPERN;
+            break;
+        case LP_PRESET_LARGE:
+            o->spmv_layout = LP_LAYOUT_PANELS;
+            o->method = LP_METHOD_HALPERN;
+            break;
+        case LP_PRESET_LARGE_FP32:
+            o->spmv_layout = LP_LAYOUT_PANELS;
+            o->method = LP_METHOD_HALPERN;
+            o->precision = LP_PREC_FP32_REFINED;
+            break;
+        case LP_PRESET_BATCH:
+        case LP_PRESET_SERVING:
+            o->spmv_layout = LP_LAYOUT_TILES;
+            o->method = LP_METHOD_HALPERN;
+            o->precision = LP_PREC_FP32_REFINED;
+            o->deferred = preset == LP_PRESET_SERVING ? 1 : 0;
+            break;
+        default:
+            break;
+    }
+    return LP_OK;
+}
+
 const char* lp_error_string(int32_t code) {
     switch (code) {
         case LP_OK: return "ok";

@@ -189,6 +189,41 @@ def test_default_options_match_the_header():
         assert getattr(o, k) == v, (k, getattr(o, k), v)
 
 
+PRESET_FIELDS = {
+    "default": {},
+    "small": dict(spmv_layout=lpg.LP_LAYOUT_TILES, method=lpg.LP_METHOD_HALPERN),
+    "large": dict(spmv_layout=lpg.LP_LAYOUT_PANELS, method=lpg.LP_METHOD_HALPERN),
+    "large_fp32": dict(spmv_layout=lpg.LP_LAYOUT_PANELS, method=lpg.LP_METHOD_HALPERN,
+                       precision=lpg.LP_PREC_FP32_REFINED),
+    "batch": dict(spmv_layout=lpg.LP_LAYOUT_TILES, method=lpg.LP_METHOD_HALPERN, precision=lpg.LP_PREC_FP32_REFINED),
+    "serving": dict(spmv_layout=lpg.LP_LAYOUT_TILES, method=lpg.LP_METHOD_HALPERN,
+                    precision=lpg.LP_PREC_FP32_REFINED, deferred=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PRESET_FIELDS))
+def test_presets_are_the_defaults_plus_their_fields(name):
+    """Every preset is lp_default_options with the fields include/lp.h lists for it."""
+    o = lpg.lp_preset_options(name)
+    d = lpg.lp_default_options()
+    for k, _ in lpg.lp_options._fields_:
+        want = PRESET_FIELDS[name].get(k, getattr(d, k))
+        assert getattr(o, k) == want, (name, k, getattr(o, k), want)
+    s = lpg.make_options(preset=name, eps_rel=1e-6)  # the binding's helper starts from the preset
+    assert s.eps_rel == 1e-6 and s.spmv_layout == o.spmv_layout and s.precision == o.precision
+
+
+def test_unknown_preset_is_rejected():
+    import ctypes as C
+
+    o = lpg.lp_default_options()
+    o.eps_rel = 0.5
+    for bad in (-1, 6, 99):
+        assert lpg.lib().lp_preset_options(C.byref(o), bad) == 1  # LP_ERR_INVALID_ARG
+        assert o.eps_rel == 0.5  # left unchanged
+    assert lpg.lib().lp_preset_options(None, 1) == 1  # LP_ERR_INVALID_ARG
+
+
 def test_presolve_default_options_match_the_header():
     o = lpg.lp_presolve_options()
     lpg.lib().lp_presolve_default_options(__import__("ctypes").byref(o))
