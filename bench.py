@@ -475,9 +475,10 @@ def run_serve(args) -> int:
 def leg_small_lp(cpu: bool) -> dict:
     """The small LP (m = 200, n = 400, 2% density, KKT-constructed), 5000 FP64 iterations with
     eps 0 and restarts active: its working set (~80 KB) sits in the caches, so it is bound by
-    latency, not HBM; reported as microseconds per iteration for lp_solve (hipGraph bundles of
-    64 iterations) and for the one-workgroup persistent launch (a batch of one), and the
-    oracle's iterations per second on one host core."""
+    latency, not HBM; reported as microseconds per iteration for lp_solve as it runs by default
+    (one workgroup from LDS: the LP fits the small-LP budget), for the kernel-per-phase loop
+    (hipGraph bundles of 64 iterations) with panels and with row tiles, and the oracle's
+    iterations per second on one host core."""
     import numpy as np
 
     import paper_2604_23951_amd as lpg
@@ -487,25 +488,22 @@ def leg_small_lp(cpu: bool) -> dict:
     iters = 5000
     out = {"workload": "small LP m=200 n=400 (2% density, KKT-constructed), FP64, 5000 iterations, eps 0",
            "iterations": iters, "bound": "latency (working set in cache)"}
-    for name, layout in (("lp_solve_us_per_iter", 0), ("lp_solve_tiles_us_per_iter", 1)):
-        with lpg.Solver(lp, eps_rel=0.0, max_iters=iters, spmv_layout=layout) as s:
+    for name, opts in (("lp_solve_us_per_iter", {}),
+                       ("kernel_loop_panels_us_per_iter", dict(spmv_layout=0, small_lp_lds=0)),
+                       ("kernel_loop_tiles_us_per_iter", dict(spmv_layout=1, small_lp_lds=0))):
+        with lpg.Solver(lp, eps_rel=0.0, max_iters=iters, **opts) as s:
             s.solve()
             ts = []
             for _ in range(3):
                 t = time.perf_counter()
-                s.solve()
+                sol = s.solve()
                 ts.append(time.perf_counter() - t)
         out[name] = float(np.median(ts)) / iters * 1e6
-    with lpg.Solver(lp, spmv_layout=1) as s:
-        lpg.solve_batch([s], eps_rel=0.0, max_iters=iters)
-        ts = []
-        for _ in range(3):
-            t = time.perf_counter()
-            lpg.solve_batch([s], eps_rel=0.0, max_iters=iters)
-            ts.append(time.perf_counter() - t)
-    out["one_workgroup_us_per_iter"] = float(np.median(ts)) / iters * 1e6
-    print(f"[bench] small LP: lp_solve {out['lp_solve_us_per_iter']:.1f} us/it, one workgroup "
-          f"{out['one_workgroup_us_per_iter']:.1f} us/it", file=sys.stderr, flush=True)
+        if not opts:
+            out["lp_solve_path"] = "one workgroup" if sol.info.solve_path == 1 else "kernel per phase"
+    print(f"[bench] small LP: lp_solve {out['lp_solve_us_per_iter']:.1f} us/it ({out['lp_solve_path']}), "
+          f"kernel loop {out['kernel_loop_panels_us_per_iter']:.1f} (panels) / "
+          f"{out['kernel_loop_tiles_us_per_iter']:.1f} (row tiles) us/it", file=sys.stderr, flush=True)
     out["cpu_baseline"] = None
     if cpu:
         import oracle

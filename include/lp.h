@@ -136,11 +136,15 @@ typedef struct lp_options {
     int32_t deferred;      /* 1: lp_create validates and prepares on the host only; device memory is
                               allocated (and the setup run) when the LP is first solved or admitted
                               by a server, and released by the server when it completes (default 0) */
-    int32_t small_lp_lds;  /* lp_solve_batch: bytes of LDS per workgroup (0 to 114688, default 114688)
-                              for LPs held on chip: an LP of the persistent launch whose matrices and
-                              iteration vectors (in its precision) fit is solved from LDS by a
-                              launch of its own (one workgroup per CU), bit-identical to the solve
-                              from global memory; 0 turns this off */
+    int32_t small_lp_lds;  /* bytes of LDS per workgroup (0 to 114688, default 114688) for LPs
+                              held on chip. lp_solve_batch: an LP of the persistent launch whose
+                              matrices and iteration vectors (in its precision) fit is solved from
+                              LDS by a launch of its own (one workgroup per CU), bit-identical to
+                              the solve from global memory. lp_solve: such an LP is solved by one
+                              workgroup from LDS (the whole loop in one launch, the row-tile
+                              products; not with kernel timing on, and not for lp_polish's
+                              solves), bit-identical to the kernel-per-phase loop with row tiles
+                              (lp_info.solve_path = 1). 0 turns both off */
     const double *x0;      /* optional warm start (host, length n, original scale) */
     const double *y0;      /* optional warm start (host, length m, original scale) */
     double eps_infeas;     /* relative tolerance of the infeasibility certificates (default 1e-8;
@@ -207,7 +211,9 @@ typedef struct lp_info {
                               1 the displacement of the evaluated point since the previous
                               evaluation, 2 the averaged point (the PDHG output in the Halpern
                               form) minus the restart anchor; 0 otherwise */
-    int32_t pad0;
+    int32_t solve_path;    /* how lp_solve ran: 0 one kernel per phase (the spmv_layout products,
+                              hipGraph periods), 1 one workgroup from LDS (an LP whose iteration
+                              arrays fit small_lp_lds, see there); batched and served LPs: 0 */
 } lp_info;
 
 /* Fill *opt with the defaults listed above. */

@@ -104,7 +104,7 @@ class lp_info(C.Structure):
         ("step_size", C.c_double), ("omega", C.c_double), ("setup_seconds", C.c_double),
         ("solve_seconds", C.c_double), ("done_clock", C.c_int64), ("clock_hz", C.c_double),
         ("polish_primal_iterations", C.c_int64), ("polish_dual_iterations", C.c_int64),
-        ("polish_seconds", C.c_double), ("ray_source", C.c_int32), ("pad0", C.c_int32),
+        ("polish_seconds", C.c_double), ("ray_source", C.c_int32), ("solve_path", C.c_int32),
     ]
 
 

@@ -88,6 +88,11 @@ struct Prep {
     double trial_us[2] = {0.0, 0.0};
 };
 
+// Device bytes of a one-workgroup lp_solve: the job (256-byte aligned), then the LP order
+// (one int), the work counter and the start clock, 256 bytes apart.
+constexpr size_t kSoloJobAligned = (sizeof(BatchJob) + 255) / 256 * 256;
+constexpr size_t kSoloJobBytes = kSoloJobAligned + 768;
+
 // Offsets of every device array inside a handle's allocation.
 struct Offsets {
     size_t arp, aci, av, at, trp, tci, tv, tt, perm, c, xl, xu, C, Ci, bl, bu, R, Ri;
@@ -95,7 +100,7 @@ struct Offsets {
     size_t xp, atyp, yp, axp, axan, atyan;
     size_t f32[15] = {0};
     size_t pA[7] = {0}, pAT[7] = {0}, pA32 = 0, pAT32 = 0;
-    size_t part, sc, tr;
+    size_t part, sc, tr, job;
 };
 
 // Problem data kept on the host by a deferred handle until it is placed on the device.
@@ -193,6 +198,7 @@ struct lp_handle {
     int* d_perm = nullptr;
     double* d_x0 = nullptr;
     double* d_y0 = nullptr;
+    char* d_job = nullptr;  // job, LP order, work counter and start clock of a one-workgroup lp_solve
     Scalars* h_sc = nullptr;  // pinned host copy of the device scalars
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -334,6 +340,7 @@ void fill_info(lp_handle* h) {
     inf.omega = sc.omega;
     inf.done_clock = sc.done_clock;
     inf.ray_source = (sc.status == LP_PRIMAL_INFEASIBLE || sc.status == LP_DUAL_INFEASIBLE) ? sc.ray_src : 0;
+    inf.solve_path = 0;  // the one-workgroup lp_solve sets 1 after this
     int khz = 0;
     inf.clock_hz = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) == hipSuccess ? 1e3 * khz : 0.0;
 }
@@ -870,6 +877,7 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
     }
     O->part = L.add(sizeof(double) * kNT * kMaxRedBlocks);
     O->sc = L.add(sizeof(Scalars));
+    O->job = L.add(kSoloJobBytes);
     O->tr = L.add(sizeof(double) * kTraceW * static_cast<size_t>(o.trace_cap > 0 ? o.trace_cap : 1));
     return L.off;
 }
@@ -1026,6 +1034,7 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     h->d_perm = I(O.perm);
     h->d_x0 = h->has_x0 ? D(O.x0) : nullptr;
     h->d_y0 = h->has_y0 ? D(O.y0) : nullptr;
+    h->d_job = b + O.job;
 
     hipStream_t s = h->stream;
     const size_t sm = sizeof(double) * static_cast<size_t>(m), sn = sizeof(double) * static_cast<size_t>(n);
@@ -1683,10 +1692,44 @@ namespace {
 // The solve loop of lp_solve from a scaled start point (x0s, y0s: device arrays or NULL for
 // 0), stopping on E_rel (term_mode 0) or on one residual alone (1 primal, 2 dual: the
 // polishing solves), with the set-up primal weight or omega0 > 0.
+// lp_solve of an LP whose iteration arrays fit the small-LP LDS budget: one workgroup runs
+// the whole loop from LDS (the persistent batched path with a batch of one), bit-identical to
+// the kernel-per-phase loop with the same row tiles; the time limit is its device deadline.
+int32_t solve_one_workgroup(lp_handle* h, size_t lds_need) {
+    hipStream_t s = h->stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    BatchJob J = make_job(h, nullptr);
+    char* b = h->d_job;
+    BatchJob* dj = reinterpret_cast<BatchJob*>(b);
+    int32_t* dorder = reinterpret_cast<int32_t*>(b + kSoloJobAligned);
+    int32_t* dcounter = reinterpret_cast<int32_t*>(b + kSoloJobAligned + 256);
+    long long* dt0 = reinterpret_cast<long long*>(b + kSoloJobAligned + 512);
+    J.t0 = dt0;
+    const int32_t first = 0;
+    HIP_TRY(h, hipMemcpyAsync(dj, &J, sizeof(BatchJob), hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(dorder, &first, sizeof(first), hipMemcpyHostToDevice, s));
+    launch_batch_start(dcounter, dt0, s);
+    const int lds_cap = static_cast<int>((lds_need + 16383) / 16384 * 16384);
+    launch_batch(dj, dorder, 1, dcounter, 1, s, lds_cap);
+    if (int32_t rc = check_launch(h, "one-workgroup solve")) return rc;
+    HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));  // also keeps J and `first` alive until their copies are done
+    fill_info(h);
+    h->info.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    h->info.solve_path = 1;
+    h->solved = true;
+    return LP_OK;
+}
+
 int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_mode, double omega0) {
     set_form(h->P, h->opt);
     hipStream_t s = h->stream;
     const DevLP& P = h->P;
+    if (term_mode == 0 && omega0 == 0.0 && x0s == h->d_x0 && y0s == h->d_y0 && !h->timing && h->opt.small_lp_lds > 0) {
+        const size_t need = small_lp_lds_bytes(P);
+        if (need <= static_cast<size_t>(h->opt.small_lp_lds) && need <= static_cast<size_t>(kSmallLpLdsMax))
+            return solve_one_workgroup(h, need);
+    }
     const auto t0 = std::chrono::steady_clock::now();
     launch_reset(P, h->opt.eps_rel, h->opt.eps_infeas, h->opt.max_iters, h->opt.eval_every, h->opt.restarts,
                  h->opt.trace_cap, s, term_mode, omega0);

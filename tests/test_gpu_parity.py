@@ -34,6 +34,9 @@ def _case(name):
 
 
 CASES = ["cfg0", "cfg0b", "large_recipe_small", "transport", "serving_recipe_small"]
+# "auto": lp_solve as it runs by default (an LP that fits the small-LP LDS budget on one
+# workgroup); "kernels": the kernel-per-phase loop (small_lp_lds = 0)
+PATHS = {"auto": {}, "kernels": {"small_lp_lds": 0}}
 
 
 def _close(a, b, tol=ITER_TOL):
@@ -66,13 +69,14 @@ def test_norm_estimate(oracle_lib, name):
     assert abs(sol.info.step_size - ref.eta) <= 1e-12 * ref.eta
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("name", CASES)
-def test_iterates_first_200(oracle_lib, name):
+def test_iterates_first_200(oracle_lib, name, path):
     lp = _case(name)
     ks = list(range(1, 201))
     ref = oracle.solve(lp, eps_rel=0.0, max_iters=200, snap_k=ks)
     worst = 0.0
-    with lpg.Solver(lp, eps_rel=0.0, max_iters=1) as s:
+    with lpg.Solver(lp, eps_rel=0.0, max_iters=1, **PATHS[path]) as s:
         for k in ks:
             s.update(eps_rel=0.0, max_iters=k)
             sol = s.solve()
@@ -89,7 +93,8 @@ def test_iterates_first_200(oracle_lib, name):
     assert len(tr) == len(ot)
     np.testing.assert_array_equal(tr[:, [0, 1, 6, 7]], ot[:, [0, 1, 6, 7]])
     np.testing.assert_allclose(tr[:, [2, 3, 4, 5, 8]], ot[:, [2, 3, 4, 5, 8]], rtol=1e-10)
-    print(f"{name}: worst relative iterate difference over 200 iterations {worst:.3e}")
+    print(f"{name} ({path}, solve path {sol.info.solve_path}): worst relative iterate difference over 200 "
+          f"iterations {worst:.3e}")
 
 
 def test_iterates_with_given_step_and_weight(oracle_lib):
@@ -104,11 +109,12 @@ def test_iterates_with_given_step_and_weight(oracle_lib):
                 assert _close(a, b) <= ITER_TOL
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("name", CASES)
-def test_solve_parity(oracle_lib, name):
+def test_solve_parity(oracle_lib, name, path):
     lp = _case(name)
     ref = oracle.solve(lp, eps_rel=1e-4, max_iters=200000)
-    with lpg.Solver(lp, eps_rel=1e-4, max_iters=200000) as s:
+    with lpg.Solver(lp, eps_rel=1e-4, max_iters=200000, **PATHS[path]) as s:
         sol = s.solve(with_trace=True)
     assert sol.status == ref.status == "optimal"
     assert sol.info.iterations == ref.iters
