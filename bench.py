@@ -151,7 +151,7 @@ def leg_batch(count: int, loop_count: int, max_iters: int, method: int, cpu_budg
     for s in solvers:
         s.close()
     # plain per-LP FP64 loop on a sub-sample
-    sub = lps[:: max(1, len(lps) // loop_count)][:loop_count]
+    sub = lps[:: max(1, len(lps) // max(loop_count, 1))][:loop_count]
     loop_t = 0.0
     loop_ok = 0
     for lp in sub:

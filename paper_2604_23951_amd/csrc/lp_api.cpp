@@ -580,12 +580,15 @@ void run_round(DevMaps& D, hipStream_t s, int capture_after) {
 
 // LPs solved one per workgroup in a single persistent launch, started on its own stream
 // so that it runs beside the block-diagonal launches of the larger LPs. The host arrays
-// stay alive until finish_persistent.
+// stay alive until finish_persistent. The runtime spreads streams over a few hardware queues
+// in creation order, and two launches whose streams share a queue run one after the other,
+// so the block-diagonal launches get the third of three streams created together (s[2])
+// rather than an older stream that may share a queue with a persistent launch.
 struct PersistentRun {
     std::vector<BatchJob> jobs;
     std::vector<int32_t> order;
     char* buf = nullptr;
-    hipStream_t s[2] = {nullptr, nullptr};
+    hipStream_t s[3] = {nullptr, nullptr, nullptr};
 };
 
 // Two persistent launches at most, each on a stream of its own: the LPs whose iteration
@@ -632,7 +635,7 @@ int32_t start_persistent(const std::vector<lp_handle*>& hs, const lp_options* bo
     long long* dt0 = reinterpret_cast<long long*>(R.buf + oc + 128);  // device clock at the start of the call
     for (BatchJob& J : R.jobs) J.t0 = dt0;
     hipError_t e = hipSuccess;
-    for (int l = 0; l < 2 && e == hipSuccess; ++l)
+    for (int l = 0; l < 3 && e == hipSuccess; ++l)
         e = hipStreamCreateWithFlags(&R.s[l], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemcpyAsync(djobs, R.jobs.data(), bj, hipMemcpyHostToDevice, R.s[0]);
     if (e == hipSuccess) e = hipMemcpyAsync(dorder, R.order.data(), bo_, hipMemcpyHostToDevice, R.s[0]);
@@ -1907,7 +1910,7 @@ int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo
             }
         }
         if (!big.empty()) {
-            if (int32_t rc = solve_block_diagonal(big, bo, h0->stream)) {
+            if (int32_t rc = solve_block_diagonal(big, bo, small.empty() ? h0->stream : pr.s[2])) {
                 if (!small.empty()) (void)finish_persistent(small, pr, false);
                 return rc;
             }
