@@ -1711,12 +1711,13 @@ int32_t solve_one_workgroup(lp_handle* h, size_t lds_need) {
     const int32_t first = 0;
     HIP_TRY(h, hipMemcpyAsync(dj, &J, sizeof(BatchJob), hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync(dorder, &first, sizeof(first), hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipStreamSynchronize(s));  // J and `first` are on this stack frame
     launch_batch_start(dcounter, dt0, s);
     const int lds_cap = static_cast<int>((lds_need + 16383) / 16384 * 16384);
     launch_batch(dj, dorder, 1, dcounter, 1, s, lds_cap);
     if (int32_t rc = check_launch(h, "one-workgroup solve")) return rc;
     HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipStreamSynchronize(s));  // also keeps J and `first` alive until their copies are done
+    HIP_TRY(h, hipStreamSynchronize(s));
     fill_info(h);
     h->info.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     h->info.solve_path = 1;
@@ -1977,6 +1978,7 @@ int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_opti
             HIP_TRY(h0, hipStreamSynchronize(s));
         }
         HIP_TRY(h0, hipMemcpyAsync(S.order, order, sizeof(int32_t) * count, hipMemcpyHostToDevice, s));
+        HIP_TRY(h0, hipStreamSynchronize(s));  // `order` is on this stack frame
         launch_batch_start(S.counter, S.t0, s);
         int cus = 256;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
