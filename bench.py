@@ -787,6 +787,9 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom["kernel"],
                      "alg_bytes_per_launch": dom["bytes"], "avg_launch_ms": dom["ms"],
+                     # the counted HBM traffic (FETCH_SIZE / WRITE_SIZE, scaled) over the same launch time
+                     "traffic_gbs": traffic / (dom["ms"] * 1e-3) / 1e9 if traffic else None,
+                     "traffic_frac": traffic / (dom["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
                      "gather_ceiling": {"gathers_per_launch": nnz, "rate_per_s": GATHER_CEILING_PER_S,
                                         "min_launch_ms": nnz / GATHER_CEILING_PER_S * 1e3,
                                         "frac": (nnz / GATHER_CEILING_PER_S * 1e3) / dom["ms"]}},
