@@ -76,6 +76,26 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def environment() -> dict:
+    """Where a line was measured: GPU, ROCm (HIP) version, host CPU and thread count, the
+    generators' seed root."""
+    env = {"cpu": cpu_model(), "nproc": os.cpu_count()}
+    try:
+        import torch
+
+        env["gpu"] = torch.cuda.get_device_name(0) if torch.cuda.is_available() else None
+        env["hip"] = getattr(torch.version, "hip", None)
+    except Exception:  # the line is still written without the device description
+        env["gpu"] = env["hip"] = None
+    try:
+        import synth
+
+        env["seed_root"] = synth.SEED_ROOT
+    except Exception:
+        env["seed_root"] = None
+    return env
+
+
 def run_cpu_baseline(lp, iters: int) -> dict:
     """The oracle as it stands, single-threaded on the host, on a bounded sample."""
     import oracle
@@ -207,6 +227,7 @@ def run_batch(args) -> int:
         "per_lp_fp64_loop": leg["per_lp_fp64_loop"], "speedup_vs_per_lp_loop": leg["speedup_vs_per_lp_loop"],
         "create_s": leg["create_s"], "cpu_baseline": leg["cpu_baseline"],
     }
+    result["environment"] = environment()
     print(json.dumps(result), flush=True)
     return 0
 
@@ -250,6 +271,7 @@ def run_blockdiag(args) -> int:
         "alg_bytes_primal_launch": prim, "alg_bytes_dual_launch": dual,
         "iteration_alg_gbs": (prim + dual) * iters / dt / 1e9,
     }
+    result["environment"] = environment()
     print(json.dumps(result), flush=True)
     return 0
 
@@ -468,6 +490,7 @@ def run_serve(args) -> int:
         "config": {"workload": leg["workload"], "pool_mean_nnz": leg["pool_mean_nnz"], "method": leg["method"]},
     }
     result.update({k: v for k, v in leg.items() if k not in ("workload", "pool_mean_nnz", "method", "lps_per_s")})
+    result["environment"] = environment()
     print(json.dumps(result), flush=True)
     return 0
 
@@ -560,6 +583,7 @@ def run_presolve(args) -> int:
                    "rel_kkt": direct.info.rel_kkt},
         "speedup_end_to_end": direct_s / pre_s,
     }
+    result["environment"] = environment()
     print(json.dumps(result), flush=True)
     return 0
 
@@ -858,6 +882,7 @@ def main(argv=None):
         result["serving"] = leg_serve(args.pool, args.rate, args.leg_serve_seconds, args.leg_sub_seconds, 30.0,
                                       args.hbm_budget_gb, args.slots, args.batch_max_iters, meth, 4,
                                       10.0 if cpu else 0.0, args.serve_eval_every)
+    result["environment"] = environment()
     print(json.dumps(result), flush=True)
     return 0
 
