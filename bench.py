@@ -40,6 +40,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # MI355X: one L1-to-L2 request per gathered entry, bounded by the requests a CU keeps in
 # flight. A product of nnz entries therefore needs at least nnz / 1.66e11 s.
 GATHER_CEILING_PER_S = 1.66e11
+# The same micro-benchmark with the gathered vector resident in L2 (1 MiB footprint): 2.2e11
+# gathers/s, the bound of products whose vectors fit the cache (the served LPs' rounds).
+L2_GATHER_RATE_PER_S = 2.2e11
 METRIC = "PDHG iters/s & HBM GB/s vs roofline; batched LPs/s to 1e-4 KKT, p50/p99"
 
 
@@ -424,6 +427,9 @@ def leg_serve(pool_size: int, rate: float, seconds: float, sub_seconds: float, d
                 "backlog_at_window_end": st_window["queued"] + st_window["running"], "rounds": st["rounds"],
                 "peak_device_bytes": st["peak_bytes"],
                 "nnz_iterations_per_s": wsec, "matrix_stream_GBps": 16 * wsec / 1e9,
+                # each iteration gathers once per nonzero in each of its two products
+                "gathered_entries_per_s": 2 * wsec,
+                "fraction_of_l2_gather_rate": 2 * wsec / L2_GATHER_RATE_PER_S,
                 "lp_iterations_per_s": st_window["lp_iterations"] / seconds}, reqs
 
     full, _ = phase(rate, seconds, 1, False)
