@@ -263,7 +263,10 @@ int32_t lp_create(lp_handle **out, int32_t m, int32_t n, int64_t nnz, const int3
 
 /* Run restarted PDHG (the form of opt->method) from the start point until E_rel <= eps_rel,
  * a certificate or a limit. Every call starts again from x0, y0 (the handle keeps the
- * problem, not the iterates). */
+ * problem, not the iterates). An LP whose iteration arrays fit small_lp_lds bytes of LDS
+ * runs the whole loop on one workgroup in one launch; any other runs one kernel per phase,
+ * an evaluation period (eval_every iterations, the evaluation, the decision) per hipGraph
+ * replay, the host reading the status once per period. lp_info.solve_path says which. */
 int32_t lp_solve(lp_handle *h);
 
 /* Feasibility polishing of the point the last lp_solve returned (the PDLP family's polishing;
