@@ -286,6 +286,42 @@ int32_t lp_solve(lp_handle *h);
  * solve that returned a certificate, or for eps <= 0. */
 int32_t lp_polish(lp_handle *h, double eps, int64_t max_iters);
 
+/* ---- checkpoint and resume ---------------------------------------------------------
+ * Not an operation of the paper: a way to split one run of the method of Section 4 (the
+ * restarted PDHG loop of lp_solve) into pieces, for callers that must give up the device
+ * between pieces or keep a run across processes.
+ * lp_solve_until runs lp_solve's loop (one kernel per phase, whatever small_lp_lds says) but
+ * pauses after the first evaluation period that ends at or beyond iteration k_pause (> 0,
+ * else LP_ERR_INVALID_ARG): the period's decision and restart are applied, the status reads
+ * LP_ITERATION_LIMIT, lp_get_solution returns the paused point and its statistics, and the
+ * handle is resumable. A solve that stops earlier (tolerance, certificate, max_iters, time
+ * limit) returns as lp_solve does and is not resumable.
+ * lp_resume continues a resumable handle's run from its device state until the handle's
+ * current eps_rel, max_iters, time_limit_s (counted from the lp_resume call) or eps_infeas
+ * stop it, or, with k_pause > 0, pauses again as lp_solve_until does; the new tolerances are
+ * first tested at the end of the next period, and max_iters at or below the paused
+ * iteration count leaves the handle paused. lp_update_options may change those four;
+ * eval_every, restarts, the iteration form and the primal-weight rule must stay
+ * (LP_ERR_INVALID_ARG). With unchanged options the iterates, restarts, decision trace and
+ * result are bit for bit those of one uninterrupted lp_solve, however the run is split.
+ * LP_ERR_NOT_SOLVED if the handle is not resumable. lp_solve, lp_polish and the batched
+ * solves end a handle's resumable state.
+ * lp_export_state copies a resumable handle's state (iterates, averages, anchors, the point
+ * of the previous evaluation, the products kept across periods, the FP32 form's corrections,
+ * shifted data and master point, the scalar state and the decision trace) into the host
+ * buffer buf of cap bytes and sets *size to its length (buf NULL: only *size;
+ * LP_ERR_INVALID_ARG if cap is smaller). lp_import_state loads such a buffer into a handle
+ * of the same LP with the same precision, trace capacity and iteration options, which must
+ * hold its device memory (not deferred, or solved once); the handle is then as the exporting
+ * one was at its pause (resumable, same lp_get_solution). LP_ERR_INVALID_ARG for a buffer of
+ * another size or version, another iteration form, or another LP (told by its sizes and a
+ * hash of the scaled cost and scaling factors). The buffer holds plain bytes of this
+ * library build (for a file kept beside it), not a portable format. */
+int32_t lp_solve_until(lp_handle *h, int64_t k_pause);
+int32_t lp_resume(lp_handle *h, int64_t k_pause);
+int32_t lp_export_state(lp_handle *h, void *buf, int64_t cap, int64_t *size);
+int32_t lp_import_state(lp_handle *h, const void *buf, int64_t size);
+
 /* Replace the solve-time options of a handle: eps_rel, max_iters, time_limit_s, eval_every,
  * restarts, eps_infeas, method, reflection, omega_steps, pw_rule and the three pid gains are
  * taken from *opt; every other field of *opt is ignored (the problem setup, the step size and the trace capacity are fixed at lp_create). */

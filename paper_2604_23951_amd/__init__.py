@@ -45,7 +45,8 @@ LP_STATIC_BATCH_MAX = 4096  # include/lp.h
 
 # names of every function include/lp.h declares
 EXPORTS = (
-    "lp_default_options", "lp_preset_options", "lp_create", "lp_update_options", "lp_solve", "lp_polish", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_default_options", "lp_preset_options", "lp_create", "lp_update_options", "lp_solve", "lp_polish", "lp_solve_until", "lp_resume",
+    "lp_export_state", "lp_import_state", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
     "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
@@ -149,6 +150,14 @@ def lib():
         L.lp_solve_batch.restype = I32
         L.lp_polish.argtypes = [P, D, I64]
         L.lp_polish.restype = I32
+        L.lp_solve_until.argtypes = [P, I64]
+        L.lp_solve_until.restype = I32
+        L.lp_resume.argtypes = [P, I64]
+        L.lp_resume.restype = I32
+        L.lp_export_state.argtypes = [P, P, I64, P]
+        L.lp_export_state.restype = I32
+        L.lp_import_state.argtypes = [P, P, I64]
+        L.lp_import_state.restype = I32
         L.lp_solve_batch_static.argtypes = [P, I32, P]
         L.lp_solve_batch_static.restype = I32
         L.lp_get_solution.argtypes = [P, P, P, P, P]
@@ -245,6 +254,27 @@ def lp_update_options(h, opt: lp_options):
 
 def lp_solve(h):
     _check(lib().lp_solve(h), h)
+
+
+def lp_solve_until(h, k_pause: int):
+    _check(lib().lp_solve_until(h, int(k_pause)), h)
+
+
+def lp_resume(h, k_pause: int = 0):
+    _check(lib().lp_resume(h, int(k_pause)), h)
+
+
+def lp_export_state(h) -> bytes:
+    size = C.c_int64()
+    _check(lib().lp_export_state(h, None, 0, C.byref(size)), h)
+    buf = C.create_string_buffer(max(size.value, 1))
+    _check(lib().lp_export_state(h, buf, size.value, C.byref(size)), h)
+    return buf.raw[: size.value]
+
+
+def lp_import_state(h, state: bytes):
+    buf = C.create_string_buffer(bytes(state), len(state))
+    _check(lib().lp_import_state(h, buf, len(state)), h)
 
 
 def lp_solve_batch(handles, opt: Optional[lp_options] = None):
@@ -404,6 +434,31 @@ class Solver:
         info = lp_get_solution(self.h, x, y, z)
         tr = lp_get_trace(self.h, self.trace_cap) if with_trace else np.zeros((0, TRACE_WIDTH))
         return Solution(STATUS.get(info.status, str(info.status)), x, y[: self.m], z, info, tr)
+
+    def _result(self, with_trace: bool = False) -> Solution:
+        x = np.empty(self.n)
+        y = np.empty(max(self.m, 1))
+        z = np.empty(self.n)
+        info = lp_get_solution(self.h, x, y, z)
+        tr = lp_get_trace(self.h, self.trace_cap) if with_trace else np.zeros((0, TRACE_WIDTH))
+        return Solution(STATUS.get(info.status, str(info.status)), x, y[: self.m], z, info, tr)
+
+    def solve_until(self, k_pause: int, with_trace: bool = False) -> Solution:
+        """lp_solve_until: run until the first evaluation at or beyond k_pause, then pause."""
+        lp_solve_until(self.h, k_pause)
+        return self._result(with_trace)
+
+    def resume(self, k_pause: int = 0, with_trace: bool = False) -> Solution:
+        """lp_resume: continue a paused run (pausing again at k_pause > 0)."""
+        lp_resume(self.h, k_pause)
+        return self._result(with_trace)
+
+    def export_state(self) -> bytes:
+        return lp_export_state(self.h)
+
+    def import_state(self, state: bytes) -> Solution:
+        lp_import_state(self.h, state)
+        return self._result()
 
     def polish(self, eps: float = 1e-8, max_iters: int = 100000) -> Solution:
         """Feasibility polishing of the last solve's point (lp_polish); returns the polished point."""

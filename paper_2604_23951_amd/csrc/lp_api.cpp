@@ -204,6 +204,8 @@ struct lp_handle {
     hipGraphExec_t gexec = nullptr;
     bool graph_failed = false;
     bool solved = false;
+    bool resumable = false;  // paused by lp_solve_until / lp_resume, or loaded by lp_import_state
+    lp_options paused_opt{};  // the options of the paused run (its form must not change on resume)
     lp_info info{};
     std::string err;
     bool timing = false;
@@ -1725,11 +1727,16 @@ int32_t solve_one_workgroup(lp_handle* h, size_t lds_need) {
     return LP_OK;
 }
 
-int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_mode, double omega0) {
+int32_t run_periods(lp_handle* h, std::chrono::steady_clock::time_point t0, long long pause_k);
+
+int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_mode, double omega0,
+                   long long pause_k = 0) {
     set_form(h->P, h->opt);
     hipStream_t s = h->stream;
     const DevLP& P = h->P;
-    if (term_mode == 0 && omega0 == 0.0 && x0s == h->d_x0 && y0s == h->d_y0 && !h->timing && h->opt.small_lp_lds > 0) {
+    h->resumable = false;
+    if (term_mode == 0 && omega0 == 0.0 && pause_k == 0 && x0s == h->d_x0 && y0s == h->d_y0 && !h->timing &&
+        h->opt.small_lp_lds > 0) {
         const size_t need = small_lp_lds_bytes(P);
         if (need <= static_cast<size_t>(h->opt.small_lp_lds) && need <= static_cast<size_t>(kSmallLpLdsMax))
             return solve_one_workgroup(h, need);
@@ -1742,6 +1749,18 @@ int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_
     if (int32_t rc = check_launch(h, "initial evaluation")) return rc;
     HIP_TRY(h, hipMemcpyAsync(h->h_sc, P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
+    return run_periods(h, t0, pause_k);
+}
+
+// The period loop of lp_solve from the device state in P: evaluation periods until the
+// status leaves "running", the host time limit, or (pause_k > 0) the first period that ends
+// at or beyond iteration pause_k, whose decision and restart have then been applied; a pause
+// leaves the iteration state untouched (the stop and the statistics of the returned point
+// write only outputs), so lp_resume continues it bit for bit. Then the point is extracted.
+int32_t run_periods(lp_handle* h, std::chrono::steady_clock::time_point t0, long long pause_k) {
+    hipStream_t s = h->stream;
+    const DevLP& P = h->P;
+    bool paused = false;
     const bool use_graph = !h->timing;
     if (use_graph) capture_graph(h);
     const int timed_it = h->opt.eval_every / 2;
@@ -1765,6 +1784,12 @@ int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_
             }
         }
         if (h->h_sc->status != kRunning) break;
+        if (pause_k > 0 && h->h_sc->k >= pause_k) {
+            launch_stop(P, LP_ITERATION_LIMIT, s);
+            launch_evaluate(P, 2, s);
+            paused = true;
+            break;
+        }
         if (h->opt.time_limit_s > 0.0 &&
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > h->opt.time_limit_s) {
             launch_stop(P, LP_TIME_LIMIT, s);
@@ -1779,6 +1804,112 @@ int32_t solve_from(lp_handle* h, const double* x0s, const double* y0s, int term_
     fill_info(h);
     h->info.solve_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     h->solved = true;
+    h->resumable = paused;
+    if (paused) h->paused_opt = h->opt;
+    return LP_OK;
+}
+
+// ---- state of a paused solve (checkpoint and resume) -------------------------------
+
+// A device array that carries a solve from one evaluation period to the next.
+struct StateSpan {
+    void* p;
+    size_t bytes;
+};
+
+// Every such array of the handle, in the order of a state buffer: the FP64 iterates,
+// averages, anchors, the point of the previous evaluation and the products kept with them;
+// in the FP32 form also the corrections, the rounded shifted data and the FP64 master point.
+std::vector<StateSpan> state_spans(const lp_handle* h) {
+    const DevLP& P = h->P;
+    const size_t dn = sizeof(double) * static_cast<size_t>(h->n), dm = sizeof(double) * static_cast<size_t>(h->m);
+    const size_t fn = sizeof(float) * static_cast<size_t>(h->n), fm = sizeof(float) * static_cast<size_t>(h->m);
+    std::vector<StateSpan> v = {{P.x, dn},    {P.xa, dn},   {P.xan, dn},   {P.aty, dn},   {P.atya, dn},
+                                {P.xp, dn},   {P.atyp, dn}, {P.atyan, dn}, {P.y, dm},     {P.ya, dm},
+                                {P.yan, dm},  {P.ax, dm},   {P.axa, dm},   {P.yp, dm},    {P.axp, dm},
+                                {P.axan, dm}};
+    if (P.fp32) {
+        const StateSpan f[] = {{P.dx, fn},   {P.dxa, fn},  {P.d32, fn},  {P.lo32, fn}, {P.hi32, fn},
+                               {P.dy, fm},   {P.dya, fm},  {P.adx, fm},  {P.rl32, fm}, {P.ru32, fm},
+                               {P.yh32, fm}, {P.xh, dn},   {P.yh, dm}};
+        v.insert(v.end(), std::begin(f), std::end(f));
+    }
+    return v;
+}
+
+struct StateHeader {
+    char magic[8];
+    int32_t version, precision;
+    int32_t m, n;
+    int64_t nnz, trace_cap, n_records, total_bytes;
+    int32_t method, eval_every, restarts, omega_steps, pw_rule, scalars_bytes;
+    double reflection, pid_kp, pid_ki, pid_kd;
+    uint64_t fingerprint;
+};
+constexpr char kStateMagic[8] = {'L', 'P', 'S', 'T', 'A', 'T', 'E', 0};
+constexpr int32_t kStateVersion = 1;
+
+// Options that fix the iterations of a run: they must be the same when it is resumed.
+bool same_form(const lp_options& a, const lp_options& b) {
+    return a.eval_every == b.eval_every && a.restarts == b.restarts && a.method == b.method &&
+           a.reflection == b.reflection && a.omega_steps == b.omega_steps && a.pw_rule == b.pw_rule &&
+           a.pid_kp == b.pid_kp && a.pid_ki == b.pid_ki && a.pid_kd == b.pid_kd;
+}
+
+// FNV-1a over the scaled cost and the two scaling vectors: tells the LP of a state buffer
+// from another one of the same sizes.
+int32_t lp_fingerprint(lp_handle* h, uint64_t* out) {
+    const size_t n = static_cast<size_t>(h->n), m = static_cast<size_t>(h->m);
+    std::vector<double> buf(2 * n + m);
+    hipStream_t s = h->stream;
+    HIP_TRY(h, hipMemcpyAsync(buf.data(), h->P.c, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(buf.data() + n, h->P.C, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    if (m) HIP_TRY(h, hipMemcpyAsync(buf.data() + 2 * n, h->P.R, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    uint64_t f = 1469598103934665603ull;
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(buf.data());
+    for (size_t i = 0; i < sizeof(double) * buf.size(); ++i) f = (f ^ p[i]) * 1099511628211ull;
+    *out = f;
+    return LP_OK;
+}
+
+StateHeader state_header(const lp_handle* h, int64_t n_records) {
+    StateHeader H{};
+    std::memcpy(H.magic, kStateMagic, sizeof(kStateMagic));
+    H.version = kStateVersion;
+    H.precision = h->opt.precision;
+    H.m = h->m;
+    H.n = h->n;
+    H.nnz = h->nnz;
+    H.trace_cap = h->opt.trace_cap;
+    H.n_records = n_records;
+    H.method = h->opt.method;
+    H.eval_every = h->opt.eval_every;
+    H.restarts = h->opt.restarts;
+    H.omega_steps = h->opt.omega_steps;
+    H.pw_rule = h->opt.pw_rule;
+    H.scalars_bytes = static_cast<int32_t>(sizeof(Scalars));
+    H.reflection = h->opt.reflection;
+    H.pid_kp = h->opt.pid_kp;
+    H.pid_ki = h->opt.pid_ki;
+    H.pid_kd = h->opt.pid_kd;
+    int64_t total = static_cast<int64_t>(sizeof(StateHeader) + sizeof(Scalars));
+    for (const StateSpan& sp : state_spans(h)) total += static_cast<int64_t>(sp.bytes);
+    H.total_bytes = total + n_records * kTraceW * static_cast<int64_t>(sizeof(double));
+    return H;
+}
+
+// Statistics and extraction of the paused point (after a pause or a state import).
+int32_t finish_paused(lp_handle* h) {
+    hipStream_t s = h->stream;
+    launch_evaluate(h->P, 2, s);
+    launch_extract(h->P, s);
+    if (int32_t rc = check_launch(h, "paused point")) return rc;
+    HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    fill_info(h);
+    h->info.solve_seconds = 0.0;
+    h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
     return LP_OK;
 }
 
@@ -1886,6 +2017,140 @@ int32_t lp_polish(lp_handle* h, double eps, int64_t max_iters) {
     }
 }
 
+int32_t lp_solve_until(lp_handle* h, int64_t k_pause) {
+    if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
+    if (k_pause <= 0) return fail(h, LP_ERR_INVALID_ARG, "k_pause must be positive");
+    try {
+        HIP_TRY(h, hipSetDevice(h->device));
+        if (int32_t rc = materialize(h)) return rc;
+        const int32_t rc = solve_from(h, h->d_x0, h->d_y0, 0, 0.0, k_pause);
+        h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
+        return rc;
+    } catch (...) {
+        return fail(h, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t lp_resume(lp_handle* h, int64_t k_pause) {
+    if (!h) return fail(nullptr, LP_ERR_INVALID_ARG, "handle is NULL");
+    if (k_pause < 0) return fail(h, LP_ERR_INVALID_ARG, "k_pause must be >= 0");
+    if (!h->on_device || !h->resumable) return fail(h, LP_ERR_NOT_SOLVED, "the handle holds no paused solve");
+    if (!same_form(h->opt, h->paused_opt))
+        return fail(h, LP_ERR_INVALID_ARG, "eval_every, restarts, the iteration form or the primal-weight rule changed");
+    try {
+        HIP_TRY(h, hipSetDevice(h->device));
+        hipStream_t s = h->stream;
+        HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        if (h->opt.max_iters <= h->h_sc->k) return LP_OK;  // nothing left to run: still paused
+        const auto t0 = std::chrono::steady_clock::now();
+        Scalars& sc = *h->h_sc;
+        sc.status = kRunning;
+        sc.eps_rel = h->opt.eps_rel;
+        sc.eps_infeas = h->opt.eps_infeas;
+        sc.max_iters = h->opt.max_iters;
+        sc.out_avg = 0;
+        sc.last_restart = 0;
+        sc.deadline = 0;
+        HIP_TRY(h, hipMemcpyAsync(h->P.sc, h->h_sc, sizeof(Scalars), hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        set_form(h->P, h->opt);
+        h->resumable = false;
+        h->solved = false;
+        const int32_t rc = run_periods(h, t0, k_pause);
+        h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
+        return rc;
+    } catch (...) {
+        return fail(h, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t lp_export_state(lp_handle* h, void* buf, int64_t cap, int64_t* size) {
+    if (!h || !size) return fail(h, LP_ERR_INVALID_ARG, "handle or size NULL");
+    if (!h->on_device || !h->resumable) return fail(h, LP_ERR_NOT_SOLVED, "the handle holds no paused solve");
+    try {
+        HIP_TRY(h, hipSetDevice(h->device));
+        hipStream_t s = h->stream;
+        HIP_TRY(h, hipMemcpyAsync(h->h_sc, h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        const long long nt = h->h_sc->n_trace;
+        const int64_t n_records = h->P.trace ? (nt < h->opt.trace_cap ? nt : h->opt.trace_cap) : 0;
+        StateHeader H = state_header(h, n_records);
+        *size = H.total_bytes;
+        if (!buf) return LP_OK;
+        if (cap < H.total_bytes) return fail(h, LP_ERR_INVALID_ARG, "buffer smaller than the state");
+        if (int32_t rc = lp_fingerprint(h, &H.fingerprint)) return rc;
+        char* out = static_cast<char*>(buf);
+        std::memcpy(out, &H, sizeof(H));
+        std::memcpy(out + sizeof(H), h->h_sc, sizeof(Scalars));
+        size_t off = sizeof(H) + sizeof(Scalars);
+        for (const StateSpan& sp : state_spans(h)) {
+            if (sp.bytes) HIP_TRY(h, hipMemcpyAsync(out + off, sp.p, sp.bytes, hipMemcpyDeviceToHost, s));
+            off += sp.bytes;
+        }
+        const size_t tb = sizeof(double) * kTraceW * static_cast<size_t>(n_records);
+        if (tb) HIP_TRY(h, hipMemcpyAsync(out + off, h->P.trace, tb, hipMemcpyDeviceToHost, s));
+        HIP_TRY(h, hipStreamSynchronize(s));
+        return LP_OK;
+    } catch (...) {
+        return fail(h, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
+int32_t lp_import_state(lp_handle* h, const void* buf, int64_t size) {
+    if (!h || !buf) return fail(h, LP_ERR_INVALID_ARG, "handle or buffer NULL");
+    if (!h->on_device) return fail(h, LP_ERR_INVALID_ARG, "the handle holds no device memory (deferred)");
+    StateHeader H;
+    if (size < static_cast<int64_t>(sizeof(H) + sizeof(Scalars)))
+        return fail(h, LP_ERR_INVALID_ARG, "buffer too small for a state");
+    std::memcpy(&H, buf, sizeof(H));
+    if (std::memcmp(H.magic, kStateMagic, sizeof(kStateMagic)) != 0 || H.version != kStateVersion ||
+        H.scalars_bytes != static_cast<int32_t>(sizeof(Scalars)))
+        return fail(h, LP_ERR_INVALID_ARG, "not a state buffer of this library");
+    if (H.m != h->m || H.n != h->n || H.nnz != h->nnz || H.precision != h->opt.precision ||
+        H.trace_cap != h->opt.trace_cap)
+        return fail(h, LP_ERR_INVALID_ARG, "state of an LP of other sizes, precision or trace capacity");
+    if (H.n_records < 0 || H.n_records > (h->opt.trace_cap > 0 ? h->opt.trace_cap : 0))
+        return fail(h, LP_ERR_INVALID_ARG, "state with a bad trace length");
+    const StateHeader E = state_header(h, H.n_records);
+    if (H.total_bytes != size || E.total_bytes != size) return fail(h, LP_ERR_INVALID_ARG, "state buffer of another size");
+    if (H.method != h->opt.method || H.eval_every != h->opt.eval_every || H.restarts != h->opt.restarts ||
+        H.omega_steps != h->opt.omega_steps || H.pw_rule != h->opt.pw_rule || H.reflection != h->opt.reflection ||
+        H.pid_kp != h->opt.pid_kp || H.pid_ki != h->opt.pid_ki || H.pid_kd != h->opt.pid_kd)
+        return fail(h, LP_ERR_INVALID_ARG, "the handle's iteration form differs from the saved run's");
+    try {
+        HIP_TRY(h, hipSetDevice(h->device));
+        uint64_t fp = 0;
+        if (int32_t rc = lp_fingerprint(h, &fp)) return rc;
+        if (fp != H.fingerprint) return fail(h, LP_ERR_INVALID_ARG, "state of another LP");
+        const char* in = static_cast<const char*>(buf);
+        Scalars sc;
+        std::memcpy(&sc, in + sizeof(H), sizeof(Scalars));
+        if (sc.status != LP_ITERATION_LIMIT || sc.n_trace < H.n_records || sc.k < 0 || sc.t < 0 ||
+            sc.trace_cap != h->opt.trace_cap || sc.eval_every != h->opt.eval_every || sc.term_mode != 0)
+            return fail(h, LP_ERR_INVALID_ARG, "state of a solve that is not paused");
+        hipStream_t s = h->stream;
+        *h->h_sc = sc;
+        HIP_TRY(h, hipMemcpyAsync(h->P.sc, h->h_sc, sizeof(Scalars), hipMemcpyHostToDevice, s));
+        size_t off = sizeof(H) + sizeof(Scalars);
+        for (const StateSpan& sp : state_spans(h)) {
+            if (sp.bytes) HIP_TRY(h, hipMemcpyAsync(sp.p, in + off, sp.bytes, hipMemcpyHostToDevice, s));
+            off += sp.bytes;
+        }
+        const size_t tb = sizeof(double) * kTraceW * static_cast<size_t>(H.n_records);
+        if (tb) HIP_TRY(h, hipMemcpyAsync(h->P.trace, in + off, tb, hipMemcpyHostToDevice, s));
+        HIP_TRY(h, hipStreamSynchronize(s));  // the copies read the caller's pageable buffer
+        set_form(h->P, h->opt);
+        if (int32_t rc = finish_paused(h)) return rc;
+        h->solved = true;
+        h->resumable = true;
+        h->paused_opt = h->opt;
+        return LP_OK;
+    } catch (...) {
+        return fail(h, LP_ERR_INTERNAL, "unexpected exception");
+    }
+}
+
 int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo) {
     if (count < 0 || (count > 0 && !hs)) return fail(nullptr, LP_ERR_INVALID_ARG, "bad batch arguments");
     if (count == 0) return LP_OK;
@@ -1899,6 +2164,7 @@ int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo
         if (bo && validate_options(*bo, &msg)) return fail(nullptr, LP_ERR_INVALID_ARG, msg);
         lp_handle* h0 = hs[0];
         HIP_TRY(h0, hipSetDevice(dev));
+        for (int32_t i = 0; i < count; ++i) hs[i]->resumable = false;  // a batch restarts every LP
         const int64_t split = bo ? bo->batch_split_nnz : 20000;
         std::vector<lp_handle*> big, small;
         for (int32_t i = 0; i < count; ++i) (hs[i]->nnz > split ? big : small).push_back(hs[i]);
@@ -1955,6 +2221,7 @@ int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_opti
         lp_handle* h0 = hs[0];
         const int dev = h0->device;
         HIP_TRY(h0, hipSetDevice(dev));
+        for (int32_t i = 0; i < count; ++i) hs[i]->resumable = false;  // a batch restarts every LP
         StaticBatchScratch S{};
         HIP_TRY(h0, static_batch_scratch(dev, &S));
         const auto t0 = std::chrono::steady_clock::now();
