@@ -65,7 +65,7 @@ class _OptsStruct(C.Structure):
         ("seed", C.c_uint64), ("x0", C.c_void_p), ("y0", C.c_void_p),
         ("n_snap", C.c_int32), ("pad1", C.c_int32), ("snap_k", C.c_void_p), ("snap_out", C.c_void_p),
         ("trace_cap", C.c_int32), ("pad2", C.c_int32), ("trace", C.c_void_p), ("eps_infeas", C.c_double),
-        ("method", C.c_int32), ("pad3", C.c_int32), ("reflection", C.c_double),
+        ("method", C.c_int32), ("restart_metric", C.c_int32), ("reflection", C.c_double),
         ("omega_steps", C.c_int32), ("pad4", C.c_int32), ("pw_rule", C.c_int32), ("pad5", C.c_int32),
         ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
         ("term_mode", C.c_int32), ("ray_candidates", C.c_int32),
@@ -231,11 +231,13 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
           snap_k: Sequence[int] = (), trace_cap: int = 4096, eps_infeas: float = 1e-8, method: int = 0,
           reflection: float = 1.0, omega_steps: int = 0, pw_rule: int = 0, pid_kp: Optional[float] = None,
           pid_ki: Optional[float] = None, pid_kd: Optional[float] = None, term_mode: int = 0,
-          ray_candidates: int = 0) -> Result:
+          ray_candidates: int = 0, restart_metric: int = 0) -> Result:
     """Run the oracle. `snap_k` lists iterations whose scaled-space state
     (x~, y~, x~avg, y~avg) is recorded right after the update of that iteration.
     `ray_candidates`: 0 both candidate rays, 1 the displacement since the previous evaluation
-    only, 2 the averaged point's displacement from the restart anchor only."""
+    only, 2 the averaged point's displacement from the restart anchor only.
+    `restart_metric` (Halpern form): 0 the restart tests compare KKT_omega values, 1 they
+    compare fixed-point residuals ||z - T(z)|| in the PDHG norm."""
     b = _Bound(lp)
     o = _OptsStruct()
     lib().ora_default_opts(C.byref(o))
@@ -256,6 +258,7 @@ def solve(lp, *, eps_rel: float = 1e-4, max_iters: int = 100000, eval_every: int
     o.pw_rule = pw_rule
     o.term_mode = term_mode
     o.ray_candidates = ray_candidates
+    o.restart_metric = restart_metric
     if pid_kp is not None:
         o.pid_kp = pid_kp
     if pid_ki is not None:

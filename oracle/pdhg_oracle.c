@@ -79,7 +79,9 @@ typedef struct {
     double *trace;       /* trace_cap * ORA_TRACE_W */
     double eps_infeas;   /* relative tolerance of the infeasibility certificates; 0: off */
     int32_t method;      /* 0: averaged PDHG; 1: reflected Halpern PDHG */
-    int32_t pad3;
+    int32_t restart_metric; /* what the restart tests compare in the Halpern form: 0 KKT_omega
+                               of T(z), 1 the fixed-point residual ||z - T(z)|| in the PDHG
+                               norm (ignored by the averaged form) */
     double reflection;   /* rho of the Halpern form, in [0, 1] */
     int32_t omega_steps; /* square-root steps of the primal-weight update (O11); 0: the form's */
     int32_t pad4;
@@ -643,6 +645,29 @@ static double dual_step(double y, double axn, double ax, double sigma, double bl
     return (lo > 0.0 ? lo : 0.0) + (hi < 0.0 ? hi : 0.0);
 }
 
+/* Fixed-point residual of the Halpern iterate z = (x, y) in the norm of the PDHG map: with
+ * d = z - T(z) = (dx, dy) and A~dx = ax - axa,
+ *   r^2 = omega ||dx||^2 + 2 eta <dy, A~dx> + ||dy||^2 / omega,
+ * which is eta times the quadratic form of [[I / tau, A~^T], [A~, I / sigma]] (tau = eta /
+ * omega, sigma = eta omega): the metric in which the map of O7 is firmly nonexpansive, a norm
+ * while eta ||A~||_2 < 1. */
+static double fixed_point_residual(int32_t m, int32_t n, const double *x, const double *xa, const double *y,
+                                   const double *ya, const double *ax, const double *axa, double omega,
+                                   double eta) {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int32_t j = 0; j < n; j++) {
+        double d = x[j] - xa[j];
+        s1 += d * d;
+    }
+    for (int32_t i = 0; i < m; i++) {
+        double d = y[i] - ya[i];
+        s2 += d * (ax[i] - axa[i]);
+        s3 += d * d;
+    }
+    double r2 = omega * s1 + 2.0 * eta * s2 + s3 / omega;
+    return sqrt(r2 > 0.0 ? r2 : 0.0);
+}
+
 /* Restarted, averaged PDHG (primal step first) on the scaled problem.
  *
  * O4  omega0 = ||c~|| / ||q~|| when both exceed 1e-10, else 1 (q: combined bounds).
@@ -675,7 +700,11 @@ static double dual_step(double y, double axn, double ax, double sigma, double bl
  * Halpern form (method 1, a reading of the newer cuPDLPx-family iteration the paper names):
  * the iterate is z <- w ((1 + rho) T(z) - rho z) + (1 - w) z_anchor with T the map of O7,
  * w = (t + 1) / (t + 2); no averages; O8-O11 act on T(z) (the only candidate), a restart
- * moves the iterate and the anchor to T(z). */
+ * moves the iterate and the anchor to T(z). With restart_metric 1 (the restart rule of that
+ * solver family) the three tests of O10 compare fixed-point residuals instead of KKT_omega
+ * values: the current one is that of the last iterate before the evaluation (whose T(z) is
+ * the candidate), the anchor's that of the first iterate of the cycle (the anchor itself),
+ * both in the cycle's weight. */
 int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out, double *z_out,
               ora_info *info) {
     double t0 = now_s();
@@ -752,6 +781,9 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
     /* primal-weight rule and the PID controller's state (integral, previous error) */
     const int pid = o->pw_rule == 2;
     double pid_int = 0.0, pid_prev = 0.0;
+    /* fixed-point residual restarts: residual of the latest iterate and of the cycle's anchor */
+    const int fpr = halpern && o->restart_metric == 1;
+    double r_cur = 0.0, r_anchor = 0.0;
     int64_t k = 0, t = 0, restarts = 0, ntr = 0;
     int status = -1, out_avg = 0;
     int64_t snap_i = 0;
@@ -773,6 +805,11 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
             for (int32_t j = 0; j < n; j++) xa[j] = primal_step(x[j], P.c[j], aty[j], tau, P.xlo[j], P.xhi[j]);
             csr_mv(m, P.rp, P.ci, P.av, xa, axa);
             for (int32_t i = 0; i < m; i++) ya[i] = dual_step(y[i], axa[i], ax[i], sigma, P.blo[i], P.bhi[i]);
+            if (fpr && (t == 0 || (k + 1) % o->eval_every == 0 || k + 1 >= o->max_iters)) {
+                double r = fixed_point_residual(m, n, x, xa, y, ya, ax, axa, omega, eta);
+                if (t == 0) r_anchor = r;
+                r_cur = r;
+            }
             double wk = (double)(t + 1) / (double)(t + 2);
             double wa = 1.0 - wk;
             double r1 = 1.0 + rho;
@@ -831,6 +868,10 @@ int ora_solve(const ora_lp *lp, const ora_opts *o, double *x_out, double *y_out,
         const double *ex = halpern ? xa : x, *ey = halpern ? ya : y;
         const double *eax = halpern ? axa : ax, *eaty = halpern ? atya : aty;
         double kc = kkt_omega(&Kc, omega), ka = kkt_omega(&Ka, omega);
+        if (fpr) {
+            kc = ka = r_cur;
+            kkt_anchor = r_anchor;
+        }
         double rec[ORA_TRACE_W];
         memset(rec, 0, sizeof(rec));
         rec[0] = (double)k;

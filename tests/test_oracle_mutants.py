@@ -2,7 +2,9 @@
 a temporary copy of the oracle source (CPU only), and the quick pin subset must fail on it.
 
 The restart cycle is covered by mutants of its implementation (candidate choice, primal-weight
-update direction, the no-progress test, the anchor reset). Its constants (0.2, 0.8, 0.36) are
+update direction, the no-progress test, the anchor reset), and so are the fixed-point
+residual restarts (the norm's coupling sign and weights, which iterate it is taken at, the
+anchor's residual). Its constants (0.2, 0.8, 0.36) are
 readings the paper does not fix, so no mutant changes them (parity unpinned for them)."""
 import os
 import subprocess
@@ -49,6 +51,14 @@ MUTANTS = {
         "eval_rays(&P, xa, ya, axa, atya, xan, yan, axan, atyan, &Rray, NULL, NULL, NULL);",
         "eval_rays(&P, xa, ya, axa, atya, xp, yp, axp, atyp, &Rray, NULL, NULL, NULL);"),
     "anchor_products_not_moved": ("memcpy(atyan, atya, nb);", "(void)0;"),
+    "residual_coupling_sign": ("double r2 = omega * s1 + 2.0 * eta * s2 + s3 / omega;",
+                               "double r2 = omega * s1 - 2.0 * eta * s2 + s3 / omega;"),
+    "residual_weights_swapped": ("double r2 = omega * s1 + 2.0 * eta * s2 + s3 / omega;",
+                                 "double r2 = s1 / omega + 2.0 * eta * s2 + omega * s3;"),
+    "residual_anchor_not_refreshed": ("if (t == 0) r_anchor = r;", "if (k == 0) r_anchor = r;"),
+    "residual_from_first_iterate_of_period": ("(t == 0 || (k + 1) % o->eval_every == 0 || k + 1 >= o->max_iters)",
+                                              "(t == 0 || k % o->eval_every == 0 || k + 1 >= o->max_iters)"),
+    "residual_restarts_on_kkt": ("kc = ka = r_cur;", "(void)0;"),
 }
 
 QUICK = [

@@ -16,6 +16,10 @@ stay unpinned. What is pinned here is that the oracle does what the rules say:
   long cycle), and the invariant that the candidate is never worse than the current point.
 * The primal-weight update balances the weighted distances moved in the cycle: with s
   square-root steps the log of the imbalance omega * dx / dy shrinks by exactly 2^-s.
+* Restarts on the fixed-point residual (Halpern form, restart_metric 1): the norm is the one
+  in which the PDHG map is firmly nonexpansive (checked on the map itself, which fixes the
+  sign of its coupling term), and every residual, anchor residual and decision of a solve is
+  recomputed from snapshots.
 """
 import math
 
@@ -228,3 +232,138 @@ def test_pid_proportional_is_smoothing(oracle_lib):
     assert np.array_equal(a.trace[:, [0, 1, 6, 7]], b.trace[:, [0, 1, 6, 7]])
     np.testing.assert_allclose(b.trace[:6, 8], a.trace[:6, 8], rtol=1e-14)
     np.testing.assert_allclose(b.trace[:, 8], a.trace[:, 8], rtol=1e-6)
+
+
+# ---- restarts on the fixed-point residual (Halpern form, restart_metric = 1) -------------
+
+def _pdhg_map(oracle_lib, lp, x, y, eta, omega):
+    """T(z): one step of the oracle's PDHG from the warm start z (no scaling, no restarts)."""
+    r = oracle_lib.solve(lp, eps_rel=0.0, max_iters=1, scaling=False, restarts=False, eta=eta, omega0=omega,
+                         method=0, x0=x, y0=y, snap_k=[1])
+    xs, ys, _, _ = oracle_lib.split_snap(r.snaps[0], lp.n, lp.m)
+    return xs.copy(), ys.copy()
+
+
+def _m_inner(a, u, v, eta, omega, sign=1.0):
+    """eta <u, M v> with the PDHG preconditioner M = [[I/tau, A^T], [A, I/sigma]]."""
+    tau, sigma = eta / omega, eta * omega
+    return eta * (u[0] @ v[0] / tau + sign * (u[1] @ (a @ v[0]) + v[1] @ (a @ u[0])) + u[1] @ v[1] / sigma)
+
+
+def _fpr(a, x, xt, y, yt, omega, eta):
+    """||z - T(z)|| in that norm, from its definition."""
+    d = (x - xt, y - yt)
+    return math.sqrt(max(_m_inner(a, d, d, eta, omega), 0.0))
+
+
+def test_residual_norm_makes_the_map_firmly_nonexpansive(oracle_lib):
+    """The norm of the residual restarts is the one in which the PDHG map is firmly
+    nonexpansive, ||Tz - Tz'||^2 <= <Tz - Tz', z - z'> (the property the Halpern iteration's
+    convergence rests on): it holds for every pair of random points with the metric above and
+    fails for most with the sign of the coupling term flipped, so the sign is fixed by the
+    map itself."""
+    held = broken = 0
+    for j in range(3):
+        lp = _lp(j)
+        a = lp.dense()
+        eta = 0.95 / np.linalg.norm(a, 2)
+        rng = np.random.default_rng([23, j])
+        lo, hi = lp.x_lo, lp.x_hi
+
+        def point():
+            x = np.where(np.isfinite(lo) & np.isfinite(hi), lo + rng.random(lp.n) * (hi - lo), 3 * rng.normal(size=lp.n))
+            return np.clip(x, lo, hi), 3 * rng.normal(size=lp.m)
+
+        for omega in (0.3, 1.0, 4.0):
+            for _ in range(6):
+                z1, z2 = point(), point()
+                t1, t2 = _pdhg_map(oracle_lib, lp, *z1, eta, omega), _pdhg_map(oracle_lib, lp, *z2, eta, omega)
+                dt, dz = (t1[0] - t2[0], t1[1] - t2[1]), (z1[0] - z2[0], z1[1] - z2[1])
+                lhs, rhs = _m_inner(a, dt, dt, eta, omega), _m_inner(a, dt, dz, eta, omega)
+                assert lhs <= rhs + 1e-12 * abs(lhs), (j, omega, lhs, rhs)
+                held += 1
+                flhs, frhs = _m_inner(a, dt, dt, eta, omega, -1.0), _m_inner(a, dt, dz, eta, omega, -1.0)
+                broken += flhs > frhs
+    assert held == 54 and broken >= 27
+
+
+def _check_fpr_decisions(oracle_lib, lp, pid=None, seen=None):
+    """Every decision of a Halpern solve with residual restarts, recomputed from snapshots:
+    the residual of the iterate before each evaluation (z_{k-1} against T(z_{k-1}), the
+    snapshot pair k-1, k) and of the cycle's anchor (the anchor against its image, the first
+    iteration of the cycle), the restart reason from them, and the primal-weight update."""
+    a = lp.dense()
+    eta = 0.95 / np.linalg.norm(a, 2)
+    kw = dict(restart_metric=1)
+    if pid is not None:
+        kw.update(pw_rule=2, pid_kp=pid[0], pid_ki=pid[1], pid_kd=pid[2])
+    base = _solve(oracle_lib, lp, eta, 1, False, **kw)
+    tr = base.trace
+    ks = [int(r[0]) for r in tr]
+    snaps = sorted({1} | {k + d for k in ks for d in (-1, 0, 1)})
+    run = _solve(oracle_lib, lp, eta, 1, False, snap_k=snaps, **kw)
+    assert np.array_equal(run.trace, tr)
+    S = {k: oracle_lib.split_snap(run.snaps[i], lp.n, lp.m) for i, k in enumerate(snaps)}
+    omega = 1.0
+    x_an, y_an = np.clip(np.zeros(lp.n), lp.x_lo, lp.x_hi), np.zeros(lp.m)
+    anc = _fpr(a, x_an, S[1][2], y_an, S[1][3], omega, eta)
+    prev, k_last, errors = math.inf, 0, []
+    for rec in tr[:-1]:
+        k = int(rec[0])
+        xa, ya = S[k][2], S[k][3]
+        r = _fpr(a, S[k - 1][0], xa, S[k - 1][1], ya, omega, eta)
+        # the oracle's A~x of the Halpern iterate is carried by linearity, numpy's is A @ x: the
+        # coupling term differs by ~1e-16 |Ax| sqrt(m), an absolute noise far below 1e-13
+        assert _close(rec[2], r, noise=1e-13) and rec[3] == rec[2], (k, rec[2], r)
+        assert _close(rec[9], anc, noise=1e-13), (k, rec[9], anc)
+        assert _close(rec[10], prev, noise=1e-13), (k, rec[10], prev)
+        t = k - k_last
+        assert int(rec[1]) == t
+        ties = [_tie(r, 0.2 * anc), _tie(r, 0.8 * anc), t == 0.36 * k, _tie(r, prev)]
+        if not any(ties):
+            why = 1 if r <= 0.2 * anc else 2 if (r <= 0.8 * anc and r > prev) else 3 if t >= 0.36 * k else 0
+            assert int(rec[7]) == why, (k, int(rec[7]), why, r / anc, r, prev, t / k)
+        why = int(rec[7])
+        if seen is not None:
+            seen.add(why)
+        if why:
+            dx, dy = np.linalg.norm(xa - x_an), np.linalg.norm(ya - y_an)
+            new = float(rec[8])
+            before = math.log(omega * dx / dy)
+            if pid is None:
+                assert abs(math.log(new * dx / dy) - before / 4.0) <= 1e-12 * (1 + abs(before)), (k, before)
+            else:
+                errors.append(before)
+                e = np.array(errors)
+                total = -(pid[0] * e.sum() + pid[1] * np.cumsum(e).sum() + pid[2] * e[-1])
+                assert abs(math.log(new) - total) <= 1e-11 * (1 + abs(total)), (k, math.log(new), total)
+            omega = new
+            x_an, y_an = xa.copy(), ya.copy()
+            anc = _fpr(a, x_an, S[k + 1][2], y_an, S[k + 1][3], omega, eta)
+            prev, k_last = math.inf, k
+        else:
+            assert float(rec[8]) == omega
+            prev = r
+
+
+@pytest.mark.parametrize("pid", [None, (0.7, 0.05, 0.2)], ids=["smoothing", "pid"])
+def test_residual_restart_decisions_recomputed(oracle_lib, pid):
+    seen = set()
+    for j in range(4):
+        _check_fpr_decisions(oracle_lib, _lp(j), pid=pid, seen=seen)
+    assert {1, 3} <= seen, seen
+
+
+def test_residual_restarts_solve_and_change_the_run(oracle_lib):
+    """The residual restarts solve these LPs to 1e-8 (E_rel rechecked by the oracle's KKT on
+    the original data) and restart at other evaluations than the KKT restarts; the averaged
+    form ignores the option."""
+    for j in range(3):
+        lp = _lp(j)
+        kkt = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=200000, method=1)
+        res = oracle_lib.solve(lp, eps_rel=1e-8, max_iters=200000, method=1, restart_metric=1)
+        assert res.status == "optimal" and res.erel <= 1e-8
+        assert not np.array_equal(kkt.trace[:, [0, 7]], res.trace[:, [0, 7]]) or kkt.iters != res.iters
+        avg = oracle_lib.solve(lp, eps_rel=1e-6, max_iters=200000, method=0)
+        avg1 = oracle_lib.solve(lp, eps_rel=1e-6, max_iters=200000, method=0, restart_metric=1)
+        assert np.array_equal(avg.trace, avg1.trace) and np.array_equal(avg.x, avg1.x)
