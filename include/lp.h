@@ -156,7 +156,13 @@ typedef struct lp_options {
                               minus the anchor of the restart cycle; see LP_PRIMAL_INFEASIBLE /
                               LP_DUAL_INFEASIBLE and lp_info.ray_source */
     int32_t method;        /* lp_method (default LP_METHOD_AVERAGED) */
-    int32_t pad2;
+    int32_t restart_metric; /* LP_METHOD_HALPERN: what the three restart tests compare. 0 (default):
+                              the KKT error of T(z) in the primal-weighted norm; 1: the
+                              fixed-point residual ||z - T(z)|| in the norm of the PDHG map,
+                              omega ||dx||^2 + 2 eta <dy, A~dx> + ||dy||^2 / omega (the restart
+                              rule of the Halpern PDHG family of Section 4's solver), for the
+                              last iterate before an evaluation and for the cycle's anchor.
+                              Termination still tests E_rel. The averaged form ignores it */
     double reflection;     /* rho of LP_METHOD_HALPERN, in [0, 1] (default 1) */
     int32_t omega_steps;   /* primal-weight update at a restart: omega <- sqrt(omega * dy / dx)
                             * applied this many times, i.e. log omega moves toward log(dy/dx)

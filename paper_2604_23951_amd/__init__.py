@@ -71,7 +71,7 @@ class lp_options(C.Structure):
         ("batch_wg_per_cu", C.c_int32),
         ("panel_slice_bytes", C.c_int64), ("batch_split_nnz", C.c_int64), ("deferred", C.c_int32),
         ("small_lp_lds", C.c_int32), ("x0", C.c_void_p), ("y0", C.c_void_p), ("eps_infeas", C.c_double),
-        ("method", C.c_int32), ("pad2", C.c_int32), ("reflection", C.c_double),
+        ("method", C.c_int32), ("restart_metric", C.c_int32), ("reflection", C.c_double),
         ("omega_steps", C.c_int32), ("pad3", C.c_int32), ("pw_rule", C.c_int32), ("pad4", C.c_int32),
         ("pid_kp", C.c_double), ("pid_ki", C.c_double), ("pid_kd", C.c_double),
         ("tile_nnz", C.c_int32), ("pad5", C.c_int32),

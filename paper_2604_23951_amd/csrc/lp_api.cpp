@@ -98,6 +98,7 @@ struct Offsets {
     size_t arp, aci, av, at, trp, tci, tv, tt, perm, c, xl, xu, C, Ci, bl, bu, R, Ri;
     size_t x, xa, xan, aty, atya, ox, oz, y, ya, yan, ax, axa, oy, x0, y0;
     size_t xp, atyp, yp, axp, axan, atyan;
+    size_t fr[6];  // residual restarts: z - T(z) of the last iterate (x, y, A~x parts), then of the anchor
     size_t f32[15] = {0};
     size_t pA[7] = {0}, pAT[7] = {0}, pA32 = 0, pAT32 = 0;
     size_t part, sc, tr, job;
@@ -254,7 +255,8 @@ int32_t validate_options(const lp_options& o, std::string* msg) {
         std::isnan(o.time_limit_s) || !(o.eps_infeas >= 0.0) || o.method < LP_METHOD_AVERAGED ||
         o.method > LP_METHOD_HALPERN || !(o.reflection >= 0.0 && o.reflection <= 1.0) || o.omega_steps < 0 ||
         o.omega_steps > 8 || o.pw_rule < LP_PW_DEFAULT || o.pw_rule > LP_PW_PID || !(o.pid_kp >= 0.0 && o.pid_kp <= 2.0) ||
-        !(o.pid_ki >= 0.0 && o.pid_ki <= 2.0) || !(o.pid_kd >= 0.0 && o.pid_kd <= 2.0)) {
+        !(o.pid_ki >= 0.0 && o.pid_ki <= 2.0) || !(o.pid_kd >= 0.0 && o.pid_kd <= 2.0) || o.restart_metric < 0 ||
+        o.restart_metric > 1) {
         *msg = "invalid option value";
         return LP_ERR_INVALID_ARG;
     }
@@ -357,6 +359,7 @@ void set_form(DevLP& P, const lp_options& o) {
     P.kp = o.pid_kp;
     P.ki = o.pid_ki;
     P.kd = o.pid_kd;
+    P.restart_metric = o.method == LP_METHOD_HALPERN ? o.restart_metric : 0;
 }
 
 BatchJob make_job(lp_handle* h, const lp_options* bo) {
@@ -854,6 +857,7 @@ size_t arena_layout(const lp_handle* h, Offsets* O) {
     O->axp = L.add(sm);
     O->axan = L.add(sm);
     O->atyan = L.add(sn);
+    for (int i = 0; i < 6; ++i) O->fr[i] = L.add(i % 3 == 0 ? sn : sm);
     O->x0 = h->has_x0 ? L.add(sn) : 0;
     O->y0 = h->has_y0 ? L.add(sm) : 0;
     const bool fp32 = o.precision == LP_PREC_FP32_REFINED;
@@ -1033,6 +1037,12 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.axp = D(O.axp);
     P.axan = D(O.axan);
     P.atyan = D(O.atyan);
+    P.fr_x = D(O.fr[0]);
+    P.fr_y = D(O.fr[1]);
+    P.fr_ax = D(O.fr[2]);
+    P.fa_x = D(O.fr[3]);
+    P.fa_y = D(O.fr[4]);
+    P.fa_ax = D(O.fr[5]);
     P.partials = D(O.part);
     P.sc = reinterpret_cast<Scalars*>(b + O.sc);
     P.trace = o.trace_cap > 0 ? D(O.tr) : nullptr;
@@ -1827,7 +1837,8 @@ std::vector<StateSpan> state_spans(const lp_handle* h) {
     std::vector<StateSpan> v = {{P.x, dn},    {P.xa, dn},   {P.xan, dn},   {P.aty, dn},   {P.atya, dn},
                                 {P.xp, dn},   {P.atyp, dn}, {P.atyan, dn}, {P.y, dm},     {P.ya, dm},
                                 {P.yan, dm},  {P.ax, dm},   {P.axa, dm},   {P.yp, dm},    {P.axp, dm},
-                                {P.axan, dm}};
+                                {P.axan, dm}, {P.fr_x, dn}, {P.fr_y, dm},  {P.fr_ax, dm}, {P.fa_x, dn},
+                                {P.fa_y, dm}, {P.fa_ax, dm}};
     if (P.fp32) {
         const StateSpan f[] = {{P.dx, fn},   {P.dxa, fn},  {P.d32, fn},  {P.lo32, fn}, {P.hi32, fn},
                                {P.dy, fm},   {P.dya, fm},  {P.adx, fm},  {P.rl32, fm}, {P.ru32, fm},
@@ -1842,7 +1853,7 @@ struct StateHeader {
     int32_t version, precision;
     int32_t m, n;
     int64_t nnz, trace_cap, n_records, total_bytes;
-    int32_t method, eval_every, restarts, omega_steps, pw_rule, scalars_bytes;
+    int32_t method, eval_every, restarts, omega_steps, pw_rule, scalars_bytes, restart_metric, pad;
     double reflection, pid_kp, pid_ki, pid_kd;
     uint64_t fingerprint;
 };
@@ -1853,7 +1864,7 @@ constexpr int32_t kStateVersion = 1;
 bool same_form(const lp_options& a, const lp_options& b) {
     return a.eval_every == b.eval_every && a.restarts == b.restarts && a.method == b.method &&
            a.reflection == b.reflection && a.omega_steps == b.omega_steps && a.pw_rule == b.pw_rule &&
-           a.pid_kp == b.pid_kp && a.pid_ki == b.pid_ki && a.pid_kd == b.pid_kd;
+           a.pid_kp == b.pid_kp && a.pid_ki == b.pid_ki && a.pid_kd == b.pid_kd && a.restart_metric == b.restart_metric;
 }
 
 // FNV-1a over the scaled cost and the two scaling vectors: tells the LP of a state buffer
@@ -1888,6 +1899,7 @@ StateHeader state_header(const lp_handle* h, int64_t n_records) {
     H.restarts = h->opt.restarts;
     H.omega_steps = h->opt.omega_steps;
     H.pw_rule = h->opt.pw_rule;
+    H.restart_metric = h->opt.restart_metric;
     H.scalars_bytes = static_cast<int32_t>(sizeof(Scalars));
     H.reflection = h->opt.reflection;
     H.pid_kp = h->opt.pid_kp;
@@ -2116,7 +2128,8 @@ int32_t lp_import_state(lp_handle* h, const void* buf, int64_t size) {
     if (H.total_bytes != size || E.total_bytes != size) return fail(h, LP_ERR_INVALID_ARG, "state buffer of another size");
     if (H.method != h->opt.method || H.eval_every != h->opt.eval_every || H.restarts != h->opt.restarts ||
         H.omega_steps != h->opt.omega_steps || H.pw_rule != h->opt.pw_rule || H.reflection != h->opt.reflection ||
-        H.pid_kp != h->opt.pid_kp || H.pid_ki != h->opt.pid_ki || H.pid_kd != h->opt.pid_kd)
+        H.pid_kp != h->opt.pid_kp || H.pid_ki != h->opt.pid_ki || H.pid_kd != h->opt.pid_kd ||
+        H.restart_metric != h->opt.restart_metric)
         return fail(h, LP_ERR_INVALID_ARG, "the handle's iteration form differs from the saved run's");
     try {
         HIP_TRY(h, hipSetDevice(h->device));
@@ -2285,13 +2298,14 @@ int32_t lp_update_options(lp_handle* h, const lp_options* opt) {
     o.pid_kp = opt->pid_kp;
     o.pid_ki = opt->pid_ki;
     o.pid_kd = opt->pid_kd;
+    o.restart_metric = opt->restart_metric;
     std::string msg;
     if (int32_t rc = validate_options(o, &msg)) return fail(h, rc, msg);
     // the captured iteration bundle bakes in the period, the form, its reflection and the
     // primal-weight steps (the kernels take the solver state by value)
     if (o.eval_every != h->opt.eval_every || o.method != h->opt.method || o.reflection != h->opt.reflection ||
         o.omega_steps != h->opt.omega_steps || o.pw_rule != h->opt.pw_rule || o.pid_kp != h->opt.pid_kp ||
-        o.pid_ki != h->opt.pid_ki || o.pid_kd != h->opt.pid_kd) {
+        o.pid_ki != h->opt.pid_ki || o.pid_kd != h->opt.pid_kd || o.restart_metric != h->opt.restart_metric) {
         if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
         if (h->graph) (void)hipGraphDestroy(h->graph);
         h->gexec = nullptr;

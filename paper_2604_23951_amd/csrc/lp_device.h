@@ -18,7 +18,8 @@ constexpr int kTileNnzMax = 4096;
 constexpr int kMaxRedBlocks = 512;
 constexpr int kNQ = 8;            // reduced quantities per candidate
 constexpr int kNR = 8;            // reduced quantities of the two candidate rays (infeasibility), 4 each
-constexpr int kNT = 2 * kNQ + kNR;  // all reduced quantities of one evaluation
+constexpr int kNF = 6;             // sums of the residual restarts: ||dx||^2, <dy, A~dx>, ||dy||^2 (last iterate, anchor)
+constexpr int kNT = 2 * kNQ + kNR + kNF;  // all reduced quantities of one evaluation
 constexpr int kTraceW = 12;
 
 constexpr int kRunning = -1;
@@ -111,6 +112,11 @@ struct DevLP {
     double *xan, *yan;                // anchor (start of the current restart cycle)
     double *xp, *yp, *axp, *atyp;     // point of the previous evaluation (candidate rays)
     double *axan, *atyan;             // A~x, A~^T y of the anchor
+    // Residual restarts of the Halpern form (restart_metric 1): z - T(z) as (x, y, A~x) parts,
+    // written by the iteration epilogues for the last iterate before an evaluation (fr_*) and
+    // for the first iterate of a restart cycle, the anchor (fa_*).
+    int restart_metric;
+    double *fr_x, *fr_y, *fr_ax, *fa_x, *fa_y, *fa_ax;
     // iteration form of the current solve: 0 averaged PDHG, 1 reflected Halpern PDHG with
     // reflection rho. In the Halpern form (x, y, ax) is the Halpern iterate and (xa, ya, axa)
     // the PDHG output T(z), the only candidate of the evaluations.

@@ -621,6 +621,14 @@ struct EpiDual32 {
     }
 };
 
+// Residual restarts: the iteration whose iterate's residual z - T(z) the next evaluation uses,
+// the last one before it (period end or max_iters).
+__device__ inline bool residual_at_last(const Scalars* sc, int it) {
+    long long last = sc->k + sc->eval_every;
+    if (last > sc->max_iters) last = sc->max_iters;
+    return sc->k + it + 1 == last;
+}
+
 // Reflected Halpern form (a reading of the newer cuPDLPx-family iteration): with T the PDHG map
 // above and the anchor z0 of the restart cycle, z <- w ((1 + rho) T(z) - rho z) + (1 - w) z0,
 // w = (t + 1) / (t + 2), t the iterations of the cycle before this one. The primal half on
@@ -634,7 +642,9 @@ struct EpiPrimalH {
     int it;
     const double *c, *xl, *xu, *xan;
     double *x, *xa;
+    double *rx_c, *rx_a;  // residual restarts: x - T(z)_x of the last iterate / of the anchor (or null)
     double tau, w, wa, r1, rho;
+    bool rec_c, rec_a;
     __device__ bool begin() {
         if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
         const long long t = sc->t + it;
@@ -642,6 +652,8 @@ struct EpiPrimalH {
         w = static_cast<double>(t + 1) / static_cast<double>(t + 2);
         wa = 1.0 - w;
         r1 = 1.0 + rho;
+        rec_c = rx_c != nullptr && residual_at_last(sc, it);
+        rec_a = rx_a != nullptr && t == 0;
         return true;
     }
     __device__ Pre load(int j) const { return Pre{c[j], xl[j], xu[j], x[j], xan[j]}; }
@@ -650,6 +662,8 @@ struct EpiPrimalH {
         const double xp = clampd(p.x - tau * g, p.lo, p.hi);
         x[j] = w * (r1 * xp - rho * p.x) + wa * p.xan;
         xa[j] = xp;
+        if (rec_c) rx_c[j] = p.x - xp;
+        if (rec_a) rx_a[j] = p.x - xp;
     }
 };
 
@@ -664,7 +678,9 @@ struct EpiDualH {
     int it;
     const double *bl, *bu, *yan, *axan;
     double *y, *ya, *ax, *axa;
+    double *ry_c, *rax_c, *ry_a, *rax_a;  // residual restarts: y and A~x parts of z - T(z) (or null)
     double sigma, w, wa, r1, rho;
+    bool rec_c, rec_a;
     __device__ bool begin() {
         if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
         const long long t = sc->t + it;
@@ -672,6 +688,8 @@ struct EpiDualH {
         w = static_cast<double>(t + 1) / static_cast<double>(t + 2);
         wa = 1.0 - w;
         r1 = 1.0 + rho;
+        rec_c = ry_c != nullptr && residual_at_last(sc, it);
+        rec_a = ry_a != nullptr && t == 0;
         return true;
     }
     __device__ Pre load(int i) const { return Pre{y[i], bl[i], bu[i], ax[i], yan[i], axan[i]}; }
@@ -685,6 +703,14 @@ struct EpiDualH {
         ya[i] = yp;
         axa[i] = s;
         ax[i] = w * (r1 * s - rho * p.ax) + wa * p.axan;
+        if (rec_c) {
+            ry_c[i] = p.y - yp;
+            rax_c[i] = p.ax - s;
+        }
+        if (rec_a) {
+            ry_a[i] = p.y - yp;
+            rax_a[i] = p.ax - s;
+        }
     }
 };
 
@@ -698,13 +724,17 @@ struct EpiPrimal32H {
     int it;
     const float *d, *lo, *hi;
     float *x, *xa;
+    double *rx_c, *rx_a;  // residual restarts (FP64 copies of the FP32 differences, or null)
     float tau, w, r1, rho;
+    bool rec_c, rec_a;
     __device__ bool begin() {
         if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
         const long long t = sc->t + it;
         tau = static_cast<float>(sc->tau);
         w = static_cast<float>(static_cast<double>(t + 1) / static_cast<double>(t + 2));
         r1 = 1.0f + rho;
+        rec_c = rx_c != nullptr && residual_at_last(sc, it);
+        rec_a = rx_a != nullptr && t == 0;
         return true;
     }
     __device__ Pre load(int j) const { return Pre{d[j], lo[j], hi[j], x[j]}; }
@@ -715,6 +745,8 @@ struct EpiPrimal32H {
         if (xp > p.hi) xp = p.hi;
         x[j] = w * (r1 * xp - rho * p.x);
         xa[j] = xp;
+        if (rec_c) rx_c[j] = static_cast<double>(p.x) - static_cast<double>(xp);
+        if (rec_a) rx_a[j] = static_cast<double>(p.x) - static_cast<double>(xp);
     }
 };
 
@@ -726,13 +758,17 @@ struct EpiDual32H {
     int it;
     const float *rl, *ru, *yh;
     float *y, *ya, *ax;
+    double *ry_c, *rax_c, *ry_a, *rax_a;  // residual restarts (FP64 copies, or null)
     float sigma, w, r1, rho;
+    bool rec_c, rec_a;
     __device__ bool begin() {
         if (sc->status != kRunning || sc->k + it >= sc->max_iters) return false;
         const long long t = sc->t + it;
         sigma = static_cast<float>(sc->sigma);
         w = static_cast<float>(static_cast<double>(t + 1) / static_cast<double>(t + 2));
         r1 = 1.0f + rho;
+        rec_c = ry_c != nullptr && residual_at_last(sc, it);
+        rec_a = ry_a != nullptr && t == 0;
         return true;
     }
     __device__ Pre load(int i) const { return Pre{y[i], rl[i], ru[i], yh[i], ax[i]}; }
@@ -748,6 +784,14 @@ struct EpiDual32H {
         y[i] = w * (r1 * yp - rho * p.y);
         ya[i] = yp;
         ax[i] = w * (r1 * s - rho * p.ax);
+        if (rec_c) {
+            ry_c[i] = static_cast<double>(p.y) - static_cast<double>(yp);
+            rax_c[i] = static_cast<double>(p.ax) - static_cast<double>(s);
+        }
+        if (rec_a) {
+            ry_a[i] = static_cast<double>(p.y) - static_cast<double>(yp);
+            rax_a[i] = static_cast<double>(p.ax) - static_cast<double>(s);
+        }
     }
 };
 
@@ -808,6 +852,8 @@ __host__ __device__ inline EpiPrimalH epi_primal_h(const DevLP& P, const Scalars
     e.x = P.x;
     e.xa = P.xa;
     e.rho = P.rho;
+    e.rx_c = P.restart_metric == 1 ? P.fr_x : nullptr;
+    e.rx_a = P.restart_metric == 1 ? P.fa_x : nullptr;
     return e;
 }
 __host__ __device__ inline EpiDualH epi_dual_h(const DevLP& P, const Scalars* sc, int it) {
@@ -823,6 +869,12 @@ __host__ __device__ inline EpiDualH epi_dual_h(const DevLP& P, const Scalars* sc
     e.ax = P.ax;
     e.axa = P.axa;
     e.rho = P.rho;
+    if (P.restart_metric == 1) {
+        e.ry_c = P.fr_y;
+        e.rax_c = P.fr_ax;
+        e.ry_a = P.fa_y;
+        e.rax_a = P.fa_ax;
+    }
     return e;
 }
 __host__ __device__ inline EpiPrimal32H epi_primal32_h(const DevLP& P, const Scalars* sc, int it) {
@@ -835,6 +887,8 @@ __host__ __device__ inline EpiPrimal32H epi_primal32_h(const DevLP& P, const Sca
     e.x = P.dx;
     e.xa = P.dxa;
     e.rho = static_cast<float>(P.rho);
+    e.rx_c = P.restart_metric == 1 ? P.fr_x : nullptr;
+    e.rx_a = P.restart_metric == 1 ? P.fa_x : nullptr;
     return e;
 }
 __host__ __device__ inline EpiDual32H epi_dual32_h(const DevLP& P, const Scalars* sc, int it) {
@@ -848,6 +902,12 @@ __host__ __device__ inline EpiDual32H epi_dual32_h(const DevLP& P, const Scalars
     e.ya = P.dya;
     e.ax = P.adx;
     e.rho = static_cast<float>(P.rho);
+    if (P.restart_metric == 1) {
+        e.ry_c = P.fr_y;
+        e.rax_c = P.fr_ax;
+        e.ry_a = P.fa_y;
+        e.rax_a = P.fa_ax;
+    }
     return e;
 }
 
@@ -1241,21 +1301,55 @@ __device__ inline void eval_terms(const DevLP& P, int mode, int start, int strid
     }
 }
 
+// Residual restarts (Halpern form, restart_metric 1): whether they are on, and their sums over
+// rows and columns start, start + stride, ...: ||dx||^2, <dy, A~dx>, ||dy||^2 of the last
+// iterate's z - T(z) (0..2) and of the anchor's (3..5).
+__device__ inline bool residual_restarts(const DevLP& P) { return P.method != 0 && P.restart_metric == 1; }
+
+__device__ inline void residual_terms(const DevLP& P, int start, int stride, double* acc) {
+    for (int i = start; i < P.m; i += stride) {
+        const double dc = P.fr_y[i], da = P.fa_y[i];
+        acc[1] += dc * P.fr_ax[i];
+        acc[2] += dc * dc;
+        acc[4] += da * P.fa_ax[i];
+        acc[5] += da * da;
+    }
+    for (int j = start; j < P.n; j += stride) {
+        const double dc = P.fr_x[j], da = P.fa_x[j];
+        acc[0] += dc * dc;
+        acc[3] += da * da;
+    }
+}
+
 // Partial sums of the evaluation quantities (see eval_terms) of one block. mode 1 (initial point) and
 // mode 2 (final point after a stop) evaluate the current iterate only; mode 2 runs whatever
 // the status.
 __device__ void kkt_partials_body(const DevLP& P, int mode, int blk, int nblk) {
     __shared__ double red[kBlock / 64][kNT];
     if (mode != 2 && P.sc->status != kRunning) return;
-    double acc[kNT];
-#pragma unroll
-    for (int q = 0; q < kNT; ++q) acc[q] = 0.0;
-    eval_terms(P, mode, blk * kBlock + threadIdx.x, nblk * kBlock, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    {
+        constexpr int kMain = kNT - kNF;
+        double acc[kMain];
 #pragma unroll
-    for (int q = 0; q < kNT; ++q) {
-        const double v = wave_sum(acc[q]);
-        if (lane == 0) red[w][q] = v;
+        for (int q = 0; q < kMain; ++q) acc[q] = 0.0;
+        eval_terms(P, mode, blk * kBlock + threadIdx.x, nblk * kBlock, acc);
+#pragma unroll
+        for (int q = 0; q < kMain; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red[w][q] = v;
+        }
+    }
+    {
+        double acc[kNF];
+#pragma unroll
+        for (int q = 0; q < kNF; ++q) acc[q] = 0.0;
+        if (mode == 0 && residual_restarts(P)) residual_terms(P, blk * kBlock + threadIdx.x, nblk * kBlock, acc);
+#pragma unroll
+        for (int q = 0; q < kNF; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red[w][kNT - kNF + q] = v;
+        }
     }
     __syncthreads();
     if (threadIdx.x < kNT) {
@@ -1357,8 +1451,17 @@ __device__ void decide_logic(const DevLP& P, Scalars* sc, const double* tot, int
     const long long k = sc->k + ex;
     long long t = sc->t + ex;
     const double omega = sc->omega;
-    const double kc = kkt_w(cur.rps2, cur.rds2, cur.pobj - cur.dobj, omega);
-    const double ka = kkt_w(avg.rps2, avg.rds2, avg.pobj - avg.dobj, omega);
+    double kc = kkt_w(cur.rps2, cur.rds2, cur.pobj - cur.dobj, omega);
+    double ka = kkt_w(avg.rps2, avg.rds2, avg.pobj - avg.dobj, omega);
+    if (residual_restarts(P)) {
+        // the restart tests compare fixed-point residuals in the norm of the PDHG map:
+        // r^2 = omega ||dx||^2 + 2 eta <dy, A~dx> + ||dy||^2 / omega
+        const double* f = tot + 2 * kNQ + kNR;
+        const double rc2 = omega * f[0] + 2.0 * sc->eta * f[1] + f[2] / omega;
+        const double ra2 = omega * f[3] + 2.0 * sc->eta * f[4] + f[5] / omega;
+        kc = ka = sqrt(rc2 > 0.0 ? rc2 : 0.0);
+        sc->kkt_anchor = sqrt(ra2 > 0.0 ? ra2 : 0.0);
+    }
     double rec[kTraceW];
     for (int f = 0; f < kTraceW; ++f) rec[f] = 0.0;
     rec[0] = (double)k;
@@ -1481,7 +1584,7 @@ __device__ void decide_body(const DevLP& P, int mode) {
     __shared__ double tot[kNT];
     Scalars* sc = P.sc;
     if (mode != 2 && sc->status != kRunning) return;
-    const int nq = (mode == 0) ? kNT : kNQ;
+    const int nq = (mode == 0) ? (residual_restarts(P) ? kNT : kNT - kNF) : kNQ;
     for (int q = 0; q < nq; ++q) {
         double v = 0.0;
         for (int b = threadIdx.x; b < P.nred; b += kBlock) v += P.partials[b * kNT + q];
@@ -1702,15 +1805,30 @@ __device__ void wg_step(const Csr& M, const T* xin, Epi e, double* lds, double* 
 // KKT quantities of the current iterate (and of the average in mode 0, of the candidate rays
 // in mode 0) summed over the whole LP by one workgroup in a fixed order; tot[] in LDS afterwards.
 __device__ void wg_kkt(const DevLP& P, int mode, double* tot, double* red16) {
-    double acc[kNT];
-#pragma unroll
-    for (int q = 0; q < kNT; ++q) acc[q] = 0.0;
-    eval_terms(P, mode, threadIdx.x, kBlock, acc);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    {
+        constexpr int kMain = kNT - kNF;
+        double acc[kMain];
 #pragma unroll
-    for (int q = 0; q < kNT; ++q) {
-        const double v = wave_sum(acc[q]);
-        if (lane == 0) red16[w * kNT + q] = v;
+        for (int q = 0; q < kMain; ++q) acc[q] = 0.0;
+        eval_terms(P, mode, threadIdx.x, kBlock, acc);
+#pragma unroll
+        for (int q = 0; q < kMain; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red16[w * kNT + q] = v;
+        }
+    }
+    // the residual-restart sums in a pass of their own (their slots stay 0 when off)
+    {
+        double acc[kNF];
+#pragma unroll
+        for (int q = 0; q < kNF; ++q) acc[q] = 0.0;
+        if (mode == 0 && residual_restarts(P)) residual_terms(P, threadIdx.x, kBlock, acc);
+#pragma unroll
+        for (int q = 0; q < kNF; ++q) {
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) red16[w * kNT + kNT - kNF + q] = v;
+        }
     }
     __syncthreads();
     if (threadIdx.x < kNT) {
