@@ -66,10 +66,13 @@ typedef enum {
                                  A^T y + z = 0 up to eps_infeas and ray objective
                                  sum_i (b_lo y_i^+ - b_hi y_i^-) + sum_k (x_lo z_k^+ - x_hi z_k^-) = 1;
                                  x is the last iterate */
-    LP_DUAL_INFEASIBLE = 5    /* the dual has no solution (the LP is unbounded if it is feasible):
+    LP_DUAL_INFEASIBLE = 5,   /* the dual has no solution (the LP is unbounded if it is feasible):
                                  x is a primal ray with c^T x = -1 and A x, x inside the recession
                                  cones of the row and variable bounds up to eps_infeas; y, z are
                                  the last iterate's */
+    LP_CANCELLED = 6          /* a server request stopped by lp_server_cancel: the point and
+                                 statistics of its current iterate when it was running, no point
+                                 (x, y, z NaN, 0 iterations) when it was still queued */
 } lp_termination;
 
 typedef enum {
@@ -425,6 +428,15 @@ int32_t lp_server_result(lp_server *srv, uint64_t ticket, double *x, double *y, 
  * completion instants in seconds on the server's clock. Never blocks. */
 int32_t lp_server_poll(lp_server *srv, uint64_t *done_tickets, int32_t cap, int32_t *n_done);
 int32_t lp_server_ticket_times(lp_server *srv, uint64_t ticket, double *times);
+
+/* Cancel a request. Still queued (not admitted): it completes at once with LP_CANCELLED and
+ * no point. Admitted (being set up or running): the worker stops it after the current round
+ * (one evaluation period) with LP_CANCELLED and the point and statistics of its current
+ * iterate, as a host-side stop of lp_solve gives them, and releases its device memory and
+ * slot. A request that completes on its own before the worker acts keeps its own status.
+ * LP_ERR_INVALID_ARG for a ticket that is not pending (unknown, completed, or already
+ * cancelled). Not an operation of the paper: the serving form's way to drop work. */
+int32_t lp_server_cancel(lp_server *srv, uint64_t ticket);
 
 /* Block until every submitted request has completed, or until timeout_s seconds (<= 0: no
  * limit); LP_ERR_INTERNAL on timeout. */

@@ -21,7 +21,7 @@ ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONS
           4: "LP_ERR_NAN_INPUT", 5: "LP_ERR_OUT_OF_MEMORY", 6: "LP_ERR_DEVICE", 7: "LP_ERR_NOT_SOLVED",
           8: "LP_ERR_INTERNAL"}
 STATUS = {0: "optimal", 1: "iteration_limit", 2: "time_limit", 3: "numerical_error", 4: "primal_infeasible",
-          5: "dual_infeasible"}
+          5: "dual_infeasible", 6: "cancelled"}
 LP_METHOD_AVERAGED = 0
 LP_METHOD_HALPERN = 1
 LP_PW_DEFAULT = 0
@@ -49,7 +49,7 @@ EXPORTS = (
     "lp_export_state", "lp_import_state", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
-    "lp_server_ticket_times", "lp_server_result", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
+    "lp_server_ticket_times", "lp_server_result", "lp_server_cancel", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
     "lp_presolve_default_options", "lp_presolve", "lp_presolve_get_info", "lp_presolve_get_reduced",
     "lp_presolve_get_maps", "lp_postsolve", "lp_presolve_destroy",
 )
@@ -190,6 +190,8 @@ def lib():
         L.lp_server_ticket_times.restype = I32
         L.lp_server_result.argtypes = [P, C.c_uint64, P, P, P, P]
         L.lp_server_result.restype = I32
+        L.lp_server_cancel.argtypes = [P, C.c_uint64]
+        L.lp_server_cancel.restype = I32
         L.lp_server_wait.argtypes = [P, D]
         L.lp_server_wait.restype = I32
         L.lp_server_stats_get.argtypes = [P, P]
@@ -527,6 +529,10 @@ class Server:
         t = (C.c_double * 3)()
         _check(lib().lp_server_ticket_times(self.h, C.c_uint64(ticket), t))
         return tuple(t)
+
+    def cancel(self, ticket: int):
+        """lp_server_cancel: a queued request completes at once, a running one after the round."""
+        _check(lib().lp_server_cancel(self.h, C.c_uint64(ticket)))
 
     def wait(self, timeout_s: float = 0.0):
         _check(lib().lp_server_wait(self.h, float(timeout_s)))

@@ -15,6 +15,8 @@
 #include <mutex>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1216,6 +1218,7 @@ struct lp_server {
     std::vector<uint64_t> done;
     std::unordered_map<uint64_t, Ticket> finished;       // completed, result not fetched yet
     std::unordered_map<uint64_t, std::array<double, 3>> times;  // submit, admit, done
+    std::unordered_set<uint64_t> cancels;  // admitted requests to stop at the end of the current round
     uint64_t next_ticket = 1;
     bool stop = false;
     lp_server_stats st{};
@@ -1324,6 +1327,44 @@ void server_round(lp_server* S, DevMaps& run_maps, DevMaps& new_maps, bool& dirt
             S->st.lp_iterations += work_it;
             S->st.nnz_iterations += work_nnz;
         }
+    }
+    // cancelled requests of the running set: stopped here, between rounds, with the statistics
+    // and the point of their current iterate (the evaluation a host-side stop runs)
+    std::vector<Ticket> cancelled;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (!S->cancels.empty() && !S->running.empty()) {
+            std::vector<Ticket> keep;
+            for (Ticket& t : S->running) (S->cancels.erase(t.id) ? cancelled : keep).push_back(t);
+            if (!cancelled.empty()) {
+                S->running = keep;
+                S->st.running = static_cast<int64_t>(S->running.size());
+            }
+        }
+    }
+    if (!cancelled.empty()) {
+        for (Ticket& t : cancelled) {
+            set_form(t.h->P, S->opt);  // the form the server's launches ran it in
+            launch_stop(t.h->P, LP_CANCELLED, s);
+            launch_evaluate(t.h->P, 2, s);
+            launch_extract(t.h->P, s);
+            (void)hipMemcpyAsync(t.h->h_sc, t.h->P.sc, sizeof(Scalars), hipMemcpyDeviceToHost, s);
+        }
+        (void)hipStreamSynchronize(s);
+        int64_t work_it = 0;
+        double work_nnz = 0.0;
+        for (Ticket& t : cancelled) {
+            fill_info(t.h);
+            t.h->solved = true;
+            const int64_t extra = t.h->info.iterations - t.counted;
+            work_it += extra;
+            work_nnz += static_cast<double>(extra) * static_cast<double>(t.h->nnz);
+            finished.push_back(t);
+        }
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->st.lp_iterations += work_it;
+        S->st.nnz_iterations += work_nnz;
+        dirty = true;
     }
     if (!finished.empty()) {
         for (Ticket& t : finished) {
@@ -1471,6 +1512,38 @@ int32_t lp_server_ticket_times(lp_server* S, uint64_t ticket, double* times) {
     auto it = S->times.find(ticket);
     if (it == S->times.end()) return fail(nullptr, LP_ERR_NOT_SOLVED, "ticket not completed");
     for (int k = 0; k < 3; ++k) times[k] = it->second[k];
+    return LP_OK;
+}
+
+int32_t lp_server_cancel(lp_server* S, uint64_t ticket) {
+    if (!S) return fail(nullptr, LP_ERR_INVALID_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+        if (it->id != ticket) continue;
+        // not admitted yet: completed at once, without a point
+        Ticket t = *it;
+        S->queue.erase(it);
+        lp_handle* h = t.h;
+        h->info = lp_info{};
+        h->info.status = LP_CANCELLED;
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        h->res_x.assign(static_cast<size_t>(h->n), nan);
+        h->res_y.assign(static_cast<size_t>(h->m), nan);
+        h->res_z.assign(static_cast<size_t>(h->n), nan);
+        h->solved = true;
+        t.t_done = S->now();
+        S->st.queued--;
+        S->st.completed++;
+        S->done.push_back(t.id);
+        S->finished[t.id] = t;
+        S->times[t.id] = {t.t_submit, t.t_admit, t.t_done};
+        S->cv_idle.notify_all();
+        return LP_OK;
+    }
+    if (ticket == 0 || ticket >= S->next_ticket || S->times.count(ticket) || S->cancels.count(ticket))
+        return fail(nullptr, LP_ERR_INVALID_ARG, "ticket is not pending (unknown, completed or already cancelled)");
+    S->cancels.insert(ticket);  // admitted: the worker stops it after the current round
+    S->cv_work.notify_one();
     return LP_OK;
 }
 
