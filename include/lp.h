@@ -531,6 +531,17 @@ int32_t lp_get_solution(lp_handle *h, double *x, double *y, double *z, lp_info *
 /* Release everything the handle owns. NULL is ignored. */
 void lp_destroy(lp_handle *h);
 
+/* The checked build (liblpgpu_checked.so, compiled with LPGPU_CHECKED=1) bounds-checks every
+ * gathered column and every accumulator row in the product kernels: an index outside its
+ * array sets a bit of a per-device word (1 panel gather, 2 panel accumulator row, 4 row-tile
+ * gather, 8 long-row gather) and is replaced by 0, so the kernel goes on without reading
+ * outside its arrays. lp_solve, lp_solve_until, lp_resume, lp_polish, lp_solve_batch and
+ * lp_solve_batch_static of that build return LP_ERR_INTERNAL when the word is set after them.
+ * lp_check_word reads and clears the word of `device` (for servers and for callers of the
+ * plain build) and sets *checked to 1 in the checked build, 0 otherwise (*word is then 0).
+ * A debugging aid, not an operation of the paper. */
+int32_t lp_check_word(int32_t device, uint32_t *word, int32_t *checked);
+
 /* Static description of an error code. */
 const char *lp_error_string(int32_t code);
 

@@ -14,7 +14,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("LPGPU_LIB_OVERRIDE", os.path.join(_HERE, "_lib", "liblpgpu.so"))
+# LPGPU_CHECKED=1 loads the bounds-checked build (include/lp.h, lp_check_word)
+LIB_PATH = os.environ.get("LPGPU_LIB_OVERRIDE", os.path.join(
+    _HERE, "_lib", "liblpgpu_checked.so" if os.environ.get("LPGPU_CHECKED") == "1" else "liblpgpu.so"))
 
 LP_OK = 0
 ERRORS = {1: "LP_ERR_INVALID_ARG", 2: "LP_ERR_INVALID_MATRIX", 3: "LP_ERR_INCONSISTENT_BOUNDS",
@@ -46,7 +48,7 @@ LP_STATIC_BATCH_MAX = 4096  # include/lp.h
 # names of every function include/lp.h declares
 EXPORTS = (
     "lp_default_options", "lp_preset_options", "lp_create", "lp_update_options", "lp_solve", "lp_polish", "lp_solve_until", "lp_resume",
-    "lp_export_state", "lp_import_state", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_error_string",
+    "lp_export_state", "lp_import_state", "lp_solve_batch", "lp_solve_batch_static", "lp_get_solution", "lp_destroy", "lp_check_word", "lp_error_string",
     "lp_last_error", "lp_get_iterates", "lp_get_scaled", "lp_get_trace", "lp_set_kernel_timing",
     "lp_get_kernel_times", "lp_get_layout", "lp_server_create", "lp_server_submit", "lp_server_poll",
     "lp_server_ticket_times", "lp_server_result", "lp_server_cancel", "lp_server_wait", "lp_server_stats_get", "lp_server_destroy",
@@ -164,6 +166,8 @@ def lib():
         L.lp_get_solution.restype = I32
         L.lp_destroy.argtypes = [P]
         L.lp_destroy.restype = None
+        L.lp_check_word.argtypes = [I32, P, P]
+        L.lp_check_word.restype = I32
         L.lp_error_string.argtypes = [I32]
         L.lp_error_string.restype = C.c_char_p
         L.lp_last_error.argtypes = [P]
@@ -300,6 +304,14 @@ def lp_get_solution(h, x=None, y=None, z=None) -> lp_info:
 def lp_destroy(h):
     if h:
         lib().lp_destroy(h)
+
+
+def lp_check_word(device: int = 0):
+    """(word, checked): the device check word (read and cleared) and whether this library is
+    the checked build."""
+    w, c = C.c_uint32(), C.c_int32()
+    _check(lib().lp_check_word(int(device), C.byref(w), C.byref(c)))
+    return w.value, bool(c.value)
 
 
 def lp_error_string(code: int) -> str:

@@ -975,13 +975,14 @@ int32_t device_setup(lp_handle* h, const int32_t* rp, const int32_t* ci, const d
     P.n = n;
     P.nnz = nnz;
     P.nred = Q.nred;
-    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), Q.shape, I(O.arp), I(O.aci), D(O.av), I(O.at), nullptr, nullptr};
-    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), Q.shape, I(O.trp), I(O.tci), D(O.tv), I(O.tt), nullptr, nullptr};
+    P.A.csr = Csr{m, ntA, static_cast<int>(nnz), Q.shape, I(O.arp), I(O.aci), D(O.av), I(O.at), nullptr, nullptr, n};
+    P.AT.csr = Csr{n, ntAT, static_cast<int>(nnz), Q.shape, I(O.trp), I(O.tci), D(O.tv), I(O.tt), nullptr, nullptr, m};
     P.A.layout = P.AT.layout = panels ? 0 : 1;
     auto bind_layout = [&](const PanelLayoutHost& L, const size_t* off, Mat& M) {
         M.pan = Panels{L.units, L.panels, L.col_bits, static_cast<int>(L.nnz_packed), L.max_unit_rows, I(off[0]), I(off[1]),
                        reinterpret_cast<const unsigned*>(b + off[2]), D(off[3]),
-                       L.is_long.empty() ? nullptr : reinterpret_cast<const unsigned char*>(b + off[6]), nullptr};
+                       L.is_long.empty() ? nullptr : reinterpret_cast<const unsigned char*>(b + off[6]), nullptr,
+                       M.csr.cols};
         M.nlong = static_cast<int>(L.long_rows.size());
         M.longrows = M.nlong ? I(off[5]) : nullptr;
     };
@@ -1684,6 +1685,15 @@ int32_t lp_preset_options(lp_options* o, int32_t preset) {
     return LP_OK;
 }
 
+int32_t lp_check_word(int32_t device, uint32_t* word, int32_t* checked) {
+    if (!word || !checked) return fail(nullptr, LP_ERR_INVALID_ARG, "word or checked NULL");
+    *checked = kChecked ? 1 : 0;
+    unsigned w = 0;
+    if (read_check_word(device, &w) != 0) return fail(nullptr, LP_ERR_DEVICE, "reading the device check word failed");
+    *word = w;
+    return LP_OK;
+}
+
 const char* lp_error_string(int32_t code) {
     switch (code) {
         case LP_OK: return "ok";
@@ -1984,6 +1994,16 @@ StateHeader state_header(const lp_handle* h, int64_t n_records) {
     return H;
 }
 
+// The checked build's report after a call that ran kernels on `device`: LP_ERR_INTERNAL when
+// a kernel met an index outside its array (the check word's bits in the message).
+int32_t with_checks(lp_handle* h, int device, int32_t rc) {
+    if (!kChecked || rc != LP_OK) return rc;
+    unsigned w = 0;
+    if (read_check_word(device, &w) != 0) return fail(h, LP_ERR_DEVICE, "reading the device check word failed");
+    if (w) return fail(h, LP_ERR_INTERNAL, "device index check failed (bits " + std::to_string(w) + ")");
+    return LP_OK;
+}
+
 // Statistics and extraction of the paused point (after a pause or a state import).
 int32_t finish_paused(lp_handle* h) {
     hipStream_t s = h->stream;
@@ -2009,7 +2029,7 @@ int32_t lp_solve(lp_handle* h) {
         if (int32_t rc = materialize(h)) return rc;
         const int32_t rc = solve_from(h, h->d_x0, h->d_y0, 0, 0.0);
         h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
-        return rc;
+        return with_checks(h, h->device, rc);
     } catch (...) {
         return fail(h, LP_ERR_INTERNAL, "unexpected exception");
     }
@@ -2096,7 +2116,7 @@ int32_t lp_polish(lp_handle* h, double eps, int64_t max_iters) {
         h->info.polish_dual_iterations = dit;
         h->info.solve_seconds = before;
         h->info.polish_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return LP_OK;
+        return with_checks(h, h->device, LP_OK);
     } catch (...) {
         return fail(h, LP_ERR_INTERNAL, "unexpected exception");
     }
@@ -2110,7 +2130,7 @@ int32_t lp_solve_until(lp_handle* h, int64_t k_pause) {
         if (int32_t rc = materialize(h)) return rc;
         const int32_t rc = solve_from(h, h->d_x0, h->d_y0, 0, 0.0, k_pause);
         h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
-        return rc;
+        return with_checks(h, h->device, rc);
     } catch (...) {
         return fail(h, LP_ERR_INTERNAL, "unexpected exception");
     }
@@ -2144,7 +2164,7 @@ int32_t lp_resume(lp_handle* h, int64_t k_pause) {
         h->solved = false;
         const int32_t rc = run_periods(h, t0, k_pause);
         h->info.polish_primal_iterations = h->info.polish_dual_iterations = 0;
-        return rc;
+        return with_checks(h, h->device, rc);
     } catch (...) {
         return fail(h, LP_ERR_INTERNAL, "unexpected exception");
     }
@@ -2273,7 +2293,7 @@ int32_t lp_solve_batch(lp_handle* const* hs, int32_t count, const lp_options* bo
         }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         for (int32_t i = 0; i < count; ++i) hs[i]->info.solve_seconds = secs;
-        return LP_OK;
+        return with_checks(nullptr, dev, LP_OK);
     } catch (const std::bad_alloc&) {
         return fail(nullptr, LP_ERR_OUT_OF_MEMORY, "host allocation failed");
     } catch (...) {
@@ -2349,7 +2369,7 @@ int32_t lp_solve_batch_static(lp_handle* const* hs, int32_t count, const lp_opti
             hs[i]->info.solve_seconds = secs;
             hs[i]->solved = true;
         }
-        return LP_OK;
+        return with_checks(nullptr, dev, LP_OK);
     } catch (...) {
         return fail(nullptr, LP_ERR_INTERNAL, "unexpected exception");
     }

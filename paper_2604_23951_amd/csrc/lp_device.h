@@ -66,6 +66,7 @@ struct Csr {
     const int* tiles;
     const int* rowlist;
     const float* v32;  // FP32 copy of v (FP32 storage form only)
+    int cols;          // length of the vector the products gather from
 };
 
 // Panel-packed layout (see lp_layout.h): unit u (one wave) owns rows
@@ -83,7 +84,19 @@ struct Panels {
     const double* v;
     const unsigned char* is_long;  // nullptr when the matrix has no long rows
     const float* v32;              // FP32 copy of v (FP32 storage form only)
+    int cols;                      // length of the gathered vector
 };
+
+// Index checks of the checked build (compiled with LPGPU_CHECKED=1): a gathered column or
+// an accumulator row outside its array sets a bit of a device word and is replaced by 0, so
+// the kernel reads nothing outside its arrays; the host reports the word after a call.
+// Bits: 1 panel gather, 2 panel accumulator row, 4 row-tile gather, 8 long-row gather.
+#ifndef LPGPU_CHECKED
+#define LPGPU_CHECKED 0
+#endif
+constexpr bool kChecked = LPGPU_CHECKED != 0;
+// Reads and clears the check word of `device` (0 in a build without checks).
+int read_check_word(int device, unsigned* word);
 
 constexpr int kUnitRowCap = 2048;  // rows per wave unit at most
 constexpr int kChunks = 4;         // 64-entry chunks a wave loads together (one group)

@@ -19,9 +19,25 @@
 
 #include <mutex>
 
+// Check word of the checked build (see lp_device.h); unused otherwise.
+__device__ unsigned int lp_check_word;
+
 namespace lpgpu {
 
 namespace {
+
+// An index into an array of n elements: itself, or, in the checked build when out of range,
+// 0 with `bit` set in the check word.
+template <class I>
+__device__ inline I checked_index(I i, int n, unsigned bit) {
+    if constexpr (kChecked) {
+        if (static_cast<unsigned>(i) >= static_cast<unsigned>(n)) {
+            atomicOr(&lp_check_word, bit);
+            return I(0);
+        }
+    }
+    return i;
+}
 
 __device__ inline double clampd(double v, double lo, double hi) {
     if (v < lo) v = lo;
@@ -145,7 +161,7 @@ __device__ void row_tree_body(const Csr& M, int r, const T* __restrict__ xin, co
             if (base + tid + k * kBlock >= p1) col[k] = 0;
         T xv[kPerThread];
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
+        for (int k = 0; k < kPerThread; ++k) xv[k] = xin[checked_index(col[k], M.cols, 8u)];
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) {
             const T pr = val[k] * xv[k];
@@ -191,7 +207,7 @@ __device__ void tile_body(const Csr& M, int b, const T* __restrict__ xin, const 
             if (p0 + tid + k * kBlock >= p1) col[k] = 0;
         T xv[kPerThread];
 #pragma unroll
-        for (int k = 0; k < kPerThread; ++k) xv[k] = xin[col[k]];
+        for (int k = 0; k < kPerThread; ++k) xv[k] = xin[checked_index(col[k], M.cols, 4u)];
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) prod[tid + k * kBlock] = val[k] * xv[k];
         __syncthreads();
@@ -277,6 +293,7 @@ struct PanelBuf {
 
 struct PanelUnit {
     int s, e, last, lane, cb;
+    int cols, rows;  // gathered vector length, accumulator rows (the checked build's bounds)
     unsigned cmask;
     __device__ int chunk_start(int g, int c) const { return s + (g * kChunks + c) * 64; }
 };
@@ -298,7 +315,7 @@ __device__ inline void panel_gather(PanelGroups<T>& G, int S, int X, int g, cons
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
         const unsigned col = U.chunk_start(g, c) + U.lane < U.e ? (G.pk[S][c] & U.cmask) : 0u;
-        G.xv[X][c] = xin[col];
+        G.xv[X][c] = xin[checked_index(col, U.cols, 1u)];
     }
 }
 
@@ -338,7 +355,7 @@ __device__ inline void panel_produce(PanelGroups<T>& G, int g, const PanelUnit& 
     T v[kChunks];
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
-        row[c] = static_cast<int>(G.pk[S][c] >> U.cb);
+        row[c] = static_cast<int>(checked_index(G.pk[S][c] >> U.cb, U.rows, 2u));
         v[c] = G.val[S][c];
     }
     panel_load(G, S, g + kStreamDepth, U, pkp, pvp);
@@ -418,6 +435,8 @@ __global__ __launch_bounds__(kBlock) void spmv_panel_kernel(Panels M, Csr L, int
     U.lane = lane;
     U.cb = M.col_bits;
     U.cmask = (1u << M.col_bits) - 1u;
+    U.cols = M.cols;
+    U.rows = M.max_rows;
     const unsigned* __restrict__ pkp = M.pk;
     const T* __restrict__ pvp = vals_of<T>(M);
     // Both roles run the same group steps with one barrier after each (the loops below have the
@@ -2565,6 +2584,20 @@ void launch_stop(const DevLP& P, int status, hipStream_t s) {
 void launch_extract(const DevLP& P, hipStream_t s) {
     const int mx = P.m > P.n ? P.m : P.n;
     hipLaunchKernelGGL(extract_kernel, dim3(grid_for(mx)), dim3(kBlock), 0, s, P);
+}
+
+}  // namespace lpgpu
+
+namespace lpgpu {
+
+int read_check_word(int device, unsigned* word) {
+    *word = 0;
+    if (!kChecked) return 0;
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(word, HIP_SYMBOL(lp_check_word), sizeof(unsigned), 0, hipMemcpyDeviceToHost);
+    const unsigned zero = 0;
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(lp_check_word), &zero, sizeof(unsigned), 0, hipMemcpyHostToDevice);
+    return static_cast<int>(e);
 }
 
 }  // namespace lpgpu
