@@ -1,8 +1,9 @@
 """Parity at the full size of the large workload (m = 1e6, n = 2e6, nnz = 1.2e7), in the
 launch configuration the benchmark times: the scaled matrix and its transpose bit-exact,
 the iterates over the first 200 iterations (crossing the first three evaluations and the
-first restart) element by element against the oracle, and converged points checked by the
-oracle's KKT function on the original data against the known optimum."""
+first restart) element by element against the oracle, converged points checked by the
+oracle's KKT function on the original data against the known optimum, and a run paused,
+carried to another handle and resumed equal to the straight run bit for bit."""
 import numpy as np
 import pytest
 
@@ -105,3 +106,31 @@ def test_full_size_fp64_halpern_to_tolerance(oracle_lib, big):
     assert chk["erel"] <= 1e-4 * (1 + 1e-9)
     assert abs(chk["erel"] - sol.info.rel_kkt) <= 1e-8 * chk["erel"]
     assert rel_obj <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [lpg.LP_PREC_FP64, lpg.LP_PREC_FP32_REFINED])
+def test_full_size_pause_export_resume(big, precision):
+    """Checkpoint and resume at full size, in the benchmark's launch configuration: 384
+    iterations straight against a pause after 128, the state carried through a host buffer
+    to a second handle and resumed there; iterates, returned point and trace bit-identical."""
+    lp = big
+    opts = dict(eps_rel=0.0, max_iters=384, pow_iters=20, precision=precision)
+    print(f"full-size checkpoint, precision {precision}", flush=True)
+    with lpg.Solver(lp, **opts) as s:
+        ref = s.solve(with_trace=True)
+        ref_it = s.iterates()
+    with lpg.Solver(lp, **opts) as a:
+        paused = a.solve_until(100)
+        assert paused.status == "iteration_limit" and paused.info.iterations == 128
+        state = a.export_state()
+    with lpg.Solver(lp, **opts) as b:
+        b.import_state(state)
+        del state
+        out = b.resume(with_trace=True)
+        out_it = b.iterates()
+    assert (out.status, out.info.iterations, out.info.restarts) == (ref.status, ref.info.iterations, ref.info.restarts)
+    np.testing.assert_array_equal(out.trace, ref.trace)
+    for u, v in zip((out.x, out.y, out.z), (ref.x, ref.y, ref.z)):
+        np.testing.assert_array_equal(u, v)
+    for u, v in zip(out_it, ref_it):
+        np.testing.assert_array_equal(u, v)
