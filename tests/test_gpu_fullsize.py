@@ -134,3 +134,28 @@ def test_full_size_pause_export_resume(big, precision):
         np.testing.assert_array_equal(u, v)
     for u, v in zip(out_it, ref_it):
         np.testing.assert_array_equal(u, v)
+
+
+def test_full_size_residual_restarts_first_200(oracle_lib, big):
+    """The Halpern form with residual restarts at full size against the oracle: iterates
+    (Halpern iterate and T(z)) at iterations around the first three evaluations within 1e-12,
+    and the decision trace (restart reasons, the residuals of the last iterate and of the
+    anchor)."""
+    lp = big
+    ks = [1, 64, 65, 128, 129, 192, 200]
+    kw = dict(method=1, restart_metric=1)
+    ref = oracle.solve(lp, eps_rel=0.0, max_iters=max(ks), pow_iters=20, snap_k=ks, **kw)
+    print("full-size residual restarts: oracle done", flush=True)
+    with lpg.Solver(lp, eps_rel=0.0, max_iters=1, pow_iters=20, **kw) as s:
+        for i, k in enumerate(ks):
+            s.update(eps_rel=0.0, max_iters=k, **kw)
+            sol = s.solve(with_trace=True)
+            assert sol.info.iterations == k
+            for a, b in zip(s.iterates(), oracle.split_snap(ref.snaps[i], lp.n, lp.m)):
+                d = float(np.max(np.abs(a - b))) / max(1.0, float(np.max(np.abs(b))))
+                assert d <= 1e-12, (k, d)
+        tr = sol.trace
+    ot = ref.trace
+    assert len(tr) == len(ot)
+    np.testing.assert_array_equal(tr[:, [0, 1, 6, 7]], ot[:, [0, 1, 6, 7]])
+    np.testing.assert_allclose(tr[:, [2, 3, 8, 9]], ot[:, [2, 3, 8, 9]], rtol=1e-9)
